@@ -1,0 +1,544 @@
+// CPU oracle for the inter-workgroup synchronization primitives of
+// Stuart & Owens, "Efficient Synchronization Primitives for GPUs" (2011).
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and the
+// CPU-baseline leg of the benchmark may load or call this library.  It shares no code,
+// header, table or constant with the GPU library: everything here is written from the
+// paper and from the plain definitions of the synthetic workloads.
+//
+// Two independent parts:
+//   (O1) closed forms -- sequential, single-threaded definitions of every workload's
+//        output.  These are the bit-exact expected values.
+//   (O2) threaded reference -- one std::thread per agent (an agent is one workgroup
+//        acting with "block semantics", Section 3), shared words are
+//        std::atomic<uint32_t>, and each primitive follows Section 5 and the appendix
+//        algorithms.  It must reproduce (O1) and hold the invariants of Section 5's
+//        definitions (barrier phase, mutual exclusion, at most n inside a semaphore).
+//
+// Critical-section "non-atomic" updates are written as a relaxed load followed by a
+// relaxed store on std::atomic: a lost update (a mutual-exclusion bug) still shows up
+// in the counts, but the program has no data race in the C++ sense.
+//
+// Every function returns 0 on success or a negative code on a detected violation.
+
+#include <atomic>
+#include <chrono>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+extern "C" {
+
+// ------------------------------------------------------------------------------------
+// Counter-based hash used by all synthetic workloads.
+//
+// The paper defines no hash; the workloads use "splitmix32", read here as the 32-bit
+// golden-ratio increment (floor(2^32 / phi) = 0x9E3779B9) followed by the 32-bit
+// MurmurHash3 finalizer (fmix32).
+// ------------------------------------------------------------------------------------
+uint32_t or_fmix32(uint32_t z) {
+  z ^= z >> 16;
+  z *= 0x85EBCA6Bu;
+  z ^= z >> 13;
+  z *= 0xC2B2AE35u;
+  z ^= z >> 16;
+  return z;
+}
+
+uint32_t or_sm32(uint32_t x) { return or_fmix32(x + 0x9E3779B9u); }
+
+// Per-(agent, operation, stream) key for the mutex and semaphore schedules:
+// key(b, j, s) = sm32(sm32(sm32(seed ^ s) ^ b) ^ j).
+uint32_t or_key(uint32_t seed, uint32_t b, uint32_t j, uint32_t s) {
+  return or_sm32(or_sm32(or_sm32(seed ^ s) ^ b) ^ j);
+}
+
+// Hash chain of the serving workload: h_0 = x, h_{i+1} = sm32(h_i), result h_L.
+uint32_t or_chain(uint32_t x, uint32_t L) {
+  uint32_t h = x;
+  for (uint32_t i = 0; i < L; ++i) h = or_sm32(h);
+  return h;
+}
+
+void or_chain_batch(uint32_t seed, const uint32_t* L, uint32_t n, uint32_t* out) {
+  for (uint32_t r = 0; r < n; ++r) out[r] = or_chain(seed ^ r, L[r]);
+}
+
+// Number of operations agent b performs when `total` operations are split over nwg
+// agents: total / nwg each, and the first (total mod nwg) agents do one more.
+uint64_t or_ops_for_agent(uint32_t nwg, uint64_t total, uint32_t b) {
+  uint64_t base = total / nwg;
+  uint64_t extra = total % nwg;
+  return base + (b < extra ? 1 : 0);
+}
+
+// ------------------------------------------------------------------------------------
+// (O1) Closed forms
+// ------------------------------------------------------------------------------------
+
+// Hash-exchange barrier workload.  In round r agent b publishes
+// sm32(seed ^ (b << 16) ^ r), everyone passes the barrier, then agent b XORs the
+// value published by agent (b + r) mod N in the same round into its checksum.
+void or_barrier_closed(uint32_t seed, uint32_t N, uint32_t R, uint32_t* chk) {
+  for (uint32_t b = 0; b < N; ++b) {
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+      uint32_t src = (uint32_t)(((uint64_t)b + r) % N);
+      c ^= or_sm32(seed ^ (src << 16) ^ r);
+    }
+    chk[b] = c;
+  }
+}
+
+// Mutex workload: agent b's j-th acquisition takes lock key(b,j,1) mod L and adds one
+// to each of that lock's W words.  Final word value = number of acquisitions of the
+// lock.  words has L*W entries, lock-major.
+void or_mutex_closed(uint32_t seed, uint32_t nwg, uint64_t total, uint32_t L, uint32_t W,
+                     uint32_t* words) {
+  std::memset(words, 0, sizeof(uint32_t) * (size_t)L * W);
+  for (uint32_t b = 0; b < nwg; ++b) {
+    uint64_t A = or_ops_for_agent(nwg, total, b);
+    for (uint64_t j = 0; j < A; ++j) {
+      uint32_t lock = or_key(seed, b, (uint32_t)j, 1) % L;
+      for (uint32_t w = 0; w < W; ++w) words[(size_t)lock * W + w] += 1;
+    }
+  }
+}
+
+// Semaphore workload: agent b's admission checksum XOR_j sm32(seed ^ (b << 16) ^ j)
+// over its own wait/post pairs j.
+void or_sem_closed(uint32_t seed, uint32_t nwg, uint64_t total, uint32_t* chk) {
+  for (uint32_t b = 0; b < nwg; ++b) {
+    uint64_t A = or_ops_for_agent(nwg, total, b);
+    uint32_t c = 0;
+    for (uint64_t j = 0; j < A; ++j) c ^= or_sm32(seed ^ (b << 16) ^ (uint32_t)j);
+    chk[b] = c;
+  }
+}
+
+// Memory-system microbenchmark schedule: issuer u (u < U) performs operation i
+// (i < n) on position (u + i) mod T of the permutation perm, i.e. on word perm[...].
+// counts[t] = number of operations that target word t.
+void or_bench_counts(uint32_t U, uint64_t n, uint32_t T, const uint32_t* perm,
+                     uint64_t* counts) {
+  std::memset(counts, 0, sizeof(uint64_t) * T);
+  for (uint32_t u = 0; u < U; ++u)
+    for (uint64_t i = 0; i < n; ++i) counts[perm[(u + i) % T]] += 1;
+}
+
+// Same count for a single word: the number of (u, i) with (u + i) mod T == p, where p
+// is the word's position in the permutation.  For each issuer the hits are the i in
+// [0, n) congruent to (p - u) mod T.
+uint64_t or_bench_count_one(uint32_t U, uint64_t n, uint32_t T, uint32_t p) {
+  uint64_t c = 0;
+  for (uint32_t u = 0; u < U; ++u) {
+    uint64_t first = ((uint64_t)p + T - (u % T)) % T;  // smallest i with (u+i)%T == p
+    if (first < n) c += (n - 1 - first) / T + 1;
+  }
+  return c;
+}
+
+// Sum of (v mod 2^32) over the integers v in [a, a + c): the total of the values an
+// atomic increment returns when a word starting at a receives c increments.
+// Uses S(m) = sum of (v mod 2^32) for v in [0, m): full 2^32 cycles contribute
+// 2^31 * (2^32 - 1) each, the remainder q contributes q (q - 1) / 2.  Result mod 2^64.
+static uint64_t sum_mod32_prefix(unsigned __int128 m) {
+  const unsigned __int128 P = (unsigned __int128)1 << 32;
+  unsigned __int128 cycles = m / P, rem = m % P;
+  unsigned __int128 s = cycles * ((P * (P - 1)) / 2);
+  if (rem > 0) s += (rem * (rem - 1)) / 2;
+  return (uint64_t)s;
+}
+uint64_t or_sum_increments(uint32_t a, uint64_t c) {
+  unsigned __int128 lo = a, hi = (unsigned __int128)a + c;
+  return sum_mod32_prefix(hi) - sum_mod32_prefix(lo);
+}
+
+// Value written by issuer u's i-th exchange: sm32(sm32(seed ^ u) ^ i).
+uint32_t or_exch_value(uint32_t seed, uint32_t u, uint32_t i) {
+  return or_sm32(or_sm32(seed ^ u) ^ i);
+}
+
+// Prefill of word t for the load / store / exchange benchmarks: sm32(seed ^ t).
+uint32_t or_prefill(uint32_t seed, uint32_t t) { return or_sm32(seed ^ t); }
+
+// Closed forms of the microbenchmark outputs (op: 0 ADD, 1 CAS-increment, 2 EXCH,
+// 3 LD, 4 ST).  finals[t] is the final word value; *sum is the uint64 sum (mod 2^64)
+// of every value the operations returned.  For EXCH the final values are not unique
+// and the function returns instead, in *sum, the conserved quantity
+// sum(initial) + sum(written), which must equal sum(returned) + sum(final).
+int or_bench_closed(int op, uint32_t seed, uint32_t U, uint64_t n, uint32_t T,
+                    const uint32_t* perm, uint32_t* finals, uint64_t* sum) {
+  std::vector<uint64_t> counts(T);
+  or_bench_counts(U, n, T, perm, counts.data());
+  uint64_t s = 0;
+  switch (op) {
+    case 0:
+    case 1:  // words start at 0; each receives counts[t] increments
+      for (uint32_t t = 0; t < T; ++t) {
+        finals[t] = (uint32_t)counts[t];
+        s += or_sum_increments(0, counts[t]);
+      }
+      break;
+    case 2:  // exchange: conservation of the multiset of values
+      for (uint32_t t = 0; t < T; ++t) {
+        finals[t] = 0;  // not unique
+        s += or_prefill(seed, t);
+      }
+      for (uint32_t u = 0; u < U; ++u)
+        for (uint64_t i = 0; i < n; ++i) s += or_exch_value(seed, u, (uint32_t)i);
+      break;
+    case 3:  // load: words keep their prefill; each load returns it
+      for (uint32_t t = 0; t < T; ++t) {
+        finals[t] = or_prefill(seed, t);
+        s += counts[t] * (uint64_t)finals[t];
+      }
+      break;
+    case 4:  // store: words start at 0; every store to word t writes sm32(seed ^ t)
+      for (uint32_t t = 0; t < T; ++t) finals[t] = counts[t] ? or_prefill(seed, t) : 0u;
+      break;
+    default:
+      return -1;
+  }
+  *sum = s;
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------
+// (O2) Threaded reference
+// ------------------------------------------------------------------------------------
+
+unsigned or_hardware_threads(void) { return std::thread::hardware_concurrency(); }
+
+}  // extern "C"
+
+namespace {
+
+using Word = std::atomic<uint32_t>;
+
+// Wrap-safe "a has reached b" for monotone 32-bit counters.
+inline bool reached(uint32_t a, uint32_t b) { return (int32_t)(a - b) >= 0; }
+
+// Waits yield the core: agents (threads) outnumber host cores.
+inline void relax() { std::this_thread::yield(); }
+
+// Backoff of Section 5 (mutex): a counter I runs from Imin; after every failed attempt
+// the agent waits I units and increments I, and wraps to Imin once I exceeds Imax.  One
+// unit is one uncontended load.
+struct Backoff {
+  uint32_t imin, imax, i;
+  Word private_word{0};
+  Backoff(uint32_t lo, uint32_t hi) : imin(lo), imax(hi), i(lo) {}
+  void operator()() {
+    for (uint32_t k = 0; k < i; ++k) (void)private_word.load(std::memory_order_relaxed);
+    relax();
+    i += 1;
+    if (i > imax) i = imin;
+  }
+};
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double seconds() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+template <class F>
+double run_agents(uint32_t n, F&& body) {
+  std::vector<std::thread> threads;
+  threads.reserve(n);
+  std::atomic<uint32_t> ready{0};
+  std::atomic<bool> go{false};
+  for (uint32_t b = 0; b < n; ++b)
+    threads.emplace_back([&, b] {
+      ready.fetch_add(1);
+      while (!go.load(std::memory_order_acquire)) relax();
+      body(b);
+    });
+  while (ready.load() != n) relax();
+  Timer t;
+  go.store(true, std::memory_order_release);
+  for (auto& th : threads) th.join();
+  return t.seconds();
+}
+
+}  // namespace
+
+extern "C" {
+
+// Barrier kinds: 0 centralized counter, 1 hierarchical (groups of agents, then a top
+// counter), 2 decentralized flag barrier with a master agent (the "XF" barrier of
+// Section 5).  The workload is the hash exchange of or_barrier_closed; the published
+// values live in two slot arrays selected by round parity, so that a round-(r+1) store
+// can never overwrite a round-r value that has not been read yet.
+// Returns 0, or -2 if the phase check failed (an agent read a slot that did not hold
+// the value of the round it is in).
+int or_barrier_threaded(int kind, uint32_t seed, uint32_t N, uint32_t R, uint32_t groups,
+                        uint32_t* chk, double* seconds) {
+  if (N == 0 || kind < 0 || kind > 2) return -1;
+  if (groups == 0) groups = 1;
+  std::vector<Word> slot(2 * (size_t)N);
+  for (auto& s : slot) s.store(0);
+  Word cnt{0};
+  // hierarchical state
+  uint32_t G = groups < N ? groups : N;
+  std::vector<Word> gcnt(G), ggen(G);
+  for (uint32_t g = 0; g < G; ++g) gcnt[g].store(0), ggen[g].store(0);
+  Word top{0}, topgen{0};
+  // flag state
+  std::vector<Word> arrive(N), release(N);
+  for (uint32_t b = 0; b < N; ++b) arrive[b].store(0), release[b].store(0);
+  std::atomic<int> bad{0};
+
+  auto members = [&](uint32_t g) { return (N - g + G - 1) / G; };  // agents b with b%G==g
+
+  auto barrier = [&](uint32_t b, uint32_t r) {
+    const uint32_t stamp = r + 1;
+    if (kind == 0) {
+      cnt.fetch_add(1, std::memory_order_acq_rel);
+      const uint32_t target = N * stamp;
+      while (!reached(cnt.load(std::memory_order_acquire), target)) relax();
+    } else if (kind == 1) {
+      const uint32_t g = b % G, m = members(g);
+      uint32_t old = gcnt[g].fetch_add(1, std::memory_order_acq_rel);
+      if (old == m * stamp - 1) {  // last agent of its group
+        uint32_t t = top.fetch_add(1, std::memory_order_acq_rel);
+        if (t == G * stamp - 1)
+          topgen.store(stamp, std::memory_order_release);
+        else
+          while (!reached(topgen.load(std::memory_order_acquire), stamp)) relax();
+        ggen[g].store(stamp, std::memory_order_release);
+      } else {
+        while (!reached(ggen[g].load(std::memory_order_acquire), stamp)) relax();
+      }
+    } else {
+      arrive[b].store(stamp, std::memory_order_release);
+      if (b == 0) {
+        for (uint32_t i = 0; i < N; ++i)
+          while (!reached(arrive[i].load(std::memory_order_acquire), stamp)) relax();
+        for (uint32_t i = 0; i < N; ++i) release[i].store(stamp, std::memory_order_release);
+      } else {
+        while (!reached(release[b].load(std::memory_order_acquire), stamp)) relax();
+      }
+    }
+  };
+
+  double t = run_agents(N, [&](uint32_t b) {
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+      slot[(size_t)(r & 1) * N + b].store(or_sm32(seed ^ (b << 16) ^ r),
+                                          std::memory_order_relaxed);
+      barrier(b, r);
+      uint32_t src = (uint32_t)(((uint64_t)b + r) % N);
+      uint32_t v = slot[(size_t)(r & 1) * N + src].load(std::memory_order_relaxed);
+      if (v != or_sm32(seed ^ (src << 16) ^ r)) bad.store(1);
+      c ^= v;
+    }
+    chk[b] = c;
+  });
+  if (seconds) *seconds = t;
+  return bad.load() ? -2 : 0;
+}
+
+// Mutex kinds: 0 spin lock by compare-and-swap, 1 spin lock by exchange (Algorithm 1),
+// 2 spin lock with the Section 5 backoff (Algorithm 2), 3 fetch-and-add ticket mutex
+// with backoff while polling (Algorithm 3), 4 polling mutex: wait with plain loads until
+// the word reads free, then one compare-and-swap.
+// Workload: see or_mutex_closed.  An owner word checks mutual exclusion inside every
+// critical section.  Returns 0, or -2 on a mutual-exclusion violation.
+int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uint32_t L,
+                      uint32_t W, uint32_t imin, uint32_t imax, uint32_t* words,
+                      double* seconds) {
+  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 4) return -1;
+  std::vector<Word> lockw(L), ticket(L), turn(L), owner(L);
+  for (uint32_t l = 0; l < L; ++l) lockw[l] = 0, ticket[l] = 0, turn[l] = 0, owner[l] = 0;
+  std::vector<Word> cs((size_t)L * W);
+  for (auto& w : cs) w.store(0);
+  std::atomic<int> bad{0};
+
+  auto lock = [&](uint32_t l, Backoff& bo) {
+    switch (kind) {
+      case 0:
+        for (;;) {
+          uint32_t e = 0;
+          if (lockw[l].compare_exchange_strong(e, 1, std::memory_order_acquire,
+                                               std::memory_order_relaxed))
+            return;
+          relax();
+        }
+      case 1:
+        while (lockw[l].exchange(1, std::memory_order_acquire) != 0) relax();
+        return;
+      case 2:
+        bo.i = bo.imin;
+        while (lockw[l].exchange(1, std::memory_order_acquire) != 0) bo();
+        return;
+      case 3: {
+        uint32_t my = ticket[l].fetch_add(1, std::memory_order_relaxed);
+        bo.i = bo.imin;
+        while (turn[l].load(std::memory_order_acquire) != my) bo();
+        return;
+      }
+      default:
+        for (;;) {
+          while (lockw[l].load(std::memory_order_relaxed) != 0) relax();
+          uint32_t e = 0;
+          if (lockw[l].compare_exchange_strong(e, 1, std::memory_order_acquire,
+                                               std::memory_order_relaxed))
+            return;
+        }
+    }
+  };
+  auto unlock = [&](uint32_t l) {
+    if (kind == 3) {
+      uint32_t t = turn[l].load(std::memory_order_relaxed);  // only the holder writes turn
+      turn[l].store(t + 1, std::memory_order_release);
+    } else {
+      lockw[l].store(0, std::memory_order_release);
+    }
+  };
+
+  double t = run_agents(nwg, [&](uint32_t b) {
+    Backoff bo(imin ? imin : 1, imax ? imax : 1);
+    uint64_t A = or_ops_for_agent(nwg, total, b);
+    for (uint64_t j = 0; j < A; ++j) {
+      uint32_t l = or_key(seed, b, (uint32_t)j, 1) % L;
+      lock(l, bo);
+      if (owner[l].exchange(b + 1, std::memory_order_relaxed) != 0) bad.store(1);
+      for (uint32_t w = 0; w < W; ++w) {
+        Word& x = cs[(size_t)l * W + w];
+        x.store(x.load(std::memory_order_relaxed) + 1, std::memory_order_relaxed);
+      }
+      if (owner[l].exchange(0, std::memory_order_relaxed) != b + 1) bad.store(1);
+      unlock(l);
+    }
+  });
+  for (size_t i = 0; i < cs.size(); ++i) words[i] = cs[i].load();
+  if (seconds) *seconds = t;
+  return bad.load() ? -2 : 0;
+}
+
+// Semaphore kinds: 0 spin semaphore (Algorithm 4), 1 spin semaphore with backoff in
+// both loops (Algorithm 4, UseBackoff), 2 fetch-and-add semaphore (Algorithm 5),
+// 3 fetch-and-add semaphore whose queued waiters yield between polls.
+// Initial value K.  Algorithm 4 keeps S = K + 1 (zero means "held"); Algorithm 5 keeps
+// count, ticket and turn starting at 0, and a queued waiter proceeds once turn is
+// strictly greater than the ticket it drew (0-based).
+// Each pair: wait, occupancy tracking, checksum update, admission count, post.
+// out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}.
+// Returns 0, -2 if occupancy ever exceeded K.
+int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t total,
+                    uint32_t imin, uint32_t imax, uint32_t* chk, uint32_t* maxocc,
+                    uint32_t* state, double* seconds) {
+  if (nwg == 0 || K == 0 || kind < 0 || kind > 3) return -1;
+  Word S{K + 1}, count{0}, ticket{0}, turn{0}, occ{0}, maxo{0}, adm{0};
+  const bool alg4 = kind <= 1, backoff = kind == 1;
+
+  auto wait = [&](Backoff& bo) {
+    if (alg4) {
+      bo.i = bo.imin;
+      for (;;) {
+        uint32_t v = S.exchange(0, std::memory_order_acquire);
+        if (v > 1) {
+          S.exchange(v - 1, std::memory_order_release);
+          return;
+        }
+        if (v == 1) S.exchange(1, std::memory_order_release);
+        if (backoff) bo(); else relax();
+      }
+    } else {
+      uint32_t old = count.fetch_add(1, std::memory_order_acq_rel);
+      if (old < K) return;
+      uint32_t idx = ticket.fetch_add(1, std::memory_order_acq_rel);
+      while (!((int32_t)(turn.load(std::memory_order_acquire) - idx) > 0)) relax();
+    }
+  };
+  auto post = [&](Backoff& bo) {
+    if (alg4) {
+      bo.i = bo.imin;
+      for (;;) {
+        uint32_t v = S.exchange(0, std::memory_order_acquire);
+        if (v > 0) {
+          S.exchange(v + 1, std::memory_order_release);
+          return;
+        }
+        if (backoff) bo(); else relax();
+      }
+    } else {
+      uint32_t old = count.fetch_sub(1, std::memory_order_acq_rel);
+      if (old > K) turn.fetch_add(1, std::memory_order_acq_rel);
+    }
+  };
+
+  double t = run_agents(nwg, [&](uint32_t b) {
+    Backoff bo(imin ? imin : 1, imax ? imax : 1);
+    uint64_t A = or_ops_for_agent(nwg, total, b);
+    uint32_t c = 0;
+    for (uint64_t j = 0; j < A; ++j) {
+      wait(bo);
+      uint32_t o = occ.fetch_add(1) + 1;
+      uint32_t m = maxo.load();
+      while (o > m && !maxo.compare_exchange_weak(m, o)) {
+      }
+      c ^= or_sm32(seed ^ (b << 16) ^ (uint32_t)j);
+      adm.fetch_add(1);
+      occ.fetch_sub(1);
+      post(bo);
+    }
+    chk[b] = c;
+  });
+  *maxocc = maxo.load();
+  state[0] = alg4 ? S.load() : count.load();
+  state[1] = ticket.load();
+  state[2] = turn.load();
+  state[3] = adm.load();
+  if (seconds) *seconds = t;
+  return *maxocc > K ? -2 : 0;
+}
+
+// Threaded microbenchmark: `threads` host threads share the U issuers round-robin and
+// perform the schedule of or_bench_counts with real atomics on a T-word array.
+// finals[T]; *sum = uint64 sum of returned values (for EXCH: returned + final).
+int or_bench_threaded(int op, uint32_t seed, uint32_t U, uint64_t n, uint32_t T,
+                      const uint32_t* perm, uint32_t threads, uint32_t* finals,
+                      uint64_t* sum, double* seconds) {
+  if (T == 0 || op < 0 || op > 4) return -1;
+  if (threads == 0) threads = 1;
+  std::vector<Word> m(T);
+  // ADD, CAS and ST start from zero; EXCH and LD start from the prefill.
+  for (uint32_t t = 0; t < T; ++t) m[t].store((op == 2 || op == 3) ? or_prefill(seed, t) : 0u);
+  std::atomic<uint64_t> total{0};
+  double secs = run_agents(threads, [&](uint32_t th) {
+    uint64_t s = 0;
+    for (uint32_t u = th; u < U; u += threads)
+      for (uint64_t i = 0; i < n; ++i) {
+        uint32_t t = perm[(u + i) % T];
+        switch (op) {
+          case 0: s += m[t].fetch_add(1, std::memory_order_relaxed); break;
+          case 1: {
+            uint32_t o = m[t].load(std::memory_order_relaxed);
+            while (!m[t].compare_exchange_weak(o, o + 1, std::memory_order_relaxed)) {
+            }
+            s += o;
+            break;
+          }
+          case 2: s += m[t].exchange(or_exch_value(seed, u, (uint32_t)i), std::memory_order_relaxed); break;
+          case 3: s += m[t].load(std::memory_order_relaxed); break;
+          default: m[t].store(or_prefill(seed, t), std::memory_order_relaxed); break;
+        }
+      }
+    total.fetch_add(s);
+  });
+  uint64_t s = total.load();
+  for (uint32_t t = 0; t < T; ++t) {
+    finals[t] = m[t].load();
+    if (op == 2) s += finals[t];
+  }
+  *sum = s;
+  if (seconds) *seconds = secs;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+"""Exhaustive-interleaving checks of every algorithm on tiny instances, and mutation
+tests that pin the checker itself: each planted mistake must be caught (CPU only)."""
+
+import pytest
+
+from oracle.modelcheck import BarrierModel, FASemModel, MutexModel, SpinSemModel, explore
+
+
+@pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
+@pytest.mark.parametrize("n,ops", [(2, 2), (3, 2), (3, 3)])
+def test_mutex_correct(kind, n, ops):
+    r = explore(MutexModel(kind, n, ops))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("K", [1, 2])
+@pytest.mark.parametrize("n,ops", [(3, 2), (3, 3)])
+def test_spin_semaphore_correct(K, n, ops):
+    r = explore(SpinSemModel(K, n, ops))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+@pytest.mark.parametrize("n,ops", [(3, 2), (3, 3)])
+def test_fa_semaphore_correct(K, n, ops):
+    r = explore(FASemModel(K, n, ops))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("kind", ["central", "xcd", "flag"])
+@pytest.mark.parametrize("n,rounds,groups", [(2, 3, 2), (3, 3, 2), (4, 3, 2), (3, 4, 3)])
+def test_barrier_correct(kind, n, rounds, groups):
+    r = explore(BarrierModel(kind, n, rounds, groups))
+    assert r.ok, r.violation
+
+
+# ---- mutation tests ------------------------------------------------------------------
+
+def test_catches_check_then_set_lock():
+    r = explore(MutexModel("sleep", 2, 1, mutant="check_then_set"))
+    assert r.violation and "mutual exclusion" in r.violation
+
+
+def test_catches_missing_unlock_as_deadlock():
+    r = explore(MutexModel("spin_cas", 2, 1, mutant="skip_release"))
+    assert r.deadlock
+
+
+def test_catches_geq_comparator_in_fa_semaphore():
+    # Waiters proceeding once turn >= their 0-based ticket admit K + 1 agents.
+    r = explore(FASemModel(1, 2, 1, mutant="geq"))
+    assert r.violation and "occupancy" in r.violation
+
+
+def test_catches_unconditional_turn_bump():
+    r = explore(FASemModel(2, 3, 2, mutant="always_bump"))
+    assert r.violation is not None
+
+
+def test_catches_spin_semaphore_off_by_one():
+    r = explore(SpinSemModel(1, 3, 1, mutant="enter_at_one"))
+    assert r.violation and "occupancy" in r.violation
+
+
+@pytest.mark.parametrize("kind", ["central", "xcd", "flag"])
+def test_catches_single_buffered_exchange(kind):
+    r = explore(BarrierModel(kind, 2, 3, 2, mutant="single_buffer"))
+    assert r.violation and "phase" in r.violation
+
+
+@pytest.mark.parametrize("kind", ["central", "flag"])
+def test_catches_barrier_that_does_not_wait(kind):
+    r = explore(BarrierModel(kind, 2, 2, mutant="no_wait"))
+    assert r.violation and "phase" in r.violation
+
+
+def test_catches_hierarchical_group_released_early():
+    r = explore(BarrierModel("xcd", 4, 2, 2, mutant="no_top_wait"))
+    assert r.violation and "phase" in r.violation

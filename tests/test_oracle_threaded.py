@@ -1,0 +1,53 @@
+"""The threaded reference (one std::thread per agent, real atomics and waits) must reach
+the closed forms and hold each primitive's invariant (CPU only)."""
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+@pytest.mark.parametrize("kind", ["central", "xcd", "flag"])
+@pytest.mark.parametrize("N,R", [(1, 20), (2, 50), (5, 40), (16, 200), (64, 20)])
+def test_barrier_threaded_matches_closed(kind, N, R):
+    seed = 42
+    chk, rc, _ = oracle.barrier_threaded(kind, seed, N, R, groups=3)
+    assert rc == 0
+    assert (chk == oracle.barrier_closed(seed, N, R)).all()
+
+
+@pytest.mark.parametrize("groups", [1, 2, 8, 100])
+def test_barrier_hierarchical_any_grouping(groups):
+    chk, rc, _ = oracle.barrier_threaded("xcd", 7, 24, 30, groups=groups)
+    assert rc == 0 and (chk == oracle.barrier_closed(7, 24, 30)).all()
+
+
+@pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep"])
+@pytest.mark.parametrize("L,W", [(1, 1), (1, 16), (3, 4)])
+def test_mutex_threaded_matches_closed(kind, L, W):
+    seed, nwg, total = 0xC0FFEE, 8, 3000
+    words, rc, _ = oracle.mutex_threaded(kind, seed, nwg, total, L, W)
+    assert rc == 0
+    assert (words == oracle.mutex_closed(seed, nwg, total, L, W)).all()
+
+
+@pytest.mark.parametrize("kind", ["spin", "spin_backoff", "ticket", "sleep"])
+@pytest.mark.parametrize("K", [1, 2, 4, 32])
+def test_sem_threaded_invariants(kind, K):
+    seed, nwg, total = 7, 12, 2400
+    r = oracle.sem_threaded(kind, K, seed, nwg, total)
+    assert r["rc"] == 0
+    assert 1 <= r["maxocc"] <= K
+    assert (r["chk"] == oracle.sem_closed(seed, nwg, total)).all()
+    s_or_count, ticket, turn, admissions = r["state"]
+    assert admissions == total
+    if kind.startswith("spin"):
+        assert s_or_count == K + 1
+    else:
+        assert s_or_count == 0 and ticket == turn
+        if K >= nwg:
+            assert ticket == 0  # nobody ever queues
+
+
+def test_hardware_threads_reported():
+    assert oracle.hardware_threads() >= 1
