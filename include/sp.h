@@ -1,0 +1,273 @@
+/*
+ * sp.h -- inter-workgroup synchronization primitives for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libsp.so.  The primitives are those of Stuart & Owens, "Efficient
+ * Synchronization Primitives for GPUs" (2011): barriers, mutexes and semaphores with
+ * block semantics (Section 3: one leader per workgroup touches the primitive, the rest
+ * of the workgroup waits at the workgroup barrier), and the memory-system
+ * microbenchmarks of Section 3 that classify a GPU by the abstraction of Section 4.
+ *
+ * Conventions for every entry point:
+ *   - Return SP_OK (0) on success or a negative SP_E_* code; nothing aborts the process.
+ *   - Pointers documented "device" must point to device memory of the context's GPU
+ *     (for example torch CUDA tensors); "host" pointers to host memory.  The caller owns
+ *     every buffer it passes; the library owns only the state objects it creates.
+ *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  It is borrowed.
+ *   - The *_run and sp_bench_* calls launch on `stream`, time the main kernel with HIP
+ *     events recorded on that stream, wait for it, check the device watchdog word and
+ *     fill `*st` (may be NULL).  Output buffers hold the results when the call returns.
+ *   - Every device wait is bounded by sp_params.timeout_ms (wall clock); on expiry the
+ *     kernel stops and the call returns SP_E_TIMEOUT.
+ */
+#ifndef SP_H
+#define SP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------------------ */
+#define SP_OK 0
+#define SP_E_INVAL (-1)      /* bad argument (zero size, out-of-range kind, ...)       */
+#define SP_E_HIP (-2)        /* a HIP runtime call failed; see sp_last_hip_error       */
+#define SP_E_NORESIDENT (-3) /* a barrier needs more co-resident workgroups than fit   */
+#define SP_E_TIMEOUT (-4)    /* the device watchdog expired                            */
+#define SP_E_PARITY (-5)     /* a kernel's own consistency check failed                */
+
+/* ---- kinds -------------------------------------------------------------------------- */
+/* Barriers (Section 5, Barrier; Section 2 for the centralized and tree barriers).      */
+enum sp_barrier_kind {
+  SP_BARRIER_CENTRAL = 0,       /* one monotone counter; waiters poll the counter      */
+  SP_BARRIER_CENTRAL_SPLIT = 1, /* counter + separate release word set by last arriver */
+  SP_BARRIER_TREE = 2,          /* two-level counter tree: fan_in groups, top counter  */
+  SP_BARRIER_FLAG = 3,          /* decentralized flag barrier with a master workgroup  */
+  SP_BARRIER_GRID_SYNC = 4,     /* comparator: HIP cooperative-groups grid.sync()      */
+  SP_BARRIER_XCD = 5,           /* per-XCD: flags through each XCD's L2, one writeback */
+                                /* and one invalidation per XCD per round              */
+  SP_BARRIER_DEFAULT = 15       /* the tuned default for this GPU                      */
+};
+
+/* Mutexes (Section 5, Mutex; Algorithms 1-3).                                          */
+enum sp_mutex_kind {
+  SP_MUTEX_SPIN_CAS = 0,     /* compare-and-swap 0 -> 1 until it succeeds              */
+  SP_MUTEX_SPIN_EXCH = 1,    /* exchange with 1 until the old value is 0 (Algorithm 1; */
+                             /* with sp_params.backoff set, Algorithm 2)               */
+  SP_MUTEX_SPIN_BACKOFF = 2, /* compare-and-swap spin lock, backoff after each failure */
+  SP_MUTEX_TICKET = 3,       /* fetch-and-add ticket mutex (Algorithm 3)               */
+  SP_MUTEX_SLEEP = 4,        /* poll with loads + s_sleep, then one compare-and-swap   */
+  SP_MUTEX_DEFAULT = 15
+};
+
+/* Semaphores (Section 5, Semaphore; Algorithms 4-5).                                   */
+enum sp_sem_kind {
+  SP_SEM_SPIN = 0,         /* exchange-based spin semaphore (Algorithm 4)              */
+  SP_SEM_SPIN_BACKOFF = 1, /* Algorithm 4 with backoff                                  */
+  SP_SEM_TICKET = 2,       /* fetch-and-add semaphore, plain polling (Algorithm 5)      */
+  SP_SEM_SLEEP = 3,        /* Algorithm 5, queued waiters s_sleep between polls         */
+  SP_SEM_DEFAULT = 15
+};
+
+/* Backoff policy (Section 5, Mutex: linear counter from I_min, wraps past I_max).     */
+enum sp_backoff_kind {
+  SP_BACKOFF_NONE = 0,
+  SP_BACKOFF_PAPER = 1, /* wait I units, I += 1, I > I_max -> I = I_min                  */
+  SP_BACKOFF_EXP = 2    /* wait I units, I = min(2 I, I_max)                             */
+};
+enum sp_backoff_unit {
+  SP_UNIT_SLEEP = 0, /* one s_sleep 1 (64 shader clocks)                               */
+  SP_UNIT_LOAD = 1   /* one uncontended agent-scope load (the paper's unit)             */
+};
+
+/* Microbenchmark operations and issue modes (Section 3).                              */
+enum sp_op { SP_OP_ADD = 0, SP_OP_CAS = 1, SP_OP_EXCH = 2, SP_OP_LD = 3, SP_OP_ST = 4 };
+enum sp_issue {
+  SP_ISSUE_PER_LANE = 0,   /* every lane issues its own operations                     */
+  SP_ISSUE_WAVE_LEADER = 1 /* lane 0 of each wavefront issues                           */
+};
+
+/* The twelve memory-system tests of Section 3 (Table 1): contention x access kind.    */
+enum sp_paper12 {
+  SP_P12_CONT_VOL_READ = 0,
+  SP_P12_CONT_VOL_WRITE = 1,
+  SP_P12_NONCONT_VOL_READ = 2,
+  SP_P12_NONCONT_VOL_WRITE = 3,
+  SP_P12_CONT_ATOM_READ = 4, /* atomic read = atomic add of 0                          */
+  SP_P12_CONT_ATOM_WRITE = 5, /* atomic write = atomic exchange with 0                 */
+  SP_P12_NONCONT_ATOM_READ = 6,
+  SP_P12_NONCONT_ATOM_WRITE = 7,
+  SP_P12_CONT_VOL_READ_AFTER_ATOM = 8, /* one atomic first, then the volatile loop     */
+  SP_P12_CONT_VOL_WRITE_AFTER_ATOM = 9,
+  SP_P12_NONCONT_VOL_READ_AFTER_ATOM = 10,
+  SP_P12_NONCONT_VOL_WRITE_AFTER_ATOM = 11
+};
+
+/* ---- parameters and statistics ----------------------------------------------------- */
+typedef struct sp_params {
+  uint32_t backoff;      /* sp_backoff_kind                                              */
+  uint32_t backoff_min;  /* I_min (units), >= 1                                          */
+  uint32_t backoff_max;  /* I_max (units), >= backoff_min                                */
+  uint32_t backoff_unit; /* sp_backoff_unit                                              */
+  uint32_t poll_sleep;   /* s_sleep 1 count between two polls of a wait loop (0 = hot)  */
+  uint32_t fan_in;       /* SP_BARRIER_TREE: number of groups (0 = number of XCDs)       */
+  uint32_t pad_bytes;    /* spacing of state words, power of two in [4, 4096]            */
+  uint32_t flags_packed; /* SP_BARRIER_FLAG: 1 = flags packed 4 B apart, 0 = pad_bytes  */
+  uint32_t timeout_ms;   /* watchdog for every device wait (0 = 20000)                   */
+  uint32_t verify;       /* mutex runs: check mutual exclusion inside every critical     */
+                         /* section with an owner word (SP_E_PARITY on a violation)       */
+  uint32_t reserved[6];
+} sp_params;
+
+typedef struct sp_stats {
+  double kernel_ms;        /* HIP-event time of the main kernel                          */
+  uint32_t nwg;            /* workgroups launched                                        */
+  uint32_t lanes;          /* threads per workgroup                                      */
+  uint32_t resident_per_cu;/* occupancy limit reported for this kernel, workgroups / CU  */
+  uint32_t device_error;   /* watchdog word after the run (0 = none)                     */
+  uint64_t ops;            /* operations performed (rounds, acquisitions, pairs, ...)    */
+  uint64_t reserved[4];
+} sp_stats;
+
+typedef struct sp_device_info {
+  char name[64];
+  char arch[64];           /* gcnArchName                                                */
+  uint32_t cu_count;
+  uint32_t xcd_count;      /* from the XCC id register of a probe launch (0 = unknown)   */
+  uint32_t wall_clock_khz; /* frequency of the constant-rate wall clock                  */
+  uint32_t clock_khz;      /* peak shader clock                                          */
+  uint64_t hbm_bytes;
+  uint32_t max_threads_per_cu;
+  uint32_t reserved[7];
+} sp_device_info;
+
+typedef struct sp_ctx sp_ctx;
+typedef struct sp_barrier sp_barrier;
+typedef struct sp_mutex sp_mutex;
+typedef struct sp_sem sp_sem;
+
+/* ---- context -------------------------------------------------------------------------
+ * sp_init: binds to HIP device `device`, reads its properties and probes the XCC count.
+ * Errors: SP_E_HIP (no such device).  *out is owned by the caller until sp_fini.       */
+int sp_init(int device, sp_ctx** out);
+int sp_fini(sp_ctx* ctx);
+int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out);
+/* Fills *p with the library's defaults.                                                */
+void sp_params_default(sp_params* p);
+/* Installs the default kind and parameters that *_DEFAULT resolves to for a primitive
+ * class (0 barrier, 1 mutex, 2 semaphore) and contention bucket (0 = low: fewer than
+ * 64 workgroups per resource, 1 = high).  Used by the autotuner (future-work item of
+ * Section 7: tuning backoff per GPU and contention level).                              */
+int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
+                   const sp_params* p);
+const char* sp_strerror(int code);
+int sp_last_hip_error(const sp_ctx* ctx);
+/* Writes the XCC id of every workgroup of a plain launch of nwg x lanes into
+ * out (device, nwg uint32).                                                             */
+int sp_probe_xcc(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t* out, void* stream);
+
+/* ---- barrier (Section 5, Barrier; Table 4 Barrier()) ------------------------------------
+ * sp_barrier_create: state for a barrier among exactly nwg workgroups (all must be
+ * co-resident, Section 5: the barrier is the primitive that needs persistent threads).
+ * Device state (counters, flags) is allocated and zeroed here and freed by destroy.
+ * Errors: SP_E_INVAL (nwg == 0, bad kind or params), SP_E_HIP.                          */
+int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params* p,
+                      sp_barrier** out);
+int sp_barrier_destroy(sp_barrier* b);
+/* Hash-exchange workload: `rounds` barriers; in round r workgroup w stores
+ * splitmix32(seed ^ (w << 16) ^ r) into slot (r & 1, w) of a 2 x nwg array, waits at the
+ * barrier, then XORs slot (r & 1, (w + r) mod nwg) into its checksum.  The slot is
+ * written by the workgroup's last thread and read by thread 64 (another wavefront when
+ * lanes > 64), so the barrier must order plain stores and loads of different
+ * wavefronts.  out_checksums: device, nwg uint32.  lanes: multiple of 64, <= 1024.
+ * Errors: SP_E_INVAL, SP_E_NORESIDENT (nwg exceeds lanes-dependent co-residency),
+ * SP_E_TIMEOUT, SP_E_HIP.  The state is reset before every run.                          */
+int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t seed,
+                        uint32_t* out_checksums, sp_stats* st, void* stream);
+/* Comparator: the same workload with the kernel boundary as the barrier (one launch per
+ * round, Section 2's "end one kernel and begin another"); graph != 0 replays the
+ * rounds from a captured HIP graph instead of launching them one by one.               */
+int sp_barrier_run_hash_launches(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t rounds,
+                                 uint32_t seed, uint32_t graph, uint32_t* slots /*device, 2*nwg*/,
+                                 uint32_t* out_checksums, sp_stats* st, void* stream);
+
+/* ---- mutex (Section 5, Mutex; Algorithms 1-3; Table 4 Lock()/Unlock()) -------------------
+ * sp_mutex_create: nlocks independent mutexes, each guarding words_per_lock uint32
+ * words that the run's critical sections update.  Each lock's state sits on its own
+ * pad_bytes-aligned line; a ticket mutex keeps ticket and turn on separate lines.
+ * Errors: SP_E_INVAL, SP_E_HIP.                                                        */
+int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_per_lock,
+                    const sp_params* p, sp_mutex** out);
+int sp_mutex_destroy(sp_mutex* m);
+/* Contention workload: total_acq acquisitions split over nwg workgroups (total / nwg
+ * each, the first total mod nwg do one more).  Workgroup w's j-th acquisition first
+ * waits key(w, j, 2) mod (max_delay_cyc + 1) shader clocks outside any lock, then locks
+ * mutex key(w, j, 1) mod nlocks, adds one to each of its words with plain loads and
+ * stores spread over the workgroup's lanes, and unlocks.  key(w, j, s) =
+ * sm32(sm32(sm32(seed ^ s) ^ w) ^ j).  out_words: device, nlocks x words_per_lock
+ * uint32 (lock-major), the final word values.  out_finish: device, nwg uint64 wall-clock
+ * ticks at which each workgroup finished, or NULL.  Errors: SP_E_INVAL, SP_E_TIMEOUT,
+ * SP_E_HIP.                                                                             */
+int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
+                 uint32_t max_delay_cyc, uint32_t seed, uint32_t* out_words,
+                 uint64_t* out_finish, sp_stats* st, void* stream);
+
+/* ---- semaphore (Section 5, Semaphore; Algorithms 4-5; Table 4 Wait()/Post()) ------------
+ * sp_sem_create: a counting semaphore with initial value K >= 1.  Algorithm 4 keeps one
+ * word S = K + 1; Algorithm 5 keeps count, ticket and turn on separate lines.
+ * Errors: SP_E_INVAL (K == 0), SP_E_HIP.                                                */
+int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out);
+int sp_sem_destroy(sp_sem* s);
+/* Workload: total_pairs wait/post pairs split over nwg workgroups as in sp_mutex_run.
+ * Inside, the leader (if track) increments an occupancy counter, raises its running
+ * maximum, counts the admission, XORs sm32(seed ^ (w << 16) ^ j) into the workgroup's
+ * checksum, holds key(w, j, 3) mod (max_hold_cyc + 1) shader clocks and decrements the
+ * occupancy.  out_chk: device, nwg uint32.  out_state: device, 8 uint32 =
+ * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, 0, 0, 0}.
+ * Errors: SP_E_INVAL, SP_E_TIMEOUT, SP_E_HIP.                                           */
+int sp_sem_run(sp_sem* s, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
+               uint32_t max_hold_cyc, uint32_t seed, uint32_t track, uint32_t* out_chk,
+               uint32_t* out_state, sp_stats* st, void* stream);
+
+/* ---- memory-system microbenchmarks (Section 3; Tables 1-3) ------------------------------
+ * sp_bench_atomic: issuer u (a lane, or a wavefront's lane 0) performs ops_per_issuer
+ * operations; its i-th targets word perm[(u + i) mod T] of buf, words stride_bytes
+ * apart.  Issuers are numbered globally: u = (workgroup * waves + wave) * issuers per
+ * wave + issuing lane.  ADD adds 1; CAS increments by a load/compare-and-swap loop; EXCH
+ * writes sm32(sm32(seed ^ u) ^ i); LD loads; ST stores sm32(seed ^ t) to word t.  All
+ * are agent-scope relaxed atomics.  The call first fills buf: 0 for ADD, CAS and ST,
+ * sm32(seed ^ t) for EXCH and LD (word t at byte offset t * stride_bytes).
+ * perm: device, T uint32.  buf: device, T * stride_bytes bytes.  out_sum: device,
+ * 1 uint64 = sum of every returned value (for EXCH: plus the final word values).
+ * Errors: SP_E_INVAL (T == 0, stride not a multiple of 4, lanes not a multiple of 64).  */
+int sp_bench_atomic(sp_ctx* ctx, uint32_t op, uint32_t nwg, uint32_t lanes, uint32_t T,
+                    uint32_t stride_bytes, uint32_t mode, uint64_t ops_per_issuer,
+                    uint32_t seed, const uint32_t* perm, uint32_t* buf, uint64_t* out_sum,
+                    sp_stats* st, void* stream);
+/* sp_bench_paper12: the twelve tests of Section 3.  Each workgroup's leader performs
+ * n_ops accesses to one word: word 0 for contentious tests, word w at byte offset
+ * w * stride_bytes (the paper uses 256 B) for noncontentious ones.  Volatile = agent-
+ * scope relaxed load or store; atomic read = add of 0; atomic write = exchange with 0.
+ * buf: device, nwg * stride_bytes bytes, zeroed by the call.  out_sum: device, 1 uint64
+ * (sum of loaded values, which stays 0).                                               */
+int sp_bench_paper12(sp_ctx* ctx, uint32_t test, uint32_t nwg, uint32_t lanes, uint32_t n_ops,
+                     uint32_t stride_bytes, uint32_t* buf, uint64_t* out_sum, sp_stats* st,
+                     void* stream);
+/* sp_bench_stream: reads `bytes` (multiple of 16) of buf with 16-byte loads and sums the
+ * uint32 words into out_sum (device, 1 uint64).  nwg = 0 picks a grid.                 */
+int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, uint32_t reps,
+                    uint64_t* out_sum, sp_stats* st, void* stream);
+/* sp_bench_pingpong: two workgroups hand a token back and forth `rounds` times through
+ * two agent-scope words (release store, relaxed polling, acquire fence), measuring the
+ * one-way coherence latency.  words: device, 2048 bytes, zeroed by the call.
+ * out: device, 4 uint32 = {word written by workgroup 1 (ends at 2 * rounds), word
+ * written by workgroup 0 (ends at 2 * rounds - 1), XCC id of workgroup 0, XCC id of
+ * workgroup 1}.  st->kernel_ms / (2 * rounds) is the one-way latency.                   */
+int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* out,
+                      sp_stats* st, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SP_H */

@@ -1,0 +1,86 @@
+// Device-side counting semaphores (Section 5, Semaphore; Algorithms 4-5; Table 4
+// Wait()/Post()).  Block semantics as for the mutexes.
+#pragma once
+
+#include "atomics.hpp"
+
+namespace sp {
+
+struct SemState {
+  uint32_t K;           // initial value: at most K workgroups inside
+  uint32_t poll_sleep;  // SP_SEM_SLEEP: s_sleep units between polls
+  uint32_t* S;          // Algorithm 4: S = K + 1 at rest, 0 while being updated
+  uint32_t* count;      // Algorithm 5: workgroups inside or queued
+  uint32_t* ticket;     // Algorithm 5: next queue ticket
+  uint32_t* turn;       // Algorithm 5: number of queued workgroups admitted
+  BackoffCfg bo;        // SP_SEM_SPIN_BACKOFF
+};
+
+// KIND: SP_SEM_SPIN / SP_SEM_SPIN_BACKOFF (Algorithm 4), SP_SEM_TICKET / SP_SEM_SLEEP
+// (Algorithm 5, the queued waiter proceeds once turn is strictly greater than the
+// 0-based ticket it drew).
+template <int KIND>
+__device__ bool sem_wait(const SemState& s, const Ctl& ctl) {
+  __shared__ uint32_t s_ok;
+  if (is_leader()) {
+    bool ok = true;
+    if constexpr (KIND == SP_SEM_SPIN || KIND == SP_SEM_SPIN_BACKOFF) {
+      Wait w(ctl, 0);
+      Backoff bo(s.bo);
+      for (;;) {
+        const uint32_t v = exch_relaxed(s.S, 0);
+        if (v > 1) {  // below capacity: take one unit
+          exch_relaxed(s.S, v - 1);
+          break;
+        }
+        if (v == 1) exch_relaxed(s.S, 1);  // at capacity: put the value back
+        if constexpr (KIND == SP_SEM_SPIN_BACKOFF) bo(s.bo);
+        if (!(ok = w.tick())) break;
+      }
+    } else {
+      Wait w(ctl, KIND == SP_SEM_SLEEP ? s.poll_sleep : 0);
+      const uint32_t old = add_relaxed(s.count, 1);
+      if (old >= s.K) {  // at capacity: queue
+        const uint32_t idx = add_relaxed(s.ticket, 1);
+        while (!((int32_t)(ld_relaxed(s.turn) - idx) > 0))
+          if (!(ok = w.tick())) break;
+      }
+    }
+    fence_acquire();
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok;
+}
+
+template <int KIND>
+__device__ bool sem_post(const SemState& s, const Ctl& ctl) {
+  __shared__ uint32_t s_ok;
+  wave_stores_complete();
+  __syncthreads();
+  if (is_leader()) {
+    bool ok = true;
+    fence_release();
+    if constexpr (KIND == SP_SEM_SPIN || KIND == SP_SEM_SPIN_BACKOFF) {
+      Wait w(ctl, 0);
+      Backoff bo(s.bo);
+      for (;;) {
+        const uint32_t v = exch_relaxed(s.S, 0);
+        if (v > 0) {
+          exch_relaxed(s.S, v + 1);
+          break;
+        }
+        if constexpr (KIND == SP_SEM_SPIN_BACKOFF) bo(s.bo);
+        if (!(ok = w.tick())) break;
+      }
+    } else {
+      const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);  // count -= 1
+      if (old > s.K) add_relaxed(s.turn, 1);                   // admit one queued waiter
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok;
+}
+
+}  // namespace sp

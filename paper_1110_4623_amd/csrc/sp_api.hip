@@ -1,0 +1,210 @@
+// Context, parameters, errors and shared launch helpers of libsp.so.
+#include <string.h>
+
+#include "sp_internal.hpp"
+
+namespace {
+
+__global__ void k_fill_u32(uint32_t* d, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    d[i] = v;
+}
+
+__global__ void k_probe_xcc(uint32_t* out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = sp::xcc_id();
+}
+
+}  // namespace
+
+namespace spi {
+
+int normalize(const sp_ctx* ctx, const sp_params* in, sp_params* out) {
+  sp_params p;
+  if (in) p = *in; else sp_params_default(&p);
+  if (p.backoff > SP_BACKOFF_EXP || p.backoff_unit > SP_UNIT_LOAD) return SP_E_INVAL;
+  if (p.backoff_min == 0) p.backoff_min = 1;
+  if (p.backoff_max < p.backoff_min) p.backoff_max = p.backoff_min;
+  if (p.backoff_max > 1u << 16) return SP_E_INVAL;
+  if (p.poll_sleep > 1024) return SP_E_INVAL;
+  if (p.pad_bytes == 0) p.pad_bytes = 128;
+  if (p.pad_bytes < 4 || p.pad_bytes > 4096 || (p.pad_bytes & (p.pad_bytes - 1))) return SP_E_INVAL;
+  if (p.fan_in == 0) p.fan_in = ctx && ctx->xcd_count ? ctx->xcd_count : 8;
+  if (p.timeout_ms == 0) p.timeout_ms = 20000;
+  *out = p;
+  return SP_OK;
+}
+
+int fill_u32(sp_ctx* ctx, uint32_t* d, uint64_t words, uint32_t value, hipStream_t s) {
+  if (words == 0) return SP_OK;
+  uint64_t blocks = std::min<uint64_t>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, d, words, value);
+  SP_HIP(ctx, hipGetLastError());
+  return SP_OK;
+}
+
+int begin_timed(sp_ctx* ctx, hipStream_t s) {
+  SP_CHECK(fill_u32(ctx, ctx->d_err, 1, 0, s));
+  SP_HIP(ctx, hipEventRecord(ctx->ev0, s));
+  return SP_OK;
+}
+
+int end_timed(sp_ctx* ctx, hipStream_t s, sp_stats* st, uint32_t nwg, uint32_t lanes,
+              uint32_t resident_per_cu, uint64_t ops) {
+  SP_HIP(ctx, hipGetLastError());
+  SP_HIP(ctx, hipEventRecord(ctx->ev1, s));
+  SP_HIP(ctx, hipStreamSynchronize(s));
+  float ms = 0.f;
+  SP_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  uint32_t err = 0;
+  SP_HIP(ctx, hipMemcpy(&err, ctx->d_err, sizeof(err), hipMemcpyDeviceToHost));
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->kernel_ms = ms;
+    st->nwg = nwg;
+    st->lanes = lanes;
+    st->resident_per_cu = resident_per_cu;
+    st->device_error = err;
+    st->ops = ops;
+  }
+  if (err == sp::DEV_TIMEOUT) return SP_E_TIMEOUT;
+  if (err != sp::DEV_OK) return SP_E_PARITY;
+  return SP_OK;
+}
+
+}  // namespace spi
+
+extern "C" {
+
+void sp_params_default(sp_params* p) {
+  memset(p, 0, sizeof(*p));
+  p->backoff = SP_BACKOFF_NONE;
+  p->backoff_min = 1;
+  p->backoff_max = 32;
+  p->backoff_unit = SP_UNIT_SLEEP;
+  p->poll_sleep = 1;
+  p->fan_in = 0;
+  p->pad_bytes = 128;
+  p->flags_packed = 0;
+  p->timeout_ms = 20000;
+}
+
+const char* sp_strerror(int code) {
+  switch (code) {
+    case SP_OK: return "ok";
+    case SP_E_INVAL: return "invalid argument";
+    case SP_E_HIP: return "HIP runtime error";
+    case SP_E_NORESIDENT: return "not enough co-resident workgroups for a global barrier";
+    case SP_E_TIMEOUT: return "device watchdog expired";
+    case SP_E_PARITY: return "device consistency check failed";
+    default: return "unknown error";
+  }
+}
+
+int sp_last_hip_error(const sp_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+int sp_init(int device, sp_ctx** out) {
+  if (!out) return SP_E_INVAL;
+  *out = nullptr;
+  sp_ctx* ctx = new sp_ctx();
+  auto fail = [&](hipError_t e) {
+    (void)e;
+    delete ctx;
+    return SP_E_HIP;
+  };
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(e);
+  ctx->device = device;
+  if ((e = hipGetDeviceProperties(&ctx->prop, device)) != hipSuccess) return fail(e);
+  ctx->cu_count = (uint32_t)ctx->prop.multiProcessorCount;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+    ctx->wall_khz = (uint32_t)khz;
+  if ((e = hipMalloc(&ctx->d_err, 256)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&ctx->d_scratch, 4096)) != hipSuccess) return fail(e);
+  if ((e = hipEventCreate(&ctx->ev0)) != hipSuccess) return fail(e);
+  if ((e = hipEventCreate(&ctx->ev1)) != hipSuccess) return fail(e);
+  if ((e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+    return fail(e);
+  // Count XCDs: launch 8 workgroups per CU and collect the distinct XCC ids.
+  {
+    uint32_t n = ctx->cu_count * 8;
+    uint32_t* d = nullptr;
+    if ((e = hipMalloc(&d, n * sizeof(uint32_t))) != hipSuccess) return fail(e);
+    hipLaunchKernelGGL(k_probe_xcc, dim3(n), dim3(64), 0, 0, d);
+    uint32_t* h = new uint32_t[n];
+    e = hipMemcpy(h, d, n * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    hipFree(d);
+    if (e != hipSuccess) {
+      delete[] h;
+      return fail(e);
+    }
+    uint32_t seen = 0;
+    for (uint32_t i = 0; i < n; ++i) seen |= 1u << (h[i] & 15);
+    delete[] h;
+    ctx->xcd_count = (uint32_t)__builtin_popcount(seen);
+  }
+  // Built-in defaults until a tuner installs measured ones.
+  for (int prim = 0; prim < 3; ++prim)
+    for (int b = 0; b < 2; ++b) {
+      sp_params_default(&ctx->defaults[prim][b].p);
+      ctx->defaults[prim][b].kind = 0;
+    }
+  ctx->defaults[0][0].kind = SP_BARRIER_CENTRAL_SPLIT;
+  ctx->defaults[0][1].kind = SP_BARRIER_XCD;
+  ctx->defaults[1][0].kind = SP_MUTEX_TICKET;
+  ctx->defaults[1][1].kind = SP_MUTEX_TICKET;
+  ctx->defaults[2][0].kind = SP_SEM_SLEEP;
+  ctx->defaults[2][1].kind = SP_SEM_SLEEP;
+  *out = ctx;
+  return SP_OK;
+}
+
+int sp_fini(sp_ctx* ctx) {
+  if (!ctx) return SP_E_INVAL;
+  hipSetDevice(ctx->device);
+  hipFree(ctx->d_err);
+  hipFree(ctx->d_scratch);
+  hipEventDestroy(ctx->ev0);
+  hipEventDestroy(ctx->ev1);
+  hipStreamDestroy(ctx->capture_stream);
+  delete ctx;
+  return SP_OK;
+}
+
+int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
+  if (!ctx || !out) return SP_E_INVAL;
+  memset(out, 0, sizeof(*out));
+  strncpy(out->name, ctx->prop.name, sizeof(out->name) - 1);
+  strncpy(out->arch, ctx->prop.gcnArchName, sizeof(out->arch) - 1);
+  out->cu_count = ctx->cu_count;
+  out->xcd_count = ctx->xcd_count;
+  out->wall_clock_khz = ctx->wall_khz;
+  out->clock_khz = (uint32_t)ctx->prop.clockRate;
+  out->hbm_bytes = (uint64_t)ctx->prop.totalGlobalMem;
+  out->max_threads_per_cu = (uint32_t)ctx->prop.maxThreadsPerMultiProcessor;
+  return SP_OK;
+}
+
+int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
+                   const sp_params* p) {
+  if (!ctx || primitive > 2 || bucket > 1) return SP_E_INVAL;
+  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_SLEEP, SP_SEM_SLEEP};
+  if (kind > max_kind[primitive]) return SP_E_INVAL;
+  sp_params q;
+  SP_CHECK(spi::normalize(ctx, p, &q));
+  ctx->defaults[primitive][bucket].kind = kind;
+  ctx->defaults[primitive][bucket].p = q;
+  return SP_OK;
+}
+
+int sp_probe_xcc(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t* out, void* stream) {
+  if (!ctx || !out || nwg == 0 || !spi::lanes_ok(lanes)) return SP_E_INVAL;
+  hipStream_t s = spi::as_stream(stream);
+  hipLaunchKernelGGL(k_probe_xcc, dim3(nwg), dim3(lanes), 0, s, out);
+  SP_HIP(ctx, hipGetLastError());
+  SP_HIP(ctx, hipStreamSynchronize(s));
+  return SP_OK;
+}
+
+}  // extern "C"

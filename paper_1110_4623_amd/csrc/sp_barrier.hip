@@ -1,0 +1,243 @@
+// Global barriers: state objects, the hash-exchange workload and its comparators
+// (Section 5, Barrier; Section 2 on kernel launches as the global synchronization).
+#include <hip/hip_cooperative_groups.h>
+#include <string.h>
+
+#include "sp/barrier.hpp"
+#include "sp_internal.hpp"
+
+struct sp_barrier {
+  sp_ctx* ctx = nullptr;
+  uint32_t kind = 0;
+  uint32_t nwg = 0;
+  sp_params p{};
+  uint32_t* d_state = nullptr;  // counters and flags
+  uint64_t state_words = 0;
+  uint32_t* d_slots = nullptr;  // 2 x nwg exchanged values
+  sp::BarrierState st{};
+};
+
+namespace {
+
+// Hash-exchange workload: the slot is written by the workgroup's last thread and read
+// by thread 64 (a different wavefront when the workgroup has more than one), with
+// plain stores and loads, so only the barrier orders them.
+template <int KIND>
+__global__ SP_FULL_OCCUPANCY void k_barrier_hash(sp::BarrierState s, uint32_t rounds, uint32_t seed,
+                               uint32_t* slots, uint32_t* out, uint32_t* err,
+                               uint64_t timeout) {
+  const sp::Ctl ctl{err, sp::wall_clock() + timeout};
+  const uint32_t b = blockIdx.x, N = s.nwg;
+  const uint32_t writer = blockDim.x - 1, reader = 64 % blockDim.x;
+  uint32_t chk = 0;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    if (threadIdx.x == writer) slots[(r & 1) * N + b] = sp::sm32(seed ^ (b << 16) ^ r);
+    if (!sp::barrier_wait<KIND>(s, r, ctl)) return;
+    if (threadIdx.x == reader) chk ^= slots[(r & 1) * N + (uint32_t)(((uint64_t)b + r) % N)];
+  }
+  if (threadIdx.x == reader) out[b] = chk;
+}
+
+// Comparator: HIP cooperative groups' grid-wide barrier.
+__global__ SP_FULL_OCCUPANCY void k_barrier_hash_gridsync(uint32_t N, uint32_t rounds, uint32_t seed,
+                                        uint32_t* slots, uint32_t* out) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  const uint32_t b = blockIdx.x;
+  const uint32_t writer = blockDim.x - 1, reader = 64 % blockDim.x;
+  uint32_t chk = 0;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    if (threadIdx.x == writer) slots[(r & 1) * N + b] = sp::sm32(seed ^ (b << 16) ^ r);
+    grid.sync();
+    if (threadIdx.x == reader) chk ^= slots[(r & 1) * N + (uint32_t)(((uint64_t)b + r) % N)];
+  }
+  if (threadIdx.x == reader) out[b] = chk;
+}
+
+// Comparator: kernel boundaries as the barrier.  Launch r (0 <= r <= rounds) first
+// consumes round r - 1, then publishes round r.
+__global__ void k_barrier_round(uint32_t N, uint32_t r, uint32_t rounds, uint32_t seed,
+                                uint32_t* slots, uint32_t* out) {
+  const uint32_t b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  if (r > 0) {
+    const uint32_t q = r - 1;
+    out[b] ^= slots[(q & 1) * N + (uint32_t)(((uint64_t)b + q) % N)];
+  }
+  if (r < rounds) slots[(r & 1) * N + b] = sp::sm32(seed ^ (b << 16) ^ r);
+}
+
+const void* barrier_kernel(uint32_t kind) {
+  switch (kind) {
+    case SP_BARRIER_CENTRAL: return (const void*)k_barrier_hash<SP_BARRIER_CENTRAL>;
+    case SP_BARRIER_CENTRAL_SPLIT: return (const void*)k_barrier_hash<SP_BARRIER_CENTRAL_SPLIT>;
+    case SP_BARRIER_TREE: return (const void*)k_barrier_hash<SP_BARRIER_TREE>;
+    case SP_BARRIER_XCD: return (const void*)k_barrier_hash<SP_BARRIER_XCD>;
+    case SP_BARRIER_FLAG: return (const void*)k_barrier_hash<SP_BARRIER_FLAG>;
+    case SP_BARRIER_GRID_SYNC: return (const void*)k_barrier_hash_gridsync;
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params* p,
+                      sp_barrier** out) {
+  if (!ctx || !out || nwg == 0 || nwg > (1u << 16)) return SP_E_INVAL;
+  *out = nullptr;
+  sp_params q;
+  if (kind == SP_BARRIER_DEFAULT) {
+    const sp_default_entry& d = ctx->defaults[0][spi::bucket_of(nwg)];
+    kind = d.kind;
+    q = d.p;
+    if (p) {  // an explicit timeout still applies
+      if (p->timeout_ms) q.timeout_ms = p->timeout_ms;
+    }
+  } else {
+    if (kind > SP_BARRIER_XCD) return SP_E_INVAL;
+    SP_CHECK(spi::normalize(ctx, p, &q));
+  }
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  sp_barrier* b = new sp_barrier();
+  b->ctx = ctx;
+  b->kind = kind;
+  b->nwg = nwg;
+  b->p = q;
+  const uint32_t sw = spi::stride_words(q);
+  // the per-XCD barrier groups by XCD; the tree by fan_in
+  const uint32_t X = std::max<uint32_t>(1, ctx->xcd_count);
+  const uint32_t G = std::min(kind == SP_BARRIER_XCD ? X : q.fan_in, nwg);
+  const uint32_t fs = q.flags_packed ? 1u : sw;
+  // per-XCD blocks of packed local arrival flags, each a whole number of 128-byte lines
+  const uint32_t xblock = (uint32_t)(((nwg + G - 1) / G + 31) / 32 * 32);
+  // layout, in lines of sw words: cnt, gen, top, topgen, mismatch, gcnt[G], ggen[G],
+  // xarrive[G], then the flag barrier's arrive and release arrays, the per-XCD packed
+  // arrival blocks and the per-XCD blocks of release flags (one line per member)
+  const uint64_t flag_lines = ((uint64_t)nwg * fs + sw - 1) / sw;
+  const uint64_t local_lines = ((uint64_t)G * xblock + sw - 1) / sw;
+  const uint64_t lrel_lines = (uint64_t)G * xblock;
+  const uint64_t lines = 5 + 3ull * G + 2 * flag_lines + local_lines + lrel_lines;
+  b->state_words = lines * sw;
+  hipError_t e = hipMalloc(&b->d_state, b->state_words * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&b->d_slots, 2ull * nwg * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(b->d_state, 0, b->state_words * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(b->d_slots, 0, 2ull * nwg * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    ctx->last_hip = (int)e;
+    hipFree(b->d_state);
+    hipFree(b->d_slots);
+    delete b;
+    return SP_E_HIP;
+  }
+  uint32_t* base = b->d_state;
+  sp::BarrierState& s = b->st;
+  s.nwg = nwg;
+  s.stride = sw;
+  s.groups = G;
+  s.flag_stride = fs;
+  s.poll_sleep = q.poll_sleep;
+  s.xblock = xblock;
+  s.cnt = base + 0 * sw;
+  s.gen = base + 1 * sw;
+  s.top = base + 2 * sw;
+  s.topgen = base + 3 * sw;
+  s.mismatch = base + 4 * sw;
+  s.gcnt = base + 5ull * sw;
+  s.ggen = base + (5ull + G) * sw;
+  s.xarrive = base + (5ull + 2 * G) * sw;
+  s.arrive = base + (5ull + 3 * G) * sw;
+  s.release = s.arrive + flag_lines * sw;
+  s.larrive = s.release + flag_lines * sw;
+  s.lrelease = s.larrive + local_lines * sw;
+  *out = b;
+  return SP_OK;
+}
+
+int sp_barrier_destroy(sp_barrier* b) {
+  if (!b) return SP_E_INVAL;
+  hipSetDevice(b->ctx->device);
+  hipFree(b->d_state);
+  hipFree(b->d_slots);
+  delete b;
+  return SP_OK;
+}
+
+int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t seed,
+                        uint32_t* out_checksums, sp_stats* st, void* stream) {
+  if (!b || !out_checksums || !spi::lanes_ok(lanes)) return SP_E_INVAL;
+  sp_ctx* ctx = b->ctx;
+  hipStream_t s = spi::as_stream(stream);
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  const void* kern = barrier_kernel(b->kind);
+  if (!kern) return SP_E_INVAL;
+  // Every workgroup must be resident at once (the barrier's persistent-threads
+  // requirement, Section 5); refuse instead of hanging.
+  int per_cu = 0;
+  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  if ((uint64_t)per_cu * ctx->cu_count < b->nwg) return SP_E_NORESIDENT;
+  SP_CHECK(spi::fill_u32(ctx, b->d_state, b->state_words, 0, s));
+  SP_CHECK(spi::fill_u32(ctx, b->d_slots, 2ull * b->nwg, 0, s));
+  SP_CHECK(spi::begin_timed(ctx, s));
+  uint64_t timeout = spi::timeout_ticks(ctx, b->p);
+  uint32_t N = b->nwg;
+  if (b->kind == SP_BARRIER_GRID_SYNC) {
+    void* args[] = {&N, &rounds, &seed, &b->d_slots, &out_checksums};
+    SP_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(N), dim3(lanes), args, 0, s));
+  } else {
+    sp::BarrierState state = b->st;
+    void* args[] = {&state, &rounds, &seed, &b->d_slots, &out_checksums, &ctx->d_err, &timeout};
+    SP_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(N), dim3(lanes), args, 0, s));
+  }
+  return spi::end_timed(ctx, s, st, N, lanes, (uint32_t)per_cu, rounds);
+}
+
+int sp_barrier_run_hash_launches(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t rounds,
+                                 uint32_t seed, uint32_t graph, uint32_t* slots,
+                                 uint32_t* out_checksums, sp_stats* st, void* stream) {
+  if (!ctx || !slots || !out_checksums || nwg == 0 || nwg > (1u << 16) || !spi::lanes_ok(lanes))
+    return SP_E_INVAL;
+  hipStream_t s = spi::as_stream(stream);
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  SP_CHECK(spi::fill_u32(ctx, out_checksums, nwg, 0, s));
+  SP_CHECK(spi::fill_u32(ctx, slots, 2ull * nwg, 0, s));
+  if (!graph) {
+    SP_CHECK(spi::begin_timed(ctx, s));
+    for (uint32_t r = 0; r <= rounds; ++r)
+      hipLaunchKernelGGL(k_barrier_round, dim3(nwg), dim3(lanes), 0, s, nwg, r, rounds, seed,
+                         slots, out_checksums);
+    return spi::end_timed(ctx, s, st, nwg, lanes, 0, rounds);
+  }
+  // Capture the rounds + 1 launches once, then time one replay of the graph.
+  hipStream_t cs = ctx->capture_stream;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  SP_HIP(ctx, hipStreamSynchronize(s));
+  SP_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  for (uint32_t r = 0; r <= rounds; ++r)
+    hipLaunchKernelGGL(k_barrier_round, dim3(nwg), dim3(lanes), 0, cs, nwg, r, rounds, seed,
+                       slots, out_checksums);
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    ctx->last_hip = (int)e;
+    if (g) hipGraphDestroy(g);
+    return SP_E_HIP;
+  }
+  int rc = spi::begin_timed(ctx, s);
+  if (rc == SP_OK) {
+    e = hipGraphLaunch(ge, s);
+    if (e != hipSuccess) {
+      ctx->last_hip = (int)e;
+      rc = SP_E_HIP;
+    } else {
+      rc = spi::end_timed(ctx, s, st, nwg, lanes, 0, rounds);
+    }
+  }
+  hipGraphExecDestroy(ge);
+  hipGraphDestroy(g);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Host-side internals of libsp.so shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "sp.h"
+#include "sp/atomics.hpp"
+
+struct sp_default_entry {
+  uint32_t kind;
+  sp_params p;
+};
+
+struct sp_ctx {
+  int device = 0;
+  hipDeviceProp_t prop{};
+  int last_hip = 0;
+  uint32_t cu_count = 0;
+  uint32_t xcd_count = 0;
+  uint32_t wall_khz = 100000;
+  uint32_t* d_err = nullptr;   // watchdog word, own 256-byte block
+  uint32_t* d_scratch = nullptr;  // small staging area (4 KiB) for state readback
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t capture_stream = nullptr;
+  sp_default_entry defaults[3][2];
+};
+
+namespace spi {
+
+// Records a failing HIP call in the context and returns SP_E_HIP from the caller.
+#define SP_HIP(ctx, call)                                      \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) {                                    \
+      if (ctx) (ctx)->last_hip = (int)e_;                      \
+      return SP_E_HIP;                                         \
+    }                                                          \
+  } while (0)
+
+#define SP_CHECK(expr)                  \
+  do {                                  \
+    int rc_ = (expr);                   \
+    if (rc_ != SP_OK) return rc_;       \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Normalized parameters (defaults filled, ranges clamped); returns SP_E_INVAL on bad
+// values.
+int normalize(const sp_ctx* ctx, const sp_params* in, sp_params* out);
+
+inline uint32_t stride_words(const sp_params& p) { return std::max<uint32_t>(1, p.pad_bytes / 4); }
+
+inline uint64_t timeout_ticks(const sp_ctx* ctx, const sp_params& p) {
+  return (uint64_t)p.timeout_ms * ctx->wall_khz;
+}
+
+inline sp::BackoffCfg backoff_cfg(const sp_params& p, uint32_t* private_word) {
+  sp::BackoffCfg c;
+  c.kind = p.backoff;
+  c.imin = p.backoff_min;
+  c.imax = p.backoff_max;
+  c.unit = p.backoff_unit;
+  c.private_word = private_word;
+  return c;
+}
+
+// Zero `words` uint32 at d with a kernel (no memset nodes, so launches stay capturable).
+int fill_u32(sp_ctx* ctx, uint32_t* d, uint64_t words, uint32_t value, hipStream_t s);
+
+// Clears the watchdog word, records ev0.
+int begin_timed(sp_ctx* ctx, hipStream_t s);
+// Records ev1, waits for the stream, reads the watchdog word, fills st.
+int end_timed(sp_ctx* ctx, hipStream_t s, sp_stats* st, uint32_t nwg, uint32_t lanes,
+              uint32_t resident_per_cu, uint64_t ops);
+
+inline bool lanes_ok(uint32_t lanes) { return lanes >= 64 && lanes <= 1024 && lanes % 64 == 0; }
+
+inline uint32_t bucket_of(uint32_t contenders) { return contenders >= 64 ? 1u : 0u; }
+
+}  // namespace spi

@@ -1,0 +1,164 @@
+// Mutexes: state objects and the contention workload (Section 5, Mutex; Section 6's
+// lock-then-unlock loop, here with a non-empty critical section and random delays).
+#include <string.h>
+
+#include "sp/mutex.hpp"
+#include "sp_internal.hpp"
+
+struct sp_mutex {
+  sp_ctx* ctx = nullptr;
+  uint32_t kind = 0;      // SP_MUTEX_* or SP_MUTEX_DEFAULT (resolved per run)
+  uint32_t nlocks = 0;
+  uint32_t W = 0;         // words per lock
+  uint32_t wstride = 0;   // uint32 words between two locks' word blocks (line multiple)
+  sp_params p{};
+  uint32_t* d_state = nullptr;  // lock, ticket and turn lines + one private line
+  uint64_t state_words = 0;
+  uint32_t* d_words = nullptr;  // critical-section words, nlocks x wstride
+};
+
+namespace {
+
+// With `owner` set, the leader swaps its id into the lock's owner word on entry and
+// back out on exit; any other value seen means two workgroups were inside at once.
+template <int KIND>
+__global__ SP_FULL_OCCUPANCY void k_mutex(sp::MutexState s, uint32_t nlocks, uint32_t W, uint32_t wstride,
+                        uint32_t* words, uint32_t nwg, uint64_t total, uint32_t max_delay,
+                        uint32_t seed, uint64_t* finish, uint32_t* owner, uint32_t* err,
+                        uint64_t timeout) {
+  const sp::Ctl ctl{err, sp::wall_clock() + timeout};
+  const uint32_t b = blockIdx.x;
+  const uint64_t A = total / nwg + (b < total % nwg ? 1 : 0);
+  for (uint64_t j = 0; j < A; ++j) {
+    const uint32_t lock = sp::sched_key(seed, b, (uint32_t)j, 1) % nlocks;
+    if (sp::is_leader()) sp::spin_cycles(sp::sched_key(seed, b, (uint32_t)j, 2) % (max_delay + 1));
+    if (!sp::mutex_lock<KIND>(s, lock, ctl)) return;
+    uint32_t* own = owner ? owner + (size_t)lock * s.stride : nullptr;
+    if (own && sp::is_leader() && sp::exch_relaxed(own, b + 1) != 0)
+      sp::cas_relaxed(err, sp::DEV_OK, sp::DEV_PARITY);
+    uint32_t* wp = words + (size_t)lock * wstride;
+    for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) wp[w] = wp[w] + 1;
+    if (own && sp::is_leader() && sp::exch_relaxed(own, 0) != b + 1)
+      sp::cas_relaxed(err, sp::DEV_OK, sp::DEV_PARITY);
+    sp::mutex_unlock<KIND>(s, lock);
+  }
+  if (sp::is_leader() && finish) finish[b] = sp::wall_clock();
+}
+
+__global__ void k_gather_words(const uint32_t* words, uint32_t nlocks, uint32_t W,
+                               uint32_t wstride, uint32_t* out) {
+  const uint64_t n = (uint64_t)nlocks * W;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = words[(i / W) * wstride + i % W];
+}
+
+const void* mutex_kernel(uint32_t kind) {
+  switch (kind) {
+    case SP_MUTEX_SPIN_CAS: return (const void*)k_mutex<SP_MUTEX_SPIN_CAS>;
+    case SP_MUTEX_SPIN_EXCH: return (const void*)k_mutex<SP_MUTEX_SPIN_EXCH>;
+    case SP_MUTEX_SPIN_BACKOFF: return (const void*)k_mutex<SP_MUTEX_SPIN_BACKOFF>;
+    case SP_MUTEX_TICKET: return (const void*)k_mutex<SP_MUTEX_TICKET>;
+    case SP_MUTEX_SLEEP: return (const void*)k_mutex<SP_MUTEX_SLEEP>;
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_per_lock,
+                    const sp_params* p, sp_mutex** out) {
+  if (!ctx || !out || nlocks == 0 || words_per_lock == 0 || nlocks > (1u << 20) ||
+      words_per_lock > (1u << 16))
+    return SP_E_INVAL;
+  if (kind > SP_MUTEX_SLEEP && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
+  *out = nullptr;
+  sp_params q;
+  SP_CHECK(spi::normalize(ctx, p, &q));
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  sp_mutex* m = new sp_mutex();
+  m->ctx = ctx;
+  m->kind = kind;
+  m->nlocks = nlocks;
+  m->W = words_per_lock;
+  m->p = q;
+  // A DEFAULT mutex may resolve to any layout, so size for the widest padding.
+  const uint32_t sw = kind == SP_MUTEX_DEFAULT ? 1024 : spi::stride_words(q);
+  m->state_words = (4ull * nlocks + 1) * sw;  // lock, ticket, turn, owner lines + private
+  const uint32_t line_words = 32;  // 128-byte lines for the critical-section words
+  m->wstride = (words_per_lock + line_words - 1) / line_words * line_words;
+  hipError_t e = hipMalloc(&m->d_state, m->state_words * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&m->d_words, (uint64_t)nlocks * m->wstride * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    ctx->last_hip = (int)e;
+    hipFree(m->d_state);
+    hipFree(m->d_words);
+    delete m;
+    return SP_E_HIP;
+  }
+  *out = m;
+  return SP_OK;
+}
+
+int sp_mutex_destroy(sp_mutex* m) {
+  if (!m) return SP_E_INVAL;
+  hipSetDevice(m->ctx->device);
+  hipFree(m->d_state);
+  hipFree(m->d_words);
+  delete m;
+  return SP_OK;
+}
+
+int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
+                 uint32_t max_delay_cyc, uint32_t seed, uint32_t* out_words,
+                 uint64_t* out_finish, sp_stats* st, void* stream) {
+  if (!m || !out_words || nwg == 0 || !spi::lanes_ok(lanes) || max_delay_cyc == 0xFFFFFFFFu)
+    return SP_E_INVAL;
+  sp_ctx* ctx = m->ctx;
+  hipStream_t s = spi::as_stream(stream);
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  uint32_t kind = m->kind;
+  sp_params q = m->p;
+  if (kind == SP_MUTEX_DEFAULT) {
+    const sp_default_entry& d = ctx->defaults[1][spi::bucket_of(nwg / m->nlocks)];
+    kind = d.kind;
+    const uint32_t t = q.timeout_ms;
+    q = d.p;
+    q.timeout_ms = t;
+  }
+  if (kind == SP_MUTEX_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) q.backoff = SP_BACKOFF_EXP;
+  if (kind == SP_MUTEX_SPIN_CAS || kind == SP_MUTEX_SLEEP) q.backoff = SP_BACKOFF_NONE;
+  const void* kern = mutex_kernel(kind);
+  if (!kern) return SP_E_INVAL;
+  const uint32_t sw = spi::stride_words(q);
+  uint32_t* base = m->d_state;
+  sp::MutexState ms;
+  ms.stride = sw;
+  ms.poll_sleep = q.poll_sleep;
+  ms.lockw = base;
+  ms.ticket = base + (uint64_t)m->nlocks * sw;
+  ms.turn = base + 2ull * m->nlocks * sw;
+  ms.bo = spi::backoff_cfg(q, base + 4ull * m->nlocks * sw);
+  uint32_t* owner = q.verify ? base + 3ull * m->nlocks * sw : nullptr;
+  SP_CHECK(spi::fill_u32(ctx, m->d_state, m->state_words, 0, s));
+  SP_CHECK(spi::fill_u32(ctx, m->d_words, (uint64_t)m->nlocks * m->wstride, 0, s));
+  int per_cu = 0;
+  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  SP_CHECK(spi::begin_timed(ctx, s));
+  uint64_t timeout = spi::timeout_ticks(ctx, q);
+  uint32_t nlocks = m->nlocks, W = m->W, wstride = m->wstride;
+  void* args[] = {&ms, &nlocks, &W, &wstride, &m->d_words, &nwg, &total_acq, &max_delay_cyc,
+                  &seed, &out_finish, &owner, &ctx->d_err, &timeout};
+  SP_HIP(ctx, hipLaunchKernel(kern, dim3(nwg), dim3(lanes), args, 0, s));
+  int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, total_acq);
+  if (rc != SP_OK && rc != SP_E_TIMEOUT && rc != SP_E_PARITY) return rc;
+  hipLaunchKernelGGL(k_gather_words, dim3(256), dim3(256), 0, s, m->d_words, nlocks, W, wstride,
+                     out_words);
+  SP_HIP(ctx, hipGetLastError());
+  SP_HIP(ctx, hipStreamSynchronize(s));
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Counting semaphores: state objects and the wait/hold/post workload (Section 5,
+// Semaphore; Section 6's wait-then-post loop, here with a tracked occupancy and holds).
+#include <string.h>
+
+#include "sp/semaphore.hpp"
+#include "sp_internal.hpp"
+
+struct sp_sem {
+  sp_ctx* ctx = nullptr;
+  uint32_t kind = 0;  // SP_SEM_* or SP_SEM_DEFAULT (resolved per run)
+  uint32_t K = 0;
+  sp_params p{};
+  uint32_t* d_state = nullptr;
+  uint64_t state_words = 0;
+};
+
+namespace {
+
+// Line indices of the semaphore state (each line `stride` words).
+enum { L_S = 0, L_COUNT, L_TICKET, L_TURN, L_OCC, L_MAXOCC, L_ADM, L_PRIVATE, L_LINES };
+
+template <int KIND>
+__global__ SP_FULL_OCCUPANCY void k_sem(sp::SemState s, uint32_t stride, uint32_t* state, uint32_t nwg,
+                      uint64_t total, uint32_t max_hold, uint32_t seed, uint32_t track,
+                      uint32_t* chk, uint32_t* err, uint64_t timeout) {
+  const sp::Ctl ctl{err, sp::wall_clock() + timeout};
+  const uint32_t b = blockIdx.x;
+  const uint64_t A = total / nwg + (b < total % nwg ? 1 : 0);
+  uint32_t* occ = state + L_OCC * stride;
+  uint32_t* maxocc = state + L_MAXOCC * stride;
+  uint32_t c = 0;
+  for (uint64_t j = 0; j < A; ++j) {
+    const uint32_t hold = sp::sched_key(seed, b, (uint32_t)j, 3) % (max_hold + 1);
+    if (!sp::sem_wait<KIND>(s, ctl)) return;
+    if (sp::is_leader()) {
+      if (track) sp::max_relaxed(maxocc, sp::add_relaxed(occ, 1) + 1);
+      c ^= sp::sm32(seed ^ (b << 16) ^ (uint32_t)j);
+      sp::spin_cycles(hold);
+      if (track) sp::add_relaxed(occ, 0xFFFFFFFFu);
+    }
+    if (!sp::sem_post<KIND>(s, ctl)) return;
+  }
+  if (sp::is_leader()) {
+    chk[b] = c;
+    sp::add_relaxed(state + L_ADM * stride, (uint32_t)A);
+  }
+}
+
+__global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg4, uint32_t* out) {
+  if (threadIdx.x == 0) {
+    out[0] = state[L_MAXOCC * stride];
+    out[1] = alg4 ? state[L_S * stride] : state[L_COUNT * stride];
+    out[2] = state[L_TICKET * stride];
+    out[3] = state[L_TURN * stride];
+    out[4] = state[L_ADM * stride];
+    out[5] = state[L_COUNT * stride];
+    out[6] = state[L_OCC * stride];
+    out[7] = 0;
+  }
+}
+
+const void* sem_kernel(uint32_t kind) {
+  switch (kind) {
+    case SP_SEM_SPIN: return (const void*)k_sem<SP_SEM_SPIN>;
+    case SP_SEM_SPIN_BACKOFF: return (const void*)k_sem<SP_SEM_SPIN_BACKOFF>;
+    case SP_SEM_TICKET: return (const void*)k_sem<SP_SEM_TICKET>;
+    case SP_SEM_SLEEP: return (const void*)k_sem<SP_SEM_SLEEP>;
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out) {
+  if (!ctx || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
+  if (kind > SP_SEM_SLEEP && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  *out = nullptr;
+  sp_params q;
+  SP_CHECK(spi::normalize(ctx, p, &q));
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  sp_sem* s = new sp_sem();
+  s->ctx = ctx;
+  s->kind = kind;
+  s->K = K;
+  s->p = q;
+  s->state_words = (uint64_t)L_LINES * 1024;  // room for the widest padding
+  hipError_t e = hipMalloc(&s->d_state, s->state_words * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    ctx->last_hip = (int)e;
+    delete s;
+    return SP_E_HIP;
+  }
+  *out = s;
+  return SP_OK;
+}
+
+int sp_sem_destroy(sp_sem* s) {
+  if (!s) return SP_E_INVAL;
+  hipSetDevice(s->ctx->device);
+  hipFree(s->d_state);
+  delete s;
+  return SP_OK;
+}
+
+int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
+               uint32_t max_hold_cyc, uint32_t seed, uint32_t track, uint32_t* out_chk,
+               uint32_t* out_state, sp_stats* st, void* stream) {
+  if (!sem || !out_chk || !out_state || nwg == 0 || !spi::lanes_ok(lanes) ||
+      max_hold_cyc == 0xFFFFFFFFu || total_pairs >= (1ull << 32))
+    return SP_E_INVAL;
+  sp_ctx* ctx = sem->ctx;
+  hipStream_t s = spi::as_stream(stream);
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  uint32_t kind = sem->kind;
+  sp_params q = sem->p;
+  if (kind == SP_SEM_DEFAULT) {
+    const sp_default_entry& d = ctx->defaults[2][spi::bucket_of(nwg / sem->K)];
+    kind = d.kind;
+    const uint32_t t = q.timeout_ms;
+    q = d.p;
+    q.timeout_ms = t;
+  }
+  if (kind == SP_SEM_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) q.backoff = SP_BACKOFF_EXP;
+  if (kind != SP_SEM_SPIN_BACKOFF) q.backoff = SP_BACKOFF_NONE;
+  const void* kern = sem_kernel(kind);
+  if (!kern) return SP_E_INVAL;
+  const uint32_t sw = spi::stride_words(q);
+  uint32_t* base = sem->d_state;
+  sp::SemState ss;
+  ss.K = sem->K;
+  ss.poll_sleep = q.poll_sleep;
+  ss.S = base + L_S * sw;
+  ss.count = base + L_COUNT * sw;
+  ss.ticket = base + L_TICKET * sw;
+  ss.turn = base + L_TURN * sw;
+  ss.bo = spi::backoff_cfg(q, base + L_PRIVATE * sw);
+  SP_CHECK(spi::fill_u32(ctx, base, sem->state_words, 0, s));
+  if (kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF)
+    SP_CHECK(spi::fill_u32(ctx, ss.S, 1, sem->K + 1, s));  // Algorithm 4: S = K + 1
+  int per_cu = 0;
+  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  SP_CHECK(spi::begin_timed(ctx, s));
+  uint64_t timeout = spi::timeout_ticks(ctx, q);
+  uint32_t stride = sw;
+  void* args[] = {&ss, &stride, &base, &nwg, &total_pairs, &max_hold_cyc, &seed, &track,
+                  &out_chk, &ctx->d_err, &timeout};
+  SP_HIP(ctx, hipLaunchKernel(kern, dim3(nwg), dim3(lanes), args, 0, s));
+  int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, total_pairs);
+  const uint32_t alg4 = kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF;
+  hipLaunchKernelGGL(k_sem_state, dim3(1), dim3(64), 0, s, base, sw, alg4, out_state);
+  SP_HIP(ctx, hipGetLastError());
+  SP_HIP(ctx, hipStreamSynchronize(s));
+  return rc;
+}
+
+}  // extern "C"

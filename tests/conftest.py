@@ -9,3 +9,19 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: longer CPU test")
+
+import pytest
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    import paper_1110_4623_amd as sp
+    c = sp.Context(0)
+    print(f"\n[gpu] {c.info}", flush=True)
+    yield c
+    c.close()
+
+
+def announce(*parts):
+    """Print what a GPU step is about to run (flushed before the launch)."""
+    print("[gpu-step]", *parts, flush=True)

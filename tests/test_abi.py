@@ -1,0 +1,59 @@
+"""The C ABI library loads and exports every entry point include/sp.h declares (CPU:
+loading only, no compute calls)."""
+
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^(?:int|void|const char\*)\s+(sp_\w+)\(", text, re.M)
+    return names
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    assert len(names) >= 20
+    assert len(names) == len(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1110_4623_amd import _native
+    missing = [n for n in _declared() if not hasattr(_native.lib, n)]
+    assert not missing, missing
+
+
+def test_error_strings():
+    from paper_1110_4623_amd import _native
+    lib = _native.lib
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.sp_strerror(code).decode()
+    assert lib.sp_strerror(-99).decode() == "unknown error"
+
+
+def test_params_default_roundtrip():
+    import ctypes
+    from paper_1110_4623_amd import _native, api
+    p = api.make_params(backoff="paper", backoff_min=2, backoff_max=64, poll_sleep=3)
+    assert (p.backoff, p.backoff_min, p.backoff_max, p.poll_sleep) == (1, 2, 64, 3)
+    assert p.pad_bytes == 128 and p.timeout_ms == 20000
+    assert ctypes.sizeof(_native.Params) == 64
+    assert ctypes.sizeof(_native.Stats) == 64
+
+
+def test_bad_arguments_rejected_without_gpu():
+    import ctypes
+    from paper_1110_4623_amd import _native
+    lib = _native.lib
+    h = ctypes.c_void_p()
+    # null context / null out pointers are argument errors, checked before any HIP call
+    assert lib.sp_barrier_create(None, 0, 16, None, ctypes.byref(h)) == _native.SP_E_INVAL
+    assert lib.sp_mutex_create(None, 0, 1, 1, None, ctypes.byref(h)) == _native.SP_E_INVAL
+    assert lib.sp_sem_create(None, 0, 1, None, ctypes.byref(h)) == _native.SP_E_INVAL
+    assert lib.sp_fini(None) == _native.SP_E_INVAL
+    assert lib.sp_barrier_run_hash(None, 64, 1, 0, None, None, None) == _native.SP_E_INVAL

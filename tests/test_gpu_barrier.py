@@ -1,0 +1,90 @@
+"""GPU parity of the global barriers on the hash-exchange workload: element-by-element
+equality of every workgroup's checksum with the oracle's closed form."""
+
+import numpy as np
+import pytest
+
+import oracle
+import sp_inputs
+from conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["central", "central_split", "tree", "flag", "xcd", "grid_sync"]
+OURS = ["central", "central_split", "tree", "flag", "xcd"]
+
+
+def _run(ctx, kind, nwg, lanes, rounds, seed, **params):
+    import paper_1110_4623_amd as sp
+    announce("barrier", kind, f"nwg={nwg} lanes={lanes} rounds={rounds} seed={seed}", params)
+    bar = sp.Barrier(ctx, kind, nwg, **params)
+    try:
+        chk, st = bar.run_hash(lanes=lanes, rounds=rounds, seed=seed)
+    finally:
+        bar.close()
+    return chk.numpy().astype(np.uint32), st
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("seed", sp_inputs.SEEDS)
+def test_small_config(ctx, kind, seed):
+    # 16 workgroups x 64 lanes x 1000 rounds
+    chk, st = _run(ctx, kind, 16, 64, 1000, seed)
+    assert (chk == oracle.barrier_closed(seed, 16, 1000)).all()
+    assert st["device_error"] == 0
+
+
+@pytest.mark.parametrize("kind", OURS)
+@pytest.mark.parametrize("nwg,lanes,rounds", [(1, 64, 10), (2, 128, 50), (7, 256, 300),
+                                               (9, 64, 300), (100, 192, 200), (257, 256, 100),
+                                               (500, 1024, 20)])
+def test_ragged_shapes(ctx, kind, nwg, lanes, rounds):
+    chk, _ = _run(ctx, kind, nwg, lanes, rounds, 0xC0FFEE)
+    assert (chk == oracle.barrier_closed(0xC0FFEE, nwg, rounds)).all()
+
+
+@pytest.mark.parametrize("kind", OURS)
+@pytest.mark.parametrize("nwg", [256, 1024, 2048])
+def test_at_scale(ctx, kind, nwg):
+    # co-resident workgroups x 256 lanes x 10^4 rounds
+    chk, st = _run(ctx, kind, nwg, 256, 10_000, 42)
+    assert (chk == oracle.barrier_closed(42, nwg, 10_000)).all()
+
+
+@pytest.mark.parametrize("params", [dict(fan_in=2), dict(fan_in=16), dict(fan_in=64),
+                                    dict(pad_bytes=4), dict(pad_bytes=4096), dict(poll_sleep=0),
+                                    dict(poll_sleep=8)])
+def test_tree_parameters(ctx, params):
+    chk, _ = _run(ctx, "tree", 512, 256, 500, 7, **params)
+    assert (chk == oracle.barrier_closed(7, 512, 500)).all()
+
+
+@pytest.mark.parametrize("params", [dict(flags_packed=1), dict(pad_bytes=64), dict(poll_sleep=0)])
+def test_flag_parameters(ctx, params):
+    chk, _ = _run(ctx, "flag", 1024, 256, 500, 7, **params)
+    assert (chk == oracle.barrier_closed(7, 1024, 500)).all()
+
+
+@pytest.mark.parametrize("params", [dict(pad_bytes=64), dict(pad_bytes=4096), dict(poll_sleep=0),
+                                    dict(poll_sleep=16)])
+def test_xcd_parameters(ctx, params):
+    chk, _ = _run(ctx, "xcd", 2048, 256, 500, 7, **params)
+    assert (chk == oracle.barrier_closed(7, 2048, 500)).all()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_kernel_boundary_comparator(ctx, graph):
+    import paper_1110_4623_amd as sp
+    announce("barrier launches", f"graph={graph}")
+    chk, st = sp.barrier_hash_launches(ctx, 64, 64, 200, 42, graph=graph)
+    assert (chk.numpy().astype(np.uint32) == oracle.barrier_closed(42, 64, 200)).all()
+
+
+def test_not_resident_is_refused(ctx):
+    import paper_1110_4623_amd as sp
+    nwg = ctx.info["cu_count"] * 64  # far more 1024-lane workgroups than can be resident
+    announce("barrier not-resident", nwg)
+    bar = sp.Barrier(ctx, "central", nwg)
+    with pytest.raises(sp.SpNotResident):
+        bar.run_hash(lanes=1024, rounds=1, seed=1)
+    bar.close()

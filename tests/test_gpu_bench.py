@@ -1,0 +1,92 @@
+"""GPU parity of the memory-system microbenchmarks against the oracle's closed forms."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import sp_inputs
+from conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("op", ["add", "cas", "ld", "st"])
+@pytest.mark.parametrize("mode", ["per_lane", "wave_leader"])
+@pytest.mark.parametrize("T,stride", [(1, 4), (32, 64), (1024, 128), (1 << 20, 128), (37, 4)])
+def test_closed_forms(ctx, op, mode, T, stride):
+    import paper_1110_4623_amd as sp
+    nwg, lanes, n, seed = 64, 256, 40, 42
+    if op == "cas" and T == 1 and mode == "per_lane":
+        n = 4  # one word, 16384 lanes retrying compare-and-swap: keep the run short
+    announce("bench", op, mode, f"T={T} stride={stride} nwg={nwg} n={n}")
+    perm_np = sp_inputs.permutation(T, seed)
+    perm = torch.from_numpy(perm_np.astype(np.int32)).cuda()
+    finals, s, st = sp.bench_atomic(ctx, op, nwg, lanes, T, stride, mode, n, seed, perm)
+    U = nwg * lanes if mode == "per_lane" else nwg * (lanes // 64)
+    ef, es = oracle.bench_closed(op, seed, U, n, perm_np)
+    assert (finals.numpy().astype(np.uint32) == ef).all()
+    if op != "st":
+        assert s == es
+
+
+@pytest.mark.parametrize("mode", ["per_lane", "wave_leader"])
+@pytest.mark.parametrize("T", [1, 32, 1024])
+def test_exchange_conservation(ctx, mode, T):
+    import paper_1110_4623_amd as sp
+    nwg, lanes, n, seed = 32, 128, 50, 7
+    announce("bench exch", mode, T)
+    perm_np = sp_inputs.permutation(T, seed)
+    perm = torch.from_numpy(perm_np.astype(np.int32)).cuda()
+    finals, s, _ = sp.bench_atomic(ctx, "exch", nwg, lanes, T, 128, mode, n, seed, perm)
+    U = nwg * lanes if mode == "per_lane" else nwg * (lanes // 64)
+    _, conserved = oracle.bench_closed("exch", seed, U, n, perm_np)
+    assert s == conserved
+
+
+def test_full_size_add_sampled(ctx):
+    # 2048 workgroups x 256 lanes per-lane adds over 2^20 words: sampled words are
+    # compared one by one with the oracle's per-word count, and the total is exact.
+    import paper_1110_4623_amd as sp
+    nwg, lanes, T, n, seed = 2048, 256, 1 << 20, 200, 42
+    announce("bench add full", nwg, lanes, T, n)
+    perm_np = sp_inputs.permutation(T, seed)
+    perm = torch.from_numpy(perm_np.astype(np.int32)).cuda()
+    finals, s, _ = sp.bench_atomic(ctx, "add", nwg, lanes, T, 128, "per_lane", n, seed, perm)
+    U = nwg * lanes
+    f = finals.numpy().astype(np.int64)
+    assert int(f.sum()) == U * n
+    inv = np.argsort(perm_np)
+    rng = np.random.default_rng(0)
+    for t in rng.choice(T, 64, replace=False):
+        assert f[t] == oracle.bench_count_one(U, n, T, int(inv[t]))
+
+
+@pytest.mark.parametrize("test", ["cont_vol_read", "cont_vol_write", "noncont_vol_read",
+                                  "noncont_vol_write", "cont_atom_read", "cont_atom_write",
+                                  "noncont_atom_read", "noncont_atom_write",
+                                  "cont_vol_read_after_atom", "cont_vol_write_after_atom",
+                                  "noncont_vol_read_after_atom", "noncont_vol_write_after_atom"])
+def test_paper12_leaves_zeros(ctx, test):
+    # add-of-zero reads and exchange-with-zero writes keep every word at 0 (Section 3)
+    import paper_1110_4623_amd as sp
+    announce("paper12", test)
+    s, buf, st = sp.paper12(ctx, test, nwg=256, lanes=64, n_ops=1000, stride=256)
+    assert s == 0
+    assert int(buf.abs().sum().item()) == 0
+
+
+def test_stream_sum(ctx):
+    import paper_1110_4623_amd as sp
+    n = 1 << 24
+    announce("stream", n)
+    buf = torch.arange(n, dtype=torch.int32, device="cuda")
+    s, st = sp.stream_read(ctx, buf, reps=2)
+    assert s == 2 * (n * (n - 1) // 2)
+
+
+def test_pingpong(ctx):
+    import paper_1110_4623_amd as sp
+    announce("pingpong")
+    out, st = sp.pingpong(ctx, 1000)
+    assert out[0] == 2000 and out[1] == 1999

@@ -1,0 +1,77 @@
+"""GPU parity of the semaphores: per-workgroup admission checksums equal the oracle's,
+the tracked occupancy never exceeds K, and each algorithm ends in its quiescent state."""
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["spin", "spin_backoff", "ticket", "sleep"]
+
+
+def _run(ctx, kind, K, nwg, lanes, total, hold, seed, **params):
+    import paper_1110_4623_amd as sp
+    announce("sem", kind, f"K={K} nwg={nwg} lanes={lanes} total={total} hold={hold}", params)
+    s = sp.Semaphore(ctx, kind, K, **params)
+    try:
+        return s.run(nwg=nwg, lanes=lanes, total=total, max_hold=hold, seed=seed)
+    finally:
+        s.close()
+
+
+def _check(r, kind, K, nwg, total, seed):
+    assert (r["chk"].numpy().astype(np.uint32) == oracle.sem_closed(seed, nwg, total)).all()
+    assert 1 <= r["maxocc"] <= K
+    s_or_count, ticket, turn, adm = r["state"]
+    assert adm == total
+    assert r["occ"] == 0
+    if kind.startswith("spin"):
+        assert s_or_count == K + 1
+    else:
+        assert s_or_count == 0 and ticket == turn
+        if K >= nwg:
+            assert ticket == 0
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("K", [1, 4, 32, 256])
+def test_small(ctx, kind, K):
+    nwg, total, seed = 128, 1 << 13, 42
+    r = _run(ctx, kind, K, nwg, 256, total, 200, seed)
+    _check(r, kind, K, nwg, total, seed)
+
+
+@pytest.mark.parametrize("kind", ["ticket", "sleep"])
+@pytest.mark.parametrize("K", [1, 4, 32, 256])
+def test_full_size(ctx, kind, K):
+    # 2048 workgroups, 2^20 wait/post pairs, holds uniform in [0, 2000] cycles
+    nwg, total, seed = 2048, 1 << 20, 0xC0FFEE
+    r = _run(ctx, kind, K, nwg, 256, total, 2000, seed)
+    _check(r, kind, K, nwg, total, seed)
+
+
+@pytest.mark.parametrize("kind", ["spin", "spin_backoff"])
+@pytest.mark.parametrize("K", [4, 32, 256])
+def test_spin_at_full_width(ctx, kind, K):
+    # Algorithm 4 with 2048 contenders: every wait and post exchanges the one word S
+    # while 2047 others do the same, so a pair costs tens of microseconds; one pair per
+    # workgroup keeps the run short at full width.
+    nwg, total, seed = 2048, 2048, 0xC0FFEE
+    r = _run(ctx, kind, K, nwg, 256, total, 2000, seed)
+    _check(r, kind, K, nwg, total, seed)
+
+
+@pytest.mark.parametrize("kind", ["spin", "spin_backoff"])
+def test_spin_as_mutex(ctx, kind):
+    nwg, total, seed = 64, 1024, 7
+    r = _run(ctx, kind, 1, nwg, 256, total, 2000, seed)
+    _check(r, kind, 1, nwg, total, seed)
+
+
+@pytest.mark.parametrize("kind", ["ticket", "sleep"])
+def test_capacity_above_agents_never_queues(ctx, kind):
+    r = _run(ctx, kind, 64, 16, 64, 4000, 50, 7)
+    _check(r, kind, 64, 16, 4000, 7)
