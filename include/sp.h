@@ -117,7 +117,10 @@ typedef struct sp_params {
   uint32_t timeout_ms;   /* watchdog for every device wait (0 = 20000)                   */
   uint32_t verify;       /* mutex runs: check mutual exclusion inside every critical     */
                          /* section with an owner word (SP_E_PARITY on a violation)       */
-  uint32_t reserved[6];
+  uint32_t cooperative;  /* barrier runs: 1 = hipLaunchCooperativeKernel; 0 = plain launch */
+                         /* after the library's own co-residency check (a workgroup that   */
+                         /* is not resident ends in SP_E_TIMEOUT through the watchdog)     */
+  uint32_t reserved[5];
 } sp_params;
 
 typedef struct sp_stats {
@@ -166,6 +169,15 @@ int sp_last_hip_error(const sp_ctx* ctx);
 /* Writes the XCC id of every workgroup of a plain launch of nwg x lanes into
  * out (device, nwg uint32).                                                             */
 int sp_probe_xcc(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t* out, void* stream);
+
+/* ---- device memory for callers without their own allocator ------------------------
+ * sp_buffer_alloc: `bytes` of device memory on the context's GPU, zero-filled; the
+ * caller frees it with sp_buffer_free.  sp_buffer_read / sp_buffer_write copy between
+ * a device buffer and host memory (synchronous).  Errors: SP_E_INVAL, SP_E_HIP.          */
+int sp_buffer_alloc(sp_ctx* ctx, uint64_t bytes, void** out);
+int sp_buffer_free(sp_ctx* ctx, void* p);
+int sp_buffer_read(sp_ctx* ctx, void* host_dst, const void* dev_src, uint64_t bytes);
+int sp_buffer_write(sp_ctx* ctx, void* dev_dst, const void* host_src, uint64_t bytes);
 
 /* ---- barrier (Section 5, Barrier; Table 4 Barrier()) ------------------------------------
  * sp_barrier_create: state for a barrier among exactly nwg workgroups (all must be
@@ -258,6 +270,10 @@ int sp_bench_paper12(sp_ctx* ctx, uint32_t test, uint32_t nwg, uint32_t lanes, u
  * uint32 words into out_sum (device, 1 uint64).  nwg = 0 picks a grid.                 */
 int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, uint32_t reps,
                     uint64_t* out_sum, sp_stats* st, void* stream);
+/* sp_bench_copy: copies `bytes` (multiple of 16) from src to dst (device, disjoint) with
+ * 16-byte loads and stores, `reps` times; the streaming read+write reference kernel.   */
+int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint32_t reps,
+                  sp_stats* st, void* stream);
 /* sp_bench_pingpong: two workgroups hand a token back and forth `rounds` times through
  * two agent-scope words (release store, relaxed polling, acquire fence), measuring the
  * one-way coherence latency.  words: device, 2048 bytes, zeroed by the call.

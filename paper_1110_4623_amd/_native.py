@@ -9,10 +9,17 @@ from __future__ import annotations
 import ctypes
 import os
 
-# Import torch first: its wheel bundles the HIP runtime (soname libamdhip64.so.7), and
-# loading it before libsp.so makes libsp.so bind to that same runtime, so device
-# pointers and streams created by torch are valid in the library.
-import torch  # noqa: F401
+# PyTorch's wheel bundles its own HIP runtime (soname libamdhip64.so.7).  Importing torch
+# before libsp.so is loaded makes libsp.so bind to that same runtime, so device pointers
+# and streams created by torch are valid in the library.  A process that never uses
+# torch sets SP_NO_TORCH=1 and the library binds to the system ROCm runtime instead; it
+# then allocates device memory through sp_buffer_alloc.
+USE_TORCH = os.environ.get("SP_NO_TORCH", "0") != "1"
+if USE_TORCH:
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        USE_TORCH = False
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsp.so")
@@ -54,7 +61,8 @@ class Params(ctypes.Structure):
         ("flags_packed", ctypes.c_uint32),
         ("timeout_ms", ctypes.c_uint32),
         ("verify", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 6),
+        ("cooperative", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 5),
     ]
 
 
@@ -130,6 +138,10 @@ def _load():
         "sp_strerror": (ctypes.c_char_p, [i32]),
         "sp_last_hip_error": (i32, [vp]),
         "sp_probe_xcc": (i32, [vp, u32, u32, vp, vp]),
+        "sp_buffer_alloc": (i32, [vp, u64, P(vp)]),
+        "sp_buffer_free": (i32, [vp, vp]),
+        "sp_buffer_read": (i32, [vp, vp, vp, u64]),
+        "sp_buffer_write": (i32, [vp, vp, vp, u64]),
         "sp_barrier_create": (i32, [vp, u32, u32, P(Params), P(vp)]),
         "sp_barrier_destroy": (i32, [vp]),
         "sp_barrier_run_hash": (i32, [vp, u32, u32, u32, vp, P(Stats), vp]),
@@ -145,6 +157,7 @@ def _load():
         "sp_bench_paper12": (i32, [vp, u32, u32, u32, u32, u32, vp, vp, P(Stats), vp]),
         "sp_bench_stream": (i32, [vp, vp, u64, u32, u32, vp, P(Stats), vp]),
         "sp_bench_pingpong": (i32, [vp, u32, vp, vp, P(Stats), vp]),
+        "sp_bench_copy": (i32, [vp, vp, vp, u64, u32, P(Stats), vp]),
         "sp_serve_run": (i32, [vp, P(ServeCfg), u32, vp, vp, vp, u32, vp, vp, P(ServeResult)]),
         "sp_serve_run_launch_per_request": (i32, [vp, P(ServeCfg), u32, vp, vp, vp, u32, vp, vp,
                                                   P(ServeResult)]),

@@ -1,60 +1,75 @@
 """Python API over libsp.so: contexts, barriers, mutexes, semaphores, microbenchmarks.
 
-Thin wrappers: they allocate output tensors with torch (device memory), pass raw
-pointers and torch's current HIP stream to the C ABI, and convert statistics.  Every
-primitive runs in the library's kernels; nothing here computes a result.
+Thin wrappers: they allocate device buffers, pass raw pointers and a HIP stream to the
+C ABI, and read results back as numpy arrays.  Every primitive runs in the library's
+kernels; nothing here computes a result.
+
+Device memory comes from PyTorch (CUDA tensors, launched on torch's current stream)
+when torch is in the process, otherwise from the library's own sp_buffer_alloc
+(launched on the null stream); see _native.USE_TORCH.
 """
 
 from __future__ import annotations
 
 import ctypes
 
-import torch
+import numpy as np
 
 from . import _native as N
 from ._native import check, lib
 
-
-def _stream() -> ctypes.c_void_p:
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+_NP = {"u32": np.uint32, "u64": np.uint64, "i64": np.int64}
 
 
-def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
-    if t is None:
-        return ctypes.c_void_p(0)
-    if not t.is_cuda or not t.is_contiguous():
-        raise ValueError("expected a contiguous CUDA (HIP) tensor")
-    return ctypes.c_void_p(t.data_ptr())
+class DeviceBuffer:
+    """Zero-filled device memory from sp_buffer_alloc (the torch-free path)."""
 
+    def __init__(self, ctx: "Context", nbytes: int):
+        self.ctx, self.nbytes = ctx, nbytes
+        p = ctypes.c_void_p()
+        check(lib.sp_buffer_alloc(ctx.h, nbytes, ctypes.byref(p)), "sp_buffer_alloc", ctx.h)
+        self.p = p
 
-def _u32(t: torch.Tensor) -> torch.Tensor:
-    """View an int32 tensor's bits as uint32 values in an int64 CPU tensor."""
-    return t.cpu().to(torch.int64) & 0xFFFFFFFF
+    def ptr(self) -> ctypes.c_void_p:
+        return self.p
 
+    def read(self, dtype, count: int) -> np.ndarray:
+        out = np.empty(count, dtype=dtype)
+        check(lib.sp_buffer_read(self.ctx.h, out.ctypes.data_as(ctypes.c_void_p), self.p,
+                                 out.nbytes), "sp_buffer_read", self.ctx.h)
+        return out
 
-def make_params(**kw) -> N.Params:
-    p = N.Params()
-    lib.sp_params_default(ctypes.byref(p))
-    for k, v in kw.items():
-        if k == "backoff" and isinstance(v, str):
-            v = N.BACKOFF[v]
-        if k == "backoff_unit" and isinstance(v, str):
-            v = N.BACKOFF_UNIT[v]
-        if not hasattr(p, k):
-            raise TypeError(f"unknown parameter {k}")
-        setattr(p, k, int(v))
-    return p
+    def write(self, arr: np.ndarray) -> None:
+        arr = np.ascontiguousarray(arr)
+        check(lib.sp_buffer_write(self.ctx.h, self.p, arr.ctypes.data_as(ctypes.c_void_p),
+                                  arr.nbytes), "sp_buffer_write", self.ctx.h)
+
+    def close(self):
+        if self.p:
+            lib.sp_buffer_free(self.ctx.h, self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:
-    """A libsp context bound to one HIP device (torch's current device by default)."""
+    """A libsp context bound to one HIP device."""
 
     def __init__(self, device: int | None = None):
-        if not torch.cuda.is_available():
-            raise RuntimeError("no HIP device visible: libsp needs an MI355X (gfx950) GPU")
-        self.device = torch.cuda.current_device() if device is None else device
-        torch.cuda.set_device(self.device)
-        torch.cuda.init()
+        self.torch = None
+        if N.USE_TORCH:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no HIP device visible: libsp needs an MI355X (gfx950) GPU")
+            self.torch = torch
+            device = torch.cuda.current_device() if device is None else device
+            torch.cuda.set_device(device)
+            torch.cuda.init()
+        self.device = 0 if device is None else device
         h = ctypes.c_void_p()
         check(lib.sp_init(self.device, ctypes.byref(h)), "sp_init")
         self.h = h
@@ -67,6 +82,54 @@ class Context:
             "max_threads_per_cu": info.max_threads_per_cu,
         }
 
+    # ---- memory and streams --------------------------------------------------------
+    def stream(self) -> ctypes.c_void_p:
+        if self.torch is not None:
+            return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+        return ctypes.c_void_p(0)
+
+    def zeros(self, count: int, dtype: str = "u32"):
+        """Zero-filled device array of `count` elements (u32, u64 or i64)."""
+        size = np.dtype(_NP[dtype]).itemsize
+        if self.torch is not None:
+            tdt = {"u32": self.torch.int32, "u64": self.torch.int64, "i64": self.torch.int64}[dtype]
+            return self.torch.zeros(max(count, 1), dtype=tdt, device="cuda")
+        return DeviceBuffer(self, max(count, 1) * size)
+
+    def upload(self, arr: np.ndarray):
+        arr = np.ascontiguousarray(arr)
+        if self.torch is not None:
+            view = arr.view(np.int32) if arr.dtype == np.uint32 else arr
+            return self.torch.from_numpy(view.copy()).cuda()
+        buf = DeviceBuffer(self, arr.nbytes)
+        buf.write(arr)
+        return buf
+
+    def read(self, buf, dtype: str, count: int | None = None) -> np.ndarray:
+        npdt = _NP[dtype]
+        if isinstance(buf, DeviceBuffer):
+            n = buf.nbytes // np.dtype(npdt).itemsize if count is None else count
+            return buf.read(npdt, n)
+        a = buf.detach().cpu().numpy()
+        a = a.view(np.uint32) if dtype == "u32" and a.dtype == np.int32 else a
+        a = a.view(np.uint64) if dtype == "u64" and a.dtype == np.int64 else a
+        return (a if count is None else a[:count]).astype(npdt, copy=False)
+
+    @staticmethod
+    def ptr(buf) -> ctypes.c_void_p:
+        if buf is None:
+            return ctypes.c_void_p(0)
+        if isinstance(buf, DeviceBuffer):
+            return buf.ptr()
+        if not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("expected a contiguous device tensor")
+        return ctypes.c_void_p(buf.data_ptr())
+
+    def synchronize(self):
+        if self.torch is not None:
+            self.torch.cuda.synchronize()
+
+    # ---- lifetime ------------------------------------------------------------------
     def close(self):
         if self.h:
             lib.sp_fini(self.h)
@@ -85,14 +148,46 @@ class Context:
         check(lib.sp_set_default(self.h, prim, bucket, kinds[kind], ctypes.byref(p)),
               "sp_set_default", self.h)
 
-    def probe_xcc(self, nwg: int, lanes: int = 64) -> torch.Tensor:
-        out = torch.zeros(nwg, dtype=torch.int32, device="cuda")
-        check(lib.sp_probe_xcc(self.h, nwg, lanes, _ptr(out), _stream()), "sp_probe_xcc", self.h)
-        return out.cpu()
+    def probe_xcc(self, nwg: int, lanes: int = 64) -> np.ndarray:
+        out = self.zeros(nwg)
+        check(lib.sp_probe_xcc(self.h, nwg, lanes, self.ptr(out), self.stream()), "sp_probe_xcc",
+              self.h)
+        return self.read(out, "u32", nwg)
 
 
-class Barrier:
+def make_params(**kw) -> N.Params:
+    p = N.Params()
+    lib.sp_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "backoff" and isinstance(v, str):
+            v = N.BACKOFF[v]
+        if k == "backoff_unit" and isinstance(v, str):
+            v = N.BACKOFF_UNIT[v]
+        if not hasattr(p, k) or k == "reserved":
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, int(v))
+    return p
+
+
+class _Handle:
+    _destroy = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            type(self)._destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Barrier(_Handle):
     """Global barrier among `nwg` co-resident workgroups (Section 5, Barrier)."""
+
+    _destroy = staticmethod(lambda h: lib.sp_barrier_destroy(h))
 
     def __init__(self, ctx: Context, kind: str, nwg: int, **params):
         self.ctx, self.kind, self.nwg = ctx, kind, nwg
@@ -101,42 +196,34 @@ class Barrier:
         check(lib.sp_barrier_create(ctx.h, N.BARRIER_KINDS[kind], nwg, ctypes.byref(p),
                                     ctypes.byref(h)), "sp_barrier_create", ctx.h)
         self.h = h
+        self._out = ctx.zeros(nwg)
 
-    def run_hash(self, lanes: int, rounds: int, seed: int, out: torch.Tensor | None = None):
-        """Hash-exchange workload; returns (checksums uint32 as int64 CPU tensor, stats)."""
-        if out is None:
-            out = torch.zeros(self.nwg, dtype=torch.int32, device="cuda")
+    def run_hash(self, lanes: int, rounds: int, seed: int):
+        """Hash-exchange workload; returns (checksums as uint32 numpy array, stats)."""
         st = N.Stats()
-        check(lib.sp_barrier_run_hash(self.h, lanes, rounds, seed & 0xFFFFFFFF, _ptr(out),
-                                      ctypes.byref(st), _stream()), "sp_barrier_run_hash", self.ctx.h)
-        return _u32(out), st.as_dict()
-
-    def close(self):
-        if self.h:
-            lib.sp_barrier_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        check(lib.sp_barrier_run_hash(self.h, lanes, rounds, seed & 0xFFFFFFFF,
+                                      self.ctx.ptr(self._out), ctypes.byref(st), self.ctx.stream()),
+              "sp_barrier_run_hash", self.ctx.h)
+        return self.ctx.read(self._out, "u32", self.nwg), st.as_dict()
 
 
 def barrier_hash_launches(ctx: Context, nwg: int, lanes: int, rounds: int, seed: int,
                           graph: bool = False):
     """Kernel-boundary comparator of the hash exchange (one launch per round)."""
-    slots = torch.zeros(2 * nwg, dtype=torch.int32, device="cuda")
-    out = torch.zeros(nwg, dtype=torch.int32, device="cuda")
+    slots = ctx.zeros(2 * nwg)
+    out = ctx.zeros(nwg)
     st = N.Stats()
     check(lib.sp_barrier_run_hash_launches(ctx.h, nwg, lanes, rounds, seed & 0xFFFFFFFF,
-                                           int(graph), _ptr(slots), _ptr(out), ctypes.byref(st),
-                                           _stream()), "sp_barrier_run_hash_launches", ctx.h)
-    return _u32(out), st.as_dict()
+                                           int(graph), ctx.ptr(slots), ctx.ptr(out),
+                                           ctypes.byref(st), ctx.stream()),
+          "sp_barrier_run_hash_launches", ctx.h)
+    return ctx.read(out, "u32", nwg), st.as_dict()
 
 
-class Mutex:
+class Mutex(_Handle):
     """`nlocks` mutexes each guarding `words_per_lock` words (Section 5, Mutex)."""
+
+    _destroy = staticmethod(lambda h: lib.sp_mutex_destroy(h))
 
     def __init__(self, ctx: Context, kind: str, nlocks: int, words_per_lock: int, **params):
         self.ctx, self.kind, self.nlocks, self.W = ctx, kind, nlocks, words_per_lock
@@ -145,32 +232,24 @@ class Mutex:
         check(lib.sp_mutex_create(ctx.h, N.MUTEX_KINDS[kind], nlocks, words_per_lock,
                                   ctypes.byref(p), ctypes.byref(h)), "sp_mutex_create", ctx.h)
         self.h = h
+        self._words = ctx.zeros(nlocks * words_per_lock)
 
     def run(self, nwg: int, lanes: int, total: int, max_delay: int, seed: int,
             finish: bool = False):
-        words = torch.zeros(self.nlocks * self.W, dtype=torch.int32, device="cuda")
-        fin = torch.zeros(nwg, dtype=torch.int64, device="cuda") if finish else None
+        """Returns (words[nlocks, W] uint32, stats, finish ticks uint64 or None)."""
+        fin = self.ctx.zeros(nwg, "u64") if finish else None
         st = N.Stats()
         check(lib.sp_mutex_run(self.h, nwg, lanes, total, max_delay, seed & 0xFFFFFFFF,
-                               _ptr(words), _ptr(fin), ctypes.byref(st), _stream()),
-              "sp_mutex_run", self.ctx.h)
-        out = _u32(words).reshape(self.nlocks, self.W)
-        return (out, st.as_dict(), fin.cpu() if fin is not None else None)
-
-    def close(self):
-        if self.h:
-            lib.sp_mutex_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+                               self.ctx.ptr(self._words), self.ctx.ptr(fin), ctypes.byref(st),
+                               self.ctx.stream()), "sp_mutex_run", self.ctx.h)
+        words = self.ctx.read(self._words, "u32", self.nlocks * self.W).reshape(self.nlocks, self.W)
+        return words, st.as_dict(), (self.ctx.read(fin, "u64", nwg) if finish else None)
 
 
-class Semaphore:
+class Semaphore(_Handle):
     """Counting semaphore with initial value K (Section 5, Semaphore)."""
+
+    _destroy = staticmethod(lambda h: lib.sp_sem_destroy(h))
 
     def __init__(self, ctx: Context, kind: str, K: int, **params):
         self.ctx, self.kind, self.K = ctx, kind, K
@@ -179,72 +258,74 @@ class Semaphore:
         check(lib.sp_sem_create(ctx.h, N.SEM_KINDS[kind], K, ctypes.byref(p), ctypes.byref(h)),
               "sp_sem_create", ctx.h)
         self.h = h
+        self._state = ctx.zeros(8)
 
     def run(self, nwg: int, lanes: int, total: int, max_hold: int, seed: int, track: bool = True):
-        chk = torch.zeros(nwg, dtype=torch.int32, device="cuda")
-        state = torch.zeros(8, dtype=torch.int32, device="cuda")
+        chk = self.ctx.zeros(nwg)
         st = N.Stats()
         check(lib.sp_sem_run(self.h, nwg, lanes, total, max_hold, seed & 0xFFFFFFFF, int(track),
-                             _ptr(chk), _ptr(state), ctypes.byref(st), _stream()),
-              "sp_sem_run", self.ctx.h)
-        s = [int(x) for x in _u32(state)]
-        return {"chk": _u32(chk), "maxocc": s[0], "state": (s[1], s[2], s[3], s[4]),
-                "count": s[5], "occ": s[6], "stats": st.as_dict()}
-
-    def close(self):
-        if self.h:
-            lib.sp_sem_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+                             self.ctx.ptr(chk), self.ctx.ptr(self._state), ctypes.byref(st),
+                             self.ctx.stream()), "sp_sem_run", self.ctx.h)
+        s = [int(x) for x in self.ctx.read(self._state, "u32", 8)]
+        return {"chk": self.ctx.read(chk, "u32", nwg), "maxocc": s[0],
+                "state": (s[1], s[2], s[3], s[4]), "count": s[5], "occ": s[6],
+                "stats": st.as_dict()}
 
 
 # ---- microbenchmarks -----------------------------------------------------------------
 
 def bench_atomic(ctx: Context, op: str, nwg: int, lanes: int, T: int, stride: int, mode: str,
-                 n: int, seed: int, perm: torch.Tensor, buf: torch.Tensor | None = None):
-    """Returns (finals uint32 as int64 CPU tensor [T], sum (int), stats)."""
+                 n: int, seed: int, perm, buf=None):
+    """perm: uint32 numpy array or device buffer of T entries.  Returns (finals uint32
+    numpy [T], sum, stats); sum is the uint64 total of returned values (plus the final
+    words for EXCH)."""
+    if isinstance(perm, np.ndarray):
+        perm = ctx.upload(perm.astype(np.uint32))
     words = T * stride // 4
-    if buf is None or buf.numel() < words:
-        buf = torch.empty(words, dtype=torch.int32, device="cuda")
-    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    if buf is None:
+        buf = ctx.zeros(words)
+    out = ctx.zeros(1, "u64")
     st = N.Stats()
     check(lib.sp_bench_atomic(ctx.h, N.OPS[op], nwg, lanes, T, stride, N.ISSUE[mode], n,
-                              seed & 0xFFFFFFFF, _ptr(perm), _ptr(buf), _ptr(out),
-                              ctypes.byref(st), _stream()), "sp_bench_atomic", ctx.h)
-    finals = _u32(buf[: words].view(T, stride // 4)[:, 0].contiguous())
-    return finals, int(out.cpu().item()) & 0xFFFFFFFFFFFFFFFF, st.as_dict()
+                              seed & 0xFFFFFFFF, ctx.ptr(perm), ctx.ptr(buf), ctx.ptr(out),
+                              ctypes.byref(st), ctx.stream()), "sp_bench_atomic", ctx.h)
+    finals = ctx.read(buf, "u32", words).reshape(T, stride // 4)[:, 0].copy()
+    return finals, int(ctx.read(out, "u64", 1)[0]), st.as_dict()
 
 
 def paper12(ctx: Context, test: str, nwg: int, lanes: int = 64, n_ops: int = 1000,
-            stride: int = 256, buf: torch.Tensor | None = None):
+            stride: int = 256, buf=None):
+    """Returns (sum of loaded values, final buffer words uint32 numpy, stats)."""
     words = nwg * stride // 4
-    if buf is None or buf.numel() < words:
-        buf = torch.empty(words, dtype=torch.int32, device="cuda")
-    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    if buf is None:
+        buf = ctx.zeros(words)
+    out = ctx.zeros(1, "u64")
     st = N.Stats()
-    check(lib.sp_bench_paper12(ctx.h, N.PAPER12[test], nwg, lanes, n_ops, stride, _ptr(buf),
-                               _ptr(out), ctypes.byref(st), _stream()), "sp_bench_paper12", ctx.h)
-    return int(out.cpu().item()), buf, st.as_dict()
+    check(lib.sp_bench_paper12(ctx.h, N.PAPER12[test], nwg, lanes, n_ops, stride, ctx.ptr(buf),
+                               ctx.ptr(out), ctypes.byref(st), ctx.stream()), "sp_bench_paper12",
+          ctx.h)
+    return int(ctx.read(out, "u64", 1)[0]), ctx.read(buf, "u32", words), st.as_dict()
 
 
-def stream_read(ctx: Context, buf: torch.Tensor, reps: int = 1, nwg: int = 0):
-    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+def stream_read(ctx: Context, buf, nbytes: int, reps: int = 1, nwg: int = 0):
+    out = ctx.zeros(1, "u64")
     st = N.Stats()
-    nbytes = buf.numel() * buf.element_size()
-    check(lib.sp_bench_stream(ctx.h, _ptr(buf), nbytes, nwg, reps, _ptr(out), ctypes.byref(st),
-                              _stream()), "sp_bench_stream", ctx.h)
-    return int(out.cpu().item()) & 0xFFFFFFFFFFFFFFFF, st.as_dict()
+    check(lib.sp_bench_stream(ctx.h, ctx.ptr(buf), nbytes, nwg, reps, ctx.ptr(out),
+                              ctypes.byref(st), ctx.stream()), "sp_bench_stream", ctx.h)
+    return int(ctx.read(out, "u64", 1)[0]), st.as_dict()
+
+
+def copy(ctx: Context, dst, src, nbytes: int, reps: int = 1):
+    st = N.Stats()
+    check(lib.sp_bench_copy(ctx.h, ctx.ptr(dst), ctx.ptr(src), nbytes, reps, ctypes.byref(st),
+                            ctx.stream()), "sp_bench_copy", ctx.h)
+    return st.as_dict()
 
 
 def pingpong(ctx: Context, rounds: int):
-    words = torch.zeros(512, dtype=torch.int32, device="cuda")
-    out = torch.zeros(4, dtype=torch.int32, device="cuda")
+    words = ctx.zeros(512)
+    out = ctx.zeros(4)
     st = N.Stats()
-    check(lib.sp_bench_pingpong(ctx.h, rounds, _ptr(words), _ptr(out), ctypes.byref(st),
-                                _stream()), "sp_bench_pingpong", ctx.h)
-    return [int(x) for x in _u32(out)], st.as_dict()
+    check(lib.sp_bench_pingpong(ctx.h, rounds, ctx.ptr(words), ctx.ptr(out), ctypes.byref(st),
+                                ctx.stream()), "sp_bench_pingpong", ctx.h)
+    return [int(x) for x in ctx.read(out, "u32", 4)], st.as_dict()

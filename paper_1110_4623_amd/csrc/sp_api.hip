@@ -207,4 +207,42 @@ int sp_probe_xcc(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t* out, void*
   return SP_OK;
 }
 
+int sp_buffer_alloc(sp_ctx* ctx, uint64_t bytes, void** out) {
+  if (!ctx || !out || bytes == 0) return SP_E_INVAL;
+  *out = nullptr;
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  void* p = nullptr;
+  SP_HIP(ctx, hipMalloc(&p, bytes));
+  hipError_t e = hipMemset(p, 0, bytes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    ctx->last_hip = (int)e;
+    hipFree(p);
+    return SP_E_HIP;
+  }
+  *out = p;
+  return SP_OK;
+}
+
+int sp_buffer_free(sp_ctx* ctx, void* p) {
+  if (!ctx || !p) return SP_E_INVAL;
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  SP_HIP(ctx, hipFree(p));
+  return SP_OK;
+}
+
+int sp_buffer_read(sp_ctx* ctx, void* host_dst, const void* dev_src, uint64_t bytes) {
+  if (!ctx || !host_dst || !dev_src) return SP_E_INVAL;
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  SP_HIP(ctx, hipMemcpy(host_dst, dev_src, bytes, hipMemcpyDeviceToHost));
+  return SP_OK;
+}
+
+int sp_buffer_write(sp_ctx* ctx, void* dev_dst, const void* host_src, uint64_t bytes) {
+  if (!ctx || !dev_dst || !host_src) return SP_E_INVAL;
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  SP_HIP(ctx, hipMemcpy(dev_dst, host_src, bytes, hipMemcpyHostToDevice));
+  return SP_OK;
+}
+
 }  // extern "C"

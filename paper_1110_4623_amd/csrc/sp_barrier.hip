@@ -182,13 +182,16 @@ int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t
   SP_CHECK(spi::begin_timed(ctx, s));
   uint64_t timeout = spi::timeout_ticks(ctx, b->p);
   uint32_t N = b->nwg;
-  if (b->kind == SP_BARRIER_GRID_SYNC) {
+  if (b->kind == SP_BARRIER_GRID_SYNC) {  // grid.sync() requires a cooperative launch
     void* args[] = {&N, &rounds, &seed, &b->d_slots, &out_checksums};
     SP_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(N), dim3(lanes), args, 0, s));
   } else {
     sp::BarrierState state = b->st;
     void* args[] = {&state, &rounds, &seed, &b->d_slots, &out_checksums, &ctx->d_err, &timeout};
-    SP_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(N), dim3(lanes), args, 0, s));
+    if (b->p.cooperative)
+      SP_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(N), dim3(lanes), args, 0, s));
+    else
+      SP_HIP(ctx, hipLaunchKernel(kern, dim3(N), dim3(lanes), args, 0, s));
   }
   return spi::end_timed(ctx, s, st, N, lanes, (uint32_t)per_cu, rounds);
 }

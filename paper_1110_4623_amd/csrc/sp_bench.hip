@@ -135,6 +135,13 @@ __global__ void k_stream(const uint4* __restrict__ buf, uint64_t n16, uint32_t r
   block_sum_to(s, out_sum);
 }
 
+// Streaming copy: 16-byte loads and stores, grid-stride.
+__global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n16) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 // Token passing between workgroup 0 and workgroup 1 through two words 1 KiB apart.
 __global__ SP_FULL_OCCUPANCY void k_pingpong(uint32_t rounds, uint32_t* words, uint32_t* out, uint32_t* err,
                            uint64_t timeout) {
@@ -257,6 +264,19 @@ int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, 
   return spi::end_timed(ctx, s, st, nwg, 256, 0, bytes * reps);
 }
 
+int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint32_t reps,
+                  sp_stats* st, void* stream) {
+  if (!ctx || !dst || !src || bytes == 0 || bytes % 16 || reps == 0) return SP_E_INVAL;
+  hipStream_t s = spi::as_stream(stream);
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  const uint32_t nwg = ctx->cu_count * 8;
+  SP_CHECK(spi::begin_timed(ctx, s));
+  for (uint32_t r = 0; r < reps; ++r)
+    hipLaunchKernelGGL(k_copy, dim3(nwg), dim3(256), 0, s, (uint4*)dst, (const uint4*)src,
+                       bytes / 16);
+  return spi::end_timed(ctx, s, st, nwg, 256, 0, 2 * bytes * reps);
+}
+
 int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* out,
                       sp_stats* st, void* stream) {
   if (!ctx || !words || !out || rounds == 0) return SP_E_INVAL;
@@ -268,9 +288,9 @@ int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* o
   sp_params_default(&q);
   uint64_t timeout = spi::timeout_ticks(ctx, q);
   SP_CHECK(spi::begin_timed(ctx, s));
-  // Both workgroups must run at once; a cooperative launch guarantees it.
+  // Both workgroups must run at once: two one-wave workgroups always fit.
   void* args[] = {&rounds, &words, &out, &ctx->d_err, &timeout};
-  SP_HIP(ctx, hipLaunchCooperativeKernel((const void*)k_pingpong, dim3(2), dim3(64), args, 0, s));
+  SP_HIP(ctx, hipLaunchKernel((const void*)k_pingpong, dim3(2), dim3(64), args, 0, s));
   return spi::end_timed(ctx, s, st, 2, 64, 0, 2ull * rounds);
 }
 

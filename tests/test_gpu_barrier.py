@@ -22,7 +22,7 @@ def _run(ctx, kind, nwg, lanes, rounds, seed, **params):
         chk, st = bar.run_hash(lanes=lanes, rounds=rounds, seed=seed)
     finally:
         bar.close()
-    return chk.numpy().astype(np.uint32), st
+    return chk, st
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -72,12 +72,18 @@ def test_xcd_parameters(ctx, params):
     assert (chk == oracle.barrier_closed(7, 2048, 500)).all()
 
 
+@pytest.mark.parametrize("kind", ["central", "xcd"])
+def test_cooperative_launch(ctx, kind):
+    chk, _ = _run(ctx, kind, 2048, 256, 300, 5, cooperative=1)
+    assert (chk == oracle.barrier_closed(5, 2048, 300)).all()
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_kernel_boundary_comparator(ctx, graph):
     import paper_1110_4623_amd as sp
     announce("barrier launches", f"graph={graph}")
     chk, st = sp.barrier_hash_launches(ctx, 64, 64, 200, 42, graph=graph)
-    assert (chk.numpy().astype(np.uint32) == oracle.barrier_closed(42, 64, 200)).all()
+    assert (chk == oracle.barrier_closed(42, 64, 200)).all()
 
 
 def test_not_resident_is_refused(ctx):

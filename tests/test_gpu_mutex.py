@@ -22,7 +22,7 @@ def _run(ctx, kind, nwg, lanes, total, L, W, delay, seed, **params):
                                finish=True)
     finally:
         m.close()
-    return words.numpy().astype(np.uint32), st, fin
+    return words, st, fin
 
 
 @pytest.mark.parametrize("kind", KINDS)
