@@ -95,6 +95,10 @@ __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_mem
 __device__ __forceinline__ uint32_t xcc_id() {
   return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xF;  // HW_REG_XCC_ID[3:0]
 }
+// Identity of the CU within its XCD: HW_REG_HW_ID bits [15:8] (CU, SH and SE ids).
+__device__ __forceinline__ uint32_t cu_in_xcc() {
+  return (__builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 4) >> 8) & 0xFF;
+}
 
 // Busy-wait `cycles` shader clocks (non-critical delays and critical-section holds).
 __device__ __forceinline__ void spin_cycles(uint32_t cycles) {

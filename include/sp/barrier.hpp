@@ -34,7 +34,12 @@ struct BarrierState {
   uint32_t* xarrive;    // xcd: per-XCD arrival stamps (groups lines)
   uint32_t* lrelease;   // xcd: per-workgroup release flags (nwg lines), XCD-major
   uint32_t* larrive;    // xcd: packed arrival flags, XCD-major blocks of xblock words
+  uint32_t* cu_count;   // xcd: workgroups registered per CU key (groups * 256 words)
+  uint32_t* cu_members; // xcd: member ids per CU key (groups * 256 * kCuSlots words)
 };
+
+// Workgroups one CU can hold at most (32 wavefront slots).
+constexpr uint32_t kCuSlots = 32;
 
 namespace detail {
 
@@ -141,53 +146,105 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
 }
 
 // Per-XCD barrier.  Workgroup w runs on XCD w mod X (X = s.groups; checked in round 0)
-// and is member k = w / X of its XCD; member 0 is the XCD's master.
+// and is member k = w / X of its XCD; member 0 is the XCD's master.  In round 0 every
+// workgroup also registers under the id of its CU, and the first one registered on each
+// CU becomes that CU's leader.
 //   1. Each member waits for its own stores to complete (they are then in the XCD's L2)
 //      and stores its arrival stamp into its XCD's packed block of arrival flags; the
 //      master's lanes scan the block.
 //   2. The master writes back the XCD's dirty L2 lines once for all its members (agent
 //      release), publishes the XCD's stamp, and polls the other XCDs' stamps
 //      (all-to-all between at most eight masters).
-//   3. The master acquires (agent scope) and its lanes store the members' release
-//      flags, one line each; each released member acquires as well.
-// Only the masters issue the L2 writeback; writebacks serialize at each XCD's L2
-// controller, so issuing one per workgroup per round would dominate the round.  The
-// acquire cannot be shared the same way: on gfx950 the only cache invalidation that
-// reaches a CU's L1 is the agent-scope one (a workgroup-scope invalidate leaves stale
-// L1 lines in place), so every workgroup invalidates for its own CU.
+//   3. Each CU leader polls the eight XCD stamps; once all are published it acquires
+//      (agent scope) and releases the other workgroups of its CU.  Every flag is its own
+//      line.
+// Writebacks and invalidations both serialize at each XCD's L2 controller.  The
+// writeback is shared by the whole XCD.  The invalidation has to reach each CU's L1, and
+// on gfx950 only the agent-scope invalidate does (a workgroup-scope one leaves stale L1
+// lines), so it is shared by the workgroups of one CU: all of them are waiting when
+// their leader invalidates, so nothing stale can re-enter the L1 before they read.
 // All flags are accessed with agent-scope atomics.
-__device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, const Ctl& ctl) {
+struct XcdLocal {
+  uint32_t key;    // CU key: XCD * 256 + CU id
+  uint32_t slot;   // registration order on the CU (0 = CU leader)
+  uint32_t ncu;    // workgroups on this CU
+  uint32_t cu_list[kCuSlots];  // CU leader only: the CU's workgroups
+};
+
+__device__ __forceinline__ void release_list(const BarrierState& s, const uint32_t* list,
+                                             uint32_t n, uint32_t stamp, uint32_t* rel) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t w = list[i];
+    if (w != blockIdx.x) st_relaxed(rel + (size_t)(w / s.groups) * s.stride, stamp);
+  }
+}
+
+__device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, const Ctl& ctl,
+                                         const XcdLocal& L) {
   __shared__ uint32_t s_ok;
   const uint32_t X = s.groups;
   const uint32_t x = blockIdx.x % X, k = blockIdx.x / X;
   const uint32_t members = (s.nwg - x + X - 1) / X;
   uint32_t* block = s.larrive + (size_t)x * s.xblock;
   uint32_t* rel = s.lrelease + (size_t)x * s.xblock * s.stride;  // member i: rel + i*stride
+  Wait w(ctl, s.poll_sleep);
+  int ok = 1;
   __syncthreads();
   if (k == 0) {
-    Wait w(ctl, s.poll_sleep);
-    int ok = scan_flags(block, 1, members, 0, stamp, w);
+    // XCD master: gather the XCD's arrivals, write the XCD's L2 back once, publish.
+    ok = scan_flags(block, 1, members, 0, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
-    if (threadIdx.x < X) {
-      if (is_leader()) st_release(s.xarrive + (size_t)x * s.stride, stamp);
-      // all-to-all between the XCD masters: lane i waits for XCD i
-      ok = poll_until(s.xarrive + (size_t)threadIdx.x * s.stride, stamp, w);
-    }
+    if (is_leader()) st_release(s.xarrive + (size_t)x * s.stride, stamp);
+  } else if (is_leader()) {
+    st_relaxed(block + k, stamp);
+  }
+  if (L.slot == 0) {
+    // CU leader: once all XCDs have published, invalidate for the CU and release it.
+    if (threadIdx.x < X) ok = poll_until(s.xarrive + (size_t)threadIdx.x * s.stride, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
     if (is_leader()) fence_acquire();
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < members; i += blockDim.x)
-      if (i != 0) st_relaxed(rel + (size_t)i * s.stride, stamp);
+    release_list(s, L.cu_list, L.ncu, stamp, rel);
     return true;
   }
   if (is_leader()) {
-    Wait w(ctl, s.poll_sleep);
-    st_relaxed(block + k, stamp);
-    const bool ok = poll_until(rel + (size_t)k * s.stride, stamp, w);
-    fence_acquire();
+    ok = poll_until(rel + (size_t)k * s.stride, stamp, w);
     s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok;
+}
+
+// Round 0 of the per-XCD barrier: check the XCD placement, register per CU, run the
+// counter tree with per-workgroup fences, then load the lists the later rounds use.
+// Returns (through *use_xcd) whether every workgroup was placed as expected.
+__device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl, XcdLocal& L,
+                                          uint32_t* use_xcd) {
+  __shared__ uint32_t s_ok;
+  const uint32_t X = s.groups;
+  __syncthreads();  // every wavefront's stores have completed (barrier_wait's entry wait)
+  if (is_leader()) {
+    const uint32_t xcc = xcc_id();
+    if (xcc != blockIdx.x % X) add_relaxed(s.mismatch, 1);
+    L.key = (xcc % X) * 256 + cu_in_xcc();
+    L.slot = add_relaxed(s.cu_count + L.key, 1);
+    if (L.slot < kCuSlots)
+      st_relaxed(s.cu_members + (size_t)L.key * kCuSlots + L.slot, blockIdx.x);
+    else
+      add_relaxed(s.mismatch, 1);
+    const bool ok = counter_arrive_wait<SP_BARRIER_TREE>(s, 1, ctl);
+    fence_acquire();
+    *use_xcd = ld_relaxed(s.mismatch) == 0;
+    L.ncu = ld_relaxed(s.cu_count + L.key);
+    s_ok = ok;
+  }
+  __syncthreads();
+  if (*use_xcd) {
+    if (L.slot == 0)
+      for (uint32_t i = threadIdx.x; i < L.ncu && i < kCuSlots; i += blockDim.x)
+        L.cu_list[i] = ld_relaxed(s.cu_members + (size_t)L.key * kCuSlots + i);
   }
   __syncthreads();
   return s_ok;
@@ -204,23 +261,12 @@ __device__ bool barrier_wait(const BarrierState& s, uint32_t round, const Ctl& c
   if constexpr (KIND == SP_BARRIER_FLAG) {
     return detail::flag_wait(s, stamp, ctl);
   } else if constexpr (KIND == SP_BARRIER_XCD) {
-    // Round 0 runs the tree barrier with per-workgroup fences and, on the way, checks
-    // that every workgroup sits on XCD (id mod X); later rounds use the per-XCD
-    // protocol only if no workgroup reported a mismatch.
-    __shared__ uint32_t s_local;
-    if (round == 0) {
-      if (is_leader() && xcc_id() != blockIdx.x % s.groups) add_relaxed(s.mismatch, 1);
-      __syncthreads();
-      if (is_leader()) {
-        const bool ok = detail::counter_arrive_wait<SP_BARRIER_TREE>(s, stamp, ctl);
-        fence_acquire();
-        s_local = ld_relaxed(s.mismatch) == 0;
-        s_ok = ok;
-      }
-      __syncthreads();
-      return s_ok;
-    }
-    if (s_local) return detail::xcd_wait(s, stamp, ctl);
+    // Round 0 sets up (and checks placement); later rounds use the per-XCD protocol if
+    // every workgroup was placed as expected, the counter tree otherwise.
+    __shared__ detail::XcdLocal s_local;
+    __shared__ uint32_t s_use;
+    if (round == 0) return detail::xcd_setup(s, ctl, s_local, &s_use);
+    if (s_use) return detail::xcd_wait(s, stamp, ctl, s_local);
     __syncthreads();
     if (is_leader()) {
       const bool ok = detail::counter_arrive_wait<SP_BARRIER_TREE>(s, stamp, ctl);

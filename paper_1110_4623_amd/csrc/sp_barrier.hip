@@ -118,7 +118,10 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   const uint64_t flag_lines = ((uint64_t)nwg * fs + sw - 1) / sw;
   const uint64_t local_lines = ((uint64_t)G * xblock + sw - 1) / sw;
   const uint64_t lrel_lines = (uint64_t)G * xblock;
-  const uint64_t lines = 5 + 3ull * G + 2 * flag_lines + local_lines + lrel_lines;
+  // per-CU registration (per-XCD barrier): counts and member ids per CU key
+  const uint64_t cu_words = (uint64_t)G * 256 * (1 + sp::kCuSlots);
+  const uint64_t cu_lines = (cu_words + sw - 1) / sw;
+  const uint64_t lines = 5 + 3ull * G + 2 * flag_lines + local_lines + lrel_lines + cu_lines;
   b->state_words = lines * sw;
   hipError_t e = hipMalloc(&b->d_state, b->state_words * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&b->d_slots, 2ull * nwg * sizeof(uint32_t));
@@ -151,6 +154,8 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.release = s.arrive + flag_lines * sw;
   s.larrive = s.release + flag_lines * sw;
   s.lrelease = s.larrive + local_lines * sw;
+  s.cu_count = s.lrelease + lrel_lines * sw;           // G * 256 words
+  s.cu_members = s.cu_count + (uint64_t)G * 256;        // G * 256 * kCuSlots words
   *out = b;
   return SP_OK;
 }

@@ -25,3 +25,11 @@ def ctx():
 def announce(*parts):
     """Print what a GPU step is about to run (flushed before the launch)."""
     print("[gpu-step]", *parts, flush=True)
+
+
+def pytest_sessionstart(session):
+    """Build the HIP library once if it is not there (tests load what is built)."""
+    lib = os.path.join(ROOT, "paper_1110_4623_amd", "libsp.so")
+    if not os.path.exists(lib):
+        from paper_1110_4623_amd import build as b
+        b.build()
