@@ -54,13 +54,13 @@ def measured_traffic(kernel_sources_dir: str) -> float | None:
         return None
 
 
-def cpu_baseline(budget_s: float = 12.0) -> dict:
+def cpu_baseline(budget_s: float = 20.0) -> dict:
     """The threaded CPU oracle (one std::thread per workgroup) on this host: the
-    hierarchical barrier with 2048 agents on the same hash exchange, for a bounded
-    number of rounds."""
+    hierarchical barrier with 2048 agents on the same hash exchange.  It runs all the
+    rounds of the workload when they fit the time budget, else the number that does."""
     import oracle
     oracle.lib()
-    probe_rounds = 8
+    probe_rounds = 256
     _, rc, secs = oracle.barrier_threaded("xcd", 42, NWG, probe_rounds, groups=8)
     rounds = max(probe_rounds, min(ROUNDS, int(budget_s / max(secs, 1e-6) * probe_rounds)))
     _, rc2, secs2 = oracle.barrier_threaded("xcd", 42, NWG, rounds, groups=8)
