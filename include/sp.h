@@ -283,6 +283,74 @@ int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint3
 int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* out,
                       sp_stats* st, void* stream);
 
+/* ---- persistent serving queue -------------------------------------------------------
+ * The paper motivates inter-workgroup primitives with work queues that persistent
+ * workgroups drain (Sections 1-2) and leaves the tuning of such designs to future work
+ * (Section 7).  Workload: requests r = 0 .. n-1 arrive at host times t_arr_s[r] seconds
+ * after the start (non-decreasing).  Request r computes the hash chain h_0 = seed ^ r,
+ * h_{i+1} = splitmix32(h_i), out[r] = h_{L[r]}, and while it runs holds
+ * ceil(nbytes[r] / unit_bytes) units of a workspace budget of budget_units units.
+ *
+ * sp_serve_run: one persistent kernel of nwg workgroups (all co-resident) drains a ring
+ * of request descriptors in pinned host memory.  The host writes a descriptor when the
+ * request arrives and publishes the ring's tail; a workgroup claims the next request with
+ * one fetch-and-add, waits for its arrival, is admitted by a weighted fetch-and-add
+ * semaphore over the budget (FIFO; include/sp/semaphore.hpp), computes the chain in its
+ * leader lane, returns its units and stores a completion flag into pinned host memory.
+ * sp_serve_run_launch_per_request: the comparator.  For each request (batch == 1) the
+ * host launches one single-workgroup kernel at its arrival time, round robin over
+ * `streams` streams, after admitting it against the same budget on the host; with
+ * batch > 1 one launch covers every request that has arrived since the previous launch
+ * (at most batch of them, one workgroup each).
+ *
+ * Both: latency[r] = host time at which the host saw request r's completion flag minus
+ * its arrival time; the same host thread observes completions in both modes.  Inputs
+ * L, nbytes, t_arr_s: host, n entries.  out: host, n uint32.  lat_us: host, n doubles,
+ * or NULL.  The call allocates its ring, flags and device buffers, runs the whole stream
+ * and returns when every request completed.  Errors: SP_E_INVAL (n == 0, a request
+ * needing more units than the budget, t_arr_s decreasing, bad sizes),
+ * SP_E_NORESIDENT (nwg not co-resident), SP_E_TIMEOUT (watchdog or host deadline),
+ * SP_E_HIP.                                                                              */
+typedef struct sp_serve_cfg {
+  uint32_t nwg;          /* sp_serve_run: persistent workgroups                            */
+  uint32_t lanes;        /* threads per workgroup, multiple of 64 (the leader lane works)  */
+  uint32_t ring_slots;   /* descriptor ring, power of two in [64, 2^24] (0 = 65536)       */
+  uint32_t budget_units; /* K: workspace units that may be held at once, in [1, 2^30)      */
+  uint64_t unit_bytes;   /* bytes per budget unit (0 = 65536)                              */
+  uint32_t seed;
+  uint32_t poll_sleep;   /* s_sleep units between polls of the workgroup next in line     */
+  uint32_t far_sleep;    /* cap on the s_sleep units of workgroups further back (0 = 64)   */
+  uint32_t timeout_ms;   /* device watchdog and host deadline beyond the last arrival      */
+                         /* (0 = 20000)                                                    */
+  uint32_t streams;      /* launch comparator: streams used round robin, 1..4 (0 = 1)      */
+  uint32_t batch;        /* launch comparator: requests per launch at most (0 = 1)         */
+  uint32_t track;        /* 1: also track the maximum units in use (three more atomics)    */
+  uint32_t reserved[5];
+} sp_serve_cfg;
+
+typedef struct sp_serve_result {
+  double wall_s;             /* first arrival to last observed completion                 */
+  double p50_us, p99_us;     /* latency percentiles (nearest rank)                        */
+  double mean_us, max_us;
+  double req_per_s;          /* n / wall_s                                                */
+  double publish_lag_max_us; /* worst delay of a publish or launch behind its arrival     */
+  uint64_t completed;
+  uint64_t launches;         /* kernel launches (1 for the persistent queue)              */
+  uint32_t max_units_in_use; /* with track: the maximum seen (<= budget_units)            */
+  uint32_t device_error;
+  uint64_t units_issued;     /* final weighted-semaphore counters (persistent queue):     */
+  uint64_t units_released;   /* both equal the sum of every request's units               */
+  uint64_t reserved[2];
+} sp_serve_result;
+
+int sp_serve_run(sp_ctx* ctx, const sp_serve_cfg* cfg, uint32_t n, const uint32_t* L,
+                 const uint64_t* nbytes, const double* t_arr_s, uint32_t* out, double* lat_us,
+                 sp_serve_result* res);
+int sp_serve_run_launch_per_request(sp_ctx* ctx, const sp_serve_cfg* cfg, uint32_t n,
+                                    const uint32_t* L, const uint64_t* nbytes,
+                                    const double* t_arr_s, uint32_t* out, double* lat_us,
+                                    sp_serve_result* res);
+
 #ifdef __cplusplus
 }
 #endif

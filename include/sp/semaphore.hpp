@@ -83,4 +83,38 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl) {
   return s_ok;
 }
 
+// ---- weighted fetch-and-add semaphore --------------------------------------------------
+// Algorithm 5 admits one unit per ticket.  A request that needs u units of a budget of K
+// draws u consecutive tickets with one fetch-and-add, [t, t + u), and is admitted once the
+// units ever returned plus K cover its last ticket: released + K >= t + u.  Returned units
+// only grow, so admitted requests hold at most K units at any time whatever order the
+// tickets were drawn in (every admitted range lies below the largest admitted end T, and
+// released >= T - K held when that request was admitted).  Admission is FIFO in ticket
+// order, and a request with u <= K always gets in once the ranges below it are returned.
+// Waiting costs one atomic plus polling loads; posting one atomic.  The budget guards
+// capacity, not data, so FENCE = false skips the acquire/release fences.
+struct WSemState {
+  uint32_t K;
+  uint32_t poll_sleep;
+  uint32_t* issued;    // tickets drawn so far (units)
+  uint32_t* released;  // units returned so far
+};
+
+// Leader-only (no workgroup barrier): returns false when the watchdog fired.
+template <bool FENCE>
+__device__ __forceinline__ bool wsem_wait_leader(const WSemState& s, uint32_t u, const Ctl& ctl) {
+  const uint32_t end = add_relaxed(s.issued, u) + u;
+  Wait w(ctl, s.poll_sleep);
+  while (!reached(ld_relaxed(s.released) + s.K, end))
+    if (!w.tick()) return false;
+  if constexpr (FENCE) fence_acquire();
+  return true;
+}
+
+template <bool FENCE>
+__device__ __forceinline__ void wsem_post_leader(const WSemState& s, uint32_t u) {
+  if constexpr (FENCE) fence_release();
+  add_relaxed(s.released, u);
+}
+
 }  // namespace sp

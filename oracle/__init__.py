@@ -77,6 +77,7 @@ def lib():
             "or_mutex_threaded": (i32, [i32, u32, u32, u64, u32, u32, u32, u32, p32, pd]),
             "or_sem_threaded": (i32, [i32, u32, u32, u32, u64, u32, u32, p32, p32, p32, pd]),
             "or_bench_threaded": (i32, [i32, u32, u32, u64, u32, p32, u32, p32, p64, pd]),
+            "or_serve_threaded": (i32, [u32, p32, p32, u32, u32, u32, p32, p32, p64, pd]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -229,3 +230,18 @@ def bench_threaded(op: str, seed: int, U: int, n: int, perm: np.ndarray, threads
     if rc != 0:
         raise ValueError(f"or_bench_threaded({op}) failed: {rc}")
     return finals, s.value, secs.value
+
+
+def serve_threaded(seed: int, lengths: np.ndarray, units: np.ndarray, K: int, agents: int):
+    """Threaded serving queue; returns dict(out, maxuse, issued, released, rc, seconds)."""
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
+    units = np.ascontiguousarray(units, dtype=np.uint32)
+    out = np.zeros(len(lengths), dtype=np.uint32)
+    maxuse = np.zeros(1, dtype=np.uint32)
+    counters = np.zeros(2, dtype=np.uint64)
+    secs = ctypes.c_double(0)
+    rc = lib().or_serve_threaded(seed & 0xFFFFFFFF, _p32(lengths), _p32(units), len(lengths), K,
+                                 agents, _p32(out), _p32(maxuse), _p64(counters),
+                                 ctypes.byref(secs))
+    return {"out": out, "maxuse": int(maxuse[0]), "issued": int(counters[0]),
+            "released": int(counters[1]), "rc": rc, "seconds": secs.value}

@@ -328,6 +328,72 @@ class FASemModel:
         return None
 
 
+class WeightedSemModel:
+    """Fetch-and-add semaphore with weighted requests, the admission rule of the serving
+    queue (Algorithm 5 with u tickets drawn at once).  issued and released start at 0.
+    wait(u): end = fetch-and-add(issued, u) + u; poll until released + K >= end.
+    post(u): fetch-and-add(released, u).
+    Agent a asks for weights[a] units on each of its `ops` requests.
+    mutant 'ignore_weight': admit once released + K >= end - u (the first ticket only).
+    mutant 'strict': admit once released + K > end.
+    mutant 'post_one': post returns one unit instead of u."""
+
+    W_TICKET, W_POLL, CS_IN, CS_OUT, POST, DONE = range(6)
+
+    def __init__(self, K: int, weights: tuple, ops: int = 2, mutant: str | None = None):
+        self.K, self.weights, self.n, self.ops, self.mutant = K, tuple(weights), len(weights), ops, mutant
+
+    def init(self):
+        return (0, 0, 0), tuple((self.W_TICKET, 0, 0) for _ in range(self.n))
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    def _admit(self, released, end, u):
+        if self.mutant == "ignore_weight":
+            return released + self.K >= end - u
+        if self.mutant == "strict":
+            return released + self.K > end
+        return released + self.K >= end
+
+    def step(self, a, sh, lo):
+        issued, released, inside = sh
+        pc, j, end = lo
+        u = self.weights[a]
+        if pc == self.W_TICKET:
+            return (issued + u, released, inside), (self.W_POLL, j, issued + u)
+        if pc == self.W_POLL:
+            return sh, ((self.CS_IN if self._admit(released, end, u) else self.W_POLL), j, end)
+        if pc == self.CS_IN:
+            return (issued, released, inside + u), (self.CS_OUT, j, end)
+        if pc == self.CS_OUT:
+            return (issued, released, inside - u), (self.POST, j, end)
+        if pc == self.POST:
+            back = 1 if self.mutant == "post_one" else u
+            nxt = self.W_TICKET if j + 1 < self.ops else self.DONE
+            return (issued, released + back, inside), (nxt, j + 1, 0)
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        issued, released, inside = sh
+        if inside > self.K:
+            return f"units in use {inside} > K={self.K}"
+        # FIFO: while a waiter cannot be admitted, nobody with a later ticket is inside
+        for lo in los:
+            if lo[0] == self.W_POLL and not released + self.K >= lo[2]:
+                for lo2 in los:
+                    if lo2[0] in (self.CS_IN, self.CS_OUT) and lo2[2] > lo[2]:
+                        return "a later ticket was admitted before an earlier one"
+        return None
+
+    def final_check(self, sh, los):
+        issued, released, inside = sh
+        total = self.ops * sum(self.weights)
+        if issued != total or released != total or inside != 0:
+            return f"final issued={issued} released={released} inside={inside}"
+        return None
+
+
 # ------------------------------------------------------------------------------------
 # Barriers running the hash-exchange workload: in round r agent b stores the round
 # number into slot[r & 1][b], passes the barrier, then reads slot[r & 1][(b + r) % N],

@@ -541,4 +541,40 @@ int or_bench_threaded(int op, uint32_t seed, uint32_t U, uint64_t n, uint32_t T,
   return 0;
 }
 
+// Threaded serving queue: `agents` threads take requests in order from a shared counter
+// (every request has already arrived), admit each against a budget of K units with the
+// weighted fetch-and-add rule (draw u tickets, wait until units returned + K cover the
+// last one), compute the request's hash chain, return the units.  out[n] = results;
+// *maxuse = most units held at once; counters = {tickets drawn, units returned}.
+// Returns 0, -1 on bad arguments, -2 if the units held ever exceeded K.
+int or_serve_threaded(uint32_t seed, const uint32_t* L, const uint32_t* units, uint32_t n,
+                      uint32_t K, uint32_t agents, uint32_t* out, uint32_t* maxuse,
+                      uint64_t* counters, double* seconds) {
+  if (agents == 0 || K == 0) return -1;
+  for (uint32_t r = 0; r < n; ++r)
+    if (units[r] > K) return -1;
+  Word head{0}, issued{0}, released{0}, inuse{0}, maxu{0};
+  double t = run_agents(agents, [&](uint32_t) {
+    for (;;) {
+      const uint32_t r = head.fetch_add(1, std::memory_order_relaxed);
+      if (r >= n) return;
+      const uint32_t u = units[r];
+      const uint32_t end = issued.fetch_add(u, std::memory_order_acq_rel) + u;
+      while (!((int32_t)(released.load(std::memory_order_acquire) + K - end) >= 0)) relax();
+      const uint32_t now = inuse.fetch_add(u) + u;
+      uint32_t m = maxu.load();
+      while (now > m && !maxu.compare_exchange_weak(m, now)) {
+      }
+      out[r] = or_chain(seed ^ r, L[r]);
+      inuse.fetch_sub(u);
+      released.fetch_add(u, std::memory_order_acq_rel);
+    }
+  });
+  *maxuse = maxu.load();
+  counters[0] = issued.load();
+  counters[1] = released.load();
+  if (seconds) *seconds = t;
+  return *maxuse > K ? -2 : 0;
+}
+
 }  // extern "C"

@@ -8,9 +8,11 @@ the primitives, and an autotuner for their parameters.  The compute path is libs
 """
 
 from .api import (Barrier, Context, DeviceBuffer, Mutex, Semaphore, barrier_hash_launches,
-                  bench_atomic, copy, make_params, paper12, pingpong, stream_read)
+                  bench_atomic, copy, make_params, paper12, pingpong, serve,
+                  serve_launch_per_request, stream_read)
 from ._native import SpError, SpNotResident, SpTimeout
 
 __all__ = ["Barrier", "Context", "DeviceBuffer", "Mutex", "Semaphore", "barrier_hash_launches",
-           "bench_atomic", "copy", "make_params", "paper12", "pingpong", "stream_read", "SpError",
+           "bench_atomic", "copy", "make_params", "paper12", "pingpong", "serve",
+           "serve_launch_per_request", "stream_read", "SpError",
            "SpNotResident", "SpTimeout"]

@@ -106,18 +106,31 @@ class ServeCfg(ctypes.Structure):
         ("unit_bytes", ctypes.c_uint64),
         ("seed", ctypes.c_uint32),
         ("poll_sleep", ctypes.c_uint32),
+        ("far_sleep", ctypes.c_uint32),
         ("timeout_ms", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 7),
+        ("streams", ctypes.c_uint32),
+        ("batch", ctypes.c_uint32),
+        ("track", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 5),
     ]
 
 
 class ServeResult(ctypes.Structure):
     _fields_ = [
         ("wall_s", ctypes.c_double),
+        ("p50_us", ctypes.c_double),
+        ("p99_us", ctypes.c_double),
+        ("mean_us", ctypes.c_double),
+        ("max_us", ctypes.c_double),
+        ("req_per_s", ctypes.c_double),
+        ("publish_lag_max_us", ctypes.c_double),
         ("completed", ctypes.c_uint64),
+        ("launches", ctypes.c_uint64),
         ("max_units_in_use", ctypes.c_uint32),
         ("device_error", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint64 * 4),
+        ("units_issued", ctypes.c_uint64),
+        ("units_released", ctypes.c_uint64),
+        ("reserved", ctypes.c_uint64 * 2),
     ]
 
 
@@ -158,8 +171,8 @@ def _load():
         "sp_bench_stream": (i32, [vp, vp, u64, u32, u32, vp, P(Stats), vp]),
         "sp_bench_pingpong": (i32, [vp, u32, vp, vp, P(Stats), vp]),
         "sp_bench_copy": (i32, [vp, vp, vp, u64, u32, P(Stats), vp]),
-        "sp_serve_run": (i32, [vp, P(ServeCfg), u32, vp, vp, vp, u32, vp, vp, P(ServeResult)]),
-        "sp_serve_run_launch_per_request": (i32, [vp, P(ServeCfg), u32, vp, vp, vp, u32, vp, vp,
+        "sp_serve_run": (i32, [vp, P(ServeCfg), u32, vp, vp, vp, vp, vp, P(ServeResult)]),
+        "sp_serve_run_launch_per_request": (i32, [vp, P(ServeCfg), u32, vp, vp, vp, vp, vp,
                                                   P(ServeResult)]),
     }
     for name, (res, args) in sig.items():

@@ -329,3 +329,54 @@ def pingpong(ctx: Context, rounds: int):
     check(lib.sp_bench_pingpong(ctx.h, rounds, ctx.ptr(words), ctx.ptr(out), ctypes.byref(st),
                                 ctx.stream()), "sp_bench_pingpong", ctx.h)
     return [int(x) for x in ctx.read(out, "u32", 4)], st.as_dict()
+
+
+def _serve_args(ctx: Context, reqs: dict, nwg: int, lanes: int, budget_units: int,
+                unit_bytes: int, seed: int, **cfg):
+    L = np.ascontiguousarray(reqs["L"], dtype=np.uint32)
+    nbytes = np.ascontiguousarray(reqs["nbytes"], dtype=np.uint64)
+    t_arr = np.ascontiguousarray(reqs["t_arr"], dtype=np.float64)
+    n = len(L)
+    if len(nbytes) != n or len(t_arr) != n:
+        raise ValueError("request table columns differ in length")
+    c = N.ServeCfg()
+    c.nwg, c.lanes, c.budget_units, c.unit_bytes, c.seed = nwg, lanes, budget_units, unit_bytes, seed
+    for k, v in cfg.items():
+        if not hasattr(c, k) or k == "reserved":
+            raise TypeError(f"unknown serving option {k}")
+        setattr(c, k, int(v))
+    out = np.zeros(n, dtype=np.uint32)
+    lat = np.zeros(n, dtype=np.float64)
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    return c, n, (vp(L), vp(nbytes), vp(t_arr), vp(out), vp(lat)), out, lat, (L, nbytes, t_arr)
+
+
+def _serve_result(r: N.ServeResult) -> dict:
+    return {k: getattr(r, k) for k, _ in N.ServeResult._fields_ if k != "reserved"}
+
+
+def serve(ctx: Context, reqs: dict, nwg: int = 1024, lanes: int = 64,
+          budget_units: int = 16384, unit_bytes: int = 65536, seed: int = 42, **cfg):
+    """Persistent serving queue (sp_serve_run) over a request table from
+    sp_inputs.request_table.  Returns (out, latency_us, result dict)."""
+    c, n, ptrs, out, lat, keep = _serve_args(ctx, reqs, nwg, lanes, budget_units, unit_bytes,
+                                             seed, **cfg)
+    res = N.ServeResult()
+    check(lib.sp_serve_run(ctx.h, ctypes.byref(c), n, *ptrs, ctypes.byref(res)),
+          "sp_serve_run", ctx.h)
+    del keep
+    return out, lat, _serve_result(res)
+
+
+def serve_launch_per_request(ctx: Context, reqs: dict, lanes: int = 64,
+                             budget_units: int = 16384, unit_bytes: int = 65536, seed: int = 42,
+                             **cfg):
+    """Comparator: one kernel launch per request (batch = 1) or per arrival batch."""
+    c, n, ptrs, out, lat, keep = _serve_args(ctx, reqs, 0, lanes, budget_units, unit_bytes,
+                                             seed, **cfg)
+    res = N.ServeResult()
+    check(lib.sp_serve_run_launch_per_request(ctx.h, ctypes.byref(c), n, *ptrs,
+                                              ctypes.byref(res)),
+          "sp_serve_run_launch_per_request", ctx.h)
+    del keep
+    return out, lat, _serve_result(res)

@@ -57,3 +57,41 @@ def test_bad_arguments_rejected_without_gpu():
     assert lib.sp_sem_create(None, 0, 1, None, ctypes.byref(h)) == _native.SP_E_INVAL
     assert lib.sp_fini(None) == _native.SP_E_INVAL
     assert lib.sp_barrier_run_hash(None, 64, 1, 0, None, None, None) == _native.SP_E_INVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of the C structs have the sizes and field offsets a C compiler
+    gives them from include/sp.h."""
+    import ctypes
+    import subprocess
+    from paper_1110_4623_amd import _native as N
+    structs = {"sp_params": N.Params, "sp_stats": N.Stats, "sp_device_info": N.DeviceInfo,
+               "sp_serve_cfg": N.ServeCfg, "sp_serve_result": N.ServeResult}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "sp.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        src.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            src.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src.append("  return 0;\n}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o",
+                           str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).split("\n")
+               if line)
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_serve_rejects_bad_tables_without_gpu():
+    import ctypes
+    from paper_1110_4623_amd import _native as N
+    c = N.ServeCfg()
+    r = N.ServeResult()
+    assert N.lib.sp_serve_run(None, ctypes.byref(c), 1, None, None, None, None, None,
+                              ctypes.byref(r)) == N.SP_E_INVAL
+    assert N.lib.sp_serve_run_launch_per_request(None, ctypes.byref(c), 1, None, None, None,
+                                                 None, None, ctypes.byref(r)) == N.SP_E_INVAL

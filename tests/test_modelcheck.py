@@ -3,7 +3,8 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 
 import pytest
 
-from oracle.modelcheck import BarrierModel, FASemModel, MutexModel, SpinSemModel, explore
+from oracle.modelcheck import (BarrierModel, FASemModel, MutexModel, SpinSemModel,
+                               WeightedSemModel, explore)
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
@@ -77,3 +78,34 @@ def test_catches_barrier_that_does_not_wait(kind):
 def test_catches_hierarchical_group_released_early():
     r = explore(BarrierModel("xcd", 4, 2, 2, mutant="no_top_wait"))
     assert r.violation and "phase" in r.violation
+
+
+# ---- weighted fetch-and-add semaphore (serving-queue admission) ---------------------
+
+@pytest.mark.parametrize("K,weights,ops", [(1, (1, 1, 1), 2), (2, (1, 2, 2), 2),
+                                           (3, (1, 2, 3), 2), (4, (3, 2, 2), 2),
+                                           (5, (5, 1), 3)])
+def test_weighted_semaphore_correct(K, weights, ops):
+    r = explore(WeightedSemModel(K, weights, ops))
+    assert r.ok, r.violation
+
+
+def test_weighted_semaphore_reduces_to_algorithm5_bound():
+    # unit weights: at most K inside, exactly like the fetch-and-add semaphore
+    r = explore(WeightedSemModel(2, (1, 1, 1), 3))
+    assert r.ok
+
+
+def test_catches_weight_ignored_at_admission():
+    r = explore(WeightedSemModel(3, (2, 2, 1), 2, mutant="ignore_weight"))
+    assert r.violation and "units in use" in r.violation
+
+
+def test_catches_strict_admission_deadlock():
+    r = explore(WeightedSemModel(2, (2, 1), 1, mutant="strict"))
+    assert r.deadlock
+
+
+def test_catches_partial_return():
+    r = explore(WeightedSemModel(3, (2, 2), 2, mutant="post_one"))
+    assert not r.ok

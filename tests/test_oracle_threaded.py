@@ -51,3 +51,26 @@ def test_sem_threaded_invariants(kind, K):
 
 def test_hardware_threads_reported():
     assert oracle.hardware_threads() >= 1
+
+
+@pytest.mark.parametrize("K,agents,lmax", [(16384, 64, 65536), (64, 32, 1024), (1, 8, 16)])
+def test_serve_threaded_matches_closed(K, agents, lmax):
+    """The threaded serving queue reproduces the closed-form chain of every request and
+    never holds more than K units; with K = 1 the admission is a mutex."""
+    import sp_inputs
+    seed = 42
+    reqs = sp_inputs.request_table(3000, 1e5, seed, lmax=lmax)
+    unit = 65536 if K > 1 else 1 << 40
+    units = ((reqs["nbytes"] + np.uint64(unit - 1)) // np.uint64(unit)).astype(np.uint32)
+    if K == 1:
+        units[:] = 1
+    r = oracle.serve_threaded(seed, reqs["L"], units, K, agents)
+    assert r["rc"] == 0
+    assert (r["out"] == oracle.chain_batch(seed, reqs["L"])).all()
+    assert r["issued"] == r["released"] == int(units.sum())
+    assert int(units.max()) <= r["maxuse"] <= K
+
+
+def test_serve_threaded_rejects_oversized_request():
+    r = oracle.serve_threaded(1, np.array([5], np.uint32), np.array([3], np.uint32), 2, 4)
+    assert r["rc"] == -1
