@@ -9,7 +9,11 @@ One step runs the whole path once over the full-size synthetic workloads:
   3. mutex: ticket lock, 2048 workgroups x 256 lanes, one lock guarding 16 words,
      2^20 acquisitions with non-critical delays uniform in [0, 1000] cycles;
   4. semaphore: fetch-and-add semaphore with K = 32, 2048 workgroups, 2^20 wait/post
-     pairs holding uniform [0, 2000] cycles.
+     pairs holding uniform [0, 2000] cycles;
+  5. serving: 2 x 10^5 requests arriving as a Poisson stream at 10^5 req/s (lognormal
+     hash-chain lengths, 1 GiB workspace budget in 64 KiB units), drained by 1024
+     persistent workgroups, then the same stream served with one kernel launch per
+     request over four streams (the comparator); p50/p99 latency of both.
 
 Prints one JSON line.  `value` is microseconds per barrier round (lower is better);
 the other primitives' throughputs ride along in `metrics`.
@@ -34,6 +38,7 @@ os.environ.setdefault("SP_NO_TORCH", "1")
 METRIC = "µs/barrier round, mutex & semaphore ops/s vs #WGs; persistent-queue p99 latency"
 NWG, LANES, ROUNDS = 2048, 256, 10_000
 MUTEX_TOTAL, SEM_TOTAL, SEM_K = 1 << 20, 1 << 20, 32
+SERVE_RATE, SERVE_N, SERVE_NWG = 1e5, 200_000, 1024
 
 
 def measured_traffic(kernel_sources_dir: str) -> float | None:
@@ -95,6 +100,7 @@ def main() -> int:
     import numpy as np
 
     import paper_1110_4623_amd as sp
+    import sp_inputs
 
     ctx = sp.Context(0)
     if args.calibrate:
@@ -111,6 +117,7 @@ def main() -> int:
     sem = sp.Semaphore(ctx, "sleep", SEM_K)
     perm1 = ctx.zeros(1)
     abuf = ctx.zeros(64)
+    reqs = sp_inputs.request_table(SERVE_N, SERVE_RATE, 42)
 
     def step():
         r = {}
@@ -123,6 +130,10 @@ def main() -> int:
         res = sem.run(NWG, LANES, SEM_TOTAL, 2000, 42, track=False)
         r["sem_ms"] = res["stats"]["kernel_ms"]
         r["sem_ok"] = res["state"][3] == SEM_TOTAL and res["state"][0] == 0
+        out_p, _, rp = sp.serve(ctx, reqs, nwg=SERVE_NWG, seed=42)
+        out_l, _, rl = sp.serve_launch_per_request(ctx, reqs, seed=42, streams=4)
+        r["serve"], r["serve_launch"] = rp, rl
+        r["serve_same"] = bool((out_p == out_l).all())
         return r
 
     for _ in range(args.warmup):
@@ -141,6 +152,9 @@ def main() -> int:
     mtx_rate = float(np.mean([MUTEX_TOTAL / (r["mtx_ms"] * 1e-3) for r in results]))
     sem_rate = float(np.mean([SEM_TOTAL / (r["sem_ms"] * 1e-3) for r in results]))
 
+    def med(key, field):
+        return round(float(np.median([r[key][field] for r in results])), 2)
+
     line = {
         "metric": METRIC,
         "value": round(us_round, 4),
@@ -153,10 +167,12 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
-        "data": "synthetic (seeded hash-exchange, lock and semaphore schedules)",
+        "data": "synthetic (seeded hash-exchange, lock and semaphore schedules, Poisson request stream)",
         "config": {"workload": f"{args.barrier} barrier, {NWG} co-resident workgroups x {LANES} "
                                f"lanes x {ROUNDS} rounds (hash exchange); ticket mutex and "
-                               f"K={SEM_K} semaphore at {NWG} workgroups, 2^20 operations each",
+                               f"K={SEM_K} semaphore at {NWG} workgroups, 2^20 operations each; "
+                               f"serving queue, {SERVE_NWG} persistent workgroups, {SERVE_N} "
+                               f"requests at {SERVE_RATE:g} req/s",
                    "nwg": NWG, "lanes": LANES, "rounds": ROUNDS},
         "metrics": {
             "barrier_us_per_round": round(us_round, 4),
@@ -167,6 +183,13 @@ def main() -> int:
             "barrier_checksums_deterministic": bool(deterministic),
             "mutex_counts_exact": all(r["mtx_ok"] for r in results),
             "semaphore_state_exact": all(r["sem_ok"] for r in results),
+            "serve_persistent_p50_us": med("serve", "p50_us"),
+            "serve_persistent_p99_us": med("serve", "p99_us"),
+            "serve_persistent_req_per_s": med("serve", "req_per_s"),
+            "serve_launch_per_request_p50_us": med("serve_launch", "p50_us"),
+            "serve_launch_per_request_p99_us": med("serve_launch", "p99_us"),
+            "serve_launch_per_request_req_per_s": med("serve_launch", "req_per_s"),
+            "serve_results_identical": all(r["serve_same"] for r in results),
         },
         "roofline": {
             "bound": "atomic",

@@ -149,6 +149,7 @@ typedef struct sp_ctx sp_ctx;
 typedef struct sp_barrier sp_barrier;
 typedef struct sp_mutex sp_mutex;
 typedef struct sp_sem sp_sem;
+typedef struct sp_graph sp_graph;
 
 /* ---- context -------------------------------------------------------------------------
  * sp_init: binds to HIP device `device`, reads its properties and probes the XCC count.
@@ -282,6 +283,29 @@ int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint3
  * workgroup 1}.  st->kernel_ms / (2 * rounds) is the one-way latency.                   */
 int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* out,
                       sp_stats* st, void* stream);
+
+/* ---- recorded batches (HIP graphs) ---------------------------------------------------
+ * Section 7 leaves the tuning of these primitives per GPU and contention level to future
+ * work; an autotuner times many short runs, and a fused sequence of persistent kernels is
+ * cheaper to replay from a graph than to launch call by call.
+ * sp_graph_begin: starts recording on `stream` (NULL: a stream owned by the context) and
+ * returns the stream to record on in *capture_stream.  Until sp_graph_end, every
+ * sp_barrier_run_hash, sp_mutex_run, sp_sem_run and sp_bench_* call made with that stream
+ * records its state resets (fill kernels, never memset nodes) and kernels instead of
+ * running them: it returns SP_OK at once, zeroes *st and leaves its outputs unwritten.
+ * Cooperative launches (SP_BARRIER_GRID_SYNC, sp_params.cooperative) and the graph mode
+ * of sp_barrier_run_hash_launches cannot be recorded (SP_E_INVAL).
+ * sp_graph_end: stops recording and instantiates the graph (*out, owned by the caller).
+ * sp_graph_launch: clears the watchdog word, replays the graph `replays` times back to
+ * back on `stream`, times all replays with HIP events, waits, and reports SP_E_TIMEOUT if
+ * any recorded kernel's watchdog expired.  st->kernel_ms covers every replay, st->ops =
+ * replays.  Outputs of the recorded calls hold the last replay's results; the state
+ * objects and buffers they name must outlive the graph.
+ * Errors: SP_E_INVAL, SP_E_HIP (capture or instantiation failed), SP_E_TIMEOUT.          */
+int sp_graph_begin(sp_ctx* ctx, void* stream, void** capture_stream);
+int sp_graph_end(sp_ctx* ctx, void* capture_stream, sp_graph** out);
+int sp_graph_launch(sp_graph* g, uint32_t replays, sp_stats* st, void* stream);
+int sp_graph_destroy(sp_graph* g);
 
 /* ---- persistent serving queue -------------------------------------------------------
  * The paper motivates inter-workgroup primitives with work queues that persistent

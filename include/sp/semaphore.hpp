@@ -103,10 +103,15 @@ struct WSemState {
 // Leader-only (no workgroup barrier): returns false when the watchdog fired.
 template <bool FENCE>
 __device__ __forceinline__ bool wsem_wait_leader(const WSemState& s, uint32_t u, const Ctl& ctl) {
+  // The first load of `released` does not depend on the fetch-and-add, so both are in
+  // flight together; a value older than the ticket is a lower bound and only delays.
   const uint32_t end = add_relaxed(s.issued, u) + u;
+  uint32_t rel = ld_relaxed(s.released);
   Wait w(ctl, s.poll_sleep);
-  while (!reached(ld_relaxed(s.released) + s.K, end))
+  while (!reached(rel + s.K, end)) {
     if (!w.tick()) return false;
+    rel = ld_relaxed(s.released);
+  }
   if constexpr (FENCE) fence_acquire();
   return true;
 }

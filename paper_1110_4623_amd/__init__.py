@@ -7,12 +7,12 @@ the primitives, and an autotuner for their parameters.  The compute path is libs
 (hand-written HIP for gfx950, C ABI in include/sp.h); this package is its binding.
 """
 
-from .api import (Barrier, Context, DeviceBuffer, Mutex, Semaphore, barrier_hash_launches,
+from .api import (Barrier, Context, DeviceBuffer, Graph, Mutex, Semaphore, barrier_hash_launches,
                   bench_atomic, copy, make_params, paper12, pingpong, serve,
                   serve_launch_per_request, stream_read)
 from ._native import SpError, SpNotResident, SpTimeout
 
-__all__ = ["Barrier", "Context", "DeviceBuffer", "Mutex", "Semaphore", "barrier_hash_launches",
+__all__ = ["Barrier", "Context", "DeviceBuffer", "Graph", "Mutex", "Semaphore", "barrier_hash_launches",
            "bench_atomic", "copy", "make_params", "paper12", "pingpong", "serve",
            "serve_launch_per_request", "stream_read", "SpError",
            "SpNotResident", "SpTimeout"]

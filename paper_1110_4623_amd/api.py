@@ -84,6 +84,8 @@ class Context:
 
     # ---- memory and streams --------------------------------------------------------
     def stream(self) -> ctypes.c_void_p:
+        if getattr(self, "_record_stream", None) is not None:
+            return self._record_stream
         if self.torch is not None:
             return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
         return ctypes.c_void_p(0)
@@ -198,13 +200,22 @@ class Barrier(_Handle):
         self.h = h
         self._out = ctx.zeros(nwg)
 
-    def run_hash(self, lanes: int, rounds: int, seed: int):
-        """Hash-exchange workload; returns (checksums as uint32 numpy array, stats)."""
+    def launch(self, lanes: int, rounds: int, seed: int) -> dict:
+        """Runs (or, inside a Graph recording, records) the hash exchange; the checksums
+        stay on the device until `checksums()`.  Returns the stats."""
         st = N.Stats()
         check(lib.sp_barrier_run_hash(self.h, lanes, rounds, seed & 0xFFFFFFFF,
                                       self.ctx.ptr(self._out), ctypes.byref(st), self.ctx.stream()),
               "sp_barrier_run_hash", self.ctx.h)
-        return self.ctx.read(self._out, "u32", self.nwg), st.as_dict()
+        return st.as_dict()
+
+    def checksums(self) -> np.ndarray:
+        return self.ctx.read(self._out, "u32", self.nwg)
+
+    def run_hash(self, lanes: int, rounds: int, seed: int):
+        """Hash-exchange workload; returns (checksums as uint32 numpy array, stats)."""
+        st = self.launch(lanes, rounds, seed)
+        return self.checksums(), st
 
 
 def barrier_hash_launches(ctx: Context, nwg: int, lanes: int, rounds: int, seed: int,
@@ -234,16 +245,25 @@ class Mutex(_Handle):
         self.h = h
         self._words = ctx.zeros(nlocks * words_per_lock)
 
+    def launch(self, nwg: int, lanes: int, total: int, max_delay: int, seed: int,
+               finish=None) -> dict:
+        """Runs (or records) the contention workload; results stay on the device until
+        `words()`.  finish: optional device buffer of nwg uint64.  Returns the stats."""
+        st = N.Stats()
+        check(lib.sp_mutex_run(self.h, nwg, lanes, total, max_delay, seed & 0xFFFFFFFF,
+                               self.ctx.ptr(self._words), self.ctx.ptr(finish), ctypes.byref(st),
+                               self.ctx.stream()), "sp_mutex_run", self.ctx.h)
+        return st.as_dict()
+
+    def words(self) -> np.ndarray:
+        return self.ctx.read(self._words, "u32", self.nlocks * self.W).reshape(self.nlocks, self.W)
+
     def run(self, nwg: int, lanes: int, total: int, max_delay: int, seed: int,
             finish: bool = False):
         """Returns (words[nlocks, W] uint32, stats, finish ticks uint64 or None)."""
         fin = self.ctx.zeros(nwg, "u64") if finish else None
-        st = N.Stats()
-        check(lib.sp_mutex_run(self.h, nwg, lanes, total, max_delay, seed & 0xFFFFFFFF,
-                               self.ctx.ptr(self._words), self.ctx.ptr(fin), ctypes.byref(st),
-                               self.ctx.stream()), "sp_mutex_run", self.ctx.h)
-        words = self.ctx.read(self._words, "u32", self.nlocks * self.W).reshape(self.nlocks, self.W)
-        return words, st.as_dict(), (self.ctx.read(fin, "u64", nwg) if finish else None)
+        st = self.launch(nwg, lanes, total, max_delay, seed, fin)
+        return self.words(), st, (self.ctx.read(fin, "u64", nwg) if finish else None)
 
 
 class Semaphore(_Handle):
@@ -260,16 +280,74 @@ class Semaphore(_Handle):
         self.h = h
         self._state = ctx.zeros(8)
 
-    def run(self, nwg: int, lanes: int, total: int, max_hold: int, seed: int, track: bool = True):
-        chk = self.ctx.zeros(nwg)
+    def launch(self, nwg: int, lanes: int, total: int, max_hold: int, seed: int,
+               track: bool = True) -> dict:
+        """Runs (or records) the wait/post workload; results stay on the device until
+        `result()`.  Returns the stats."""
+        if getattr(self, "_chk_n", None) != nwg:
+            self._chk, self._chk_n = self.ctx.zeros(nwg), nwg
         st = N.Stats()
         check(lib.sp_sem_run(self.h, nwg, lanes, total, max_hold, seed & 0xFFFFFFFF, int(track),
-                             self.ctx.ptr(chk), self.ctx.ptr(self._state), ctypes.byref(st),
+                             self.ctx.ptr(self._chk), self.ctx.ptr(self._state), ctypes.byref(st),
                              self.ctx.stream()), "sp_sem_run", self.ctx.h)
+        return st.as_dict()
+
+    def result(self) -> dict:
         s = [int(x) for x in self.ctx.read(self._state, "u32", 8)]
-        return {"chk": self.ctx.read(chk, "u32", nwg), "maxocc": s[0],
-                "state": (s[1], s[2], s[3], s[4]), "count": s[5], "occ": s[6],
-                "stats": st.as_dict()}
+        return {"chk": self.ctx.read(self._chk, "u32", self._chk_n), "maxocc": s[0],
+                "state": (s[1], s[2], s[3], s[4]), "count": s[5], "occ": s[6]}
+
+    def run(self, nwg: int, lanes: int, total: int, max_hold: int, seed: int, track: bool = True):
+        st = self.launch(nwg, lanes, total, max_hold, seed, track)
+        return dict(self.result(), stats=st)
+
+
+class Graph:
+    """Records the primitive runs made inside a `with` block into one HIP graph
+    (sp_graph_begin/end) and replays them with `launch`.  Inside the block, use the
+    wrappers' `launch` methods (results stay on the device); read results after a
+    replay with `checksums()`, `words()` or `result()`."""
+
+    def __init__(self, ctx: Context):
+        self.ctx, self.h = ctx, None
+
+    def __enter__(self):
+        cs = ctypes.c_void_p()
+        # record on the context's own stream, so that nothing else (torch's work on its
+        # current stream) is captured
+        check(lib.sp_graph_begin(self.ctx.h, None, ctypes.byref(cs)), "sp_graph_begin",
+              self.ctx.h)
+        self._cs = cs
+        self.ctx._record_stream = cs
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        self.ctx._record_stream = None
+        g = ctypes.c_void_p()
+        rc = lib.sp_graph_end(self.ctx.h, self._cs, ctypes.byref(g))
+        if exc_type is None:
+            check(rc, "sp_graph_end", self.ctx.h)
+            self.h = g
+        elif rc == 0:
+            lib.sp_graph_destroy(g)
+        return False
+
+    def launch(self, replays: int = 1) -> dict:
+        st = N.Stats()
+        check(lib.sp_graph_launch(self.h, replays, ctypes.byref(st), self.ctx.stream()),
+              "sp_graph_launch", self.ctx.h)
+        return st.as_dict()
+
+    def close(self):
+        if self.h:
+            lib.sp_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- microbenchmarks -----------------------------------------------------------------

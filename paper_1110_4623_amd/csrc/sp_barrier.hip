@@ -187,6 +187,8 @@ int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t
   SP_CHECK(spi::begin_timed(ctx, s));
   uint64_t timeout = spi::timeout_ticks(ctx, b->p);
   uint32_t N = b->nwg;
+  const bool coop = b->kind == SP_BARRIER_GRID_SYNC || b->p.cooperative;
+  if (coop && spi::capturing(s)) return SP_E_INVAL;  // cooperative launches are not recorded
   if (b->kind == SP_BARRIER_GRID_SYNC) {  // grid.sync() requires a cooperative launch
     void* args[] = {&N, &rounds, &seed, &b->d_slots, &out_checksums};
     SP_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(N), dim3(lanes), args, 0, s));
@@ -208,6 +210,7 @@ int sp_barrier_run_hash_launches(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint
     return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
+  if (graph && spi::capturing(s)) return SP_E_INVAL;
   SP_CHECK(spi::fill_u32(ctx, out_checksums, nwg, 0, s));
   SP_CHECK(spi::fill_u32(ctx, slots, 2ull * nwg, 0, s));
   if (!graph) {

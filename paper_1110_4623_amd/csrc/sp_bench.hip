@@ -226,7 +226,7 @@ int sp_bench_atomic(sp_ctx* ctx, uint32_t op, uint32_t nwg, uint32_t lanes, uint
     hipLaunchKernelGGL(k_sum_words, dim3(std::min<uint32_t>((T + 255) / 256, 4096)), dim3(256), 0,
                        s, buf, T, sw, sum);
     SP_HIP(ctx, hipGetLastError());
-    SP_HIP(ctx, hipStreamSynchronize(s));
+    SP_CHECK(spi::sync_unless_capturing(ctx, s));
   }
   return SP_OK;
 }

@@ -71,9 +71,16 @@ inline sp::BackoffCfg backoff_cfg(const sp_params& p, uint32_t* private_word) {
 // Zero `words` uint32 at d with a kernel (no memset nodes, so launches stay capturable).
 int fill_u32(sp_ctx* ctx, uint32_t* d, uint64_t words, uint32_t value, hipStream_t s);
 
-// Clears the watchdog word, records ev0.
+// True while `s` is being captured into a HIP graph (sp_graph_begin): run calls then
+// record their kernels and skip timing, host waits and host readbacks.
+bool capturing(hipStream_t s);
+// hipStreamSynchronize(s), or nothing while `s` is being captured.
+int sync_unless_capturing(sp_ctx* ctx, hipStream_t s);
+
+// Clears the watchdog word, records ev0 (nothing under capture).
 int begin_timed(sp_ctx* ctx, hipStream_t s);
-// Records ev1, waits for the stream, reads the watchdog word, fills st.
+// Records ev1, waits for the stream, reads the watchdog word, fills st (under capture:
+// zeroes st and returns SP_OK).
 int end_timed(sp_ctx* ctx, hipStream_t s, sp_stats* st, uint32_t nwg, uint32_t lanes,
               uint32_t resident_per_cu, uint64_t ops);
 

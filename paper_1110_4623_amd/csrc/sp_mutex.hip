@@ -157,7 +157,7 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
   hipLaunchKernelGGL(k_gather_words, dim3(256), dim3(256), 0, s, m->d_words, nlocks, W, wstride,
                      out_words);
   SP_HIP(ctx, hipGetLastError());
-  SP_HIP(ctx, hipStreamSynchronize(s));
+  SP_CHECK(spi::sync_unless_capturing(ctx, s));
   return rc;
 }
 

@@ -151,7 +151,7 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   const uint32_t alg4 = kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF;
   hipLaunchKernelGGL(k_sem_state, dim3(1), dim3(64), 0, s, base, sw, alg4, out_state);
   SP_HIP(ctx, hipGetLastError());
-  SP_HIP(ctx, hipStreamSynchronize(s));
+  SP_CHECK(spi::sync_unless_capturing(ctx, s));
   return rc;
 }
 

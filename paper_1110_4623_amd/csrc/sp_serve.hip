@@ -11,12 +11,11 @@
 //            completion flag c (pinned host memory);
 //   host:    a second thread sees the flag and stamps the completion time.
 //
-// Only the workgroup holding the ticket the tail reaches next polls host memory (one
-// PCIe read per poll); it copies the tail into a device word that the other waiting
-// workgroups poll, each sleeping in proportion to its distance from the head.
-// Descriptors carry their request id, so a slot read before the host's write landed is
-// recognised and read again: correctness does not depend on how host writes and device
-// reads are ordered across PCIe.
+// The workgroups nearest the arrival front poll their own ring slot in host memory;
+// the others poll a device word that tracks the front, sleeping in proportion to their
+// distance from it.  Descriptors carry their request id, so a slot read before the
+// host's write landed is recognised and read again: correctness does not depend on how
+// host writes and device reads are ordered across PCIe.
 #include <string.h>
 
 #include <algorithm>
@@ -32,7 +31,7 @@
 namespace {
 
 // Device state lines (each `stride` words apart).
-enum { S_HEAD = 0, S_DTAIL, S_READY, S_ISSUED, S_RELEASED, S_INUSE, S_MAXUSE, S_LINES };
+enum { S_HEAD = 0, S_FRONT, S_READY, S_ISSUED, S_RELEASED, S_INUSE, S_MAXUSE, S_LINES };
 constexpr uint32_t kStride = 32;            // 128-byte lines
 constexpr uint32_t kMaxSleepUnits = 2048;   // cap of a waiting workgroup's sleep
 constexpr uint64_t kStopBit = 1ull << 63;   // in the host tail word: abandon the run
@@ -40,7 +39,7 @@ constexpr uint32_t kIdEmpty = 0xFFFFFFFFu;  // request id of a never-written rin
 
 struct ServeArgs {
   uint32_t* st;            // device state lines
-  const uint64_t* h_tail;  // pinned: published tail (low 32 bits) | kStopBit
+  const uint64_t* h_tail;  // pinned: published count (low 32 bits, informational) | kStopBit
   uint32_t* h_started;     // pinned: set once every workgroup is running
   const uint64_t* h_ring;  // pinned: 2 words per slot, (id << 32) | L and (id << 32) | units
   uint32_t* h_done;        // pinned: completion flag per request
@@ -55,8 +54,17 @@ __device__ __forceinline__ void st_sys(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// The hash chain of one request.  Only the leader lane is active here; reading the
+// inputs through readfirstlane makes them wave-uniform, so the serial chain runs on the
+// scalar ALU (one instruction per dependent step) instead of as one-lane vector
+// instructions with quarter-rate 32-bit multiplies.  Both the persistent kernel and the
+// launch comparator use this routine.
 __device__ __forceinline__ uint32_t chain(uint32_t x, uint32_t L) {
-  for (uint32_t i = 0; i < L; ++i) x = sp::sm32(x);
+  x = __builtin_amdgcn_readfirstlane(x);
+  L = __builtin_amdgcn_readfirstlane(L);
+  uint32_t i = 0;
+  for (; i + 4 <= L; i += 4) x = sp::sm32(sp::sm32(sp::sm32(sp::sm32(x))));
+  for (; i < L; ++i) x = sp::sm32(x);
   return x;
 }
 
@@ -76,28 +84,35 @@ __device__ __forceinline__ bool read_desc(const uint64_t* ring, uint32_t mask, u
   }
 }
 
-// Waits until request c has been published.  The workgroup next in line polls the host
-// tail and forwards it to the device copy; the others poll the device copy.
-__device__ bool await_arrival(const ServeArgs& a, uint32_t c, uint32_t* dtail, const sp::Ctl& ctl) {
+// Waits until request c is in the ring and reads its descriptor.  `front` (device) is a
+// lower bound on the number of requests published so far.  Workgroups fewer than kNear
+// tickets past the front poll their own ring slot in host memory, so one PCIe read both
+// detects the arrival and fetches the descriptor, and a burst of arrivals is detected by
+// up to kNear workgroups at once; the others poll `front`, sleeping in proportion to
+// their distance.  A workgroup that finds its request moves the front past it.
+constexpr int32_t kNear = 16;
+
+__device__ bool await_desc(const ServeArgs& a, uint32_t c, uint32_t* front, uint32_t* L,
+                           uint32_t* units, const sp::Ctl& ctl) {
+  const uint64_t* slot = a.h_ring + 2 * (size_t)(c & a.mask);
   sp::Wait w(ctl, 0);
-  for (;;) {
-    const uint32_t t = sp::ld_relaxed(dtail);
-    if ((int32_t)(t - c) > 0) return true;
-    const uint32_t d = c - t;
-    if (d == 0) {
-      const uint64_t ts = ld_sys64(a.h_tail);
-      if (ts & kStopBit) {
+  for (uint32_t k = 1;; ++k) {
+    const int32_t d = (int32_t)(c - sp::ld_relaxed(front));
+    if (d < kNear) {
+      const uint64_t w0 = ld_sys64(slot), w1 = ld_sys64(slot + 1);
+      if ((uint32_t)(w0 >> 32) == c && (uint32_t)(w1 >> 32) == c) {
+        *L = (uint32_t)w0;
+        *units = (uint32_t)w1;
+        if (d >= 0) sp::max_relaxed(front, c + 1);
+        return true;
+      }
+      if ((k & 63) == 0 && (ld_sys64(a.h_tail) & kStopBit)) {
         sp::cas_relaxed(ctl.err, sp::DEV_OK, sp::DEV_TIMEOUT);
         return false;
       }
-      const uint32_t ht = (uint32_t)ts;
-      if ((int32_t)(ht - c) > 0) {
-        sp::max_relaxed(dtail, ht);
-        return true;
-      }
       sp::sleep_units(a.poll_sleep);
     } else {
-      const uint64_t s = (uint64_t)d * a.far_sleep;
+      const uint64_t s = (uint64_t)(d - kNear + 1) * a.far_sleep;
       sp::sleep_units(s < kMaxSleepUnits ? (uint32_t)s : kMaxSleepUnits);
     }
     if (!w.tick()) return false;
@@ -110,7 +125,7 @@ __global__ SP_FULL_OCCUPANCY void k_serve(ServeArgs a, uint32_t* err, uint64_t t
   if (!sp::is_leader()) return;
   const sp::Ctl ctl{err, sp::wall_clock() + timeout};
   uint32_t* head = a.st + S_HEAD * kStride;
-  uint32_t* dtail = a.st + S_DTAIL * kStride;
+  uint32_t* front = a.st + S_FRONT * kStride;
   uint32_t* inuse = a.st + S_INUSE * kStride;
   uint32_t* maxuse = a.st + S_MAXUSE * kStride;
   const sp::WSemState ws{a.K, a.poll_sleep, a.st + S_ISSUED * kStride, a.st + S_RELEASED * kStride};
@@ -119,8 +134,7 @@ __global__ SP_FULL_OCCUPANCY void k_serve(ServeArgs a, uint32_t* err, uint64_t t
     const uint32_t c = sp::add_relaxed(head, 1);
     if (c >= a.n) return;
     uint32_t L, u;
-    if (!await_arrival(a, c, dtail, ctl)) return;
-    if (!read_desc(a.h_ring, a.mask, c, &L, &u, ctl)) return;
+    if (!await_desc(a, c, front, &L, &u, ctl)) return;
     if (!sp::wsem_wait_leader<false>(ws, u, ctl)) return;
     if (a.track) sp::max_relaxed(maxuse, sp::add_relaxed(inuse, u) + u);
     a.out[c] = chain(a.seed ^ c, L);
@@ -203,12 +217,12 @@ struct Buffers {
   uint32_t* d_out = nullptr;
   std::vector<hipStream_t> streams;
   ~Buffers() {
-    for (hipStream_t s : streams) hipStreamDestroy(s);
-    if (h_tail) hipHostFree(h_tail);
-    if (h_ring) hipHostFree(h_ring);
-    if (h_done) hipHostFree(h_done);
-    if (d_state) hipFree(d_state);
-    if (d_out) hipFree(d_out);
+    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+    if (h_tail) (void)hipHostFree(h_tail);
+    if (h_ring) (void)hipHostFree(h_ring);
+    if (h_done) (void)hipHostFree(h_done);
+    if (d_state) (void)hipFree(d_state);
+    if (d_out) (void)hipFree(d_out);
   }
 };
 
@@ -371,7 +385,7 @@ int serve(sp_ctx* ctx, const sp_serve_cfg* cfg_in, uint32_t n, const uint32_t* L
     while (!__atomic_load_n(b.h_started, __ATOMIC_ACQUIRE)) {
       if (now_ns() > give_up || hipStreamQuery(s0) != hipErrorNotReady) {
         __atomic_store_n(b.h_tail, kStopBit, __ATOMIC_RELEASE);
-        hipStreamSynchronize(s0);
+        (void)hipStreamSynchronize(s0);
         return SP_E_TIMEOUT;
       }
     }

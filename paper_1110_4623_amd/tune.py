@@ -1,0 +1,228 @@
+"""Autotuner: picks each primitive's algorithm and parameters per contention level.
+
+Section 7 proposes tuning the backoff parameters for each GPU under differing levels of
+contention.  This tuner widens that to every choice the library exposes: for barriers the
+algorithm, the tree's fan-in, flag packing and the polling sleep; for mutexes and
+semaphores the algorithm, the backoff policy and bounds, and the polling sleep; for the
+serving queue the polling sleeps and the number of persistent workgroups.  Each candidate
+runs a short representative workload through libsp (barrier, mutex and semaphore
+candidates are recorded into a HIP graph once and timed over replays); the fastest
+candidate whose results pass the workload's own consistency checks wins.  The winners
+are installed with sp_set_default, so that the *_DEFAULT kinds resolve to them, and can
+be saved to and loaded from a JSON cache keyed by the device.
+
+Contention buckets follow the library: bucket 0 has fewer than 64 workgroups per
+resource (per barrier, per lock, per K semaphore units), bucket 1 has 64 or more.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from . import api
+
+BUCKET_SPLIT = 64
+LIMIT_MS = 3000  # watchdog of every tuning run: a slower candidate is rejected
+
+
+def _median(xs):
+    return float(np.median(np.asarray(xs, dtype=np.float64)))
+
+
+def _graph_time(ctx, record, replays: int) -> float:
+    """Records `record()` into a graph and returns ms per replay (median of 3 launches)."""
+    g = api.Graph(ctx)
+    with g:
+        record()
+    try:
+        g.launch(1)  # warm-up
+        ms = [g.launch(replays)["kernel_ms"] / replays for _ in range(3)]
+    finally:
+        g.close()
+    return _median(ms)
+
+
+# ---- barriers ---------------------------------------------------------------------------
+
+def barrier_candidates():
+    out = [("central", {}), ("central_split", {}), ("xcd", {}),
+           ("flag", {"flags_packed": 0}), ("flag", {"flags_packed": 1})]
+    out += [("tree", {"fan_in": f}) for f in (4, 8, 16, 32)]
+    return [(k, dict(p, poll_sleep=ps)) for k, p in out for ps in (0, 1, 4)]
+
+
+def tune_barrier(ctx, nwg: int, lanes: int = 256, rounds: int = 1000, seed: int = 42,
+                 candidates=None, limit_ms: int = LIMIT_MS) -> dict:
+    """Times every candidate barrier on the hash exchange among nwg workgroups.  The
+    checksums are deterministic, so every correct candidate returns the same ones; a
+    candidate that disagrees with the majority is rejected."""
+    rows = []
+    for kind, params in candidates or barrier_candidates():
+        b = api.Barrier(ctx, kind, nwg, timeout_ms=limit_ms, **params)
+        try:
+            ms = _graph_time(ctx, lambda: b.launch(lanes, rounds, seed), 2)
+            chk = b.checksums()
+        except api.N.SpError as e:  # not co-resident, or slower than the limit
+            rows.append({"kind": kind, "params": params, "error": str(e)})
+            continue
+        finally:
+            b.close()
+        rows.append({"kind": kind, "params": params, "us_per_round": ms * 1e3 / rounds,
+                     "chk": chk.tobytes()})
+    ok = [r for r in rows if "chk" in r]
+    if not ok:
+        raise RuntimeError("no barrier candidate ran")
+    votes: dict[bytes, int] = {}
+    for r in ok:
+        votes[r["chk"]] = votes.get(r["chk"], 0) + 1
+    majority = max(votes, key=votes.get)
+    for r in ok:
+        r["consistent"] = r["chk"] == majority
+        del r["chk"]
+    best = min((r for r in ok if r["consistent"]), key=lambda r: r["us_per_round"])
+    return {"nwg": nwg, "lanes": lanes, "rounds": rounds, "best": best, "candidates": rows}
+
+
+# ---- mutexes ------------------------------------------------------------------------------
+
+def mutex_candidates():
+    out = [("spin_cas", {}), ("spin_exch", {})]
+    for policy in ("exp", "paper"):
+        for imax in (8, 32, 128):
+            out.append(("spin_backoff", {"backoff": policy, "backoff_min": 1, "backoff_max": imax}))
+    out += [("ticket", {"poll_sleep": ps}) for ps in (0, 1, 4)]
+    out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
+    return out
+
+
+def tune_mutex(ctx, nwg: int, nlocks: int = 1, words: int = 16, total: int = 4096,
+               max_delay: int = 1000, lanes: int = 256, seed: int = 42, candidates=None,
+               limit_ms: int = LIMIT_MS) -> dict:
+    """Times every candidate mutex on the contention workload.  With one lock every
+    critical-section word must end at exactly `total`; with several, every lock's words
+    must agree and sum to `total`."""
+    rows = []
+    for kind, params in candidates or mutex_candidates():
+        m = api.Mutex(ctx, kind, nlocks, words, timeout_ms=limit_ms, **params)
+        try:
+            ms = _graph_time(ctx, lambda: m.launch(nwg, lanes, total, max_delay, seed), 1)
+            w = m.words()
+        except api.N.SpError as e:
+            rows.append({"kind": kind, "params": params, "error": str(e), "consistent": False})
+            continue
+        finally:
+            m.close()
+        ok = bool((w == w[:, :1]).all() and int(w[:, 0].sum()) == total)
+        rows.append({"kind": kind, "params": params, "acq_per_s": total / (ms * 1e-3),
+                     "consistent": ok})
+    best = max((r for r in rows if r["consistent"]), key=lambda r: r["acq_per_s"])
+    return {"nwg": nwg, "nlocks": nlocks, "total": total, "best": best, "candidates": rows}
+
+
+# ---- semaphores ---------------------------------------------------------------------------
+
+def semaphore_candidates():
+    out = [("spin", {})]
+    for policy in ("exp", "paper"):
+        for imax in (8, 32):
+            out.append(("spin_backoff", {"backoff": policy, "backoff_min": 1, "backoff_max": imax}))
+    out += [("ticket", {"poll_sleep": 0})]
+    out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
+    return out
+
+
+def tune_semaphore(ctx, nwg: int, K: int, total: int = 8192, max_hold: int = 2000,
+                   lanes: int = 256, seed: int = 42, candidates=None,
+                   limit_ms: int = LIMIT_MS) -> dict:
+    """Times every candidate semaphore on the wait/post workload; a candidate must admit
+    exactly `total` times and never hold more than K."""
+    rows = []
+    for kind, params in candidates or semaphore_candidates():
+        s = api.Semaphore(ctx, kind, K, timeout_ms=limit_ms, **params)
+        try:
+            s.launch(nwg, lanes, 1, 0, seed)  # sizes the checksum buffer before recording
+            ms = _graph_time(ctx, lambda: s.launch(nwg, lanes, total, max_hold, seed), 1)
+            r = s.result()
+        except api.N.SpError as e:
+            rows.append({"kind": kind, "params": params, "error": str(e), "consistent": False})
+            continue
+        finally:
+            s.close()
+        ok = r["state"][3] == total and 1 <= r["maxocc"] <= K
+        rows.append({"kind": kind, "params": params, "pairs_per_s": total / (ms * 1e-3),
+                     "consistent": bool(ok)})
+    best = max((r for r in rows if r["consistent"]), key=lambda r: r["pairs_per_s"])
+    return {"nwg": nwg, "K": K, "total": total, "best": best, "candidates": rows}
+
+
+# ---- serving queue ----------------------------------------------------------------------
+
+def tune_serve(ctx, reqs: dict, seed: int = 42, budget_units: int = 16384,
+               unit_bytes: int = 65536, candidates=None) -> dict:
+    """Runs the request stream with each candidate configuration of the persistent queue
+    and keeps the one with the lowest p99 latency; every candidate must return the same
+    per-request results."""
+    cands = candidates or [dict(nwg=nwg, poll_sleep=ps, far_sleep=fs)
+                           for nwg in (256, 1024) for ps in (0, 2) for fs in (1, 4, 16)]
+    rows, ref = [], None
+    for c in cands:
+        out, _, res = api.serve(ctx, reqs, seed=seed, budget_units=budget_units,
+                                unit_bytes=unit_bytes, **c)
+        if ref is None:
+            ref = out
+        rows.append({"cfg": c, "p50_us": res["p50_us"], "p99_us": res["p99_us"],
+                     "req_per_s": res["req_per_s"], "consistent": bool((out == ref).all())})
+    best = min((r for r in rows if r["consistent"]), key=lambda r: r["p99_us"])
+    return {"n": int(len(reqs["L"])), "best": best, "candidates": rows}
+
+
+# ---- whole tuning pass, cache, installation ------------------------------------------------
+
+def device_key(ctx) -> str:
+    i = ctx.info
+    return f"{i['arch']}/{i['cu_count']}cu/{i['xcd_count']}xcd"
+
+
+def tune_all(ctx, quick: bool = False) -> dict:
+    """Tunes barriers (16 and 1024 workgroups), one contended lock (16 and 1024
+    workgroups) and a K = 32 semaphore (256 and 2048 workgroups, 8 and 64 per unit)."""
+    rounds = 300 if quick else 1000
+    mt = 1024 if quick else 4096
+    res = {"device": device_key(ctx), "barrier": {}, "mutex": {}, "semaphore": {}}
+    res["barrier"]["0"] = tune_barrier(ctx, 16, rounds=rounds)
+    res["barrier"]["1"] = tune_barrier(ctx, 1024, rounds=rounds)
+    res["mutex"]["0"] = tune_mutex(ctx, 16, total=mt)
+    res["mutex"]["1"] = tune_mutex(ctx, 1024, total=mt)
+    res["semaphore"]["0"] = tune_semaphore(ctx, 256, 32, total=2 * mt)
+    res["semaphore"]["1"] = tune_semaphore(ctx, 2048, 32, total=2 * mt)
+    return res
+
+
+def apply(ctx, tuned: dict) -> None:
+    """Installs the winners as the library's defaults for this context."""
+    if tuned.get("device") not in (None, device_key(ctx)):
+        raise ValueError(f"tuning for {tuned['device']} does not match {device_key(ctx)}")
+    for prim in ("barrier", "mutex", "semaphore"):
+        for bucket, r in tuned.get(prim, {}).items():
+            best = r["best"]
+            ctx.set_default(prim, int(bucket), best["kind"], **best["params"])
+
+
+def save(tuned: dict, path: str) -> None:
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(tuned, f, indent=1)
+
+
+def load(path: str) -> dict:
+    with open(path) as f:
+        return json.load(f)
+
+
+def default_cache_path() -> str:
+    return os.environ.get("SP_TUNER_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_1110_4623_amd",
+                                       "tuner.json"))

@@ -1,0 +1,49 @@
+"""Host logic of the autotuner (no GPU): installation of the winners and the cache."""
+
+import pytest
+
+
+class FakeCtx:
+    info = {"arch": "gfx950:sramecc+:xnack-", "cu_count": 256, "xcd_count": 8}
+
+    def __init__(self):
+        self.calls = []
+
+    def set_default(self, prim, bucket, kind, **params):
+        self.calls.append((prim, bucket, kind, params))
+
+
+def _tuned(device):
+    best = lambda k, p: {"best": {"kind": k, "params": p, "consistent": True}}  # noqa: E731
+    return {"device": device,
+            "barrier": {"0": best("central_split", {"poll_sleep": 1}), "1": best("xcd", {})},
+            "mutex": {"0": best("ticket", {}), "1": best("sleep", {"poll_sleep": 4})},
+            "semaphore": {"1": best("sleep", {"poll_sleep": 16})}}
+
+
+def test_apply_installs_every_bucket(tmp_path):
+    from paper_1110_4623_amd import tune
+    ctx = FakeCtx()
+    path = str(tmp_path / "sub" / "t.json")
+    tune.save(_tuned(tune.device_key(ctx)), path)
+    tune.apply(ctx, tune.load(path))
+    assert ("barrier", 1, "xcd", {}) in ctx.calls
+    assert ("mutex", 1, "sleep", {"poll_sleep": 4}) in ctx.calls
+    assert ("semaphore", 1, "sleep", {"poll_sleep": 16}) in ctx.calls
+    assert len(ctx.calls) == 5
+
+
+def test_apply_refuses_another_device():
+    from paper_1110_4623_amd import tune
+    with pytest.raises(ValueError):
+        tune.apply(FakeCtx(), _tuned("gfx942/304cu/8xcd"))
+
+
+def test_candidate_lists_cover_every_kind():
+    from paper_1110_4623_amd import tune
+    assert {k for k, _ in tune.barrier_candidates()} == {"central", "central_split", "xcd",
+                                                          "flag", "tree"}
+    assert {k for k, _ in tune.mutex_candidates()} == {"spin_cas", "spin_exch", "spin_backoff",
+                                                        "ticket", "sleep"}
+    assert {k for k, _ in tune.semaphore_candidates()} == {"spin", "spin_backoff", "ticket",
+                                                            "sleep"}
