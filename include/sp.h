@@ -198,6 +198,22 @@ int sp_barrier_destroy(sp_barrier* b);
  * SP_E_TIMEOUT, SP_E_HIP.  The state is reset before every run.                          */
 int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t seed,
                         uint32_t* out_checksums, sp_stats* st, void* stream);
+/* sp_barrier_info_get: after a run (call it once the run has returned), how the last
+ * run synchronized.  For SP_BARRIER_XCD: xcd_path = 1 if every workgroup's registration
+ * fit (at most ceil(nwg / XCDs) rounded up to 32 per XCD, 32 per CU), so the per-XCD
+ * protocol was used; otherwise the run fell back to the counter tree (same results) and
+ * cu_overflow counts the registrations that did not fit.  misplaced counts workgroups
+ * that did not run on XCD (id mod XCDs), the dispatcher's usual placement: the barrier
+ * reads each workgroup's XCD and does not depend on it.                                 */
+typedef struct sp_barrier_info {
+  uint32_t kind;
+  uint32_t nwg;
+  uint32_t xcd_path;
+  uint32_t misplaced;
+  uint32_t cu_overflow;
+  uint32_t reserved[3];
+} sp_barrier_info;
+int sp_barrier_info_get(sp_barrier* b, sp_barrier_info* out);
 /* Comparator: the same workload with the kernel boundary as the barrier (one launch per
  * round, Section 2's "end one kernel and begin another"); graph != 0 replays the
  * rounds from a captured HIP graph instead of launching them one by one.               */

@@ -19,6 +19,7 @@ struct BarrierState {
   uint32_t nwg;         // workgroups taking part
   uint32_t stride;      // uint32 words between padded state words
   uint32_t groups;      // tree: number of groups (<= nwg); xcd: number of XCDs
+  uint32_t tgroups;     // groups of the counter tree (tree, xcd round 0 and fallback), <= nwg
   uint32_t flag_stride; // flag barrier: uint32 words between flags (1 = packed)
   uint32_t poll_sleep;  // s_sleep units between polls
   uint32_t xblock;      // xcd: uint32 words of each XCD's block of local arrival flags
@@ -30,12 +31,14 @@ struct BarrierState {
   uint32_t* topgen;     // tree: top release word
   uint32_t* arrive;     // flag barrier: arrival flags (nwg)
   uint32_t* release;    // flag barrier: release flags (nwg)
-  uint32_t* mismatch;   // xcd: set when a workgroup is not on XCD (id mod groups)
+  uint32_t* mismatch;   // xcd: workgroups not on XCD (id mod groups), informational
+  uint32_t* overflow;   // xcd: registrations that did not fit (nonzero = tree fallback)
   uint32_t* xarrive;    // xcd: per-XCD arrival stamps (groups lines)
   uint32_t* lrelease;   // xcd: per-workgroup release flags (nwg lines), XCD-major
   uint32_t* larrive;    // xcd: packed arrival flags, XCD-major blocks of xblock words
   uint32_t* cu_count;   // xcd: workgroups registered per CU key (groups * 256 words)
-  uint32_t* cu_members; // xcd: member ids per CU key (groups * 256 * kCuSlots words)
+  uint32_t* cu_members; // xcd: member indices per CU key (groups * 256 * kCuSlots words)
+  uint32_t* xcount;     // xcd: members registered per XCD (groups words)
 };
 
 // Workgroups one CU can hold at most (32 wavefront slots).
@@ -74,7 +77,7 @@ __device__ __forceinline__ bool counter_arrive_wait(const BarrierState& s, uint3
     // w mod G; the last arriver of a group arrives at the top counter; the last group
     // publishes the top release word, which each group's last arriver copies into its
     // group's release word.
-    const uint32_t G = s.groups;
+    const uint32_t G = s.tgroups;
     const uint32_t g = blockIdx.x % G;
     const uint32_t members = (s.nwg - g + G - 1) / G;
     uint32_t* gc = s.gcnt + (size_t)g * s.stride;
@@ -145,37 +148,43 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
   return s_ok;
 }
 
-// Per-XCD barrier.  Workgroup w runs on XCD w mod X (X = s.groups; checked in round 0)
-// and is member k = w / X of its XCD; member 0 is the XCD's master.  In round 0 every
-// workgroup also registers under the id of its CU, and the first one registered on each
-// CU becomes that CU's leader.
+// Per-XCD barrier.  In round 0 every workgroup registers under the XCD it runs on (the
+// XCC id register), which makes it member k of that XCD in registration order (member 0
+// is the XCD's master), and under the id of its CU, where the first workgroup to register
+// becomes the CU's leader.  The placement is read, not assumed: the dispatcher normally
+// sends workgroup w to XCD w mod 8, but not always (after a cooperative launch, for
+// example, later dispatches have been measured to start one XCD further on).  Later rounds:
 //   1. Each member waits for its own stores to complete (they are then in the XCD's L2)
 //      and stores its arrival stamp into its XCD's packed block of arrival flags; the
 //      master's lanes scan the block.
 //   2. The master writes back the XCD's dirty L2 lines once for all its members (agent
-//      release), publishes the XCD's stamp, and polls the other XCDs' stamps
-//      (all-to-all between at most eight masters).
-//   3. Each CU leader polls the eight XCD stamps; once all are published it acquires
-//      (agent scope) and releases the other workgroups of its CU.  Every flag is its own
-//      line.
+//      release) and publishes the XCD's stamp.
+//   3. Each CU leader polls the stamps of every XCD that has members; once all are
+//      published it acquires (agent scope) and releases the other workgroups of its CU.
+//      Every flag is its own line.
 // Writebacks and invalidations both serialize at each XCD's L2 controller.  The
 // writeback is shared by the whole XCD.  The invalidation has to reach each CU's L1, and
 // on gfx950 only the agent-scope invalidate does (a workgroup-scope one leaves stale L1
 // lines), so it is shared by the workgroups of one CU: all of them are waiting when
 // their leader invalidates, so nothing stale can re-enter the L1 before they read.
-// All flags are accessed with agent-scope atomics.
+// If an XCD holds more members than its flag block or a CU more than kCuSlots, every
+// workgroup falls back to the counter tree.  All flags are agent-scope atomics.
 struct XcdLocal {
-  uint32_t key;    // CU key: XCD * 256 + CU id
-  uint32_t slot;   // registration order on the CU (0 = CU leader)
-  uint32_t ncu;    // workgroups on this CU
-  uint32_t cu_list[kCuSlots];  // CU leader only: the CU's workgroups
+  uint32_t x;        // the XCD this workgroup runs on
+  uint32_t k;        // member index within the XCD (0 = master)
+  uint32_t members;  // members of this XCD
+  uint32_t xmask;    // XCDs that have members (bit i = XCD i)
+  uint32_t key;      // CU key: XCD * 256 + CU id
+  uint32_t slot;     // registration order on the CU (0 = CU leader)
+  uint32_t ncu;      // workgroups on this CU
+  uint32_t cu_list[kCuSlots];  // CU leader only: member indices of the CU's workgroups
 };
 
-__device__ __forceinline__ void release_list(const BarrierState& s, const uint32_t* list,
-                                             uint32_t n, uint32_t stamp, uint32_t* rel) {
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const uint32_t w = list[i];
-    if (w != blockIdx.x) st_relaxed(rel + (size_t)(w / s.groups) * s.stride, stamp);
+__device__ __forceinline__ void release_list(const BarrierState& s, const XcdLocal& L,
+                                             uint32_t stamp, uint32_t* rel) {
+  for (uint32_t i = threadIdx.x; i < L.ncu; i += blockDim.x) {
+    const uint32_t k = L.cu_list[i];
+    if (k != L.k) st_relaxed(rel + (size_t)k * s.stride, stamp);
   }
 }
 
@@ -183,61 +192,68 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
                                          const XcdLocal& L) {
   __shared__ uint32_t s_ok;
   const uint32_t X = s.groups;
-  const uint32_t x = blockIdx.x % X, k = blockIdx.x / X;
-  const uint32_t members = (s.nwg - x + X - 1) / X;
-  uint32_t* block = s.larrive + (size_t)x * s.xblock;
-  uint32_t* rel = s.lrelease + (size_t)x * s.xblock * s.stride;  // member i: rel + i*stride
+  uint32_t* block = s.larrive + (size_t)L.x * s.xblock;
+  uint32_t* rel = s.lrelease + (size_t)L.x * s.xblock * s.stride;  // member k: rel + k*stride
   Wait w(ctl, s.poll_sleep);
   int ok = 1;
   __syncthreads();
-  if (k == 0) {
+  if (L.k == 0) {
     // XCD master: gather the XCD's arrivals, write the XCD's L2 back once, publish.
-    ok = scan_flags(block, 1, members, 0, stamp, w);
+    ok = scan_flags(block, 1, L.members, 0, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
-    if (is_leader()) st_release(s.xarrive + (size_t)x * s.stride, stamp);
+    if (is_leader()) st_release(s.xarrive + (size_t)L.x * s.stride, stamp);
   } else if (is_leader()) {
-    st_relaxed(block + k, stamp);
+    st_relaxed(block + L.k, stamp);
   }
   if (L.slot == 0) {
-    // CU leader: once all XCDs have published, invalidate for the CU and release it.
-    if (threadIdx.x < X) ok = poll_until(s.xarrive + (size_t)threadIdx.x * s.stride, stamp, w);
+    // CU leader: once every populated XCD has published, invalidate for the CU and
+    // release it.
+    if (threadIdx.x < X && ((L.xmask >> threadIdx.x) & 1))
+      ok = poll_until(s.xarrive + (size_t)threadIdx.x * s.stride, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
     if (is_leader()) fence_acquire();
     __syncthreads();
-    release_list(s, L.cu_list, L.ncu, stamp, rel);
+    release_list(s, L, stamp, rel);
     return true;
   }
   if (is_leader()) {
-    ok = poll_until(rel + (size_t)k * s.stride, stamp, w);
+    ok = poll_until(rel + (size_t)L.k * s.stride, stamp, w);
     s_ok = ok;
   }
   __syncthreads();
   return s_ok;
 }
 
-// Round 0 of the per-XCD barrier: check the XCD placement, register per CU, run the
-// counter tree with per-workgroup fences, then load the lists the later rounds use.
-// Returns (through *use_xcd) whether every workgroup was placed as expected.
+// Round 0 of the per-XCD barrier: register per XCD and per CU, run the counter tree
+// with per-workgroup fences, then load what the later rounds use.
 __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl, XcdLocal& L,
                                           uint32_t* use_xcd) {
   __shared__ uint32_t s_ok;
   const uint32_t X = s.groups;
   __syncthreads();  // every wavefront's stores have completed (barrier_wait's entry wait)
   if (is_leader()) {
-    const uint32_t xcc = xcc_id();
+    const uint32_t xcc = xcc_id() % X;
     if (xcc != blockIdx.x % X) add_relaxed(s.mismatch, 1);
-    L.key = (xcc % X) * 256 + cu_in_xcc();
+    L.x = xcc;
+    L.k = add_relaxed(s.xcount + xcc, 1);
+    if (L.k >= s.xblock) add_relaxed(s.overflow, 1);
+    L.key = xcc * 256 + cu_in_xcc();
     L.slot = add_relaxed(s.cu_count + L.key, 1);
     if (L.slot < kCuSlots)
-      st_relaxed(s.cu_members + (size_t)L.key * kCuSlots + L.slot, blockIdx.x);
+      st_relaxed(s.cu_members + (size_t)L.key * kCuSlots + L.slot, L.k);
     else
-      add_relaxed(s.mismatch, 1);
+      add_relaxed(s.overflow, 1);
     const bool ok = counter_arrive_wait<SP_BARRIER_TREE>(s, 1, ctl);
     fence_acquire();
-    *use_xcd = ld_relaxed(s.mismatch) == 0;
+    *use_xcd = ld_relaxed(s.overflow) == 0;
     L.ncu = ld_relaxed(s.cu_count + L.key);
+    L.members = ld_relaxed(s.xcount + xcc);
+    uint32_t mask = 0;
+    for (uint32_t i = 0; i < X; ++i)
+      if (ld_relaxed(s.xcount + i) != 0) mask |= 1u << i;
+    L.xmask = mask;
     s_ok = ok;
   }
   __syncthreads();
@@ -261,8 +277,8 @@ __device__ bool barrier_wait(const BarrierState& s, uint32_t round, const Ctl& c
   if constexpr (KIND == SP_BARRIER_FLAG) {
     return detail::flag_wait(s, stamp, ctl);
   } else if constexpr (KIND == SP_BARRIER_XCD) {
-    // Round 0 sets up (and checks placement); later rounds use the per-XCD protocol if
-    // every workgroup was placed as expected, the counter tree otherwise.
+    // Round 0 registers every workgroup by XCD and CU; later rounds use the per-XCD
+    // protocol unless a registration did not fit, the counter tree otherwise.
     __shared__ detail::XcdLocal s_local;
     __shared__ uint32_t s_use;
     if (round == 0) return detail::xcd_setup(s, ctl, s_local, &s_use);

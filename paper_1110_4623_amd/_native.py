@@ -97,6 +97,17 @@ class DeviceInfo(ctypes.Structure):
     ]
 
 
+class BarrierInfo(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_uint32),
+        ("nwg", ctypes.c_uint32),
+        ("xcd_path", ctypes.c_uint32),
+        ("misplaced", ctypes.c_uint32),
+        ("cu_overflow", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
+    ]
+
+
 class ServeCfg(ctypes.Structure):
     _fields_ = [
         ("nwg", ctypes.c_uint32),
@@ -157,6 +168,7 @@ def _load():
         "sp_buffer_write": (i32, [vp, vp, vp, u64]),
         "sp_barrier_create": (i32, [vp, u32, u32, P(Params), P(vp)]),
         "sp_barrier_destroy": (i32, [vp]),
+        "sp_barrier_info_get": (i32, [vp, P(BarrierInfo)]),
         "sp_barrier_run_hash": (i32, [vp, u32, u32, u32, vp, P(Stats), vp]),
         "sp_barrier_run_hash_launches": (i32, [vp, u32, u32, u32, u32, u32, vp, vp, P(Stats), vp]),
         "sp_mutex_create": (i32, [vp, u32, u32, u32, P(Params), P(vp)]),

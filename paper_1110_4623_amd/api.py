@@ -212,6 +212,13 @@ class Barrier(_Handle):
     def checksums(self) -> np.ndarray:
         return self.ctx.read(self._out, "u32", self.nwg)
 
+    def info(self) -> dict:
+        """How the last run synchronized (per-XCD path used, or why not)."""
+        i = N.BarrierInfo()
+        check(lib.sp_barrier_info_get(self.h, ctypes.byref(i)), "sp_barrier_info_get", self.ctx.h)
+        return {"xcd_path": bool(i.xcd_path), "misplaced": i.misplaced,
+                "cu_overflow": i.cu_overflow}
+
     def run_hash(self, lanes: int, rounds: int, seed: int):
         """Hash-exchange workload; returns (checksums as uint32 numpy array, stats)."""
         st = self.launch(lanes, rounds, seed)

@@ -108,7 +108,8 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   const uint32_t sw = spi::stride_words(q);
   // the per-XCD barrier groups by XCD; the tree by fan_in
   const uint32_t X = std::max<uint32_t>(1, ctx->xcd_count);
-  const uint32_t G = std::min(kind == SP_BARRIER_XCD ? X : q.fan_in, nwg);
+  // (the per-XCD barrier keeps a group for every XCD: the placement decides which are used)
+  const uint32_t G = kind == SP_BARRIER_XCD ? X : std::min(q.fan_in, nwg);
   const uint32_t fs = q.flags_packed ? 1u : sw;
   // per-XCD blocks of packed local arrival flags, each a whole number of 128-byte lines
   const uint32_t xblock = (uint32_t)(((nwg + G - 1) / G + 31) / 32 * 32);
@@ -118,8 +119,9 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   const uint64_t flag_lines = ((uint64_t)nwg * fs + sw - 1) / sw;
   const uint64_t local_lines = ((uint64_t)G * xblock + sw - 1) / sw;
   const uint64_t lrel_lines = (uint64_t)G * xblock;
-  // per-CU registration (per-XCD barrier): counts and member ids per CU key
-  const uint64_t cu_words = (uint64_t)G * 256 * (1 + sp::kCuSlots);
+  // per-CU and per-XCD registration (per-XCD barrier): counts and member indices per CU
+  // key, member counts per XCD, the overflow word
+  const uint64_t cu_words = (uint64_t)G * 256 * (1 + sp::kCuSlots) + G + 1;
   const uint64_t cu_lines = (cu_words + sw - 1) / sw;
   const uint64_t lines = 5 + 3ull * G + 2 * flag_lines + local_lines + lrel_lines + cu_lines;
   b->state_words = lines * sw;
@@ -139,6 +141,7 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.nwg = nwg;
   s.stride = sw;
   s.groups = G;
+  s.tgroups = std::min(G, nwg);
   s.flag_stride = fs;
   s.poll_sleep = q.poll_sleep;
   s.xblock = xblock;
@@ -156,6 +159,8 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.lrelease = s.larrive + local_lines * sw;
   s.cu_count = s.lrelease + lrel_lines * sw;           // G * 256 words
   s.cu_members = s.cu_count + (uint64_t)G * 256;        // G * 256 * kCuSlots words
+  s.xcount = s.cu_members + (uint64_t)G * 256 * sp::kCuSlots;  // G words
+  s.overflow = s.xcount + G;                                   // 1 word
   *out = b;
   return SP_OK;
 }
@@ -166,6 +171,24 @@ int sp_barrier_destroy(sp_barrier* b) {
   hipFree(b->d_state);
   hipFree(b->d_slots);
   delete b;
+  return SP_OK;
+}
+
+int sp_barrier_info_get(sp_barrier* b, sp_barrier_info* out) {
+  if (!b || !out) return SP_E_INVAL;
+  sp_ctx* ctx = b->ctx;
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  memset(out, 0, sizeof(*out));
+  out->kind = b->kind;
+  out->nwg = b->nwg;
+  if (b->kind == SP_BARRIER_XCD) {
+    uint32_t w[2] = {0, 0};
+    SP_HIP(ctx, hipMemcpy(&w[0], b->st.mismatch, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    SP_HIP(ctx, hipMemcpy(&w[1], b->st.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    out->misplaced = w[0];
+    out->cu_overflow = w[1];
+    out->xcd_path = w[1] == 0;
+  }
   return SP_OK;
 }
 

@@ -66,7 +66,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     import subprocess
     from paper_1110_4623_amd import _native as N
     structs = {"sp_params": N.Params, "sp_stats": N.Stats, "sp_device_info": N.DeviceInfo,
-               "sp_serve_cfg": N.ServeCfg, "sp_serve_result": N.ServeResult}
+               "sp_serve_cfg": N.ServeCfg, "sp_serve_result": N.ServeResult,
+               "sp_barrier_info": N.BarrierInfo}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "sp.h"', "int main(void) {"]
     for cname, py in structs.items():
         src.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')

@@ -94,3 +94,38 @@ def test_not_resident_is_refused(ctx):
     with pytest.raises(sp.SpNotResident):
         bar.run_hash(lanes=1024, rounds=1, seed=1)
     bar.close()
+
+
+@pytest.mark.parametrize("nwg,lanes", [(3, 64), (13, 128), (1024, 256), (2048, 256)])
+def test_xcd_barrier_reads_placement_after_cooperative_launch(ctx, nwg, lanes):
+    """After a cooperative launch the dispatcher has been seen to start later launches one
+    XCD further on (workgroup w on XCD (w - 1) mod 8).  The per-XCD barrier registers
+    every workgroup under the XCD it actually runs on, so it keeps its fast path and its
+    exact results whatever the rotation."""
+    import paper_1110_4623_amd as sp
+    announce("grid_sync then xcd", f"nwg={nwg} lanes={lanes}")
+    g = sp.Barrier(ctx, "grid_sync", 256)
+    try:
+        g.run_hash(256, 10, 1)
+    finally:
+        g.close()
+    b = sp.Barrier(ctx, "xcd", nwg)
+    try:
+        for seed in (42, 7):
+            chk, _ = b.run_hash(lanes, 300, seed)
+            assert (chk == oracle.barrier_closed(seed, nwg, 300)).all()
+            info = b.info()
+            assert info["xcd_path"] and info["cu_overflow"] == 0, info
+    finally:
+        b.close()
+
+
+def test_xcd_barrier_info_fresh_placement(ctx):
+    import paper_1110_4623_amd as sp
+    b = sp.Barrier(ctx, "xcd", 512)
+    try:
+        chk, _ = b.run_hash(256, 100, 3)
+        assert (chk == oracle.barrier_closed(3, 512, 100)).all()
+        assert b.info()["xcd_path"]
+    finally:
+        b.close()
