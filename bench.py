@@ -87,9 +87,6 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--barrier", default="xcd")
-    ap.add_argument("--calibrate", action="store_true",
-                    help="only run a plain 1 GiB device-to-device copy three times (reference "
-                         "kernel of known size for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the primitives synchronize workgroups of a single "
@@ -103,15 +100,6 @@ def main() -> int:
     import sp_inputs
 
     ctx = sp.Context(0)
-    if args.calibrate:
-        nbytes = 1 << 30
-        src, dst = ctx.zeros(nbytes // 4), ctx.zeros(nbytes // 4)
-        st = sp.copy(ctx, dst, src, nbytes, reps=3)
-        print(json.dumps({"calibration": "k_copy", "bytes_read_per_launch": nbytes,
-                          "bytes_written_per_launch": nbytes, "launches": 3,
-                          "GB_per_s": round(2 * nbytes * 3 / (st["kernel_ms"] * 1e-3) / 1e9, 1)}),
-              flush=True)
-        return 0
     bar = sp.Barrier(ctx, args.barrier, NWG)
     mtx = sp.Mutex(ctx, "ticket", 1, 16)
     sem = sp.Semaphore(ctx, "sleep", SEM_K)

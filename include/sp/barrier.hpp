@@ -181,10 +181,11 @@ struct XcdLocal {
 };
 
 __device__ __forceinline__ void release_list(const BarrierState& s, const XcdLocal& L,
-                                             uint32_t stamp, uint32_t* rel) {
-  for (uint32_t i = threadIdx.x; i < L.ncu; i += blockDim.x) {
+                                             uint32_t ncu, uint32_t self, uint32_t stamp,
+                                             uint32_t* rel) {
+  for (uint32_t i = threadIdx.x; i < ncu; i += blockDim.x) {
     const uint32_t k = L.cu_list[i];
-    if (k != L.k) st_relaxed(rel + (size_t)k * s.stride, stamp);
+    if (k != self) st_relaxed(rel + (size_t)k * s.stride, stamp);
   }
 }
 
@@ -192,34 +193,40 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
                                          const XcdLocal& L) {
   __shared__ uint32_t s_ok;
   const uint32_t X = s.groups;
-  uint32_t* block = s.larrive + (size_t)L.x * s.xblock;
-  uint32_t* rel = s.lrelease + (size_t)L.x * s.xblock * s.stride;  // member k: rel + k*stride
+  // The registration is the same for the whole workgroup: keep it in scalar registers.
+  const uint32_t x = __builtin_amdgcn_readfirstlane(L.x);
+  const uint32_t k = __builtin_amdgcn_readfirstlane(L.k);
+  const uint32_t members = __builtin_amdgcn_readfirstlane(L.members);
+  const uint32_t xmask = __builtin_amdgcn_readfirstlane(L.xmask);
+  const uint32_t slot = __builtin_amdgcn_readfirstlane(L.slot);
+  uint32_t* block = s.larrive + (size_t)x * s.xblock;
+  uint32_t* rel = s.lrelease + (size_t)x * s.xblock * s.stride;  // member k: rel + k*stride
   Wait w(ctl, s.poll_sleep);
   int ok = 1;
   __syncthreads();
-  if (L.k == 0) {
+  if (k == 0) {
     // XCD master: gather the XCD's arrivals, write the XCD's L2 back once, publish.
-    ok = scan_flags(block, 1, L.members, 0, stamp, w);
+    ok = scan_flags(block, 1, members, 0, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
-    if (is_leader()) st_release(s.xarrive + (size_t)L.x * s.stride, stamp);
+    if (is_leader()) st_release(s.xarrive + (size_t)x * s.stride, stamp);
   } else if (is_leader()) {
-    st_relaxed(block + L.k, stamp);
+    st_relaxed(block + k, stamp);
   }
-  if (L.slot == 0) {
+  if (slot == 0) {
     // CU leader: once every populated XCD has published, invalidate for the CU and
     // release it.
-    if (threadIdx.x < X && ((L.xmask >> threadIdx.x) & 1))
+    if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
       ok = poll_until(s.xarrive + (size_t)threadIdx.x * s.stride, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
     if (is_leader()) fence_acquire();
     __syncthreads();
-    release_list(s, L, stamp, rel);
+    release_list(s, L, __builtin_amdgcn_readfirstlane(L.ncu), k, stamp, rel);
     return true;
   }
   if (is_leader()) {
-    ok = poll_until(rel + (size_t)L.k * s.stride, stamp, w);
+    ok = poll_until(rel + (size_t)k * s.stride, stamp, w);
     s_ok = ok;
   }
   __syncthreads();
