@@ -143,6 +143,14 @@ def main() -> int:
     def med(key, field):
         return round(float(np.median([r[key][field] for r in results])), 2)
 
+    traffic = measured_traffic(ROOT) if args.barrier == "xcd" else None
+    # the same kernel against the HBM roofline: measured bytes per launch over its time
+    hbm_view = None
+    if traffic is not None:
+        gbps = traffic / (bar_ms * 1e-3) / 1e9
+        hbm_view = {"bound": "hbm", "achieved": round(gbps, 2), "peak": 8000.0, "unit": "GB/s",
+                    "frac": round(gbps / 8000.0, 5)}
+
     line = {
         "metric": METRIC,
         "value": round(us_round, 4),
@@ -186,9 +194,10 @@ def main() -> int:
             "peak": round(a1 / 1e9, 6),
             "unit": "G arrivals/s vs contended atomics/s",
             "frac": round(arrivals / a1, 4),
-            "traffic": measured_traffic(ROOT) if args.barrier == "xcd" else None,
+            "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "peak_source": "measured in this run: contended agent-scope atomic adds to one word",
+            "hbm_view": hbm_view,
         },
     }
     if not args.no_cpu_baseline:

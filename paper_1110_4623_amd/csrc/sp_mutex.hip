@@ -32,7 +32,8 @@ __global__ SP_FULL_OCCUPANCY void k_mutex(sp::MutexState s, uint32_t nlocks, uin
   for (uint64_t j = 0; j < A; ++j) {
     const uint32_t lock = sp::sched_key(seed, b, (uint32_t)j, 1) % nlocks;
     if (sp::is_leader()) sp::spin_cycles(sp::sched_key(seed, b, (uint32_t)j, 2) % (max_delay + 1));
-    if (!sp::mutex_lock<KIND>(s, lock, ctl)) return;
+    sp::MutexHold hold;
+    if (!sp::mutex_lock<KIND>(s, lock, ctl, &hold)) return;
     uint32_t* own = owner ? owner + (size_t)lock * s.stride : nullptr;
     if (own && sp::is_leader() && sp::exch_relaxed(own, b + 1) != 0)
       sp::cas_relaxed(err, sp::DEV_OK, sp::DEV_PARITY);
@@ -40,7 +41,7 @@ __global__ SP_FULL_OCCUPANCY void k_mutex(sp::MutexState s, uint32_t nlocks, uin
     for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) wp[w] = wp[w] + 1;
     if (own && sp::is_leader() && sp::exch_relaxed(own, 0) != b + 1)
       sp::cas_relaxed(err, sp::DEV_OK, sp::DEV_PARITY);
-    sp::mutex_unlock<KIND>(s, lock);
+    sp::mutex_unlock<KIND>(s, lock, &hold);
   }
   if (sp::is_leader() && finish) finish[b] = sp::wall_clock();
 }

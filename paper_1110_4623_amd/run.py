@@ -6,21 +6,20 @@
   python -m paper_1110_4623_amd.run serve --rate 1e5 --n 200000
   python -m paper_1110_4623_amd.run copy --bytes 1073741824
 
-Meant for profilers (one workload per process) and quick checks.  Like bench.py it does
-not import PyTorch unless SP_NO_TORCH=0 is set, so the library runs on the system ROCm
-runtime.  `--repeat` runs the workload that many times.
+Meant for profilers (one workload per process) and quick checks.  The package decides
+at import whether to use PyTorch's HIP runtime: run with SP_NO_TORCH=1 in the environment
+(as bench.py does for itself) to use the system ROCm runtime instead.  `--repeat` runs
+the workload that many times.
 """
 
 from __future__ import annotations
 
 import argparse
 import json
-import os
 import sys
 
 
 def main(argv=None) -> int:
-    os.environ.setdefault("SP_NO_TORCH", "1")
     from . import api
 
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
