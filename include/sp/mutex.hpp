@@ -35,7 +35,10 @@ struct MutexHold {
 //   SP_MUTEX_SLEEP        poll the lock word with loads and s_sleep until it reads free,
 //                         then one compare-and-swap (waiting by polling, Section 5's GPU
 //                         sleeping)
-template <int KIND>
+// FENCED = false: the caller's critical sections touch the protected data only with
+// agent-scope (coherent) loads and stores, so the lock needs no acquire fence and the
+// unlock no release fence; the unlock still waits until the section's stores completed.
+template <int KIND, bool FENCED = true>
 __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
                            MutexHold* hold = nullptr) {
   __shared__ uint32_t s_ok;
@@ -69,7 +72,7 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
         if (!ok || cas_relaxed(m, 0, 1) == 0) break;
       }
     }
-    fence_acquire();
+    if constexpr (FENCED) fence_acquire();
     s_ok = ok;
   }
   __syncthreads();
@@ -78,18 +81,17 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
 
 // `hold`: the record mutex_lock filled in (leader's copy), or nullptr, in which case the
 // ticket mutex loads turn to find the value to publish.
-template <int KIND>
+template <int KIND, bool FENCED = true>
 __device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold* hold = nullptr) {
   wave_stores_complete();
   __syncthreads();
   if (is_leader()) {
-    if constexpr (KIND == SP_MUTEX_TICKET) {
-      uint32_t* turn = s.turn + (size_t)lock * s.stride;
-      const uint32_t served = hold ? hold->ticket : ld_relaxed(turn);  // only the holder writes turn
-      st_release(turn, served + 1);
-    } else {
-      st_release(s.lockw + (size_t)lock * s.stride, 0);
-    }
+    uint32_t* w = KIND == SP_MUTEX_TICKET ? s.turn + (size_t)lock * s.stride
+                                          : s.lockw + (size_t)lock * s.stride;
+    // ticket: only the holder writes turn, so it can publish its own ticket + 1
+    const uint32_t v = KIND != SP_MUTEX_TICKET ? 0u : (hold ? hold->ticket : ld_relaxed(w)) + 1;
+    if constexpr (FENCED) st_release(w, v);
+    else st_relaxed(w, v);
   }
 }
 

@@ -62,7 +62,8 @@ class Params(ctypes.Structure):
         ("timeout_ms", ctypes.c_uint32),
         ("verify", ctypes.c_uint32),
         ("cooperative", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 5),
+        ("coherent_cs", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 4),
     ]
 
 

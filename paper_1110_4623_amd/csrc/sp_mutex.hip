@@ -21,7 +21,7 @@ namespace {
 
 // With `owner` set, the leader swaps its id into the lock's owner word on entry and
 // back out on exit; any other value seen means two workgroups were inside at once.
-template <int KIND>
+template <int KIND, bool FENCED>
 __global__ SP_FULL_OCCUPANCY void k_mutex(sp::MutexState s, uint32_t nlocks, uint32_t W, uint32_t wstride,
                         uint32_t* words, uint32_t nwg, uint64_t total, uint32_t max_delay,
                         uint32_t seed, uint64_t* finish, uint32_t* owner, uint32_t* err,
@@ -33,15 +33,20 @@ __global__ SP_FULL_OCCUPANCY void k_mutex(sp::MutexState s, uint32_t nlocks, uin
     const uint32_t lock = sp::sched_key(seed, b, (uint32_t)j, 1) % nlocks;
     if (sp::is_leader()) sp::spin_cycles(sp::sched_key(seed, b, (uint32_t)j, 2) % (max_delay + 1));
     sp::MutexHold hold;
-    if (!sp::mutex_lock<KIND>(s, lock, ctl, &hold)) return;
+    if (!sp::mutex_lock<KIND, FENCED>(s, lock, ctl, &hold)) return;
     uint32_t* own = owner ? owner + (size_t)lock * s.stride : nullptr;
     if (own && sp::is_leader() && sp::exch_relaxed(own, b + 1) != 0)
       sp::cas_relaxed(err, sp::DEV_OK, sp::DEV_PARITY);
     uint32_t* wp = words + (size_t)lock * wstride;
-    for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) wp[w] = wp[w] + 1;
+    if constexpr (FENCED) {
+      for (uint32_t w = threadIdx.x; w < W; w += blockDim.x) wp[w] = wp[w] + 1;
+    } else {  // coherent critical section: agent-scope loads and stores
+      for (uint32_t w = threadIdx.x; w < W; w += blockDim.x)
+        sp::st_relaxed(wp + w, sp::ld_relaxed(wp + w) + 1);
+    }
     if (own && sp::is_leader() && sp::exch_relaxed(own, 0) != b + 1)
       sp::cas_relaxed(err, sp::DEV_OK, sp::DEV_PARITY);
-    sp::mutex_unlock<KIND>(s, lock, &hold);
+    sp::mutex_unlock<KIND, FENCED>(s, lock, &hold);
   }
   if (sp::is_leader() && finish) finish[b] = sp::wall_clock();
 }
@@ -54,15 +59,20 @@ __global__ void k_gather_words(const uint32_t* words, uint32_t nlocks, uint32_t 
     out[i] = words[(i / W) * wstride + i % W];
 }
 
-const void* mutex_kernel(uint32_t kind) {
+template <bool FENCED>
+const void* mutex_kernel_f(uint32_t kind) {
   switch (kind) {
-    case SP_MUTEX_SPIN_CAS: return (const void*)k_mutex<SP_MUTEX_SPIN_CAS>;
-    case SP_MUTEX_SPIN_EXCH: return (const void*)k_mutex<SP_MUTEX_SPIN_EXCH>;
-    case SP_MUTEX_SPIN_BACKOFF: return (const void*)k_mutex<SP_MUTEX_SPIN_BACKOFF>;
-    case SP_MUTEX_TICKET: return (const void*)k_mutex<SP_MUTEX_TICKET>;
-    case SP_MUTEX_SLEEP: return (const void*)k_mutex<SP_MUTEX_SLEEP>;
+    case SP_MUTEX_SPIN_CAS: return (const void*)k_mutex<SP_MUTEX_SPIN_CAS, FENCED>;
+    case SP_MUTEX_SPIN_EXCH: return (const void*)k_mutex<SP_MUTEX_SPIN_EXCH, FENCED>;
+    case SP_MUTEX_SPIN_BACKOFF: return (const void*)k_mutex<SP_MUTEX_SPIN_BACKOFF, FENCED>;
+    case SP_MUTEX_TICKET: return (const void*)k_mutex<SP_MUTEX_TICKET, FENCED>;
+    case SP_MUTEX_SLEEP: return (const void*)k_mutex<SP_MUTEX_SLEEP, FENCED>;
     default: return nullptr;
   }
+}
+
+const void* mutex_kernel(uint32_t kind, bool coherent_cs) {
+  return coherent_cs ? mutex_kernel_f<false>(kind) : mutex_kernel_f<true>(kind);
 }
 
 }  // namespace
@@ -128,10 +138,11 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
     const uint32_t t = q.timeout_ms;
     q = d.p;
     q.timeout_ms = t;
+    q.coherent_cs = m->p.coherent_cs;  // a property of the caller's critical sections
   }
   if (kind == SP_MUTEX_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) q.backoff = SP_BACKOFF_EXP;
   if (kind == SP_MUTEX_SPIN_CAS || kind == SP_MUTEX_SLEEP) q.backoff = SP_BACKOFF_NONE;
-  const void* kern = mutex_kernel(kind);
+  const void* kern = mutex_kernel(kind, q.coherent_cs != 0);
   if (!kern) return SP_E_INVAL;
   const uint32_t sw = spi::stride_words(q);
   uint32_t* base = m->d_state;

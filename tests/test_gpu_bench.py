@@ -89,3 +89,35 @@ def test_pingpong(ctx):
     announce("pingpong")
     out, st = sp.pingpong(ctx, 1000)
     assert out[0] == 2000 and out[1] == 1999
+
+
+@pytest.mark.parametrize("nwg", [1, 8, 2048])
+@pytest.mark.parametrize("mode", ["per_lane", "wave_leader"])
+@pytest.mark.parametrize("op", ["add", "cas", "exch", "ld", "st"])
+def test_config_grid_at_full_width(ctx, op, mode, nwg):
+    """The memory-system grid at its own workgroup counts (up to 2048 x 256 lanes): every
+    target count and two strides, every final word (and returned-value sum) against the
+    oracle's closed form, with a few operations per issuer.  Compare-and-swap with every
+    lane on 1 or 32 words is left out at 2048 workgroups: its retries grow with the square
+    of the contenders."""
+    import paper_1110_4623_amd as sp
+    lanes, seed = 256, 0xC0FFEE
+    n = 2 if mode == "per_lane" else 16
+    U = nwg * lanes if mode == "per_lane" else nwg * (lanes // 64)
+    buf = ctx.zeros((1 << 20) * 128 // 4)
+    for T in (1, 32, 1024, 1 << 20):
+        if op == "cas" and mode == "per_lane" and nwg == 2048 and T <= 32:
+            continue
+        perm_np = sp_inputs.permutation(T, seed)
+        perm = ctx.upload(perm_np)
+        ef, es = oracle.bench_closed(op, seed, U, n, perm_np)
+        for stride in (4, 128):
+            announce("bench grid", op, mode, f"nwg={nwg} T={T} stride={stride} n={n}")
+            finals, s, _ = sp.bench_atomic(ctx, op, nwg, lanes, T, stride, mode, n, seed, perm,
+                                           buf)
+            if op == "exch":
+                assert s == es  # conservation: returned + final = initial + written
+            else:
+                assert (finals == ef).all(), (T, stride)
+                if op != "st":
+                    assert s == es

@@ -81,3 +81,25 @@ def test_watchdog_timeout_path(ctx):
     m.close()
     words, _, _ = _run(ctx, "ticket", 64, 64, 1000, 1, 1, 0, 1)
     assert (words == 1000).all()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("L,W", [(1, 16), (16, 16), (256, 1)])
+def test_coherent_critical_sections(ctx, kind, L, W):
+    """coherent_cs: critical sections with agent-scope accesses and no fences around them
+    give the same exact counts (owner word checked on every entry)."""
+    total, seed = 1 << 13, 42
+    nwg = 64 if kind.startswith("spin") else 256
+    words, st, _ = _run(ctx, kind, nwg, 256, total, L, W, 200, seed, coherent_cs=1, verify=1)
+    assert st["device_error"] == 0
+    assert (words == oracle.mutex_closed(seed, nwg, total, L, W)).all()
+
+
+def test_coherent_critical_sections_full_size_ticket(ctx):
+    total, seed, nwg = 1 << 20, 7, 2048
+    fenced, st_f, _ = _run(ctx, "ticket", nwg, 256, total, 1, 16, 1000, seed)
+    coh, st_c, _ = _run(ctx, "ticket", nwg, 256, total, 1, 16, 1000, seed, coherent_cs=1)
+    expect = oracle.mutex_closed(seed, nwg, total, 1, 16)
+    assert (fenced == expect).all() and (coh == expect).all()
+    print(f"[mutex] ticket 2048 WG one lock: fenced {total / st_f['kernel_ms'] * 1e3:.3e} acq/s, "
+          f"coherent {total / st_c['kernel_ms'] * 1e3:.3e} acq/s", flush=True)
