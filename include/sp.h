@@ -67,6 +67,10 @@ enum sp_sem_kind {
   SP_SEM_SPIN_BACKOFF = 1, /* Algorithm 4 with backoff                                  */
   SP_SEM_TICKET = 2,       /* fetch-and-add semaphore, plain polling (Algorithm 5)      */
   SP_SEM_SLEEP = 3,        /* Algorithm 5, queued waiters s_sleep between polls         */
+  SP_SEM_COUNTERS = 4,     /* two monotone counters: wait draws a ticket t (fetch-and-  */
+                           /* add) and enters once posts + K > t; post adds one to the  */
+                           /* posts; FIFO like Algorithm 5, one atomic per operation,   */
+                           /* s_sleep between polls                                     */
   SP_SEM_DEFAULT = 15
 };
 
@@ -258,7 +262,8 @@ int sp_sem_destroy(sp_sem* s);
  * maximum, counts the admission, XORs sm32(seed ^ (w << 16) ^ j) into the workgroup's
  * checksum, holds key(w, j, 3) mod (max_hold_cyc + 1) shader clocks and decrements the
  * occupancy.  out_chk: device, nwg uint32.  out_state: device, 8 uint32 =
- * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, 0, 0, 0}.
+ * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, 0, 0, 0}
+ * (SP_SEM_COUNTERS: count stays 0, ticket = tickets drawn, turn = posts made).
  * Errors: SP_E_INVAL, SP_E_TIMEOUT, SP_E_HIP.                                           */
 int sp_sem_run(sp_sem* s, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
                uint32_t max_hold_cyc, uint32_t seed, uint32_t track, uint32_t* out_chk,

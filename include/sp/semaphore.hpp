@@ -11,14 +11,18 @@ struct SemState {
   uint32_t poll_sleep;  // SP_SEM_SLEEP: s_sleep units between polls
   uint32_t* S;          // Algorithm 4: S = K + 1 at rest, 0 while being updated
   uint32_t* count;      // Algorithm 5: workgroups inside or queued
-  uint32_t* ticket;     // Algorithm 5: next queue ticket
-  uint32_t* turn;       // Algorithm 5: number of queued workgroups admitted
+  uint32_t* ticket;     // Algorithm 5: next queue ticket; counters: tickets drawn
+  uint32_t* turn;       // Algorithm 5: number of queued workgroups admitted; counters:
+                        // posts made
   BackoffCfg bo;        // SP_SEM_SPIN_BACKOFF
 };
 
 // KIND: SP_SEM_SPIN / SP_SEM_SPIN_BACKOFF (Algorithm 4), SP_SEM_TICKET / SP_SEM_SLEEP
 // (Algorithm 5, the queued waiter proceeds once turn is strictly greater than the
-// 0-based ticket it drew).
+// 0-based ticket it drew), SP_SEM_COUNTERS (every waiter draws ticket t from one monotone
+// counter and enters once the posts counter plus K exceeds t: the unit case of the
+// weighted semaphore below, with Algorithm 5's FIFO order but one atomic per wait and
+// one per post instead of Algorithm 5's two dependent ones on a queued post).
 template <int KIND>
 __device__ bool sem_wait(const SemState& s, const Ctl& ctl) {
   __shared__ uint32_t s_ok;
@@ -36,6 +40,14 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl) {
         if (v == 1) exch_relaxed(s.S, 1);  // at capacity: put the value back
         if constexpr (KIND == SP_SEM_SPIN_BACKOFF) bo(s.bo);
         if (!(ok = w.tick())) break;
+      }
+    } else if constexpr (KIND == SP_SEM_COUNTERS) {
+      Wait w(ctl, s.poll_sleep);
+      const uint32_t t = add_relaxed(s.ticket, 1);
+      uint32_t posts = ld_relaxed(s.turn);  // in flight with the ticket; a lower bound
+      while (!((int32_t)(posts + s.K - t) > 0)) {
+        if (!(ok = w.tick())) break;
+        posts = ld_relaxed(s.turn);
       }
     } else {
       Wait w(ctl, KIND == SP_SEM_SLEEP ? s.poll_sleep : 0);
@@ -73,6 +85,8 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl) {
         if constexpr (KIND == SP_SEM_SPIN_BACKOFF) bo(s.bo);
         if (!(ok = w.tick())) break;
       }
+    } else if constexpr (KIND == SP_SEM_COUNTERS) {
+      add_relaxed(s.turn, 1);
     } else {
       const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);  // count -= 1
       if (old > s.K) add_relaxed(s.turn, 1);                   // admit one queued waiter

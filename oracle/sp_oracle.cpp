@@ -426,13 +426,15 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 // Initial value K.  Algorithm 4 keeps S = K + 1 (zero means "held"); Algorithm 5 keeps
 // count, ticket and turn starting at 0, and a queued waiter proceeds once turn is
 // strictly greater than the ticket it drew (0-based).
+// kind: 0 Algorithm 4, 1 Algorithm 4 with backoff, 2 Algorithm 5, 3 Algorithm 5 with
+// yielding polls, 4 two monotone counters (ticket t enters once posts + K > t).
 // Each pair: wait, occupancy tracking, checksum update, admission count, post.
 // out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}.
 // Returns 0, -2 if occupancy ever exceeded K.
 int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t total,
                     uint32_t imin, uint32_t imax, uint32_t* chk, uint32_t* maxocc,
                     uint32_t* state, double* seconds) {
-  if (nwg == 0 || K == 0 || kind < 0 || kind > 3) return -1;
+  if (nwg == 0 || K == 0 || kind < 0 || kind > 4) return -1;
   Word S{K + 1}, count{0}, ticket{0}, turn{0}, occ{0}, maxo{0}, adm{0};
   const bool alg4 = kind <= 1, backoff = kind == 1;
 
@@ -448,6 +450,10 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
         if (v == 1) S.exchange(1, std::memory_order_release);
         if (backoff) bo(); else relax();
       }
+    } else if (kind == 4) {
+      // two monotone counters: ticket t enters once posts + K > t
+      const uint32_t t = ticket.fetch_add(1, std::memory_order_acq_rel);
+      while (!((int32_t)(turn.load(std::memory_order_acquire) + K - t) > 0)) relax();
     } else {
       uint32_t old = count.fetch_add(1, std::memory_order_acq_rel);
       if (old < K) return;
@@ -466,6 +472,8 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
         }
         if (backoff) bo(); else relax();
       }
+    } else if (kind == 4) {
+      turn.fetch_add(1, std::memory_order_acq_rel);
     } else {
       uint32_t old = count.fetch_sub(1, std::memory_order_acq_rel);
       if (old > K) turn.fetch_add(1, std::memory_order_acq_rel);

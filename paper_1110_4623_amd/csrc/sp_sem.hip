@@ -65,6 +65,7 @@ const void* sem_kernel(uint32_t kind) {
     case SP_SEM_SPIN_BACKOFF: return (const void*)k_sem<SP_SEM_SPIN_BACKOFF>;
     case SP_SEM_TICKET: return (const void*)k_sem<SP_SEM_TICKET>;
     case SP_SEM_SLEEP: return (const void*)k_sem<SP_SEM_SLEEP>;
+    case SP_SEM_COUNTERS: return (const void*)k_sem<SP_SEM_COUNTERS>;
     default: return nullptr;
   }
 }
@@ -75,7 +76,7 @@ extern "C" {
 
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out) {
   if (!ctx || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
-  if (kind > SP_SEM_SLEEP && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_SEM_COUNTERS && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));

@@ -131,6 +131,7 @@ def semaphore_candidates():
             out.append(("spin_backoff", {"backoff": policy, "backoff_min": 1, "backoff_max": imax}))
     out += [("ticket", {"poll_sleep": 0})]
     out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
+    out += [("counters", {"poll_sleep": ps}) for ps in (0, 1, 4)]
     return out
 
 

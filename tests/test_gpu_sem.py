@@ -9,7 +9,7 @@ from conftest import announce
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["spin", "spin_backoff", "ticket", "sleep"]
+KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters"]
 
 
 def _run(ctx, kind, K, nwg, lanes, total, hold, seed, **params):
@@ -30,6 +30,8 @@ def _check(r, kind, K, nwg, total, seed):
     assert r["occ"] == 0
     if kind.startswith("spin"):
         assert s_or_count == K + 1
+    elif kind == "counters":
+        assert s_or_count == 0 and ticket == turn == total
     else:
         assert s_or_count == 0 and ticket == turn
         if K >= nwg:
@@ -44,7 +46,7 @@ def test_small(ctx, kind, K):
     _check(r, kind, K, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters"])
 @pytest.mark.parametrize("K", [1, 4, 32, 256])
 def test_full_size(ctx, kind, K):
     # 2048 workgroups, 2^20 wait/post pairs, holds uniform in [0, 2000] cycles
@@ -74,7 +76,7 @@ def test_spin_as_mutex(ctx, kind):
     _check(r, kind, 1, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters"])
 def test_capacity_above_agents_never_queues(ctx, kind):
     r = _run(ctx, kind, 64, 16, 64, 4000, 50, 7)
     _check(r, kind, 64, 16, 4000, 7)

@@ -46,4 +46,4 @@ def test_candidate_lists_cover_every_kind():
     assert {k for k, _ in tune.mutex_candidates()} == {"spin_cas", "spin_exch", "spin_backoff",
                                                         "ticket", "sleep"}
     assert {k for k, _ in tune.semaphore_candidates()} == {"spin", "spin_backoff", "ticket",
-                                                            "sleep"}
+                                                            "sleep", "counters"}
