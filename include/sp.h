@@ -58,6 +58,11 @@ enum sp_mutex_kind {
   SP_MUTEX_SPIN_BACKOFF = 2, /* compare-and-swap spin lock, backoff after each failure */
   SP_MUTEX_TICKET = 3,       /* fetch-and-add ticket mutex (Algorithm 3)               */
   SP_MUTEX_SLEEP = 4,        /* poll with loads + s_sleep, then one compare-and-swap   */
+  SP_MUTEX_RING = 5,         /* Section 5's ring-buffer mutex: write one's id at the    */
+                             /* ring's tail, poll until the head's entry is one's own;  */
+                             /* unlock advances the head                                */
+  SP_MUTEX_ARRAY = 6,        /* array queue lock: draw ticket t, poll only slot t mod Q */
+                             /* (its own line) until it holds t; unlock grants the next */
   SP_MUTEX_DEFAULT = 15
 };
 

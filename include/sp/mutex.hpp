@@ -13,7 +13,10 @@ struct MutexState {
   uint32_t poll_sleep;  // SP_MUTEX_SLEEP: s_sleep units between polls
   uint32_t* lockw;      // lock words (0 free, 1 held), one line per lock
   uint32_t* ticket;     // ticket mutex: next ticket, one line per lock
-  uint32_t* turn;       // ticket mutex: ticket being served, one line per lock
+  uint32_t* turn;       // ticket mutex: ticket being served; ring: head; one line per lock
+  uint32_t* queue;      // ring / array: qlen slots per lock, qstride words apart
+  uint32_t qlen;        // slots per lock (power of two; the ring needs >= contenders)
+  uint32_t qstride;     // words between slots
   BackoffCfg bo;        // backoff between failed attempts
 };
 
@@ -35,6 +38,14 @@ struct MutexHold {
 //   SP_MUTEX_SLEEP        poll the lock word with loads and s_sleep until it reads free,
 //                         then one compare-and-swap (waiting by polling, Section 5's GPU
 //                         sleeping)
+//   SP_MUTEX_RING         Section 5's ring-buffer mutex: draw ticket t, write the arrival's
+//                         id (t + 1) into slot t of the ring, then poll the head and the
+//                         slot it points at until that slot holds one's own id; unlock
+//                         advances the head.  Two reads per poll.
+//   SP_MUTEX_ARRAY        array queue lock: draw ticket t and poll only slot t (its own
+//                         line) until it holds t; unlock writes t + 1 into slot t + 1.  A
+//                         grant is overwritten only after its owner entered and left, so
+//                         any number of slots is correct; more slots spread the polling.
 // FENCED = false: the caller's critical sections touch the protected data only with
 // agent-scope (coherent) loads and stores, so the lock needs no acquire fence and the
 // unlock no release fence; the unlock still waits until the section's stores completed.
@@ -44,7 +55,8 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
   __shared__ uint32_t s_ok;
   if (is_leader()) {
     uint32_t* m = s.lockw + (size_t)lock * s.stride;
-    Wait w(ctl, KIND == SP_MUTEX_SLEEP ? s.poll_sleep : 0);
+    Wait w(ctl, (KIND == SP_MUTEX_SLEEP || KIND == SP_MUTEX_RING || KIND == SP_MUTEX_ARRAY)
+                    ? s.poll_sleep : 0);
     Backoff bo(s.bo);
     bool ok = true;
     if constexpr (KIND == SP_MUTEX_SPIN_CAS || KIND == SP_MUTEX_SPIN_BACKOFF) {
@@ -65,6 +77,25 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
         if (!(ok = w.tick())) break;
       }
       if (hold) hold->ticket = my;
+    } else if constexpr (KIND == SP_MUTEX_RING) {
+      const uint32_t t = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
+      uint32_t* q = s.queue + (size_t)lock * s.qlen * s.qstride;
+      const uint32_t mask = s.qlen - 1;
+      st_relaxed(q + (size_t)(t & mask) * s.qstride, t + 1);
+      const uint32_t* head = s.turn + (size_t)lock * s.stride;
+      for (;;) {
+        const uint32_t h = ld_relaxed(head);
+        if (ld_relaxed(q + (size_t)(h & mask) * s.qstride) == t + 1) break;
+        if (!(ok = w.tick())) break;
+      }
+      if (hold) hold->ticket = t;
+    } else if constexpr (KIND == SP_MUTEX_ARRAY) {
+      const uint32_t t = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
+      const uint32_t* slot =
+          s.queue + ((size_t)lock * s.qlen + (t & (s.qlen - 1))) * s.qstride;
+      while (ld_relaxed(slot) != t)
+        if (!(ok = w.tick())) break;
+      if (hold) hold->ticket = t;
     } else {
       for (;;) {
         while (ld_relaxed(m) != 0)
@@ -79,17 +110,28 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
   return s_ok;
 }
 
-// `hold`: the record mutex_lock filled in (leader's copy), or nullptr, in which case the
-// ticket mutex loads turn to find the value to publish.
+// `hold`: the record mutex_lock filled in (leader's copy).  It may be nullptr except for
+// SP_MUTEX_ARRAY: the ticket and ring mutexes then load turn / head to find the value to
+// publish.
 template <int KIND, bool FENCED = true>
 __device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold* hold = nullptr) {
   wave_stores_complete();
   __syncthreads();
   if (is_leader()) {
-    uint32_t* w = KIND == SP_MUTEX_TICKET ? s.turn + (size_t)lock * s.stride
-                                          : s.lockw + (size_t)lock * s.stride;
-    // ticket: only the holder writes turn, so it can publish its own ticket + 1
-    const uint32_t v = KIND != SP_MUTEX_TICKET ? 0u : (hold ? hold->ticket : ld_relaxed(w)) + 1;
+    uint32_t* w;
+    uint32_t v;
+    if constexpr (KIND == SP_MUTEX_TICKET || KIND == SP_MUTEX_RING) {
+      // only the holder writes turn / head, so it can publish its own ticket + 1
+      w = s.turn + (size_t)lock * s.stride;
+      v = (hold ? hold->ticket : ld_relaxed(w)) + 1;
+    } else if constexpr (KIND == SP_MUTEX_ARRAY) {
+      // the holder's ticket is needed: nothing else records it
+      v = hold->ticket + 1;
+      w = s.queue + ((size_t)lock * s.qlen + (v & (s.qlen - 1))) * s.qstride;
+    } else {
+      w = s.lockw + (size_t)lock * s.stride;
+      v = 0;
+    }
     if constexpr (FENCED) st_release(w, v);
     else st_relaxed(w, v);
   }

@@ -202,6 +202,88 @@ class MutexModel:
         return None
 
 
+class QueueLockModel:
+    """Queue mutexes over a ring of Q slots; tail draws tickets, FIFO by construction.
+    kind: 'ring'  -- Section 5's ring-buffer mutex: an arriving agent draws ticket t,
+                     writes its id (t + 1) into slot t mod Q, then polls head and the
+                     slot head points at until that slot holds its id; unlock stores
+                     head = t + 1;
+          'array' -- every agent polls only its own slot t mod Q until it holds t;
+                     unlock grants slot (t + 1) mod Q the value t + 1.
+    mutant: 'small_ring' -- Q = n - 1, fewer slots than contenders (the ring needs one
+                            slot per contender: an id can be overwritten before its
+                            owner reaches the head);
+            'skip_write' -- ring without writing one's own id;
+            'grant_self' -- array unlock writes t + 1 into its own slot t mod Q."""
+
+    ACQ, WRITE, POLL_H, POLL_R, POLL, CS_IN, CS_LD, CS_ST, CS_OUT, REL, DONE = range(11)
+
+    def __init__(self, kind: str, n: int = 3, ops: int = 2, Q: int | None = None,
+                 mutant: str | None = None):
+        self.kind, self.n, self.ops, self.mutant = kind, n, ops, mutant
+        self.Q = (n - 1 if mutant == "small_ring" else n) if Q is None else Q
+
+    def init(self):
+        # shared = (tail, head, slots, data, inside, entries); local = (pc, j, tmp, t)
+        return (0, 0, (0,) * self.Q, 0, 0, 0), tuple((self.ACQ, 0, 0, 0) for _ in range(self.n))
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    def _slot(self, slots, i, v):
+        return slots[:i] + (v,) + slots[i + 1:]
+
+    def step(self, a, sh, lo):
+        tail, head, slots, data, inside, entries = sh
+        pc, j, tmp, t = lo
+        Q = self.Q
+        if pc == self.ACQ:
+            sh = (tail + 1, head, slots, data, inside, entries)
+            return sh, ((self.WRITE if self.kind == "ring" else self.POLL), j, tmp, tail)
+        if pc == self.WRITE:
+            if self.mutant != "skip_write":
+                slots = self._slot(slots, t % Q, t + 1)
+            return (tail, head, slots, data, inside, entries), (self.POLL_H, j, tmp, t)
+        if pc == self.POLL_H:
+            return sh, (self.POLL_R, j, head, t)
+        if pc == self.POLL_R:
+            return sh, ((self.CS_IN if slots[tmp % Q] == t + 1 else self.POLL_H), j, tmp, t)
+        if pc == self.POLL:
+            return sh, ((self.CS_IN if slots[t % Q] == t else self.POLL), j, tmp, t)
+        if pc == self.CS_IN:
+            return (tail, head, slots, data, inside + 1, entries), (self.CS_LD, j, tmp, t)
+        if pc == self.CS_LD:
+            return sh, (self.CS_ST, j, data, t)
+        if pc == self.CS_ST:
+            return (tail, head, slots, tmp + 1, inside, entries), (self.CS_OUT, j, tmp, t)
+        if pc == self.CS_OUT:
+            return (tail, head, slots, data, inside - 1, entries + 1), (self.REL, j, tmp, t)
+        if pc == self.REL:
+            nxt = self.ACQ if j + 1 < self.ops else self.DONE
+            if self.kind == "ring":
+                return (tail, t + 1, slots, data, inside, entries), (nxt, j + 1, tmp, t)
+            at = t % Q if self.mutant == "grant_self" else (t + 1) % Q
+            slots = self._slot(slots, at, t + 1)
+            return (tail, head, slots, data, inside, entries), (nxt, j + 1, tmp, t)
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        if sh[4] > 1:
+            return f"mutual exclusion violated: {sh[4]} inside"
+        for pc, j, tmp, t in los:
+            if pc == self.CS_LD and t != sh[5]:
+                return f"queue order violated: ticket {t} entered after {sh[5]} entries"
+        return None
+
+    def final_check(self, sh, los):
+        total = self.n * self.ops
+        if sh[3] != total or sh[0] != total:
+            return f"final data {sh[3]} tail {sh[0]} != {total}"
+        if self.kind == "ring" and sh[1] != total:
+            return f"final head {sh[1]} != {total}"
+        return None
+
+
 # ------------------------------------------------------------------------------------
 # Semaphores with initial value K.  Each agent performs `ops` wait/post pairs with an
 # occupancy counter incremented on entry and decremented on exit.

@@ -345,41 +345,65 @@ int or_barrier_threaded(int kind, uint32_t seed, uint32_t N, uint32_t R, uint32_
 // Mutex kinds: 0 spin lock by compare-and-swap, 1 spin lock by exchange (Algorithm 1),
 // 2 spin lock with the Section 5 backoff (Algorithm 2), 3 fetch-and-add ticket mutex
 // with backoff while polling (Algorithm 3), 4 polling mutex: wait with plain loads until
-// the word reads free, then one compare-and-swap.
+// the word reads free, then one compare-and-swap, 5 ring-buffer mutex (Section 5's design
+// alternative: enqueue one's id, wait until the head's entry is one's own), 6 array queue
+// lock (wait on one's own slot, unlock grants the next).
 // Workload: see or_mutex_closed.  An owner word checks mutual exclusion inside every
 // critical section.  Returns 0, or -2 on a mutual-exclusion violation.
 int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uint32_t L,
                       uint32_t W, uint32_t imin, uint32_t imax, uint32_t* words,
                       double* seconds) {
-  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 4) return -1;
+  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 6) return -1;
   std::vector<Word> lockw(L), ticket(L), turn(L), owner(L);
   for (uint32_t l = 0; l < L; ++l) lockw[l] = 0, ticket[l] = 0, turn[l] = 0, owner[l] = 0;
+  // kinds 5 (ring) and 6 (array): Q slots per lock, Q a power of two >= agents
+  uint32_t Q = 1;
+  while (Q < nwg) Q <<= 1;
+  std::vector<Word> slots(kind >= 5 ? (size_t)L * Q : 0);
+  for (auto& w : slots) w.store(0);
   std::vector<Word> cs((size_t)L * W);
   for (auto& w : cs) w.store(0);
   std::atomic<int> bad{0};
 
-  auto lock = [&](uint32_t l, Backoff& bo) {
+  // returns the ticket the lock was taken with (ticket, ring and array kinds)
+  auto lock = [&](uint32_t l, Backoff& bo) -> uint32_t {
     switch (kind) {
       case 0:
         for (;;) {
           uint32_t e = 0;
           if (lockw[l].compare_exchange_strong(e, 1, std::memory_order_acquire,
                                                std::memory_order_relaxed))
-            return;
+            return 0;
           relax();
         }
       case 1:
         while (lockw[l].exchange(1, std::memory_order_acquire) != 0) relax();
-        return;
+        return 0;
       case 2:
         bo.i = bo.imin;
         while (lockw[l].exchange(1, std::memory_order_acquire) != 0) bo();
-        return;
+        return 0;
       case 3: {
         uint32_t my = ticket[l].fetch_add(1, std::memory_order_relaxed);
         bo.i = bo.imin;
         while (turn[l].load(std::memory_order_acquire) != my) bo();
-        return;
+        return my;
+      }
+      case 5: {  // ring: enqueue one's id, wait until the head's entry is one's own
+        uint32_t my = ticket[l].fetch_add(1, std::memory_order_relaxed);
+        Word* ring = &slots[(size_t)l * Q];
+        ring[my & (Q - 1)].store(my + 1, std::memory_order_relaxed);
+        for (;;) {
+          uint32_t h = turn[l].load(std::memory_order_acquire);
+          if (ring[h & (Q - 1)].load(std::memory_order_acquire) == my + 1) return my;
+          relax();
+        }
+      }
+      case 6: {  // array: wait on one's own slot
+        uint32_t my = ticket[l].fetch_add(1, std::memory_order_relaxed);
+        Word& slot = slots[(size_t)l * Q + (my & (Q - 1))];
+        while (slot.load(std::memory_order_acquire) != my) relax();
+        return my;
       }
       default:
         for (;;) {
@@ -387,14 +411,18 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
           uint32_t e = 0;
           if (lockw[l].compare_exchange_strong(e, 1, std::memory_order_acquire,
                                                std::memory_order_relaxed))
-            return;
+            return 0;
         }
     }
   };
-  auto unlock = [&](uint32_t l) {
+  auto unlock = [&](uint32_t l, uint32_t my) {
     if (kind == 3) {
       uint32_t t = turn[l].load(std::memory_order_relaxed);  // only the holder writes turn
       turn[l].store(t + 1, std::memory_order_release);
+    } else if (kind == 5) {
+      turn[l].store(my + 1, std::memory_order_release);  // advance the ring's head
+    } else if (kind == 6) {
+      slots[(size_t)l * Q + ((my + 1) & (Q - 1))].store(my + 1, std::memory_order_release);
     } else {
       lockw[l].store(0, std::memory_order_release);
     }
@@ -405,14 +433,14 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
     uint64_t A = or_ops_for_agent(nwg, total, b);
     for (uint64_t j = 0; j < A; ++j) {
       uint32_t l = or_key(seed, b, (uint32_t)j, 1) % L;
-      lock(l, bo);
+      const uint32_t my = lock(l, bo);
       if (owner[l].exchange(b + 1, std::memory_order_relaxed) != 0) bad.store(1);
       for (uint32_t w = 0; w < W; ++w) {
         Word& x = cs[(size_t)l * W + w];
         x.store(x.load(std::memory_order_relaxed) + 1, std::memory_order_relaxed);
       }
       if (owner[l].exchange(0, std::memory_order_relaxed) != b + 1) bad.store(1);
-      unlock(l);
+      unlock(l, my);
     }
   });
   for (size_t i = 0; i < cs.size(); ++i) words[i] = cs[i].load();

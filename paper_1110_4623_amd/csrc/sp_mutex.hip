@@ -15,6 +15,8 @@ struct sp_mutex {
   uint32_t* d_state = nullptr;  // lock, ticket and turn lines + one private line
   uint64_t state_words = 0;
   uint32_t* d_words = nullptr;  // critical-section words, nlocks x wstride
+  uint32_t* d_queue = nullptr;  // ring / array mutexes: slots, sized per run
+  uint64_t queue_words = 0;
 };
 
 namespace {
@@ -67,6 +69,8 @@ const void* mutex_kernel_f(uint32_t kind) {
     case SP_MUTEX_SPIN_BACKOFF: return (const void*)k_mutex<SP_MUTEX_SPIN_BACKOFF, FENCED>;
     case SP_MUTEX_TICKET: return (const void*)k_mutex<SP_MUTEX_TICKET, FENCED>;
     case SP_MUTEX_SLEEP: return (const void*)k_mutex<SP_MUTEX_SLEEP, FENCED>;
+    case SP_MUTEX_RING: return (const void*)k_mutex<SP_MUTEX_RING, FENCED>;
+    case SP_MUTEX_ARRAY: return (const void*)k_mutex<SP_MUTEX_ARRAY, FENCED>;
     default: return nullptr;
   }
 }
@@ -84,7 +88,7 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
   if (!ctx || !out || nlocks == 0 || words_per_lock == 0 || nlocks > (1u << 20) ||
       words_per_lock > (1u << 16))
     return SP_E_INVAL;
-  if (kind > SP_MUTEX_SLEEP && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_MUTEX_ARRAY && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -118,6 +122,7 @@ int sp_mutex_destroy(sp_mutex* m) {
   hipSetDevice(m->ctx->device);
   hipFree(m->d_state);
   hipFree(m->d_words);
+  if (m->d_queue) hipFree(m->d_queue);
   delete m;
   return SP_OK;
 }
@@ -154,6 +159,30 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
   ms.turn = base + 2ull * m->nlocks * sw;
   ms.bo = spi::backoff_cfg(q, base + 4ull * m->nlocks * sw);
   uint32_t* owner = q.verify ? base + 3ull * m->nlocks * sw : nullptr;
+  ms.queue = nullptr;
+  ms.qlen = 1;
+  ms.qstride = 1;
+  if (kind == SP_MUTEX_RING || kind == SP_MUTEX_ARRAY) {
+    // The ring needs a slot per contender (each workgroup has at most one arrival
+    // outstanding); the array lock is correct with any number and polls one line each.
+    uint32_t Q = 64;
+    while (Q < nwg) Q <<= 1;
+    ms.qlen = Q;
+    ms.qstride = kind == SP_MUTEX_RING ? 1 : sw;  // ring entries packed, array slots padded
+    const uint64_t words = (uint64_t)m->nlocks * Q * ms.qstride;
+    if (words > (1ull << 28)) return SP_E_INVAL;  // 1 GiB of slots at most
+    if (words > m->queue_words) {
+      if (spi::capturing(s)) return SP_E_INVAL;  // no allocation while recording
+      SP_HIP(ctx, hipStreamSynchronize(s));
+      if (m->d_queue) SP_HIP(ctx, hipFree(m->d_queue));
+      m->d_queue = nullptr;
+      m->queue_words = 0;
+      SP_HIP(ctx, hipMalloc(&m->d_queue, words * sizeof(uint32_t)));
+      m->queue_words = words;
+    }
+    ms.queue = m->d_queue;
+    SP_CHECK(spi::fill_u32(ctx, m->d_queue, words, 0, s));
+  }
   SP_CHECK(spi::fill_u32(ctx, m->d_state, m->state_words, 0, s));
   SP_CHECK(spi::fill_u32(ctx, m->d_words, (uint64_t)m->nlocks * m->wstride, 0, s));
   int per_cu = 0;

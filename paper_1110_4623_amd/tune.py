@@ -95,6 +95,8 @@ def mutex_candidates():
             out.append(("spin_backoff", {"backoff": policy, "backoff_min": 1, "backoff_max": imax}))
     out += [("ticket", {"poll_sleep": ps}) for ps in (0, 1, 4)]
     out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
+    out += [("array", {"poll_sleep": ps}) for ps in (0, 1, 4)]
+    out += [("ring", {"poll_sleep": 0})]
     return out
 
 

@@ -9,7 +9,7 @@ from conftest import announce
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep"]
+KINDS = ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep", "ring", "array"]
 
 
 def _run(ctx, kind, nwg, lanes, total, L, W, delay, seed, **params):
@@ -43,16 +43,16 @@ def test_workgroup_counts(ctx, kind, nwg):
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_full_size_single_lock(ctx, kind):
-    # 2048 workgroups x 256 lanes contend for one lock with 16 words.  The ticket lock
-    # runs all 2^20 acquisitions; the spin and polling locks hand the lock over far more
-    # slowly with 2048 contenders (every waiter hammers the lock word), so they run 2^14
-    # acquisitions at the same contention.
-    total = 1 << 20 if kind == "ticket" else 1 << 14
+    # 2048 workgroups x 256 lanes contend for one lock with 16 words.  The queue locks
+    # (ticket, ring, array) run all 2^20 acquisitions; the spin and polling locks hand the
+    # lock over far more slowly with 2048 contenders (every waiter hammers the lock word),
+    # so they run 2^14 acquisitions at the same contention.
+    total = 1 << 20 if kind in ("ticket", "ring", "array") else 1 << 14
     words, st, fin = _run(ctx, kind, 2048, 256, total, 1, 16, 1000, 0xC0FFEE)
     assert (words == total).all()
 
 
-@pytest.mark.parametrize("kind", ["spin_backoff", "ticket"])
+@pytest.mark.parametrize("kind", ["spin_backoff", "ticket", "array", "ring"])
 @pytest.mark.parametrize("L,W", [(16, 256), (256, 16)])
 def test_full_size_many_locks(ctx, kind, L, W):
     total, seed = 1 << 20, 42

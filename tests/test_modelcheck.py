@@ -3,7 +3,7 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 
 import pytest
 
-from oracle.modelcheck import (BarrierModel, FASemModel, MutexModel, SpinSemModel,
+from oracle.modelcheck import (BarrierModel, FASemModel, MutexModel, QueueLockModel, SpinSemModel,
                                WeightedSemModel, explore)
 
 
@@ -108,4 +108,36 @@ def test_catches_strict_admission_deadlock():
 
 def test_catches_partial_return():
     r = explore(WeightedSemModel(3, (2, 2), 2, mutant="post_one"))
+    assert not r.ok
+
+
+# ---- queue mutexes -----------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["ring", "array"])
+@pytest.mark.parametrize("n,ops", [(2, 2), (3, 2), (3, 3)])
+def test_queue_locks_correct(kind, n, ops):
+    r = explore(QueueLockModel(kind, n, ops))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("Q", [1, 2])
+def test_array_lock_needs_no_slot_per_contender(Q):
+    # a grant is overwritten only after its owner entered and left, so any Q works; Q
+    # only spreads the polling over lines
+    r = explore(QueueLockModel("array", 3, 2, Q=Q))
+    assert r.ok, r.violation
+
+
+def test_catches_ring_smaller_than_contenders():
+    r = explore(QueueLockModel("ring", 3, 2, mutant="small_ring"))
+    assert not r.ok
+
+
+def test_catches_ring_without_own_id():
+    r = explore(QueueLockModel("ring", 2, 1, mutant="skip_write"))
+    assert r.deadlock
+
+
+def test_catches_array_granting_itself():
+    r = explore(QueueLockModel("array", 2, 2, mutant="grant_self"))
     assert not r.ok

@@ -22,7 +22,8 @@ def test_barrier_hierarchical_any_grouping(groups):
     assert rc == 0 and (chk == oracle.barrier_closed(7, 24, 30)).all()
 
 
-@pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep"])
+@pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep",
+                                  "ring", "array"])
 @pytest.mark.parametrize("L,W", [(1, 1), (1, 16), (3, 4)])
 def test_mutex_threaded_matches_closed(kind, L, W):
     seed, nwg, total = 0xC0FFEE, 8, 3000
