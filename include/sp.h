@@ -274,6 +274,23 @@ int sp_sem_run(sp_sem* s, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
                uint32_t max_hold_cyc, uint32_t seed, uint32_t track, uint32_t* out_chk,
                uint32_t* out_state, sp_stats* st, void* stream);
 
+/* ---- condition variables (Section 7's future work) ------------------------------------
+ * Device API in include/sp/cond.hpp: cond_wait (register, unlock, wait, relock; Mesa
+ * semantics), cond_signal_leader, cond_broadcast_leader.
+ * sp_cond_run_bounded_buffer: the classic use.  Workgroups [0, producers) put their share
+ * of `items` values (producer w's j-th value is sm32(seed ^ (w << 16) ^ j); shares split
+ * as in sp_mutex_run) into a ring of `capacity` words; the other nwg - producers
+ * workgroups take their share.  One mutex of kind mutex_kind (SP_MUTEX_SPIN_CAS, _TICKET,
+ * _SLEEP or _ARRAY) guards the ring; producers wait on "not full" while it holds capacity
+ * values, consumers on "not empty" while it is empty, and each signals the other after
+ * its put or take.  All nwg workgroups must be co-resident.  out: device, 6 uint64 =
+ * {xor of the values taken, their sum, values taken, values put, most values ever in the
+ * ring (<= capacity), values left (0)}.  p: poll_sleep, pad_bytes, timeout_ms are used.
+ * Errors: SP_E_INVAL, SP_E_NORESIDENT, SP_E_TIMEOUT, SP_E_HIP.                          */
+int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, uint32_t producers,
+                               uint32_t lanes, uint32_t capacity, uint64_t items, uint32_t seed,
+                               const sp_params* p, uint64_t* out, sp_stats* st, void* stream);
+
 /* ---- memory-system microbenchmarks (Section 3; Tables 1-3) ------------------------------
  * sp_bench_atomic: issuer u (a lane, or a wavefront's lane 0) performs ops_per_issuer
  * operations; its i-th targets word perm[(u + i) mod T] of buf, words stride_bytes

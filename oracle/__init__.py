@@ -79,6 +79,8 @@ def lib():
             "or_sem_threaded": (i32, [i32, u32, u32, u32, u64, u32, u32, p32, p32, p32, pd]),
             "or_bench_threaded": (i32, [i32, u32, u32, u64, u32, p32, u32, p32, p64, pd]),
             "or_serve_threaded": (i32, [u32, p32, p32, u32, u32, u32, p32, p32, p64, pd]),
+            "or_bb_closed": (None, [u32, u32, u64, p64]),
+            "or_bb_threaded": (i32, [u32, u32, u32, u64, u32, p64, pd]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -246,3 +248,20 @@ def serve_threaded(seed: int, lengths: np.ndarray, units: np.ndarray, K: int, ag
                                  ctypes.byref(secs))
     return {"out": out, "maxuse": int(maxuse[0]), "issued": int(counters[0]),
             "released": int(counters[1]), "rc": rc, "seconds": secs.value}
+
+
+def bb_closed(seed: int, producers: int, items: int) -> tuple[int, int]:
+    """(xor, sum) of every value the bounded buffer's producers put."""
+    out = np.zeros(2, dtype=np.uint64)
+    lib().or_bb_closed(seed & 0xFFFFFFFF, producers, items, _p64(out))
+    return int(out[0]), int(out[1])
+
+
+def bb_threaded(seed: int, producers: int, consumers: int, items: int, capacity: int) -> dict:
+    out = np.zeros(6, dtype=np.uint64)
+    secs = ctypes.c_double(0)
+    rc = lib().or_bb_threaded(seed & 0xFFFFFFFF, producers, consumers, items, capacity, _p64(out),
+                              ctypes.byref(secs))
+    v = [int(x) for x in out]
+    return {"xor": v[0], "sum": v[1], "taken": v[2], "put": v[3], "max_count": v[4],
+            "left": v[5], "rc": rc, "seconds": secs.value}

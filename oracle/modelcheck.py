@@ -284,6 +284,95 @@ class QueueLockModel:
         return None
 
 
+class CondModel:
+    """Bounded buffer on a mutex and two condition variables (Mesa semantics).
+    The mutex is one atomic test-and-set word.  A condition variable is two counters:
+    wait(c): t = waiters[c]++ (while holding the mutex); unlock; poll until
+    signals[c] > t; lock again.  signal(c): if signals[c] < waiters[c], signals[c] += 1
+    (one compare-and-swap step).  Producers put `items` values each into a buffer of
+    capacity C (while count == C: wait(not_full); put; signal(not_empty)); consumers take
+    their quota (while count == 0: wait(not_empty); take; signal(not_full)).
+    Checks: 0 <= count <= C, mutual exclusion, every item consumed, no deadlock.
+    mutant 'late_register': wait draws its ticket after unlocking (a lost wakeup);
+    mutant 'if_not_while': the predicate is tested once, not re-tested after waking;
+    mutant 'no_signal': producers do not signal."""
+
+    # local program counters
+    (LOCK, CHECK, REG, UNLOCK_W, POLL, RELOCK, ACT, SIGNAL, UNLOCK, DONE) = range(10)
+
+    def __init__(self, producers: int = 1, consumers: int = 2, items: int = 2, C: int = 1,
+                 mutant: str | None = None):
+        self.P, self.Cn, self.items, self.C, self.mutant = producers, consumers, items, C, mutant
+        self.n = producers + consumers
+        total = producers * items
+        self.quota = [items] * producers + [total // consumers + (1 if i < total % consumers
+                                                                  else 0)
+                                            for i in range(consumers)]
+
+    def init(self):
+        # shared = (mutex, count, inside, waiters(2), signals(2)); cv 0 = not_full, 1 = not_empty
+        return (0, 0, 0, (0, 0), (0, 0)), tuple((self.LOCK, 0, 0) for _ in range(self.n))
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    def step(self, a, sh, lo):
+        mutex, count, inside, W, S = sh
+        pc, j, t = lo
+        prod = a < self.P
+        cv_wait = 0 if prod else 1     # producers wait on not_full, consumers on not_empty
+        cv_sig = 1 if prod else 0
+        if pc == self.LOCK:
+            if mutex:
+                return sh, lo
+            return (1, count, inside + 1, W, S), (self.CHECK, j, t)
+        if pc == self.CHECK:  # predicate test while holding the mutex
+            blocked = count == self.C if prod else count == 0
+            if blocked:
+                return sh, (self.REG if self.mutant != "late_register" else self.UNLOCK_W, j, t)
+            return sh, (self.ACT, j, t)
+        if pc == self.REG:  # register with the condition variable (mutex held)
+            W2 = tuple(w + (1 if i == cv_wait else 0) for i, w in enumerate(W))
+            nxt = self.UNLOCK_W if self.mutant != "late_register" else self.POLL
+            return (mutex, count, inside, W2, S), (nxt, j, W[cv_wait])
+        if pc == self.UNLOCK_W:
+            nxt = self.POLL if self.mutant != "late_register" else self.REG
+            return (0, count, inside - 1, W, S), (nxt, j, t)
+        if pc == self.POLL:
+            return sh, ((self.RELOCK if S[cv_wait] > t else self.POLL), j, t)
+        if pc == self.RELOCK:
+            if mutex:
+                return sh, lo
+            nxt = self.ACT if self.mutant == "if_not_while" else self.CHECK
+            return (1, count, inside + 1, W, S), (nxt, j, t)
+        if pc == self.ACT:
+            count2 = count + 1 if prod else count - 1
+            return (mutex, count2, inside, W, S), (self.SIGNAL, j, t)
+        if pc == self.SIGNAL:
+            if self.mutant == "no_signal" and prod:
+                return sh, (self.UNLOCK, j, t)
+            if S[cv_sig] < W[cv_sig]:
+                S = tuple(x + (1 if i == cv_sig else 0) for i, x in enumerate(S))
+            return (mutex, count, inside, W, S), (self.UNLOCK, j, t)
+        if pc == self.UNLOCK:
+            nxt = self.LOCK if j + 1 < self.quota[a] else self.DONE
+            return (0, count, inside - 1, W, S), (nxt, j + 1, t)
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        mutex, count, inside, W, S = sh
+        if inside > 1:
+            return f"mutual exclusion violated: {inside} inside"
+        if not 0 <= count <= self.C:
+            return f"buffer count {count} outside [0, {self.C}]"
+        return None
+
+    def final_check(self, sh, los):
+        if sh[1] != 0:
+            return f"items left in the buffer: {sh[1]}"
+        return None
+
+
 # ------------------------------------------------------------------------------------
 # Semaphores with initial value K.  Each agent performs `ops` wait/post pairs with an
 # occupancy counter incremented on entry and decremented on exit.

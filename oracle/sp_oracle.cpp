@@ -22,6 +22,8 @@
 // Every function returns 0 on success or a negative code on a detected violation.
 
 #include <atomic>
+#include <condition_variable>
+#include <mutex>
 #include <chrono>
 #include <cstdint>
 #include <cstring>
@@ -611,6 +613,81 @@ int or_serve_threaded(uint32_t seed, const uint32_t* L, const uint32_t* units, u
   counters[1] = released.load();
   if (seconds) *seconds = t;
   return *maxuse > K ? -2 : 0;
+}
+
+// Bounded buffer (condition variables).  Producer w < P puts its share of `items`
+// values, the j-th being sm32(seed ^ (w << 16) ^ j); shares split as or_ops_for_agent.
+// Closed form of what the consumers take in total: out[0] = xor, out[1] = sum (uint64).
+void or_bb_closed(uint32_t seed, uint32_t P, uint64_t items, uint64_t* out) {
+  uint32_t x = 0;
+  uint64_t s = 0;
+  for (uint32_t w = 0; w < P; ++w) {
+    const uint64_t A = or_ops_for_agent(P, items, w);
+    for (uint64_t j = 0; j < A; ++j) {
+      const uint32_t v = or_sm32(seed ^ (w << 16) ^ (uint32_t)j);
+      x ^= v;
+      s += v;
+    }
+  }
+  out[0] = x;
+  out[1] = s;
+}
+
+// Threaded bounded buffer on std::mutex and std::condition_variable: P producer and C
+// consumer threads share a ring of `capacity` values.  out: {xor, sum, taken, put,
+// most values in the ring at once, values left}.  Returns 0, or -2 if the ring ever
+// held more than capacity or fewer than 0 values.
+int or_bb_threaded(uint32_t seed, uint32_t P, uint32_t C, uint64_t items, uint32_t capacity,
+                   uint64_t* out, double* seconds) {
+  if (P == 0 || C == 0 || capacity == 0) return -1;
+  std::mutex mu;
+  std::condition_variable not_full, not_empty;
+  std::vector<uint32_t> ring(capacity);
+  uint64_t head = 0, tail = 0, count = 0, maxc = 0, put = 0, taken = 0, sum = 0;
+  uint32_t x = 0;
+  int bad = 0;
+  double t = run_agents(P + C, [&](uint32_t a) {
+    if (a < P) {
+      const uint64_t A = or_ops_for_agent(P, items, a);
+      for (uint64_t j = 0; j < A; ++j) {
+        const uint32_t v = or_sm32(seed ^ (a << 16) ^ (uint32_t)j);
+        std::unique_lock<std::mutex> lk(mu);
+        not_full.wait(lk, [&] { return count < capacity; });
+        ring[tail++ % capacity] = v;
+        ++count;
+        ++put;
+        if (count > maxc) maxc = count;
+        if (count > capacity) bad = 1;
+        not_empty.notify_one();
+      }
+    } else {
+      const uint64_t A = or_ops_for_agent(C, items, a - P);
+      uint32_t lx = 0;
+      uint64_t ls = 0;
+      for (uint64_t j = 0; j < A; ++j) {
+        std::unique_lock<std::mutex> lk(mu);
+        not_empty.wait(lk, [&] { return count > 0; });
+        const uint32_t v = ring[head++ % capacity];
+        --count;
+        ++taken;
+        not_full.notify_one();
+        lk.unlock();
+        lx ^= v;
+        ls += v;
+      }
+      std::lock_guard<std::mutex> g(mu);
+      x ^= lx;
+      sum += ls;
+    }
+  });
+  out[0] = x;
+  out[1] = sum;
+  out[2] = taken;
+  out[3] = put;
+  out[4] = maxc;
+  out[5] = count;
+  if (seconds) *seconds = t;
+  return bad ? -2 : 0;
 }
 
 }  // extern "C"

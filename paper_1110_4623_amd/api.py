@@ -309,6 +309,22 @@ class Semaphore(_Handle):
         return dict(self.result(), stats=st)
 
 
+def bounded_buffer(ctx: Context, mutex_kind: str, nwg: int, producers: int, capacity: int,
+                   items: int, seed: int, lanes: int = 64, **params) -> dict:
+    """Producer/consumer ring on a mutex and two condition variables
+    (sp_cond_run_bounded_buffer)."""
+    out = ctx.zeros(6, "u64")
+    p = make_params(**params)
+    st = N.Stats()
+    check(lib.sp_cond_run_bounded_buffer(ctx.h, N.MUTEX_KINDS[mutex_kind], nwg, producers, lanes,
+                                         capacity, items, seed & 0xFFFFFFFF, ctypes.byref(p),
+                                         ctx.ptr(out), ctypes.byref(st), ctx.stream()),
+          "sp_cond_run_bounded_buffer", ctx.h)
+    v = [int(x) for x in ctx.read(out, "u64", 6)]
+    return {"xor": v[0], "sum": v[1], "taken": v[2], "put": v[3], "max_count": v[4],
+            "left": v[5], "stats": st.as_dict()}
+
+
 class Graph:
     """Records the primitive runs made inside a `with` block into one HIP graph
     (sp_graph_begin/end) and replays them with `launch`.  Inside the block, use the

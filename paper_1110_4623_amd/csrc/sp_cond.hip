@@ -1,0 +1,194 @@
+// Condition variables: the bounded-buffer workload (a mutex and two condition variables,
+// the classic use; Section 7 names condition variables as the safer alternative to
+// semaphores for waiting on a predicate).
+#include <string.h>
+
+#include "sp/cond.hpp"
+#include "sp_internal.hpp"
+
+namespace {
+
+// Buffer state words (each on its own line), protected by the mutex.
+enum { B_COUNT = 0, B_HEAD, B_TAIL, B_MAX, B_LINES };
+// Condition-variable counters (each on its own line).
+enum { C_NF_WAITERS = 0, C_NF_SIGNALS, C_NE_WAITERS, C_NE_SIGNALS, C_LINES };
+constexpr uint32_t kLine = 32;  // words per 128-byte line
+
+// Workgroups [0, producers) put their share of `items` values sm32(seed ^ (w << 16) ^ j)
+// into a ring of `capacity` words; the others take their share.  Only the leader touches
+// the buffer (plain loads and stores, ordered by the mutex); the whole workgroup takes
+// part in every mutex and condition-variable call.  res: 4 uint64 per workgroup = {xor of
+// values taken, sum of values taken, values taken or put, 0}.
+template <int MKIND>
+__global__ SP_FULL_OCCUPANCY void k_bounded_buffer(sp::MutexState m, sp::CondState not_full,
+                                                   sp::CondState not_empty, uint32_t* bstate,
+                                                   uint32_t* buf, uint32_t capacity,
+                                                   uint32_t producers, uint64_t items,
+                                                   uint32_t seed, unsigned long long* res,
+                                                   uint32_t* err, uint64_t timeout) {
+  const sp::Ctl ctl{err, sp::wall_clock() + timeout};
+  __shared__ uint32_t s_blocked;
+  const uint32_t b = blockIdx.x;
+  const bool prod = b < producers;
+  const uint32_t consumers = gridDim.x - producers;
+  const uint32_t parts = prod ? producers : consumers;
+  const uint32_t idx = prod ? b : b - producers;
+  const uint64_t A = items / parts + (idx < items % parts ? 1 : 0);
+  uint32_t* count = bstate + B_COUNT * kLine;
+  uint32_t* head = bstate + B_HEAD * kLine;
+  uint32_t* tail = bstate + B_TAIL * kLine;
+  uint32_t* maxc = bstate + B_MAX * kLine;
+  const sp::CondState& mine = prod ? not_full : not_empty;
+  const sp::CondState& other = prod ? not_empty : not_full;
+  uint32_t x = 0;
+  unsigned long long sum = 0;
+  uint64_t done = 0;
+  for (uint64_t j = 0; j < A; ++j) {
+    sp::MutexHold hold;
+    if (!sp::mutex_lock<MKIND>(m, 0, ctl, &hold)) return;
+    for (;;) {
+      if (sp::is_leader()) s_blocked = prod ? (*count == capacity) : (*count == 0);
+      __syncthreads();
+      const bool blocked = s_blocked;
+      __syncthreads();
+      if (!blocked) break;
+      if (!sp::cond_wait<MKIND>(mine, m, 0, &hold, ctl)) return;
+    }
+    if (sp::is_leader()) {
+      if (prod) {
+        const uint32_t v = sp::sm32(seed ^ (b << 16) ^ (uint32_t)j);
+        const uint32_t t = *tail;
+        buf[t % capacity] = v;
+        *tail = t + 1;
+        const uint32_t c = *count + 1;
+        *count = c;
+        if (c > *maxc) *maxc = c;
+      } else {
+        const uint32_t h = *head;
+        const uint32_t v = buf[h % capacity];
+        *head = h + 1;
+        *count = *count - 1;
+        x ^= v;
+        sum += v;
+      }
+      sp::cond_signal_leader(other);
+    }
+    sp::mutex_unlock<MKIND>(m, 0, &hold);
+    ++done;
+  }
+  if (sp::is_leader()) {
+    res[4 * (size_t)b + 0] = x;
+    res[4 * (size_t)b + 1] = sum;
+    res[4 * (size_t)b + 2] = done;
+    res[4 * (size_t)b + 3] = 0;
+  }
+}
+
+// out[0] = xor of taken values, out[1] = sum, out[2] = values taken, out[3] = values put,
+// out[4] = most values ever in the buffer, out[5] = values left in it.
+__global__ void k_bb_reduce(const unsigned long long* res, uint32_t nwg, uint32_t producers,
+                            const uint32_t* bstate, unsigned long long* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long x = 0, s = 0, taken = 0, put = 0;
+  for (uint32_t b = 0; b < nwg; ++b) {
+    if (b < producers) {
+      put += res[4 * (size_t)b + 2];
+    } else {
+      x ^= res[4 * (size_t)b + 0];
+      s += res[4 * (size_t)b + 1];
+      taken += res[4 * (size_t)b + 2];
+    }
+  }
+  out[0] = x;
+  out[1] = s;
+  out[2] = taken;
+  out[3] = put;
+  out[4] = bstate[B_MAX * kLine];
+  out[5] = bstate[B_COUNT * kLine];
+}
+
+const void* bb_kernel(uint32_t kind) {
+  switch (kind) {
+    case SP_MUTEX_SPIN_CAS: return (const void*)k_bounded_buffer<SP_MUTEX_SPIN_CAS>;
+    case SP_MUTEX_TICKET: return (const void*)k_bounded_buffer<SP_MUTEX_TICKET>;
+    case SP_MUTEX_SLEEP: return (const void*)k_bounded_buffer<SP_MUTEX_SLEEP>;
+    case SP_MUTEX_ARRAY: return (const void*)k_bounded_buffer<SP_MUTEX_ARRAY>;
+    default: return nullptr;
+  }
+}
+
+struct DevMem {
+  uint32_t* p = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, uint32_t producers,
+                               uint32_t lanes, uint32_t capacity, uint64_t items, uint32_t seed,
+                               const sp_params* p, uint64_t* out, sp_stats* st, void* stream) {
+  if (!ctx || !out || nwg < 2 || producers == 0 || producers >= nwg || !spi::lanes_ok(lanes) ||
+      capacity == 0 || capacity > (1u << 24) || items == 0 || items >= (1ull << 32))
+    return SP_E_INVAL;
+  const void* kern = bb_kernel(mutex_kind);
+  if (!kern) return SP_E_INVAL;
+  sp_params q;
+  SP_CHECK(spi::normalize(ctx, p, &q));
+  hipStream_t s = spi::as_stream(stream);
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  if (spi::capturing(s)) return SP_E_INVAL;  // allocates its buffers
+  // Producers and consumers wait for each other: all must be resident at once.
+  int per_cu = 0;
+  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  if ((uint64_t)per_cu * ctx->cu_count < nwg) return SP_E_NORESIDENT;
+  const uint32_t sw = spi::stride_words(q);
+  uint32_t Q = 64;
+  while (Q < nwg) Q <<= 1;
+  const uint64_t mutex_words = 5ull * sw + (mutex_kind == SP_MUTEX_ARRAY ? (uint64_t)Q * sw : 0);
+  const uint64_t cond_words = (uint64_t)C_LINES * kLine;
+  const uint64_t bstate_words = (uint64_t)B_LINES * kLine;
+  const uint64_t res_words = 8ull * nwg;  // 4 uint64 per workgroup
+  const uint64_t total = mutex_words + cond_words + bstate_words + capacity + res_words + 64;
+  DevMem mem;
+  SP_HIP(ctx, hipMalloc(&mem.p, total * sizeof(uint32_t)));
+  uint32_t* base = mem.p;
+  sp::MutexState ms;
+  ms.stride = sw;
+  ms.poll_sleep = q.poll_sleep;
+  ms.lockw = base;
+  ms.ticket = base + sw;
+  ms.turn = base + 2ull * sw;
+  ms.bo = spi::backoff_cfg(q, base + 3ull * sw);
+  ms.queue = base + 5ull * sw;
+  ms.qlen = Q;
+  ms.qstride = sw;
+  uint32_t* cond = base + mutex_words;
+  sp::CondState nf{cond + C_NF_WAITERS * kLine, cond + C_NF_SIGNALS * kLine, q.poll_sleep};
+  sp::CondState ne{cond + C_NE_WAITERS * kLine, cond + C_NE_SIGNALS * kLine, q.poll_sleep};
+  uint32_t* bstate = cond + cond_words;
+  uint32_t* buf = bstate + bstate_words;
+  // 8-byte aligned per-workgroup results, then the 6 reduced values
+  uint64_t off = (uint64_t)(buf + capacity - base);
+  off = (off + 1) & ~1ull;
+  unsigned long long* res = reinterpret_cast<unsigned long long*>(base + off);
+  SP_CHECK(spi::fill_u32(ctx, base, total, 0, s));
+  SP_CHECK(spi::begin_timed(ctx, s));
+  uint64_t timeout = spi::timeout_ticks(ctx, q);
+  unsigned long long* resp = res;
+  void* args[] = {&ms, &nf, &ne, &bstate, &buf, &capacity, &producers, &items, &seed, &resp,
+                  &ctx->d_err, &timeout};
+  SP_HIP(ctx, hipLaunchKernel(kern, dim3(nwg), dim3(lanes), args, 0, s));
+  int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, items);
+  hipLaunchKernelGGL(k_bb_reduce, dim3(1), dim3(64), 0, s, res, nwg, producers, bstate,
+                     reinterpret_cast<unsigned long long*>(out));
+  const hipError_t launch = hipGetLastError();
+  SP_HIP(ctx, hipStreamSynchronize(s));  // before the buffers are freed
+  SP_HIP(ctx, launch);
+  return rc;
+}
+
+}  // extern "C"

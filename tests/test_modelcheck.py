@@ -3,8 +3,8 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 
 import pytest
 
-from oracle.modelcheck import (BarrierModel, FASemModel, MutexModel, QueueLockModel, SpinSemModel,
-                               WeightedSemModel, explore)
+from oracle.modelcheck import (BarrierModel, CondModel, FASemModel, MutexModel, QueueLockModel,
+                               SpinSemModel, WeightedSemModel, explore)
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
@@ -141,3 +141,27 @@ def test_catches_ring_without_own_id():
 def test_catches_array_granting_itself():
     r = explore(QueueLockModel("array", 2, 2, mutant="grant_self"))
     assert not r.ok
+
+
+# ---- condition variables (bounded buffer) ---------------------------------------------
+
+@pytest.mark.parametrize("P,Cn,items,C", [(1, 1, 3, 1), (1, 2, 2, 1), (2, 1, 2, 1),
+                                          (2, 2, 1, 1), (1, 2, 3, 2)])
+def test_condition_variables_correct(P, Cn, items, C):
+    r = explore(CondModel(P, Cn, items, C))
+    assert r.ok, r.violation
+
+
+def test_catches_lost_wakeup():
+    r = explore(CondModel(1, 1, 2, 1, mutant="late_register"))
+    assert r.deadlock
+
+
+def test_catches_predicate_not_rechecked():
+    r = explore(CondModel(1, 2, 2, 1, mutant="if_not_while"))
+    assert r.violation is not None
+
+
+def test_catches_missing_signal():
+    r = explore(CondModel(1, 1, 2, 1, mutant="no_signal"))
+    assert r.deadlock

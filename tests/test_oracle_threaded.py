@@ -77,3 +77,26 @@ def test_serve_threaded_matches_closed(K, agents, lmax):
 def test_serve_threaded_rejects_oversized_request():
     r = oracle.serve_threaded(1, np.array([5], np.uint32), np.array([3], np.uint32), 2, 4)
     assert r["rc"] == -1
+
+
+@pytest.mark.parametrize("P,C,items,cap", [(1, 1, 500, 1), (4, 3, 3000, 2), (3, 5, 2001, 16),
+                                           (8, 8, 4096, 1024)])
+def test_bounded_buffer_threaded_matches_closed(P, C, items, cap):
+    """std::mutex + std::condition_variable producers and consumers take exactly what
+    was put: the xor and sum of everything taken equal the closed form."""
+    r = oracle.bb_threaded(7, P, C, items, cap)
+    assert r["rc"] == 0
+    assert (r["xor"], r["sum"]) == oracle.bb_closed(7, P, items)
+    assert r["taken"] == r["put"] == items and r["left"] == 0
+    assert 1 <= r["max_count"] <= cap
+
+
+def test_bounded_buffer_closed_brute_force():
+    seed, P, items = 0xC0FFEE, 3, 10
+    x, s = 0, 0
+    for w in range(P):
+        for j in range(oracle.ops_for_agent(P, items, w)):
+            v = oracle.sm32(seed ^ (w << 16) ^ j)
+            x ^= v
+            s += v
+    assert oracle.bb_closed(seed, P, items) == (x, s)
