@@ -162,18 +162,27 @@ int sp_init(int device, sp_ctx** out) {
     delete[] h;
     ctx->xcd_count = (uint32_t)__builtin_popcount(seen);
   }
-  // Built-in defaults until a tuner installs measured ones.
+  // Built-in defaults: the winners of a full tuning pass on an MI355X (fewer than 64 /
+  // at least 64 workgroups per resource); a tuner run installs its own with
+  // sp_set_default.
   for (int prim = 0; prim < 3; ++prim)
     for (int b = 0; b < 2; ++b) {
       sp_params_default(&ctx->defaults[prim][b].p);
       ctx->defaults[prim][b].kind = 0;
     }
-  ctx->defaults[0][0].kind = SP_BARRIER_CENTRAL_SPLIT;
-  ctx->defaults[0][1].kind = SP_BARRIER_XCD;
-  ctx->defaults[1][0].kind = SP_MUTEX_TICKET;
+  ctx->defaults[0][0].kind = SP_BARRIER_CENTRAL;  // 1.7 us/round at 16 workgroups
+  ctx->defaults[0][0].p.poll_sleep = 0;
+  ctx->defaults[0][1].kind = SP_BARRIER_XCD;      // 6.6 us/round at 1024
+  ctx->defaults[0][1].p.poll_sleep = 0;
+  ctx->defaults[1][0].kind = SP_MUTEX_SPIN_BACKOFF;  // paper's linear backoff, I_max 8
+  ctx->defaults[1][0].p.backoff = SP_BACKOFF_PAPER;
+  ctx->defaults[1][0].p.backoff_max = 8;
   ctx->defaults[1][1].kind = SP_MUTEX_TICKET;
+  ctx->defaults[1][1].p.poll_sleep = 4;
   ctx->defaults[2][0].kind = SP_SEM_SLEEP;
-  ctx->defaults[2][1].kind = SP_SEM_SLEEP;
+  ctx->defaults[2][0].p.poll_sleep = 4;
+  ctx->defaults[2][1].kind = SP_SEM_COUNTERS;
+  ctx->defaults[2][1].p.poll_sleep = 4;
   *out = ctx;
   return SP_OK;
 }

@@ -229,3 +229,42 @@ def default_cache_path() -> str:
     return os.environ.get("SP_TUNER_CACHE",
                           os.path.join(os.path.expanduser("~"), ".cache", "paper_1110_4623_amd",
                                        "tuner.json"))
+
+
+def main(argv=None) -> int:
+    """python -m paper_1110_4623_amd.tune [--out PATH] [--quick] [--serve-rate R]:
+    tunes every primitive on this GPU, prints the winners, saves the cache."""
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="tune the synchronization primitives")
+    ap.add_argument("--out", default=None, help="cache path (default: SP_TUNER_CACHE or "
+                                                "~/.cache/paper_1110_4623_amd/tuner.json)")
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="also tune the serving queue at this arrival rate (req/s)")
+    a = ap.parse_args(argv)
+    ctx = api.Context(0)
+    res = tune_all(ctx, quick=a.quick)
+    if a.serve_rate > 0:
+        import sp_inputs
+        n = int(max(2e4, 2 * a.serve_rate)) if not a.quick else 5000
+        res["serve"] = tune_serve(ctx, sp_inputs.request_table(n, a.serve_rate, 42))
+    for prim in ("barrier", "mutex", "semaphore"):
+        for bucket, r in res[prim].items():
+            b = r["best"]
+            metric = {k: v for k, v in b.items() if k.endswith("_per_s") or k.startswith("us_")}
+            print(f"{prim:9s} bucket {bucket}: {b['kind']:13s} {b['params']} {metric}",
+                  flush=True)
+    if "serve" in res:
+        b = res["serve"]["best"]
+        print(f"serve: {b['cfg']} p50 {b['p50_us']:.1f} us p99 {b['p99_us']:.1f} us", flush=True)
+    path = a.out or default_cache_path()
+    save(res, path)
+    print(f"saved {path}", flush=True)
+    ctx.close()
+    sys.stdout.flush()
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
