@@ -183,6 +183,11 @@ int sp_init(int device, sp_ctx** out) {
   ctx->defaults[2][0].p.poll_sleep = 4;
   ctx->defaults[2][1].kind = SP_SEM_COUNTERS;
   ctx->defaults[2][1].p.poll_sleep = 4;
+  // resolve the "auto" fields (fan_in = XCD count, ...) as sp_set_default does
+  for (int prim = 0; prim < 3; ++prim)
+    for (int b = 0; b < 2; ++b)
+      if (spi::normalize(ctx, &ctx->defaults[prim][b].p, &ctx->defaults[prim][b].p) != SP_OK)
+        return fail(hipErrorInvalidValue);
   *out = ctx;
   return SP_OK;
 }

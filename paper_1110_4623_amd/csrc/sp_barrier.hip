@@ -91,10 +91,9 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   if (kind == SP_BARRIER_DEFAULT) {
     const sp_default_entry& d = ctx->defaults[0][spi::bucket_of(nwg)];
     kind = d.kind;
-    q = d.p;
-    if (p) {  // an explicit timeout still applies
-      if (p->timeout_ms) q.timeout_ms = p->timeout_ms;
-    }
+    sp_params dp = d.p;
+    if (p && p->timeout_ms) dp.timeout_ms = p->timeout_ms;  // an explicit timeout applies
+    SP_CHECK(spi::normalize(ctx, &dp, &q));  // fills fan_in and the other "auto" fields
   } else {
     if (kind > SP_BARRIER_XCD) return SP_E_INVAL;
     SP_CHECK(spi::normalize(ctx, p, &q));
