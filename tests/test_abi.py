@@ -96,3 +96,34 @@ def test_serve_rejects_bad_tables_without_gpu():
                               ctypes.byref(r)) == N.SP_E_INVAL
     assert N.lib.sp_serve_run_launch_per_request(None, ctypes.byref(c), 1, None, None, None,
                                                  None, None, ctypes.byref(r)) == N.SP_E_INVAL
+
+
+def test_newer_entry_points_reject_bad_arguments_without_gpu():
+    import ctypes
+    from paper_1110_4623_amd import _native as N
+    lib = N.lib
+    st = N.Stats()
+    p = N.Params()
+    lib.sp_params_default(ctypes.byref(p))
+    # no context / no output / no consumers: argument errors before any HIP call
+    assert lib.sp_cond_run_bounded_buffer(None, 3, 4, 2, 64, 8, 100, 1, ctypes.byref(p), None,
+                                          ctypes.byref(st), None) == N.SP_E_INVAL
+    g = ctypes.c_void_p()
+    assert lib.sp_graph_begin(None, None, ctypes.byref(g)) == N.SP_E_INVAL
+    assert lib.sp_graph_end(None, None, ctypes.byref(g)) == N.SP_E_INVAL
+    assert lib.sp_graph_launch(None, 1, ctypes.byref(st), None) == N.SP_E_INVAL
+    assert lib.sp_graph_destroy(None) == N.SP_E_INVAL
+    info = N.BarrierInfo()
+    assert lib.sp_barrier_info_get(None, ctypes.byref(info)) == N.SP_E_INVAL
+
+
+def test_kind_tables_match_the_header():
+    """The Python name -> kind maps use the enum values include/sp.h defines."""
+    import re
+    from paper_1110_4623_amd import _native as N
+    text = open(os.path.join(ROOT, "include", "sp.h")).read()
+    enum = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(SP_\w+)\s*=\s*(\d+)", text)}
+    for prefix, table in (("SP_BARRIER_", N.BARRIER_KINDS), ("SP_MUTEX_", N.MUTEX_KINDS),
+                          ("SP_SEM_", N.SEM_KINDS)):
+        for name, value in table.items():
+            assert enum[prefix + name.upper()] == value, (prefix, name)
