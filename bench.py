@@ -101,6 +101,8 @@ def main() -> int:
 
     ctx = sp.Context(0)
     bar = sp.Barrier(ctx, args.barrier, NWG)
+    # the same barrier for data exchanged with agent-scope accesses: no cache maintenance
+    bar_coh = sp.Barrier(ctx, args.barrier, NWG, coherent_cs=1)
     mtx = sp.Mutex(ctx, "ticket", 1, 16)
     sem = sp.Semaphore(ctx, "sleep", SEM_K)
     perm1 = ctx.zeros(1)
@@ -113,6 +115,8 @@ def main() -> int:
         r["a1_ms"], r["a1_ops"] = st["kernel_ms"], st["ops"]
         chk, st = bar.run_hash(LANES, ROUNDS, 42)
         r["bar_ms"], r["bar_chk"] = st["kernel_ms"], chk
+        chk_c, st_c = bar_coh.run_hash(LANES, ROUNDS, 42)
+        r["bar_coh_ms"], r["bar_coh_same"] = st_c["kernel_ms"], bool((chk_c == chk).all())
         words, st, _ = mtx.run(NWG, LANES, MUTEX_TOTAL, 1000, 42)
         r["mtx_ms"], r["mtx_ok"] = st["kernel_ms"], bool((words == MUTEX_TOTAL).all())
         res = sem.run(NWG, LANES, SEM_TOTAL, 2000, 42, track=False)
@@ -176,6 +180,9 @@ def main() -> int:
                    "nwg": NWG, "lanes": LANES, "rounds": ROUNDS},
         "metrics": {
             "barrier_us_per_round": round(us_round, 4),
+            "barrier_coherent_data_us_per_round": round(
+                float(np.mean([r["bar_coh_ms"] for r in results])) * 1e3 / ROUNDS, 4),
+            "barrier_coherent_checksums_identical": all(r["bar_coh_same"] for r in results),
             "barrier_arrivals_per_s": round(arrivals, 1),
             "mutex_ticket_acq_per_s": round(mtx_rate, 1),
             "semaphore_k32_pairs_per_s": round(sem_rate, 1),

@@ -129,11 +129,14 @@ typedef struct sp_params {
   uint32_t cooperative;  /* barrier runs: 1 = hipLaunchCooperativeKernel; 0 = plain launch */
                          /* after the library's own co-residency check (a workgroup that   */
                          /* is not resident ends in SP_E_TIMEOUT through the watchdog)     */
-  uint32_t coherent_cs;  /* mutex runs: 1 = the critical sections access the protected     */
-                         /* words with agent-scope loads and stores, which every XCD sees  */
+  uint32_t coherent_cs;  /* mutexes: 1 = the critical sections access the protected words */
+                         /* with agent-scope loads and stores, which every XCD sees        */
                          /* without cache maintenance, so lock and unlock skip the acquire */
-                         /* invalidate and the release writeback; 0 = plain accesses,      */
-                         /* fenced (the general contract)                                  */
+                         /* invalidate and the release writeback.  Barriers: 1 = the data  */
+                         /* exchanged across the barrier is accessed that way (the paper's */
+                         /* volatile accesses), so the barrier does no cache maintenance   */
+                         /* (and the per-XCD barrier needs no per-CU release hop).         */
+                         /* 0 = plain accesses, fenced (the general contract)              */
   uint32_t reserved[4];
 } sp_params;
 

@@ -23,6 +23,9 @@ struct BarrierState {
   uint32_t flag_stride; // flag barrier: uint32 words between flags (1 = packed)
   uint32_t poll_sleep;  // s_sleep units between polls
   uint32_t xblock;      // xcd: uint32 words of each XCD's block of local arrival flags
+  uint32_t fenced;      // 1: order plain memory (release / acquire fences); 0: the data
+                        // exchanged across the barrier is accessed with agent-scope
+                        // loads and stores, so the barrier does no cache maintenance
   uint32_t* cnt;        // centralized counter
   uint32_t* gen;        // centralized split: release word
   uint32_t* gcnt;       // tree: per-group counters (groups lines)
@@ -58,17 +61,23 @@ template <int KIND>
 __device__ __forceinline__ bool counter_arrive_wait(const BarrierState& s, uint32_t stamp,
                                                     const Ctl& ctl) {
   Wait w(ctl, s.poll_sleep);
+  const bool f = s.fenced;
   if constexpr (KIND == SP_BARRIER_CENTRAL) {
     // Two-stage atomic barrier: one increment per workgroup, then poll the counter.
-    add_release(s.cnt, 1);
+    if (f) fence_release();
+    add_relaxed(s.cnt, 1);
     return poll_until(s.cnt, s.nwg * stamp, w);
   } else if constexpr (KIND == SP_BARRIER_CENTRAL_SPLIT) {
     // Same counter; the last arriver publishes a separate release word, so pollers
     // read a line that receives no read-modify-writes.
-    const uint32_t old = add_release(s.cnt, 1);
+    if (f) fence_release();
+    const uint32_t old = add_relaxed(s.cnt, 1);
     if (old == s.nwg * stamp - 1) {
-      fence_acquire();
-      st_release(s.gen, stamp);
+      if (f) {
+        fence_acquire();
+        fence_release();
+      }
+      st_relaxed(s.gen, stamp);
       return true;
     }
     return poll_until(s.gen, stamp, w);
@@ -82,18 +91,28 @@ __device__ __forceinline__ bool counter_arrive_wait(const BarrierState& s, uint3
     const uint32_t members = (s.nwg - g + G - 1) / G;
     uint32_t* gc = s.gcnt + (size_t)g * s.stride;
     uint32_t* gg = s.ggen + (size_t)g * s.stride;
-    const uint32_t old = add_release(gc, 1);
+    if (f) fence_release();
+    const uint32_t old = add_relaxed(gc, 1);
     if (old != members * stamp - 1) return poll_until(gg, stamp, w);
-    fence_acquire();
-    const uint32_t t = add_release(s.top, 1);
-    if (t == G * stamp - 1) {
+    if (f) {
       fence_acquire();
-      st_release(s.topgen, stamp);
+      fence_release();
+    }
+    const uint32_t t = add_relaxed(s.top, 1);
+    if (t == G * stamp - 1) {
+      if (f) {
+        fence_acquire();
+        fence_release();
+      }
+      st_relaxed(s.topgen, stamp);
     } else {
       if (!poll_until(s.topgen, stamp, w)) return false;
-      fence_acquire();
+      if (f) {
+        fence_acquire();
+        fence_release();
+      }
     }
-    st_release(gg, stamp);
+    st_relaxed(gg, stamp);
     return true;
   }
 }
@@ -127,10 +146,10 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
     __syncthreads();
     Wait w(ctl, s.poll_sleep);
     int ok = scan_flags(s.arrive, fs, s.nwg, 0, stamp, w);
-    fence_acquire();
+    if (s.fenced) fence_acquire();
     ok = __syncthreads_and(ok);
     if (ok) {
-      fence_release();
+      if (s.fenced) fence_release();
       for (uint32_t i = threadIdx.x; i < s.nwg; i += blockDim.x)
         if (i != 0) st_relaxed(s.release + (size_t)i * fs, stamp);
     }
@@ -139,9 +158,10 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
   __syncthreads();
   if (is_leader()) {
     Wait w(ctl, s.poll_sleep);
-    st_release(s.arrive + (size_t)blockIdx.x * fs, stamp);
+    if (s.fenced) fence_release();
+    st_relaxed(s.arrive + (size_t)blockIdx.x * fs, stamp);
     const bool ok = poll_until(s.release + (size_t)blockIdx.x * fs, stamp, w);
-    fence_acquire();
+    if (s.fenced) fence_acquire();
     s_ok = ok;
   }
   __syncthreads();
@@ -209,9 +229,19 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
     ok = scan_flags(block, 1, members, 0, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
-    if (is_leader()) st_release(s.xarrive + (size_t)x * s.stride, stamp);
+    if (is_leader()) {
+      if (s.fenced) fence_release();
+      st_relaxed(s.xarrive + (size_t)x * s.stride, stamp);
+    }
   } else if (is_leader()) {
     st_relaxed(block + k, stamp);
+  }
+  if (!s.fenced) {
+    // Coherent data: no cache maintenance, so nothing is shared per CU; every workgroup
+    // polls the populated XCDs' stamps itself (two flag hops per round).
+    if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
+      ok = poll_until(s.xarrive + (size_t)threadIdx.x * s.stride, stamp, w);
+    return __syncthreads_and(ok);
   }
   if (slot == 0) {
     // CU leader: once every populated XCD has published, invalidate for the CU and
@@ -253,7 +283,7 @@ __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl,
     else
       add_relaxed(s.overflow, 1);
     const bool ok = counter_arrive_wait<SP_BARRIER_TREE>(s, 1, ctl);
-    fence_acquire();
+    fence_acquire();  // round 0 only: always, so the registrations below read fresh
     *use_xcd = ld_relaxed(s.overflow) == 0;
     L.ncu = ld_relaxed(s.cu_count + L.key);
     L.members = ld_relaxed(s.xcount + xcc);
@@ -293,7 +323,7 @@ __device__ bool barrier_wait(const BarrierState& s, uint32_t round, const Ctl& c
     __syncthreads();
     if (is_leader()) {
       const bool ok = detail::counter_arrive_wait<SP_BARRIER_TREE>(s, stamp, ctl);
-      fence_acquire();
+      if (s.fenced) fence_acquire();
       s_ok = ok;
     }
     __syncthreads();
@@ -302,7 +332,7 @@ __device__ bool barrier_wait(const BarrierState& s, uint32_t round, const Ctl& c
     __syncthreads();
     if (is_leader()) {
       const bool ok = detail::counter_arrive_wait<KIND>(s, stamp, ctl);
-      fence_acquire();
+      if (s.fenced) fence_acquire();
       s_ok = ok;
     }
     __syncthreads();

@@ -20,8 +20,10 @@ struct sp_barrier {
 namespace {
 
 // Hash-exchange workload: the slot is written by the workgroup's last thread and read
-// by thread 64 (a different wavefront when the workgroup has more than one), with
-// plain stores and loads, so only the barrier orders them.
+// by thread 64 (a different wavefront when the workgroup has more than one), with plain
+// stores and loads, so only the barrier orders them -- or, for a barrier created with
+// coherent_cs, with agent-scope stores and loads (the paper's volatile accesses), which
+// the barrier then orders without cache maintenance.
 template <int KIND>
 __global__ SP_FULL_OCCUPANCY void k_barrier_hash(sp::BarrierState s, uint32_t rounds, uint32_t seed,
                                uint32_t* slots, uint32_t* out, uint32_t* err,
@@ -30,10 +32,19 @@ __global__ SP_FULL_OCCUPANCY void k_barrier_hash(sp::BarrierState s, uint32_t ro
   const uint32_t b = blockIdx.x, N = s.nwg;
   const uint32_t writer = blockDim.x - 1, reader = 64 % blockDim.x;
   uint32_t chk = 0;
+  const bool coherent = !s.fenced;
   for (uint32_t r = 0; r < rounds; ++r) {
-    if (threadIdx.x == writer) slots[(r & 1) * N + b] = sp::sm32(seed ^ (b << 16) ^ r);
+    if (threadIdx.x == writer) {
+      uint32_t* p = slots + (r & 1) * N + b;
+      const uint32_t v = sp::sm32(seed ^ (b << 16) ^ r);
+      if (coherent) sp::st_relaxed(p, v);
+      else *p = v;
+    }
     if (!sp::barrier_wait<KIND>(s, r, ctl)) return;
-    if (threadIdx.x == reader) chk ^= slots[(r & 1) * N + (uint32_t)(((uint64_t)b + r) % N)];
+    if (threadIdx.x == reader) {
+      const uint32_t* p = slots + (r & 1) * N + (uint32_t)(((uint64_t)b + r) % N);
+      chk ^= coherent ? sp::ld_relaxed(p) : *p;
+    }
   }
   if (threadIdx.x == reader) out[b] = chk;
 }
@@ -93,6 +104,7 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
     kind = d.kind;
     sp_params dp = d.p;
     if (p && p->timeout_ms) dp.timeout_ms = p->timeout_ms;  // an explicit timeout applies
+    if (p) dp.coherent_cs = p->coherent_cs;  // a property of the caller's data accesses
     SP_CHECK(spi::normalize(ctx, &dp, &q));  // fills fan_in and the other "auto" fields
   } else {
     if (kind > SP_BARRIER_XCD) return SP_E_INVAL;
@@ -141,6 +153,7 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.stride = sw;
   s.groups = G;
   s.tgroups = std::min(G, nwg);
+  s.fenced = q.coherent_cs ? 0u : 1u;
   s.flag_stride = fs;
   s.poll_sleep = q.poll_sleep;
   s.xblock = xblock;

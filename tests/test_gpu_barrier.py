@@ -129,3 +129,25 @@ def test_xcd_barrier_info_fresh_placement(ctx):
         assert b.info()["xcd_path"]
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("kind", ["central", "central_split", "tree", "flag", "xcd"])
+@pytest.mark.parametrize("nwg,lanes", [(16, 64), (257, 128), (2048, 256)])
+def test_coherent_data_barriers(ctx, kind, nwg, lanes):
+    """coherent_cs: the exchanged slots are written and read with agent-scope accesses
+    and the barrier does no cache maintenance; the checksums are the oracle's."""
+    import paper_1110_4623_amd as sp
+    if kind in ("central", "central_split", "tree", "flag") and nwg == 2048:
+        rounds = 200
+    else:
+        rounds = 1000
+    announce("coherent barrier", kind, f"nwg={nwg} lanes={lanes} rounds={rounds}")
+    b = sp.Barrier(ctx, kind, nwg, coherent_cs=1)
+    try:
+        for seed in (42, 0xC0FFEE):
+            chk, _ = b.run_hash(lanes, rounds, seed)
+            assert (chk == oracle.barrier_closed(seed, nwg, rounds)).all()
+        if kind == "xcd":
+            assert b.info()["xcd_path"]
+    finally:
+        b.close()
