@@ -110,6 +110,9 @@ def tune_mutex(ctx, nwg: int, nlocks: int = 1, words: int = 16, total: int = 409
     for kind, params in candidates or mutex_candidates():
         m = api.Mutex(ctx, kind, nlocks, words, timeout_ms=limit_ms, **params)
         try:
+            # one eager run first: queue mutexes size their slots on first use, which a
+            # graph recording cannot do
+            m.launch(nwg, lanes, nwg, 0, seed)
             ms = _graph_time(ctx, lambda: m.launch(nwg, lanes, total, max_delay, seed), 1)
             w = m.words()
         except api.N.SpError as e:

@@ -80,3 +80,14 @@ def test_tune_serve_picks_a_consistent_config(ctx):
                                                dict(nwg=1024, poll_sleep=2, far_sleep=1)])
     assert all(c["consistent"] for c in r["candidates"])
     assert r["best"]["p99_us"] == min(c["p99_us"] for c in r["candidates"])
+
+
+def test_tune_mutex_times_queue_locks(ctx):
+    """Queue mutexes allocate their slots on first use; the tuner warms every candidate up
+    before recording it, so they are timed rather than rejected."""
+    from paper_1110_4623_amd import tune
+    announce("tune queue mutexes")
+    r = tune.tune_mutex(ctx, 256, total=1024, candidates=[("array", {"poll_sleep": 0}),
+                                                           ("ring", {"poll_sleep": 0})])
+    for c in r["candidates"]:
+        assert c["consistent"] and "error" not in c, c
