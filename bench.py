@@ -200,7 +200,7 @@ def main() -> int:
         },
         "roofline": {
             "bound": "atomic",
-            "kernel": f"k_barrier_hash<{args.barrier}>",
+            "kernel": f"k_barrier_hash<{args.barrier}, plain data>",
             "achieved": round(arrivals / 1e9, 6),
             "peak": round(a1 / 1e9, 6),
             "unit": "G arrivals/s vs contended atomics/s",

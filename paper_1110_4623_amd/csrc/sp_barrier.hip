@@ -24,7 +24,7 @@ namespace {
 // stores and loads, so only the barrier orders them -- or, for a barrier created with
 // coherent_cs, with agent-scope stores and loads (the paper's volatile accesses), which
 // the barrier then orders without cache maintenance.
-template <int KIND>
+template <int KIND, bool COHERENT>
 __global__ SP_FULL_OCCUPANCY void k_barrier_hash(sp::BarrierState s, uint32_t rounds, uint32_t seed,
                                uint32_t* slots, uint32_t* out, uint32_t* err,
                                uint64_t timeout) {
@@ -32,18 +32,18 @@ __global__ SP_FULL_OCCUPANCY void k_barrier_hash(sp::BarrierState s, uint32_t ro
   const uint32_t b = blockIdx.x, N = s.nwg;
   const uint32_t writer = blockDim.x - 1, reader = 64 % blockDim.x;
   uint32_t chk = 0;
-  const bool coherent = !s.fenced;
   for (uint32_t r = 0; r < rounds; ++r) {
     if (threadIdx.x == writer) {
       uint32_t* p = slots + (r & 1) * N + b;
       const uint32_t v = sp::sm32(seed ^ (b << 16) ^ r);
-      if (coherent) sp::st_relaxed(p, v);
+      if constexpr (COHERENT) sp::st_relaxed(p, v);
       else *p = v;
     }
     if (!sp::barrier_wait<KIND>(s, r, ctl)) return;
     if (threadIdx.x == reader) {
       const uint32_t* p = slots + (r & 1) * N + (uint32_t)(((uint64_t)b + r) % N);
-      chk ^= coherent ? sp::ld_relaxed(p) : *p;
+      if constexpr (COHERENT) chk ^= sp::ld_relaxed(p);
+      else chk ^= *p;
     }
   }
   if (threadIdx.x == reader) out[b] = chk;
@@ -78,16 +78,24 @@ __global__ void k_barrier_round(uint32_t N, uint32_t r, uint32_t rounds, uint32_
   if (r < rounds) slots[(r & 1) * N + b] = sp::sm32(seed ^ (b << 16) ^ r);
 }
 
-const void* barrier_kernel(uint32_t kind) {
+// The coherent-data variant is its own instantiation (its slot accesses differ, and a
+// kernel trace then tells the two apart); the barrier protocol reads s.fenced.
+template <bool COHERENT>
+const void* barrier_kernel_c(uint32_t kind) {
   switch (kind) {
-    case SP_BARRIER_CENTRAL: return (const void*)k_barrier_hash<SP_BARRIER_CENTRAL>;
-    case SP_BARRIER_CENTRAL_SPLIT: return (const void*)k_barrier_hash<SP_BARRIER_CENTRAL_SPLIT>;
-    case SP_BARRIER_TREE: return (const void*)k_barrier_hash<SP_BARRIER_TREE>;
-    case SP_BARRIER_XCD: return (const void*)k_barrier_hash<SP_BARRIER_XCD>;
-    case SP_BARRIER_FLAG: return (const void*)k_barrier_hash<SP_BARRIER_FLAG>;
+    case SP_BARRIER_CENTRAL: return (const void*)k_barrier_hash<SP_BARRIER_CENTRAL, COHERENT>;
+    case SP_BARRIER_CENTRAL_SPLIT:
+      return (const void*)k_barrier_hash<SP_BARRIER_CENTRAL_SPLIT, COHERENT>;
+    case SP_BARRIER_TREE: return (const void*)k_barrier_hash<SP_BARRIER_TREE, COHERENT>;
+    case SP_BARRIER_XCD: return (const void*)k_barrier_hash<SP_BARRIER_XCD, COHERENT>;
+    case SP_BARRIER_FLAG: return (const void*)k_barrier_hash<SP_BARRIER_FLAG, COHERENT>;
     case SP_BARRIER_GRID_SYNC: return (const void*)k_barrier_hash_gridsync;
     default: return nullptr;
   }
+}
+
+const void* barrier_kernel(uint32_t kind, bool coherent) {
+  return coherent ? barrier_kernel_c<true>(kind) : barrier_kernel_c<false>(kind);
 }
 
 }  // namespace
@@ -210,7 +218,7 @@ int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t
   sp_ctx* ctx = b->ctx;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
-  const void* kern = barrier_kernel(b->kind);
+  const void* kern = barrier_kernel(b->kind, b->st.fenced == 0);
   if (!kern) return SP_E_INVAL;
   // Every workgroup must be resident at once (the barrier's persistent-threads
   // requirement, Section 5); refuse instead of hanging.
