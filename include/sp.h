@@ -326,6 +326,19 @@ int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, 
  * 16-byte loads and stores, `reps` times; the streaming read+write reference kernel.   */
 int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint32_t reps,
                   sp_stats* st, void* stream);
+/* sp_bench_litmus: memory-model litmus tests on `pairs` pairs of workgroups that run on
+ * different XCDs, `iters` trials per pair, both sides meeting every trial.
+ * test 0, message passing: plain data store, flag store; flag poll, plain data load;
+ *   forbidden: the data older than the flag.  variant 0 release + acquire fences (the
+ *   primitives' idiom), 1 no acquire, 2 no release, 3 neither.
+ * test 1, store buffering: each side stores its word then loads the other's (agent-scope
+ *   relaxed accesses); forbidden: both loads old.  variant 0 an agent-scope sequentially
+ *   consistent fence between store and load, 1 none.
+ * out: device, 1 uint64 = forbidden outcomes observed (0 expected for variant 0).
+ * Errors: SP_E_INVAL (pairs not in [1, 1024], unknown test or variant), SP_E_TIMEOUT,
+ * SP_E_HIP.                                                                             */
+int sp_bench_litmus(sp_ctx* ctx, uint32_t test, uint32_t variant, uint32_t pairs,
+                    uint32_t iters, uint64_t* out, sp_stats* st, void* stream);
 /* sp_bench_pingpong: two workgroups hand a token back and forth `rounds` times through
  * two agent-scope words (release store, relaxed polling, acquire fence), measuring the
  * one-way coherence latency.  words: device, 2048 bytes, zeroed by the call.

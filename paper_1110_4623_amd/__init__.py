@@ -9,12 +9,12 @@ the primitives, and an autotuner for their parameters.  The compute path is libs
 
 from .api import (Barrier, Context, DeviceBuffer, Graph, Mutex, Semaphore, barrier_hash_launches,
                   bounded_buffer,
-                  bench_atomic, copy, make_params, paper12, pingpong, serve,
+                  bench_atomic, copy, litmus, make_params, paper12, pingpong, serve,
                   serve_launch_per_request, stream_read)
 from ._native import SpError, SpNotResident, SpTimeout
 
 __all__ = ["Barrier", "Context", "DeviceBuffer", "Graph", "Mutex", "Semaphore", "barrier_hash_launches",
            "bounded_buffer",
-           "bench_atomic", "copy", "make_params", "paper12", "pingpong", "serve",
+           "bench_atomic", "copy", "litmus", "make_params", "paper12", "pingpong", "serve",
            "serve_launch_per_request", "stream_read", "SpError",
            "SpNotResident", "SpTimeout"]

@@ -423,6 +423,21 @@ def copy(ctx: Context, dst, src, nbytes: int, reps: int = 1):
     return st.as_dict()
 
 
+LITMUS = {"mp": (0, {"fenced": 0, "no_acquire": 1, "no_release": 2, "none": 3}),
+          "sb": (1, {"fenced": 0, "none": 1})}
+
+
+def litmus(ctx: Context, test: str, variant: str, pairs: int, iters: int) -> dict:
+    """Memory-model litmus test (sp_bench_litmus); returns forbidden outcomes and trials."""
+    t, variants = LITMUS[test]
+    out = ctx.zeros(1, "u64")
+    st = N.Stats()
+    check(lib.sp_bench_litmus(ctx.h, t, variants[variant], pairs, iters, ctx.ptr(out),
+                              ctypes.byref(st), ctx.stream()), "sp_bench_litmus", ctx.h)
+    return {"forbidden": int(ctx.read(out, "u64", 1)[0]), "trials": pairs * iters,
+            "stats": st.as_dict()}
+
+
 def pingpong(ctx: Context, rounds: int):
     words = ctx.zeros(512)
     out = ctx.zeros(4)

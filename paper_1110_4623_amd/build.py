@@ -27,7 +27,7 @@ CFLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 SOURCES = ["sp_api.hip", "sp_barrier.hip", "sp_mutex.hip", "sp_sem.hip", "sp_bench.hip",
-           "sp_serve.hip", "sp_cond.hip"]
+           "sp_serve.hip", "sp_cond.hip", "sp_litmus.hip"]
 
 
 def sources():
