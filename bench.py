@@ -131,10 +131,12 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     ctx.synchronize()  # every library call returns after its kernels finished
+    clock_before = sp.shader_clock_mhz(ctx)
     t0 = time.perf_counter()
     results = [step() for _ in range(args.steps)]
     ctx.synchronize()
     wall = time.perf_counter() - t0
+    clock_after = sp.shader_clock_mhz(ctx)
 
     bar_ms = float(np.mean([r["bar_ms"] for r in results]))
     us_round = bar_ms * 1e3 / ROUNDS
@@ -197,6 +199,7 @@ def main() -> int:
             "serve_launch_per_request_p99_us": med("serve_launch", "p99_us"),
             "serve_launch_per_request_req_per_s": med("serve_launch", "req_per_s"),
             "serve_results_identical": all(r["serve_same"] for r in results),
+            "shader_clock_mhz_before_after": [round(clock_before, 1), round(clock_after, 1)],
         },
         "roofline": {
             "bound": "atomic",

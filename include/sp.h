@@ -322,6 +322,10 @@ int sp_bench_paper12(sp_ctx* ctx, uint32_t test, uint32_t nwg, uint32_t lanes, u
  * uint32 words into out_sum (device, 1 uint64).  nwg = 0 picks a grid.                 */
 int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, uint32_t reps,
                     uint64_t* out_sum, sp_stats* st, void* stream);
+/* sp_bench_clock: one lane spins for `ms` milliseconds of the constant-rate wall clock
+ * and counts shader clocks meanwhile (clock64 against wall_clock64).  out: device, 2
+ * uint64 scratch; *mhz (host) = the shader clock rate observed.  ms in [1, 10000].      */
+int sp_bench_clock(sp_ctx* ctx, uint32_t ms, uint64_t* out, double* mhz, void* stream);
 /* sp_bench_copy: copies `bytes` (multiple of 16) from src to dst (device, disjoint) with
  * 16-byte loads and stores, `reps` times; the streaming read+write reference kernel.   */
 int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint32_t reps,

@@ -438,6 +438,15 @@ def litmus(ctx: Context, test: str, variant: str, pairs: int, iters: int) -> dic
             "stats": st.as_dict()}
 
 
+def shader_clock_mhz(ctx: Context, ms: int = 20) -> float:
+    """Shader clock rate observed by one spinning lane over `ms` of wall clock."""
+    out = ctx.zeros(2, "u64")
+    mhz = ctypes.c_double(0)
+    check(lib.sp_bench_clock(ctx.h, ms, ctx.ptr(out), ctypes.byref(mhz), ctx.stream()),
+          "sp_bench_clock", ctx.h)
+    return mhz.value
+
+
 def pingpong(ctx: Context, rounds: int):
     words = ctx.zeros(512)
     out = ctx.zeros(4)

@@ -135,6 +135,17 @@ __global__ void k_stream(const uint4* __restrict__ buf, uint64_t n16, uint32_t r
   block_sum_to(s, out_sum);
 }
 
+// Clock probe: one lane spins for `wall_ticks` ticks of the constant-rate wall clock and
+// counts the shader clock meanwhile.
+__global__ void k_clock(uint64_t wall_ticks, unsigned long long* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint64_t w0 = sp::wall_clock(), c0 = sp::shader_clock();
+  uint64_t w = w0;
+  while (w - w0 < wall_ticks) w = sp::wall_clock();
+  out[0] = sp::shader_clock() - c0;
+  out[1] = w - w0;
+}
+
 // Streaming copy: 16-byte loads and stores, grid-stride.
 __global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n16) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16;
@@ -262,6 +273,21 @@ int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, 
   hipLaunchKernelGGL(k_stream, dim3(nwg), dim3(256), 0, s, (const uint4*)buf, bytes / 16, reps,
                      reinterpret_cast<unsigned long long*>(out_sum));
   return spi::end_timed(ctx, s, st, nwg, 256, 0, bytes * reps);
+}
+
+int sp_bench_clock(sp_ctx* ctx, uint32_t ms, uint64_t* out, double* mhz, void* stream) {
+  if (!ctx || !out || !mhz || ms == 0 || ms > 10000) return SP_E_INVAL;
+  hipStream_t s = spi::as_stream(stream);
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  const uint64_t ticks = (uint64_t)ms * ctx->wall_khz;
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s, ticks,
+                     reinterpret_cast<unsigned long long*>(out));
+  SP_HIP(ctx, hipGetLastError());
+  SP_HIP(ctx, hipStreamSynchronize(s));
+  uint64_t h[2];
+  SP_HIP(ctx, hipMemcpy(h, out, sizeof(h), hipMemcpyDeviceToHost));
+  *mhz = h[1] ? (double)h[0] / (double)h[1] * ctx->wall_khz / 1e3 : 0.0;
+  return SP_OK;
 }
 
 int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint32_t reps,

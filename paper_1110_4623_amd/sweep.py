@@ -114,15 +114,22 @@ def ceilings(ctx, rows) -> dict:
     buf = ctx.zeros(nbytes // 4)
     api.stream_read(ctx, buf, nbytes, 1)
     _, st = api.stream_read(ctx, buf, nbytes, 3)
-    del buf
     stream = 3 * nbytes / (st["kernel_ms"] * 1e-3) / 1e9
+    # L2-resident: 16 MiB read by 2048 workgroups is 2 MiB per XCD (inside its 4 MB L2) and
+    # 64 KiB per CU (beyond its 32 KiB L1)
+    small = 16 << 20
+    api.stream_read(ctx, buf, small, 5, nwg=2048)
+    _, st = api.stream_read(ctx, buf, small, 200, nwg=2048)
+    l2 = 200 * small / (st["kernel_ms"] * 1e-3) / 1e9
+    del buf
     out, st = api.pingpong(ctx, 20000)
     lcoh = st["kernel_ms"] * 1e6 / (2 * 20000)
     return {"A1_ops_per_s": a1 and a1["ops_per_s"], "A1_setting": a1 and
             {k: a1[k] for k in ("op", "mode", "nwg")},
             "A_dist_ops_per_s": ad and ad["ops_per_s"], "A_dist_setting": ad and
             {k: ad[k] for k in ("op", "mode", "nwg")},
-            "stream_read_GB_per_s": stream, "coherence_latency_ns": lcoh,
+            "stream_read_GB_per_s": stream, "l2_read_GB_per_s": l2,
+            "coherence_latency_ns": lcoh, "shader_clock_mhz": api.shader_clock_mhz(ctx),
             "pingpong_xcc": out[2:4]}
 
 

@@ -121,3 +121,10 @@ def test_config_grid_at_full_width(ctx, op, mode, nwg):
                 assert (finals == ef).all(), (T, stride)
                 if op != "st":
                     assert s == es
+
+
+def test_shader_clock_probe(ctx):
+    import paper_1110_4623_amd as sp
+    mhz = sp.shader_clock_mhz(ctx, 10)
+    print(f"[clock] shader clock {mhz:.0f} MHz", flush=True)
+    assert 300 < mhz < 4000
