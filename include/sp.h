@@ -63,6 +63,9 @@ enum sp_mutex_kind {
                              /* unlock advances the head                                */
   SP_MUTEX_ARRAY = 6,        /* array queue lock: draw ticket t, poll only slot t mod Q */
                              /* (its own line) until it holds t; unlock grants the next */
+  SP_MUTEX_ADAPTIVE = 7,     /* ticket mutex whose waiters sleep in proportion to their */
+                             /* distance from the head, scaled by a hand-over time each */
+                             /* workgroup learns online from its own waits              */
   SP_MUTEX_DEFAULT = 15
 };
 

@@ -26,6 +26,7 @@ struct MutexState {
 // on every hand-over).
 struct MutexHold {
   uint32_t ticket;
+  uint32_t handoff;  // SP_MUTEX_ADAPTIVE: learned wall-clock ticks per hand-over (0 = none yet)
 };
 
 // KIND:
@@ -46,6 +47,16 @@ struct MutexHold {
 //                         line) until it holds t; unlock writes t + 1 into slot t + 1.  A
 //                         grant is overwritten only after its owner entered and left, so
 //                         any number of slots is correct; more slots spread the polling.
+//   SP_MUTEX_ADAPTIVE     ticket mutex with proportional waiting tuned online (Section 5's
+//                         aggressive lock that reverts to backoff): a waiter d tickets from
+//                         the head sleeps about (d - 1) / 4 hand-over times before polling
+//                         again, the one next in line polls without sleeping; each
+//                         workgroup keeps a running average of the hand-over time in its
+//                         MutexHold (which must then persist across acquisitions), measured
+//                         as the rate at which the head advanced between its first and last
+//                         polls that saw the head short of its ticket -- not its own
+//                         elapsed wait, which would include its own lag in noticing its
+//                         turn and feed oversleeping back into the estimate.
 // FENCED = false: the caller's critical sections touch the protected data only with
 // agent-scope (coherent) loads and stores, so the lock needs no acquire fence and the
 // unlock no release fence; the unlock still waits until the section's stores completed.
@@ -77,6 +88,41 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
         if (!(ok = w.tick())) break;
       }
       if (hold) hold->ticket = my;
+    } else if constexpr (KIND == SP_MUTEX_ADAPTIVE) {
+      const uint32_t my = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
+      const uint32_t* turn = s.turn + (size_t)lock * s.stride;
+      const uint32_t learned = hold ? hold->handoff : 0;
+      uint64_t t_first = 0, t_last = 0;
+      uint32_t c_first = 0, c_last = 0;
+      bool seen = false;
+      for (;;) {
+        const uint32_t cur = ld_relaxed(turn);
+        const uint64_t now = wall_clock();
+        if (cur == my) break;
+        if (!seen) {
+          seen = true;
+          t_first = now;
+          c_first = cur;
+        }
+        t_last = now;
+        c_last = cur;
+        const uint32_t d = my - cur;
+        if (d > 1 && learned) {
+          // (d - 1) / 4 hand-overs; one wall tick (10 ns) is ~0.375 s_sleep units at 2.4 GHz
+          const uint64_t units = ((uint64_t)(d - 1) * learned * 3) / 32;
+          sleep_units(units < 4096 ? (uint32_t)units : 4096u);
+        }
+        if (!(ok = w.tick())) break;
+      }
+      if (hold) {
+        hold->ticket = my;
+        const uint32_t moved = c_last - c_first;
+        if (seen && moved > 0) {
+          const uint32_t sample = (uint32_t)((t_last - t_first) / moved);
+          const uint32_t avg = learned ? (7 * learned + sample) / 8 : sample;
+          hold->handoff = avg < 100000 ? avg : 100000;  // at most 1 ms of wall clock
+        }
+      }
     } else if constexpr (KIND == SP_MUTEX_RING) {
       const uint32_t t = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
       uint32_t* q = s.queue + (size_t)lock * s.qlen * s.qstride;
@@ -120,7 +166,7 @@ __device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold
   if (is_leader()) {
     uint32_t* w;
     uint32_t v;
-    if constexpr (KIND == SP_MUTEX_TICKET || KIND == SP_MUTEX_RING) {
+    if constexpr (KIND == SP_MUTEX_TICKET || KIND == SP_MUTEX_RING || KIND == SP_MUTEX_ADAPTIVE) {
       // only the holder writes turn / head, so it can publish its own ticket + 1
       w = s.turn + (size_t)lock * s.stride;
       v = (hold ? hold->ticket : ld_relaxed(w)) + 1;

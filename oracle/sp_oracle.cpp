@@ -349,13 +349,14 @@ int or_barrier_threaded(int kind, uint32_t seed, uint32_t N, uint32_t R, uint32_
 // with backoff while polling (Algorithm 3), 4 polling mutex: wait with plain loads until
 // the word reads free, then one compare-and-swap, 5 ring-buffer mutex (Section 5's design
 // alternative: enqueue one's id, wait until the head's entry is one's own), 6 array queue
-// lock (wait on one's own slot, unlock grants the next).
+// lock (wait on one's own slot, unlock grants the next), 7 ticket mutex waiting in
+// proportion to the distance from the head.
 // Workload: see or_mutex_closed.  An owner word checks mutual exclusion inside every
 // critical section.  Returns 0, or -2 on a mutual-exclusion violation.
 int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uint32_t L,
                       uint32_t W, uint32_t imin, uint32_t imax, uint32_t* words,
                       double* seconds) {
-  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 6) return -1;
+  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 7) return -1;
   std::vector<Word> lockw(L), ticket(L), turn(L), owner(L);
   for (uint32_t l = 0; l < L; ++l) lockw[l] = 0, ticket[l] = 0, turn[l] = 0, owner[l] = 0;
   // kinds 5 (ring) and 6 (array): Q slots per lock, Q a power of two >= agents
@@ -391,6 +392,15 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
         while (turn[l].load(std::memory_order_acquire) != my) bo();
         return my;
       }
+      case 7: {  // ticket lock, waiting in proportion to the distance from the head
+        uint32_t my = ticket[l].fetch_add(1, std::memory_order_relaxed);
+        for (;;) {
+          const uint32_t cur = turn[l].load(std::memory_order_acquire);
+          if (cur == my) return my;
+          for (uint32_t k = 1; k < my - cur && k < 64; ++k) relax();
+          relax();
+        }
+      }
       case 5: {  // ring: enqueue one's id, wait until the head's entry is one's own
         uint32_t my = ticket[l].fetch_add(1, std::memory_order_relaxed);
         Word* ring = &slots[(size_t)l * Q];
@@ -418,7 +428,7 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
     }
   };
   auto unlock = [&](uint32_t l, uint32_t my) {
-    if (kind == 3) {
+    if (kind == 3 || kind == 7) {
       uint32_t t = turn[l].load(std::memory_order_relaxed);  // only the holder writes turn
       turn[l].store(t + 1, std::memory_order_release);
     } else if (kind == 5) {

@@ -44,7 +44,7 @@ __global__ SP_FULL_OCCUPANCY void k_bounded_buffer(sp::MutexState m, sp::CondSta
   unsigned long long sum = 0;
   uint64_t done = 0;
   for (uint64_t j = 0; j < A; ++j) {
-    sp::MutexHold hold;
+    sp::MutexHold hold{0, 0};
     if (!sp::mutex_lock<MKIND>(m, 0, ctl, &hold)) return;
     for (;;) {
       if (sp::is_leader()) s_blocked = prod ? (*count == capacity) : (*count == 0);

@@ -31,10 +31,10 @@ __global__ SP_FULL_OCCUPANCY void k_mutex(sp::MutexState s, uint32_t nlocks, uin
   const sp::Ctl ctl{err, sp::wall_clock() + timeout};
   const uint32_t b = blockIdx.x;
   const uint64_t A = total / nwg + (b < total % nwg ? 1 : 0);
+  sp::MutexHold hold{0, 0};  // persists: the adaptive mutex learns across acquisitions
   for (uint64_t j = 0; j < A; ++j) {
     const uint32_t lock = sp::sched_key(seed, b, (uint32_t)j, 1) % nlocks;
     if (sp::is_leader()) sp::spin_cycles(sp::sched_key(seed, b, (uint32_t)j, 2) % (max_delay + 1));
-    sp::MutexHold hold;
     if (!sp::mutex_lock<KIND, FENCED>(s, lock, ctl, &hold)) return;
     uint32_t* own = owner ? owner + (size_t)lock * s.stride : nullptr;
     if (own && sp::is_leader() && sp::exch_relaxed(own, b + 1) != 0)
@@ -71,6 +71,7 @@ const void* mutex_kernel_f(uint32_t kind) {
     case SP_MUTEX_SLEEP: return (const void*)k_mutex<SP_MUTEX_SLEEP, FENCED>;
     case SP_MUTEX_RING: return (const void*)k_mutex<SP_MUTEX_RING, FENCED>;
     case SP_MUTEX_ARRAY: return (const void*)k_mutex<SP_MUTEX_ARRAY, FENCED>;
+    case SP_MUTEX_ADAPTIVE: return (const void*)k_mutex<SP_MUTEX_ADAPTIVE, FENCED>;
     default: return nullptr;
   }
 }
@@ -88,7 +89,7 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
   if (!ctx || !out || nlocks == 0 || words_per_lock == 0 || nlocks > (1u << 20) ||
       words_per_lock > (1u << 16))
     return SP_E_INVAL;
-  if (kind > SP_MUTEX_ARRAY && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_MUTEX_ADAPTIVE && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -146,7 +147,8 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
     q.coherent_cs = m->p.coherent_cs;  // a property of the caller's critical sections
   }
   if (kind == SP_MUTEX_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) q.backoff = SP_BACKOFF_EXP;
-  if (kind == SP_MUTEX_SPIN_CAS || kind == SP_MUTEX_SLEEP) q.backoff = SP_BACKOFF_NONE;
+  if (kind == SP_MUTEX_SPIN_CAS || kind == SP_MUTEX_SLEEP || kind == SP_MUTEX_ADAPTIVE)
+    q.backoff = SP_BACKOFF_NONE;
   const void* kern = mutex_kernel(kind, q.coherent_cs != 0);
   if (!kern) return SP_E_INVAL;
   const uint32_t sw = spi::stride_words(q);

@@ -96,7 +96,7 @@ def mutex_candidates():
     out += [("ticket", {"poll_sleep": ps}) for ps in (0, 1, 4)]
     out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
     out += [("array", {"poll_sleep": ps}) for ps in (0, 1, 4)]
-    out += [("ring", {"poll_sleep": 0})]
+    out += [("ring", {"poll_sleep": 0}), ("adaptive", {})]
     return out
 
 

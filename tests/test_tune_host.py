@@ -44,6 +44,7 @@ def test_candidate_lists_cover_every_kind():
     assert {k for k, _ in tune.barrier_candidates()} == {"central", "central_split", "xcd",
                                                           "flag", "tree"}
     assert {k for k, _ in tune.mutex_candidates()} == {"spin_cas", "spin_exch", "spin_backoff",
-                                                        "ticket", "sleep", "ring", "array"}
+                                                        "ticket", "sleep", "ring", "array",
+                                                        "adaptive"}
     assert {k for k, _ in tune.semaphore_candidates()} == {"spin", "spin_backoff", "ticket",
                                                             "sleep", "counters"}
