@@ -117,13 +117,6 @@ const void* bb_kernel(uint32_t kind) {
   }
 }
 
-struct DevMem {
-  uint32_t* p = nullptr;
-  ~DevMem() {
-    if (p) (void)hipFree(p);
-  }
-};
-
 }  // namespace
 
 extern "C" {
@@ -153,9 +146,9 @@ int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, u
   const uint64_t bstate_words = (uint64_t)B_LINES * kLine;
   const uint64_t res_words = 8ull * nwg;  // 4 uint64 per workgroup
   const uint64_t total = mutex_words + cond_words + bstate_words + capacity + res_words + 64;
-  DevMem mem;
+  spi::DeviceScratch mem;
   SP_HIP(ctx, hipMalloc(&mem.p, total * sizeof(uint32_t)));
-  uint32_t* base = mem.p;
+  uint32_t* base = mem.as<uint32_t>();
   sp::MutexState ms;
   ms.stride = sw;
   ms.poll_sleep = q.poll_sleep;

@@ -86,6 +86,22 @@ int end_timed(sp_ctx* ctx, hipStream_t s, sp_stats* st, uint32_t nwg, uint32_t l
 
 inline bool lanes_ok(uint32_t lanes) { return lanes >= 64 && lanes <= 1024 && lanes % 64 == 0; }
 
+// Device memory owned for the duration of one call; the caller synchronizes the stream
+// before it goes out of scope.
+struct DeviceScratch {
+  void* p = nullptr;
+  DeviceScratch() = default;
+  DeviceScratch(const DeviceScratch&) = delete;
+  DeviceScratch& operator=(const DeviceScratch&) = delete;
+  ~DeviceScratch() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
 inline uint32_t bucket_of(uint32_t contenders) { return contenders >= 64 ? 1u : 0u; }
 
 }  // namespace spi

@@ -106,13 +106,6 @@ __global__ void k_litmus_sum(const unsigned long long* bad, uint32_t pairs,
   out[0] = s;
 }
 
-struct DevMem {
-  void* p = nullptr;
-  ~DevMem() {
-    if (p) (void)hipFree(p);
-  }
-};
-
 }  // namespace
 
 extern "C" {
@@ -126,18 +119,18 @@ int sp_bench_litmus(sp_ctx* ctx, uint32_t test, uint32_t variant, uint32_t pairs
   SP_HIP(ctx, hipSetDevice(ctx->device));
   if (spi::capturing(s)) return SP_E_INVAL;
   const uint64_t mem_words = (uint64_t)pairs * kPairLines * kLine;
-  DevMem mem, bad;
+  spi::DeviceScratch mem, bad;
   SP_HIP(ctx, hipMalloc(&mem.p, mem_words * sizeof(uint32_t)));
   SP_HIP(ctx, hipMalloc(&bad.p, (size_t)pairs * sizeof(unsigned long long)));
-  SP_CHECK(spi::fill_u32(ctx, static_cast<uint32_t*>(mem.p), mem_words, 0, s));
-  SP_CHECK(spi::fill_u32(ctx, static_cast<uint32_t*>(bad.p), 2ull * pairs, 0, s));
+  SP_CHECK(spi::fill_u32(ctx, mem.as<uint32_t>(), mem_words, 0, s));
+  SP_CHECK(spi::fill_u32(ctx, bad.as<uint32_t>(), 2ull * pairs, 0, s));
   SP_CHECK(spi::begin_timed(ctx, s));
   sp_params q;
   sp_params_default(&q);
   const uint64_t timeout = spi::timeout_ticks(ctx, q);
   const uint32_t nwg = 2 * pairs;  // both sides of every pair resident: 2048 at most
-  auto* badp = static_cast<unsigned long long*>(bad.p);
-  auto* memp = static_cast<uint32_t*>(mem.p);
+  auto* badp = bad.as<unsigned long long>();
+  auto* memp = mem.as<uint32_t>();
   if (test == 0)
     hipLaunchKernelGGL(k_litmus_mp, dim3(nwg), dim3(64), 0, s, memp, iters, variant, badp,
                        ctx->d_err, timeout);
