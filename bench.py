@@ -15,8 +15,13 @@ One step runs the whole path once over the full-size synthetic workloads:
      persistent workgroups, then the same stream served with one kernel launch per
      request over four streams (the comparator); p50/p99 latency of both.
 
-Prints one JSON line.  `value` is microseconds per barrier round (lower is better);
-the other primitives' throughputs ride along in `metrics`.
+Every step also times the kernel-boundary comparator: one launch per round of the same
+hash exchange, 10^4 + 1 launches replayed from one HIP graph.
+
+Prints one JSON line.  `value` is microseconds per barrier round (lower is better), the
+mean over the timed steps (the figure a kernel trace's average duration gives); the
+median and minimum ride along with the other primitives' throughputs in `metrics`, and
+`env` records the device, its clock, the occupancy and the build.
 
 The process does not import PyTorch: the library binds to the system ROCm runtime and
 allocates its buffers itself (SP_NO_TORCH), which is also what rocprofv3 profiles.
@@ -80,11 +85,25 @@ def cpu_baseline(budget_s: float = 20.0) -> dict:
             "ok": rc == 0 and rc2 == 0}
 
 
+def environment(ctx, resident_per_cu: int) -> dict:
+    """Device, runtime and build the figures were taken with."""
+    from paper_1110_4623_amd import build
+    try:
+        rocm = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        rocm = None
+    return {"device": ctx.info["name"] or None, "arch": ctx.info["arch"], "cus": ctx.info["cu_count"],
+            "xcds": ctx.info["xcd_count"], "peak_shader_clock_mhz": ctx.info["clock_khz"] / 1e3,
+            "barrier_resident_workgroups_per_cu": int(resident_per_cu), "rocm": rocm,
+            "hipcc_flags": " ".join(os.path.relpath(f, ROOT) if os.path.isabs(f) else f
+                                    for f in build.CFLAGS)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--barrier", default="xcd")
     args = ap.parse_args()
@@ -114,7 +133,9 @@ def main() -> int:
         _, _, st = sp.bench_atomic(ctx, "add", NWG, LANES, 1, 4, "wave_leader", 100, 42, perm1, abuf)
         r["a1_ms"], r["a1_ops"] = st["kernel_ms"], st["ops"]
         chk, st = bar.run_hash(LANES, ROUNDS, 42)
-        r["bar_ms"], r["bar_chk"] = st["kernel_ms"], chk
+        r["bar_ms"], r["bar_chk"], r["bar_occ"] = st["kernel_ms"], chk, st["resident_per_cu"]
+        chk_k, st_k = sp.barrier_hash_launches(ctx, NWG, LANES, ROUNDS, 42, graph=True)
+        r["bar_kb_ms"], r["bar_kb_same"] = st_k["kernel_ms"], bool((chk_k == chk).all())
         chk_c, st_c = bar_coh.run_hash(LANES, ROUNDS, 42)
         r["bar_coh_ms"], r["bar_coh_same"] = st_c["kernel_ms"], bool((chk_c == chk).all())
         words, st, _ = mtx.run(NWG, LANES, MUTEX_TOTAL, 1000, 42)
@@ -140,6 +161,8 @@ def main() -> int:
 
     bar_ms = float(np.mean([r["bar_ms"] for r in results]))
     us_round = bar_ms * 1e3 / ROUNDS
+    per_round = np.array([r["bar_ms"] for r in results]) * 1e3 / ROUNDS
+    kb_us = float(np.median([r["bar_kb_ms"] for r in results])) * 1e3 / ROUNDS
     a1 = float(np.mean([r["a1_ops"] / (r["a1_ms"] * 1e-3) for r in results]))
     arrivals = NWG * ROUNDS / (bar_ms * 1e-3)
     deterministic = all((r["bar_chk"] == results[0]["bar_chk"]).all() for r in results)
@@ -182,6 +205,10 @@ def main() -> int:
                    "nwg": NWG, "lanes": LANES, "rounds": ROUNDS},
         "metrics": {
             "barrier_us_per_round": round(us_round, 4),
+            "barrier_us_per_round_median": round(float(np.median(per_round)), 4),
+            "barrier_us_per_round_min": round(float(per_round.min()), 4),
+            "kernel_boundary_graph_us_per_round": round(kb_us, 4),
+            "kernel_boundary_checksums_identical": all(r["bar_kb_same"] for r in results),
             "barrier_coherent_data_us_per_round": round(
                 float(np.mean([r["bar_coh_ms"] for r in results])) * 1e3 / ROUNDS, 4),
             "barrier_coherent_checksums_identical": all(r["bar_coh_same"] for r in results),
@@ -213,6 +240,7 @@ def main() -> int:
             "peak_source": "measured in this run: contended agent-scope atomic adds to one word",
             "hbm_view": hbm_view,
         },
+        "env": environment(ctx, results[0]["bar_occ"]),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

@@ -198,13 +198,19 @@ def barrier(ctx, rounds: int = 10_000, lanes: int = 256, seed: int = 42, quick: 
             try:
                 b.run_hash(lanes, 100, seed)
                 chk, st = b.run_hash(lanes, rounds, seed)
+                # the same kernel and grid with zero rounds: what the launch itself costs
+                empty_ms = b.launch(lanes, 0, seed)["kernel_ms"]
             finally:
                 b.close()
             chks[kind] = chk.tobytes()
             us = st["kernel_ms"] * 1e3 / rounds
             rows.append({"kind": kind, "nwg": N, "rounds": rounds, "us_per_round": us,
+                         "empty_launch_us": empty_ms * 1e3,
+                         "us_per_round_minus_empty_launch":
+                             (st["kernel_ms"] - empty_ms) * 1e3 / rounds,
                          "arrivals_per_s": N * rounds / (st["kernel_ms"] * 1e-3)})
-            _log(f"barrier {kind:13s} N={N:5d} {us:8.2f} us/round")
+            _log(f"barrier {kind:13s} N={N:5d} {us:8.2f} us/round (empty launch "
+                 f"{empty_ms * 1e3:.1f} us)")
         for kind in ("launch", "graph"):
             chk, st = api.barrier_hash_launches(ctx, N, lanes, rounds, seed, graph=kind == "graph")
             chks[kind] = chk.tobytes()

@@ -1,0 +1,51 @@
+"""bench.py's output contract: one JSON line with the fields the measurement needs."""
+
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from conftest import ROOT, announce
+
+
+def _bench(*args, timeout=300):
+    env = dict(os.environ, SP_NO_TORCH="1")
+    return subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), *args],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=timeout)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    p = _bench("--gpus", "2", timeout=60)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
+
+
+@pytest.mark.gpu
+def test_one_step_prints_the_contract_line():
+    announce("bench.py", "--steps 1 --warmup 0 --no-cpu-baseline")
+    p = _bench("--steps", "1", "--warmup", "0", "--no-cpu-baseline")
+    assert p.returncode == 0, p.stderr[-2000:]
+    lines = [l for l in p.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+              "metrics", "roofline", "env"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 1 and d["warmup"] == 0
+    assert d["value"] > 0 and d["higher_is_better"] is False and d["dtype"] == "u32"
+    assert "workload" in d["config"]
+    m = d["metrics"]
+    for flag in ("barrier_checksums_deterministic", "barrier_coherent_checksums_identical",
+                 "kernel_boundary_checksums_identical", "mutex_counts_exact",
+                 "semaphore_state_exact", "serve_results_identical"):
+        assert m[flag] is True, flag
+    assert m["barrier_us_per_round_min"] <= m["barrier_us_per_round_median"]
+    r = d["roofline"]
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in r, k
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-2)
+    assert d["env"]["arch"].startswith("gfx950")
+    assert "packed-fp32-ops" in d["env"]["hipcc_flags"]
