@@ -140,7 +140,15 @@ typedef struct sp_params {
                          /* volatile accesses), so the barrier does no cache maintenance   */
                          /* (and the per-XCD barrier needs no per-CU release hop).         */
                          /* 0 = plain accesses, fenced (the general contract)              */
-  uint32_t reserved[4];
+  uint32_t xcd_copies;   /* SP_BARRIER_XCD: copies of the XCD stamps that the workgroups    */
+                         /* poll for the release (default 64).  0 = one line per XCD stamp, */
+                         /* which every poller reads.  C in [1, 256], a power of two: C     */
+                         /* padded lines that each hold every XCD's stamp packed; each      */
+                         /* XCD's master writes its stamp into every copy and the           */
+                         /* workgroups of a CU poll copy (XCD + number of XCDs * rank of    */
+                         /* the CU in its XCD) mod C, which spreads the polling over C      */
+                         /* lines.  Timing only; results are the same.                      */
+  uint32_t reserved[3];
 } sp_params;
 
 typedef struct sp_stats {

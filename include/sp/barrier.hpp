@@ -26,6 +26,8 @@ struct BarrierState {
   uint32_t fenced;      // 1: order plain memory (release / acquire fences); 0: the data
                         // exchanged across the barrier is accessed with agent-scope
                         // loads and stores, so the barrier does no cache maintenance
+  uint32_t xcopies;     // xcd: copies of the XCD stamps (0 = xarrive, one line per XCD)
+  uint32_t xmstride;    // xcd: words between two copies (>= groups, whole lines)
   uint32_t* cnt;        // centralized counter
   uint32_t* gen;        // centralized split: release word
   uint32_t* gcnt;       // tree: per-group counters (groups lines)
@@ -42,6 +44,9 @@ struct BarrierState {
   uint32_t* cu_count;   // xcd: workgroups registered per CU key (groups * 256 words)
   uint32_t* cu_members; // xcd: member indices per CU key (groups * 256 * kCuSlots words)
   uint32_t* xcount;     // xcd: members registered per XCD (groups words)
+  uint32_t* xcu;        // xcd: CU leaders registered per XCD (groups words)
+  uint32_t* cu_rank;    // xcd: rank of each CU key within its XCD (groups * 256 words)
+  uint32_t* xmail;      // xcd: xcopies copies, each holding every XCD's stamp packed
 };
 
 // Workgroups one CU can hold at most (32 wavefront slots).
@@ -181,7 +186,9 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
 //      release) and publishes the XCD's stamp.
 //   3. Each CU leader polls the stamps of every XCD that has members; once all are
 //      published it acquires (agent scope) and releases the other workgroups of its CU.
-//      Every flag is its own line.
+//      Every flag is its own line.  With xcopies = C > 0 the masters write their stamps
+//      into C lines that each hold all of them packed, and the CUs spread their polls
+//      over the copies by their rank in their XCD (fewer pollers per line).
 // Writebacks and invalidations both serialize at each XCD's L2 controller.  The
 // writeback is shared by the whole XCD.  The invalidation has to reach each CU's L1, and
 // on gfx950 only the agent-scope invalidate does (a workgroup-scope one leaves stale L1
@@ -197,6 +204,7 @@ struct XcdLocal {
   uint32_t key;      // CU key: XCD * 256 + CU id
   uint32_t slot;     // registration order on the CU (0 = CU leader)
   uint32_t ncu;      // workgroups on this CU
+  uint32_t mail;     // the copy of the XCD stamps this workgroup polls (xcopies > 0)
   uint32_t cu_list[kCuSlots];  // CU leader only: member indices of the CU's workgroups
 };
 
@@ -224,30 +232,42 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
   Wait w(ctl, s.poll_sleep);
   int ok = 1;
   __syncthreads();
+  const uint32_t C = s.xcopies;
   if (k == 0) {
-    // XCD master: gather the XCD's arrivals, write the XCD's L2 back once, publish.
+    // XCD master: gather the XCD's arrivals, write the XCD's L2 back once, publish (in
+    // every copy of the stamps, by the first wavefront after its writeback).
     ok = scan_flags(block, 1, members, 0, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
-    if (is_leader()) {
+    if (C == 0) {
+      if (is_leader()) {
+        if (s.fenced) fence_release();
+        st_relaxed(s.xarrive + (size_t)x * s.stride, stamp);
+      }
+    } else if (threadIdx.x < 64) {
       if (s.fenced) fence_release();
-      st_relaxed(s.xarrive + (size_t)x * s.stride, stamp);
+      for (uint32_t c = threadIdx.x; c < C; c += 64)
+        st_relaxed(s.xmail + (size_t)c * s.xmstride + x, stamp);
     }
   } else if (is_leader()) {
     st_relaxed(block + k, stamp);
   }
+  // The populated XCDs' stamps: one line each, or packed in this CU's copy.
+  const uint32_t* stamps =
+      C ? s.xmail + (size_t)__builtin_amdgcn_readfirstlane(L.mail) * s.xmstride : s.xarrive;
+  const uint32_t sstride = C ? 1 : s.stride;
   if (!s.fenced) {
     // Coherent data: no cache maintenance, so nothing is shared per CU; every workgroup
     // polls the populated XCDs' stamps itself (two flag hops per round).
     if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
-      ok = poll_until(s.xarrive + (size_t)threadIdx.x * s.stride, stamp, w);
+      ok = poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
     return __syncthreads_and(ok);
   }
   if (slot == 0) {
     // CU leader: once every populated XCD has published, invalidate for the CU and
     // release it.
     if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
-      ok = poll_until(s.xarrive + (size_t)threadIdx.x * s.stride, stamp, w);
+      ok = poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
     if (is_leader()) fence_acquire();
@@ -278,10 +298,13 @@ __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl,
     if (L.k >= s.xblock) add_relaxed(s.overflow, 1);
     L.key = xcc * 256 + cu_in_xcc();
     L.slot = add_relaxed(s.cu_count + L.key, 1);
+    if (L.slot == 0) st_relaxed(s.cu_rank + L.key, add_relaxed(s.xcu + xcc, 1));
     if (L.slot < kCuSlots)
       st_relaxed(s.cu_members + (size_t)L.key * kCuSlots + L.slot, L.k);
     else
       add_relaxed(s.overflow, 1);
+    // the registration stores are complete before the arrival (with or without fences)
+    wave_stores_complete();
     const bool ok = counter_arrive_wait<SP_BARRIER_TREE>(s, 1, ctl);
     fence_acquire();  // round 0 only: always, so the registrations below read fresh
     *use_xcd = ld_relaxed(s.overflow) == 0;
@@ -291,6 +314,7 @@ __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl,
     for (uint32_t i = 0; i < X; ++i)
       if (ld_relaxed(s.xcount + i) != 0) mask |= 1u << i;
     L.xmask = mask;
+    L.mail = s.xcopies ? (xcc + X * ld_relaxed(s.cu_rank + L.key)) % s.xcopies : 0;
     s_ok = ok;
   }
   __syncthreads();

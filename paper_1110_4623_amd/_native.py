@@ -64,7 +64,8 @@ class Params(ctypes.Structure):
         ("verify", ctypes.c_uint32),
         ("cooperative", ctypes.c_uint32),
         ("coherent_cs", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 4),
+        ("xcd_copies", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 

@@ -31,6 +31,7 @@ int normalize(const sp_ctx* ctx, const sp_params* in, sp_params* out) {
   if (p.pad_bytes < 4 || p.pad_bytes > 4096 || (p.pad_bytes & (p.pad_bytes - 1))) return SP_E_INVAL;
   if (p.fan_in == 0) p.fan_in = ctx && ctx->xcd_count ? ctx->xcd_count : 8;
   if (p.timeout_ms == 0) p.timeout_ms = 20000;
+  if (p.xcd_copies > 256 || (p.xcd_copies & (p.xcd_copies - 1))) return SP_E_INVAL;
   *out = p;
   return SP_OK;
 }
@@ -105,6 +106,7 @@ void sp_params_default(sp_params* p) {
   p->pad_bytes = 128;
   p->flags_packed = 0;
   p->timeout_ms = 20000;
+  p->xcd_copies = 64;
 }
 
 const char* sp_strerror(int code) {

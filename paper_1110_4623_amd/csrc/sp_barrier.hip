@@ -140,9 +140,14 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   const uint64_t lrel_lines = (uint64_t)G * xblock;
   // per-CU and per-XCD registration (per-XCD barrier): counts and member indices per CU
   // key, member counts per XCD, the overflow word
-  const uint64_t cu_words = (uint64_t)G * 256 * (1 + sp::kCuSlots) + G + 1;
+  const uint64_t cu_words = (uint64_t)G * 256 * (2 + sp::kCuSlots) + 2ull * G + 1;
+  // copies of the XCD stamps, each one word per XCD, padded to at least a line
+  const uint32_t copies = kind == SP_BARRIER_XCD ? q.xcd_copies : 0;
+  const uint32_t mstride = (std::max(sw, G) + sw - 1) / sw * sw;
+  const uint64_t mail_lines = (uint64_t)copies * (mstride / sw);
   const uint64_t cu_lines = (cu_words + sw - 1) / sw;
-  const uint64_t lines = 5 + 3ull * G + 2 * flag_lines + local_lines + lrel_lines + cu_lines;
+  const uint64_t lines =
+      5 + 3ull * G + 2 * flag_lines + local_lines + lrel_lines + cu_lines + mail_lines;
   b->state_words = lines * sw;
   hipError_t e = hipMalloc(&b->d_state, b->state_words * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&b->d_slots, 2ull * nwg * sizeof(uint32_t));
@@ -162,6 +167,8 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.groups = G;
   s.tgroups = std::min(G, nwg);
   s.fenced = q.coherent_cs ? 0u : 1u;
+  s.xcopies = copies;
+  s.xmstride = mstride;
   s.flag_stride = fs;
   s.poll_sleep = q.poll_sleep;
   s.xblock = xblock;
@@ -181,6 +188,9 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.cu_members = s.cu_count + (uint64_t)G * 256;        // G * 256 * kCuSlots words
   s.xcount = s.cu_members + (uint64_t)G * 256 * sp::kCuSlots;  // G words
   s.overflow = s.xcount + G;                                   // 1 word
+  s.xcu = s.overflow + 1;                                      // G words
+  s.cu_rank = s.xcu + G;                                       // G * 256 words
+  s.xmail = s.cu_count + cu_lines * sw;  // xcopies copies of xmstride words
   *out = b;
   return SP_OK;
 }

@@ -48,8 +48,9 @@ def _graph_time(ctx, record, replays: int) -> float:
 # ---- barriers ---------------------------------------------------------------------------
 
 def barrier_candidates():
-    out = [("central", {}), ("central_split", {}), ("xcd", {}),
+    out = [("central", {}), ("central_split", {}),
            ("flag", {"flags_packed": 0}), ("flag", {"flags_packed": 1})]
+    out += [("xcd", {"xcd_copies": c}) for c in (0, 8, 64, 256)]
     out += [("tree", {"fan_in": f}) for f in (4, 8, 16, 32)]
     return [(k, dict(p, poll_sleep=ps)) for k, p in out for ps in (0, 1, 4)]
 

@@ -151,3 +151,52 @@ def test_coherent_data_barriers(ctx, kind, nwg, lanes):
             assert b.info()["xcd_path"]
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("copies", [1, 8, 64, 256])
+@pytest.mark.parametrize("coherent", [0, 1])
+@pytest.mark.parametrize("nwg,lanes", [(5, 64), (300, 128), (2048, 256)])
+def test_xcd_stamp_copies(ctx, copies, coherent, nwg, lanes):
+    """xcd_copies: the XCD masters publish into several packed copies of the stamps and
+    the CUs poll different copies; the checksums stay the oracle's."""
+    import paper_1110_4623_amd as sp
+    announce("xcd copies", f"copies={copies} coherent={coherent} nwg={nwg} lanes={lanes}")
+    b = sp.Barrier(ctx, "xcd", nwg, xcd_copies=copies, coherent_cs=coherent)
+    try:
+        for seed in (42, 7):
+            chk, _ = b.run_hash(lanes, 400, seed)
+            assert (chk == oracle.barrier_closed(seed, nwg, 400)).all()
+        assert b.info()["xcd_path"]
+    finally:
+        b.close()
+
+
+def test_xcd_stamp_copies_after_cooperative_launch(ctx):
+    import paper_1110_4623_amd as sp
+    announce("grid_sync then xcd copies=8")
+    g = sp.Barrier(ctx, "grid_sync", 256)
+    try:
+        g.run_hash(256, 10, 1)
+    finally:
+        g.close()
+    b = sp.Barrier(ctx, "xcd", 2048, xcd_copies=8)
+    try:
+        chk, _ = b.run_hash(256, 300, 11)
+        assert (chk == oracle.barrier_closed(11, 2048, 300)).all()
+        assert b.info()["xcd_path"]
+    finally:
+        b.close()
+
+
+@pytest.mark.parametrize("params", [dict(xcd_copies=3), dict(xcd_copies=512)])
+def test_xcd_stamp_copies_invalid(ctx, params):
+    import paper_1110_4623_amd as sp
+    with pytest.raises(sp.SpError):
+        sp.Barrier(ctx, "xcd", 64, **params)
+
+
+@pytest.mark.parametrize("pad", [4, 16, 4096])
+def test_xcd_stamp_copies_with_small_and_large_padding(ctx, pad):
+    """A copy holds every XCD's stamp even when the padding is below 8 words."""
+    chk, _ = _run(ctx, "xcd", 1024, 128, 300, 42, xcd_copies=64, pad_bytes=pad)
+    assert (chk == oracle.barrier_closed(42, 1024, 300)).all()
