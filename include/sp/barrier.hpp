@@ -40,7 +40,8 @@ struct BarrierState {
   uint32_t* overflow;   // xcd: registrations that did not fit (nonzero = tree fallback)
   uint32_t* xarrive;    // xcd: per-XCD arrival stamps (groups lines)
   uint32_t* lrelease;   // xcd: per-workgroup release flags (nwg lines), XCD-major
-  uint32_t* larrive;    // xcd: packed arrival flags, XCD-major blocks of xblock words
+  uint32_t* larrive;    // xcd: arrival flags kArriveWords apart, XCD-major blocks of
+                        // xblock flags
   uint32_t* cu_count;   // xcd: workgroups registered per CU key (groups * 256 words)
   uint32_t* cu_members; // xcd: member indices per CU key (groups * 256 * kCuSlots words)
   uint32_t* xcount;     // xcd: members registered per XCD (groups words)
@@ -51,6 +52,10 @@ struct BarrierState {
 
 // Workgroups one CU can hold at most (32 wavefront slots).
 constexpr uint32_t kCuSlots = 32;
+// Words between two arrival flags of an XCD's block: 16 bytes, eight flags per 128-byte
+// line.  Packed flags put 32 concurrent writers on every line and one line per flag
+// makes the master's scan touch a line per member; eight per line measured fastest.
+constexpr uint32_t kArriveWords = 4;
 
 namespace detail {
 
@@ -180,8 +185,8 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
 // sends workgroup w to XCD w mod 8, but not always (after a cooperative launch, for
 // example, later dispatches have been measured to start one XCD further on).  Later rounds:
 //   1. Each member waits for its own stores to complete (they are then in the XCD's L2)
-//      and stores its arrival stamp into its XCD's packed block of arrival flags; the
-//      master's lanes scan the block.
+//      and stores its arrival stamp into its XCD's block of arrival flags (16 bytes
+//      apart); the master's lanes scan the block.
 //   2. The master writes back the XCD's dirty L2 lines once for all its members (agent
 //      release) and publishes the XCD's stamp.
 //   3. Each CU leader acquires (agent scope) once its own XCD's stamp is published,
@@ -228,7 +233,7 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
   const uint32_t members = __builtin_amdgcn_readfirstlane(L.members);
   const uint32_t xmask = __builtin_amdgcn_readfirstlane(L.xmask);
   const uint32_t slot = __builtin_amdgcn_readfirstlane(L.slot);
-  uint32_t* block = s.larrive + (size_t)x * s.xblock;
+  uint32_t* block = s.larrive + (size_t)x * s.xblock * kArriveWords;
   uint32_t* rel = s.lrelease + (size_t)x * s.xblock * s.stride;  // member k: rel + k*stride
   Wait w(ctl, s.poll_sleep);
   int ok = 1;
@@ -237,7 +242,7 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
   if (k == 0) {
     // XCD master: gather the XCD's arrivals, write the XCD's L2 back once, publish (in
     // every copy of the stamps, by the first wavefront after its writeback).
-    ok = scan_flags(block, 1, members, 0, stamp, w);
+    ok = scan_flags(block, kArriveWords, members, 0, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
     if (C == 0) {
@@ -251,7 +256,7 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
         st_relaxed(s.xmail + (size_t)c * s.xmstride + x, stamp);
     }
   } else if (is_leader()) {
-    st_relaxed(block + k, stamp);
+    st_relaxed(block + (size_t)k * kArriveWords, stamp);
   }
   // The populated XCDs' stamps: one line each, or packed in this CU's copy.
   const uint32_t* stamps =

@@ -133,10 +133,10 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   // per-XCD blocks of packed local arrival flags, each a whole number of 128-byte lines
   const uint32_t xblock = (uint32_t)(((nwg + G - 1) / G + 31) / 32 * 32);
   // layout, in lines of sw words: cnt, gen, top, topgen, mismatch, gcnt[G], ggen[G],
-  // xarrive[G], then the flag barrier's arrive and release arrays, the per-XCD packed
+  // xarrive[G], then the flag barrier's arrive and release arrays, the per-XCD
   // arrival blocks and the per-XCD blocks of release flags (one line per member)
   const uint64_t flag_lines = ((uint64_t)nwg * fs + sw - 1) / sw;
-  const uint64_t local_lines = ((uint64_t)G * xblock + sw - 1) / sw;
+  const uint64_t local_lines = ((uint64_t)G * xblock * sp::kArriveWords + sw - 1) / sw;
   const uint64_t lrel_lines = (uint64_t)G * xblock;
   // per-CU and per-XCD registration (per-XCD barrier): counts and member indices per CU
   // key, member counts per XCD, the overflow word
