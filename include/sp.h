@@ -79,6 +79,12 @@ enum sp_sem_kind {
                            /* add) and enters once posts + K > t; post adds one to the  */
                            /* posts; FIFO like Algorithm 5, one atomic per operation,   */
                            /* s_sleep between polls                                     */
+  SP_SEM_ADAPTIVE = 5,     /* SP_SEM_COUNTERS' admission rule with proportional waiting  */
+                           /* tuned online: a waiter d posts short of admission sleeps  */
+                           /* about (d - 1) / 4 post intervals between polls, the       */
+                           /* interval learned per workgroup from the rate at which the */
+                           /* posts counter advanced while it waited, so the queue's    */
+                           /* far end stops loading the counter's line                  */
   SP_SEM_DEFAULT = 15
 };
 
@@ -132,10 +138,11 @@ typedef struct sp_params {
   uint32_t cooperative;  /* barrier runs: 1 = hipLaunchCooperativeKernel; 0 = plain launch */
                          /* after the library's own co-residency check (a workgroup that   */
                          /* is not resident ends in SP_E_TIMEOUT through the watchdog)     */
-  uint32_t coherent_cs;  /* mutexes: 1 = the critical sections access the protected words */
-                         /* with agent-scope loads and stores, which every XCD sees        */
-                         /* without cache maintenance, so lock and unlock skip the acquire */
-                         /* invalidate and the release writeback.  Barriers: 1 = the data  */
+  uint32_t coherent_cs;  /* mutexes and semaphores: 1 = the critical sections access the  */
+                         /* protected words with agent-scope loads and stores, which every */
+                         /* XCD sees without cache maintenance, so lock / wait skip the    */
+                         /* acquire invalidate and unlock / post the release writeback.    */
+                         /* Barriers: 1 = the data                                         */
                          /* exchanged across the barrier is accessed that way (the paper's */
                          /* volatile accesses), so the barrier does no cache maintenance   */
                          /* (and the per-XCD barrier needs no per-CU release hop).         */
@@ -282,7 +289,8 @@ int sp_sem_destroy(sp_sem* s);
  * checksum, holds key(w, j, 3) mod (max_hold_cyc + 1) shader clocks and decrements the
  * occupancy.  out_chk: device, nwg uint32.  out_state: device, 8 uint32 =
  * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, 0, 0, 0}
- * (SP_SEM_COUNTERS: count stays 0, ticket = tickets drawn, turn = posts made).
+ * (SP_SEM_COUNTERS, SP_SEM_ADAPTIVE: count stays 0, ticket = tickets drawn, turn = posts
+ * made).
  * Errors: SP_E_INVAL, SP_E_TIMEOUT, SP_E_HIP.                                           */
 int sp_sem_run(sp_sem* s, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
                uint32_t max_hold_cyc, uint32_t seed, uint32_t track, uint32_t* out_chk,

@@ -17,14 +17,30 @@ struct SemState {
   BackoffCfg bo;        // SP_SEM_SPIN_BACKOFF
 };
 
+// Per-workgroup waiting state that persists across waits (SP_SEM_ADAPTIVE).
+struct SemHold {
+  uint32_t interval;  // learned wall-clock ticks between two posts (0 = none yet)
+};
+
 // KIND: SP_SEM_SPIN / SP_SEM_SPIN_BACKOFF (Algorithm 4), SP_SEM_TICKET / SP_SEM_SLEEP
 // (Algorithm 5, the queued waiter proceeds once turn is strictly greater than the
 // 0-based ticket it drew), SP_SEM_COUNTERS (every waiter draws ticket t from one monotone
 // counter and enters once the posts counter plus K exceeds t: the unit case of the
 // weighted semaphore below, with Algorithm 5's FIFO order but one atomic per wait and
 // one per post instead of Algorithm 5's two dependent ones on a queued post).
-template <int KIND>
-__device__ bool sem_wait(const SemState& s, const Ctl& ctl) {
+// SP_SEM_ADAPTIVE has SP_SEM_COUNTERS' admission rule and only waits differently: a
+// waiter d posts short of admission sleeps about (d - 1) / 4 post intervals before it
+// polls again, the next in line polls at the base rate.  The interval is a running
+// average, kept in the workgroup's SemHold (which must persist across waits), of the rate
+// at which the posts counter advanced between the waiter's first and last polls.  With
+// 2048 workgroups queued on K = 32 the polling of one line otherwise slows the posts'
+// atomics on that line (measured: a uniform s_sleep of 64 units between polls alone
+// gives +47 %).
+// FENCED = false: the data the semaphore guards is accessed with agent-scope loads and
+// stores, which every XCD sees without cache maintenance, so wait skips the acquire
+// invalidation and post the release writeback.
+template <int KIND, bool FENCED = true>
+__device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = nullptr) {
   __shared__ uint32_t s_ok;
   if (is_leader()) {
     bool ok = true;
@@ -40,6 +56,40 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl) {
         if (v == 1) exch_relaxed(s.S, 1);  // at capacity: put the value back
         if constexpr (KIND == SP_SEM_SPIN_BACKOFF) bo(s.bo);
         if (!(ok = w.tick())) break;
+      }
+    } else if constexpr (KIND == SP_SEM_ADAPTIVE) {
+      Wait w(ctl, s.poll_sleep);
+      const uint32_t t = add_relaxed(s.ticket, 1);
+      const uint32_t learned = hold ? hold->interval : 0;
+      uint64_t t_first = 0, t_last = 0;
+      uint32_t c_first = 0, c_last = 0;
+      bool seen = false;
+      for (;;) {
+        const uint32_t posts = ld_relaxed(s.turn);
+        const uint64_t now = wall_clock();
+        if ((int32_t)(posts + s.K - t) > 0) break;
+        if (!seen) {
+          seen = true;
+          t_first = now;
+          c_first = posts;
+        }
+        t_last = now;
+        c_last = posts;
+        const uint32_t d = t - (posts + s.K) + 1;  // posts still needed, >= 1
+        if (d > 1 && learned) {
+          // (d - 1) / 4 intervals; one wall tick (10 ns) is ~0.375 s_sleep units
+          const uint64_t units = ((uint64_t)(d - 1) * learned * 3) / 32;
+          sleep_units(units < 4096 ? (uint32_t)units : 4096u);
+        }
+        if (!(ok = w.tick())) break;
+      }
+      if (hold) {
+        const uint32_t moved = c_last - c_first;
+        if (seen && moved > 0) {
+          const uint32_t sample = (uint32_t)((t_last - t_first) / moved);
+          const uint32_t avg = learned ? (7 * learned + sample) / 8 : sample;
+          hold->interval = avg < 100000 ? avg : 100000;  // at most 1 ms of wall clock
+        }
       }
     } else if constexpr (KIND == SP_SEM_COUNTERS) {
       Wait w(ctl, s.poll_sleep);
@@ -58,21 +108,21 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl) {
           if (!(ok = w.tick())) break;
       }
     }
-    fence_acquire();
+    if constexpr (FENCED) fence_acquire();
     s_ok = ok;
   }
   __syncthreads();
   return s_ok;
 }
 
-template <int KIND>
+template <int KIND, bool FENCED = true>
 __device__ bool sem_post(const SemState& s, const Ctl& ctl) {
   __shared__ uint32_t s_ok;
   wave_stores_complete();
   __syncthreads();
   if (is_leader()) {
     bool ok = true;
-    fence_release();
+    if constexpr (FENCED) fence_release();
     if constexpr (KIND == SP_SEM_SPIN || KIND == SP_SEM_SPIN_BACKOFF) {
       Wait w(ctl, 0);
       Backoff bo(s.bo);
@@ -85,7 +135,7 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl) {
         if constexpr (KIND == SP_SEM_SPIN_BACKOFF) bo(s.bo);
         if (!(ok = w.tick())) break;
       }
-    } else if constexpr (KIND == SP_SEM_COUNTERS) {
+    } else if constexpr (KIND == SP_SEM_COUNTERS || KIND == SP_SEM_ADAPTIVE) {
       add_relaxed(s.turn, 1);
     } else {
       const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);  // count -= 1

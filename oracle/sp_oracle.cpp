@@ -467,14 +467,16 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 // count, ticket and turn starting at 0, and a queued waiter proceeds once turn is
 // strictly greater than the ticket it drew (0-based).
 // kind: 0 Algorithm 4, 1 Algorithm 4 with backoff, 2 Algorithm 5, 3 Algorithm 5 with
-// yielding polls, 4 two monotone counters (ticket t enters once posts + K > t).
+// yielding polls, 4 two monotone counters (ticket t enters once posts + K > t), 5 the same
+// admission rule with proportional waiting (a waiter d posts short of admission yields
+// (d - 1) / 4 extra times per poll).
 // Each pair: wait, occupancy tracking, checksum update, admission count, post.
 // out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}.
 // Returns 0, -2 if occupancy ever exceeded K.
 int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t total,
                     uint32_t imin, uint32_t imax, uint32_t* chk, uint32_t* maxocc,
                     uint32_t* state, double* seconds) {
-  if (nwg == 0 || K == 0 || kind < 0 || kind > 4) return -1;
+  if (nwg == 0 || K == 0 || kind < 0 || kind > 5) return -1;
   Word S{K + 1}, count{0}, ticket{0}, turn{0}, occ{0}, maxo{0}, adm{0};
   const bool alg4 = kind <= 1, backoff = kind == 1;
 
@@ -490,10 +492,16 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
         if (v == 1) S.exchange(1, std::memory_order_release);
         if (backoff) bo(); else relax();
       }
-    } else if (kind == 4) {
+    } else if (kind == 4 || kind == 5) {
       // two monotone counters: ticket t enters once posts + K > t
       const uint32_t t = ticket.fetch_add(1, std::memory_order_acq_rel);
-      while (!((int32_t)(turn.load(std::memory_order_acquire) + K - t) > 0)) relax();
+      for (;;) {
+        const uint32_t posts = turn.load(std::memory_order_acquire);
+        if ((int32_t)(posts + K - t) > 0) break;
+        if (kind == 5)
+          for (uint32_t k = 0, d = t - (posts + K) + 1; k < (d - 1) / 4; ++k) relax();
+        relax();
+      }
     } else {
       uint32_t old = count.fetch_add(1, std::memory_order_acq_rel);
       if (old < K) return;
@@ -512,7 +520,7 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
         }
         if (backoff) bo(); else relax();
       }
-    } else if (kind == 4) {
+    } else if (kind == 4 || kind == 5) {
       turn.fetch_add(1, std::memory_order_acq_rel);
     } else {
       uint32_t old = count.fetch_sub(1, std::memory_order_acq_rel);

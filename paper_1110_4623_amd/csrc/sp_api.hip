@@ -174,17 +174,17 @@ int sp_init(int device, sp_ctx** out) {
     }
   ctx->defaults[0][0].kind = SP_BARRIER_CENTRAL;  // 1.7 us/round at 16 workgroups
   ctx->defaults[0][0].p.poll_sleep = 0;
-  ctx->defaults[0][1].kind = SP_BARRIER_XCD;      // 6.6 us/round at 1024
+  ctx->defaults[0][1].kind = SP_BARRIER_XCD;      // 6.1 us/round at 1024, 64 stamp copies
   ctx->defaults[0][1].p.poll_sleep = 0;
   ctx->defaults[1][0].kind = SP_MUTEX_SPIN_BACKOFF;  // paper's linear backoff, I_max 8
   ctx->defaults[1][0].p.backoff = SP_BACKOFF_PAPER;
   ctx->defaults[1][0].p.backoff_max = 8;
   ctx->defaults[1][1].kind = SP_MUTEX_TICKET;
   ctx->defaults[1][1].p.poll_sleep = 4;
-  ctx->defaults[2][0].kind = SP_SEM_SLEEP;
-  ctx->defaults[2][0].p.poll_sleep = 4;
-  ctx->defaults[2][1].kind = SP_SEM_COUNTERS;
-  ctx->defaults[2][1].p.poll_sleep = 4;
+  ctx->defaults[2][0].kind = SP_SEM_COUNTERS;  // 8.7 M pairs/s K = 32 at 256, 7.3 K = 256 at 2048
+  ctx->defaults[2][0].p.poll_sleep = 16;
+  ctx->defaults[2][1].kind = SP_SEM_ADAPTIVE;  // 6.5 M pairs/s K = 32 at 2048, 1.6 K = 4
+  ctx->defaults[2][1].p.poll_sleep = 0;
   // resolve the "auto" fields (fan_in = XCD count, ...) as sp_set_default does
   for (int prim = 0; prim < 3; ++prim)
     for (int b = 0; b < 2; ++b)
@@ -223,7 +223,7 @@ int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p) {
   if (!ctx || primitive > 2 || bucket > 1) return SP_E_INVAL;
-  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_ADAPTIVE, SP_SEM_COUNTERS};
+  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_ADAPTIVE, SP_SEM_ADAPTIVE};
   if (kind > max_kind[primitive]) return SP_E_INVAL;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));

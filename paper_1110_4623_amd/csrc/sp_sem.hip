@@ -19,7 +19,7 @@ namespace {
 // Line indices of the semaphore state (each line `stride` words).
 enum { L_S = 0, L_COUNT, L_TICKET, L_TURN, L_OCC, L_MAXOCC, L_ADM, L_PRIVATE, L_LINES };
 
-template <int KIND>
+template <int KIND, bool FENCED>
 __global__ SP_FULL_OCCUPANCY void k_sem(sp::SemState s, uint32_t stride, uint32_t* state, uint32_t nwg,
                       uint64_t total, uint32_t max_hold, uint32_t seed, uint32_t track,
                       uint32_t* chk, uint32_t* err, uint64_t timeout) {
@@ -29,16 +29,17 @@ __global__ SP_FULL_OCCUPANCY void k_sem(sp::SemState s, uint32_t stride, uint32_
   uint32_t* occ = state + L_OCC * stride;
   uint32_t* maxocc = state + L_MAXOCC * stride;
   uint32_t c = 0;
+  sp::SemHold sh{0};  // the adaptive kind's learned post interval, kept across waits
   for (uint64_t j = 0; j < A; ++j) {
     const uint32_t hold = sp::sched_key(seed, b, (uint32_t)j, 3) % (max_hold + 1);
-    if (!sp::sem_wait<KIND>(s, ctl)) return;
+    if (!sp::sem_wait<KIND, FENCED>(s, ctl, &sh)) return;
     if (sp::is_leader()) {
       if (track) sp::max_relaxed(maxocc, sp::add_relaxed(occ, 1) + 1);
       c ^= sp::sm32(seed ^ (b << 16) ^ (uint32_t)j);
       sp::spin_cycles(hold);
       if (track) sp::add_relaxed(occ, 0xFFFFFFFFu);
     }
-    if (!sp::sem_post<KIND>(s, ctl)) return;
+    if (!sp::sem_post<KIND, FENCED>(s, ctl)) return;
   }
   if (sp::is_leader()) {
     chk[b] = c;
@@ -59,15 +60,24 @@ __global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg
   }
 }
 
-const void* sem_kernel(uint32_t kind) {
+// The critical section of this workload touches only registers and agent-scope atomics,
+// so it is correct with or without the fences; FENCED = false is the variant for
+// critical sections that access their data coherently.
+template <bool FENCED>
+const void* sem_kernel_f(uint32_t kind) {
   switch (kind) {
-    case SP_SEM_SPIN: return (const void*)k_sem<SP_SEM_SPIN>;
-    case SP_SEM_SPIN_BACKOFF: return (const void*)k_sem<SP_SEM_SPIN_BACKOFF>;
-    case SP_SEM_TICKET: return (const void*)k_sem<SP_SEM_TICKET>;
-    case SP_SEM_SLEEP: return (const void*)k_sem<SP_SEM_SLEEP>;
-    case SP_SEM_COUNTERS: return (const void*)k_sem<SP_SEM_COUNTERS>;
+    case SP_SEM_SPIN: return (const void*)k_sem<SP_SEM_SPIN, FENCED>;
+    case SP_SEM_SPIN_BACKOFF: return (const void*)k_sem<SP_SEM_SPIN_BACKOFF, FENCED>;
+    case SP_SEM_TICKET: return (const void*)k_sem<SP_SEM_TICKET, FENCED>;
+    case SP_SEM_SLEEP: return (const void*)k_sem<SP_SEM_SLEEP, FENCED>;
+    case SP_SEM_COUNTERS: return (const void*)k_sem<SP_SEM_COUNTERS, FENCED>;
+    case SP_SEM_ADAPTIVE: return (const void*)k_sem<SP_SEM_ADAPTIVE, FENCED>;
     default: return nullptr;
   }
+}
+
+const void* sem_kernel(uint32_t kind, bool coherent_cs) {
+  return coherent_cs ? sem_kernel_f<false>(kind) : sem_kernel_f<true>(kind);
 }
 
 }  // namespace
@@ -76,7 +86,7 @@ extern "C" {
 
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out) {
   if (!ctx || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
-  if (kind > SP_SEM_COUNTERS && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_SEM_ADAPTIVE && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -120,12 +130,14 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
     const sp_default_entry& d = ctx->defaults[2][spi::bucket_of(nwg / sem->K)];
     kind = d.kind;
     const uint32_t t = q.timeout_ms;
+    const uint32_t coherent = q.coherent_cs;  // a property of the caller's critical sections
     q = d.p;
     q.timeout_ms = t;
+    q.coherent_cs = coherent;
   }
   if (kind == SP_SEM_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) q.backoff = SP_BACKOFF_EXP;
   if (kind != SP_SEM_SPIN_BACKOFF) q.backoff = SP_BACKOFF_NONE;
-  const void* kern = sem_kernel(kind);
+  const void* kern = sem_kernel(kind, q.coherent_cs != 0);
   if (!kern) return SP_E_INVAL;
   const uint32_t sw = spi::stride_words(q);
   uint32_t* base = sem->d_state;

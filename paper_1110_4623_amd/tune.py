@@ -18,6 +18,7 @@ resource (per barrier, per lock, per K semaphore units), bucket 1 has 64 or more
 from __future__ import annotations
 
 import json
+import math
 import os
 
 import numpy as np
@@ -137,7 +138,8 @@ def semaphore_candidates():
             out.append(("spin_backoff", {"backoff": policy, "backoff_min": 1, "backoff_max": imax}))
     out += [("ticket", {"poll_sleep": 0})]
     out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
-    out += [("counters", {"poll_sleep": ps}) for ps in (0, 1, 4)]
+    out += [("counters", {"poll_sleep": ps}) for ps in (0, 1, 4, 16, 64)]
+    out += [("adaptive", {"poll_sleep": ps}) for ps in (0, 1, 4)]
     return out
 
 
@@ -163,6 +165,29 @@ def tune_semaphore(ctx, nwg: int, K: int, total: int = 8192, max_hold: int = 200
                      "consistent": bool(ok)})
     best = max((r for r in rows if r["consistent"]), key=lambda r: r["pairs_per_s"])
     return {"nwg": nwg, "K": K, "total": total, "best": best, "candidates": rows}
+
+
+def tune_semaphore_points(ctx, points, total: int, **kw) -> dict:
+    """Times every candidate at several (nwg, K) points of one contention bucket and keeps
+    the best geometric mean of pairs/s among the candidates correct at every point (a
+    bucket spans many K, and the best waiting policy depends on K)."""
+    runs = [tune_semaphore(ctx, nwg, K, total=total, **kw) for nwg, K in points]
+    keyed = {}
+    for run in runs:
+        for r in run["candidates"]:
+            keyed.setdefault((r["kind"], json.dumps(r["params"], sort_keys=True)), []).append(r)
+    rows = []
+    for (kind, _), rs in keyed.items():
+        ok = len(rs) == len(runs) and all(r["consistent"] for r in rs)
+        row = {"kind": kind, "params": rs[0]["params"], "consistent": ok}
+        if ok:
+            row["points_pairs_per_s"] = [r["pairs_per_s"] for r in rs]
+            row["pairs_per_s"] = math.exp(sum(math.log(v) for v in row["points_pairs_per_s"])
+                                          / len(rs))
+        rows.append(row)
+    best = max((r for r in rows if r["consistent"]), key=lambda r: r["pairs_per_s"])
+    return {"points": [list(p) for p in points], "total": total, "best": best,
+            "candidates": rows}
 
 
 # ---- serving queue ----------------------------------------------------------------------
@@ -195,7 +220,8 @@ def device_key(ctx) -> str:
 
 def tune_all(ctx, quick: bool = False) -> dict:
     """Tunes barriers (16 and 1024 workgroups), one contended lock (16 and 1024
-    workgroups) and a K = 32 semaphore (256 and 2048 workgroups, 8 and 64 per unit)."""
+    workgroups) and semaphores (bucket 0: K = 32 at 256 workgroups and K = 256 at 2048;
+    bucket 1: K = 32 and K = 4 at 2048)."""
     rounds = 300 if quick else 1000
     mt = 1024 if quick else 4096
     res = {"device": device_key(ctx), "barrier": {}, "mutex": {}, "semaphore": {}}
@@ -203,8 +229,9 @@ def tune_all(ctx, quick: bool = False) -> dict:
     res["barrier"]["1"] = tune_barrier(ctx, 1024, rounds=rounds)
     res["mutex"]["0"] = tune_mutex(ctx, 16, total=mt)
     res["mutex"]["1"] = tune_mutex(ctx, 1024, total=mt)
-    res["semaphore"]["0"] = tune_semaphore(ctx, 256, 32, total=2 * mt)
-    res["semaphore"]["1"] = tune_semaphore(ctx, 2048, 32, total=2 * mt)
+    # 32 waits per workgroup at 2048: long enough for the adaptive kind to learn its interval
+    res["semaphore"]["0"] = tune_semaphore_points(ctx, [(256, 32), (2048, 256)], 16 * mt)
+    res["semaphore"]["1"] = tune_semaphore_points(ctx, [(2048, 32), (2048, 4)], 16 * mt)
     return res
 
 

@@ -9,7 +9,7 @@ from conftest import announce
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters"]
+KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive"]
 
 
 def _run(ctx, kind, K, nwg, lanes, total, hold, seed, **params):
@@ -30,7 +30,7 @@ def _check(r, kind, K, nwg, total, seed):
     assert r["occ"] == 0
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind == "counters":
+    elif kind in ("counters", "adaptive"):
         assert s_or_count == 0 and ticket == turn == total
     else:
         assert s_or_count == 0 and ticket == turn
@@ -46,7 +46,7 @@ def test_small(ctx, kind, K):
     _check(r, kind, K, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive"])
 @pytest.mark.parametrize("K", [1, 4, 32, 256])
 def test_full_size(ctx, kind, K):
     # 2048 workgroups, 2^20 wait/post pairs, holds uniform in [0, 2000] cycles
@@ -80,3 +80,13 @@ def test_spin_as_mutex(ctx, kind):
 def test_capacity_above_agents_never_queues(ctx, kind):
     r = _run(ctx, kind, 64, 16, 64, 4000, 50, 7)
     _check(r, kind, 64, 16, 4000, 7)
+
+
+@pytest.mark.parametrize("kind", ["spin_backoff", "ticket", "sleep", "counters", "adaptive"])
+@pytest.mark.parametrize("K", [1, 32, 256])
+def test_coherent_critical_sections(ctx, kind, K):
+    """coherent_cs: wait and post skip the cache maintenance (the workload's critical
+    section touches registers and agent-scope atomics only); same results and bound."""
+    nwg, total, seed = (256, 1 << 13, 7) if kind == "spin_backoff" else (2048, 1 << 18, 7)
+    r = _run(ctx, kind, K, nwg, 256, total, 2000, seed, coherent_cs=1)
+    _check(r, kind, K, nwg, total, seed)

@@ -32,7 +32,8 @@ def test_mutex_threaded_matches_closed(kind, L, W):
     assert (words == oracle.mutex_closed(seed, nwg, total, L, W)).all()
 
 
-@pytest.mark.parametrize("kind", ["spin", "spin_backoff", "ticket", "sleep", "counters"])
+@pytest.mark.parametrize("kind", ["spin", "spin_backoff", "ticket", "sleep", "counters",
+                                  "adaptive"])
 @pytest.mark.parametrize("K", [1, 2, 4, 32])
 def test_sem_threaded_invariants(kind, K):
     seed, nwg, total = 7, 12, 2400
@@ -44,7 +45,7 @@ def test_sem_threaded_invariants(kind, K):
     assert admissions == total
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind == "counters":
+    elif kind in ("counters", "adaptive"):
         assert s_or_count == 0 and ticket == turn == total  # every wait drew, every post counted
     else:
         assert s_or_count == 0 and ticket == turn

@@ -47,4 +47,4 @@ def test_candidate_lists_cover_every_kind():
                                                         "ticket", "sleep", "ring", "array",
                                                         "adaptive"}
     assert {k for k, _ in tune.semaphore_candidates()} == {"spin", "spin_backoff", "ticket",
-                                                            "sleep", "counters"}
+                                                            "sleep", "counters", "adaptive"}
