@@ -48,3 +48,26 @@ def test_candidate_lists_cover_every_kind():
                                                         "adaptive"}
     assert {k for k, _ in tune.semaphore_candidates()} == {"spin", "spin_backoff", "ticket",
                                                             "sleep", "counters", "adaptive"}
+
+
+def test_semaphore_points_rank_by_geometric_mean(monkeypatch):
+    """A candidate must be correct at every point; the best geometric mean wins, so a
+    candidate fast at one K and slow at the other loses to a steady one."""
+    import math
+    from paper_1110_4623_amd import tune
+    rates = {(2048, 32): {"a": 10.0, "b": 6.0, "c": 9.0},
+             (2048, 4): {"a": 1.0, "b": 2.0, "c": 3.0}}
+
+    def fake(ctx, nwg, K, total, **kw):
+        rows = [{"kind": k, "params": {"poll_sleep": 1}, "pairs_per_s": v,
+                 "consistent": not (k == "c" and K == 4)}
+                for k, v in rates[(nwg, K)].items()]
+        return {"nwg": nwg, "K": K, "total": total, "candidates": rows}
+
+    monkeypatch.setattr(tune, "tune_semaphore", fake)
+    r = tune.tune_semaphore_points(None, [(2048, 32), (2048, 4)], 1024)
+    by_kind = {row["kind"]: row for row in r["candidates"]}
+    assert not by_kind["c"]["consistent"] and "pairs_per_s" not in by_kind["c"]
+    assert by_kind["a"]["pairs_per_s"] == pytest.approx(math.sqrt(10.0))
+    assert by_kind["b"]["pairs_per_s"] == pytest.approx(math.sqrt(12.0))
+    assert r["best"]["kind"] == "b" and r["points"] == [[2048, 32], [2048, 4]]
