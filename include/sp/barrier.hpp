@@ -189,9 +189,8 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
 //      apart); the master's lanes scan the block.
 //   2. The master writes back the XCD's dirty L2 lines once for all its members (agent
 //      release) and publishes the XCD's stamp.
-//   3. Each CU leader acquires (agent scope) once its own XCD's stamp is published,
-//      then polls the stamps of every XCD that has members and, once all are
-//      published, releases the other workgroups of its CU.
+//   3. Each CU leader polls the stamps of every XCD that has members; once all are
+//      published it acquires (agent scope) and releases the other workgroups of its CU.
 //      Every flag is its own line.  With xcopies = C > 0 the masters write their stamps
 //      into C lines that each hold all of them packed, and the CUs spread their polls
 //      over the copies by their rank in their XCD (fewer pollers per line).
@@ -270,21 +269,16 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
     return __syncthreads_and(ok);
   }
   if (slot == 0) {
-    // CU leader: invalidate for the CU as soon as its own XCD has published, then wait
-    // for every populated XCD and release the CU.  The own stamp already makes the
-    // invalidation safe: every workgroup of this XCD has arrived (their loads have all
-    // returned) and no data is loaded on the XCD before a release, and the XCD's
-    // writeback is done, so nothing stale can enter the L2 or this CU's L1 afterwards.
-    // The invalidations of an XCD's CUs serialize at its L2; starting them at the own
-    // stamp overlaps that queue with the wait for the other XCDs.
-    if (is_leader()) {
-      ok = poll_until(stamps + (size_t)x * sstride, stamp, w);
-      if (ok) fence_acquire();
-    }
+    // CU leader: once every populated XCD has published, invalidate for the CU and
+    // release it.  The invalidation has to follow the last XCD's writeback: a line that
+    // a kernel on another stream reads on this XCD before then (say, other words of a
+    // line that participants elsewhere write) would otherwise stay stale in the L2.
     if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
-      ok = ok && poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
+      ok = poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
+    if (is_leader()) fence_acquire();
+    __syncthreads();
     release_list(s, L, __builtin_amdgcn_readfirstlane(L.ncu), k, stamp, rel);
     return true;
   }
