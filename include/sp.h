@@ -197,7 +197,11 @@ void sp_params_default(sp_params* p);
 /* Installs the default kind and parameters that *_DEFAULT resolves to for a primitive
  * class (0 barrier, 1 mutex, 2 semaphore) and contention bucket (0 = low: fewer than
  * 64 workgroups per resource, 1 = high).  Used by the autotuner (future-work item of
- * Section 7: tuning backoff per GPU and contention level).                              */
+ * Section 7: tuning backoff per GPU and contention level).  Until a call replaces them,
+ * the defaults are a tuning pass's winners on an MI355X: barrier central (low) and
+ * per-XCD with 64 stamp copies (high); mutex spin with the paper's backoff, I_max 8
+ * (low) and ticket with s_sleep 4 (high); semaphore two counters with s_sleep 16 (low)
+ * and adaptive (high).                                                                  */
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p);
 const char* sp_strerror(int code);

@@ -2,12 +2,13 @@
 
 Section 7 proposes tuning the backoff parameters for each GPU under differing levels of
 contention.  This tuner widens that to every choice the library exposes: for barriers the
-algorithm, the tree's fan-in, flag packing and the polling sleep; for mutexes and
-semaphores the algorithm, the backoff policy and bounds, and the polling sleep; for the
-serving queue the polling sleeps and the number of persistent workgroups.  Each candidate
-runs a short representative workload through libsp (barrier, mutex and semaphore
-candidates are recorded into a HIP graph once and timed over replays); the fastest
-candidate whose results pass the workload's own consistency checks wins.  The winners
+algorithm, the tree's fan-in, flag packing, the per-XCD barrier's stamp copies and the
+polling sleep; for mutexes and semaphores the algorithm, the backoff policy and bounds,
+and the polling sleep; for the serving queue the polling sleeps and the number of
+persistent workgroups.  Each candidate runs a short representative workload through libsp
+(barrier, mutex and semaphore candidates are recorded into a HIP graph once and timed over
+replays); the fastest candidate whose results pass the workload's own consistency checks
+wins (semaphores: the best geometric mean over two K of the bucket).  The winners
 are installed with sp_set_default, so that the *_DEFAULT kinds resolve to them, and can
 be saved to and loaded from a JSON cache keyed by the device.
 
