@@ -6,8 +6,10 @@ One step runs the whole path once over the full-size synthetic workloads:
      (the A1 ceiling the barrier and lock figures are compared with);
   2. barrier: the per-XCD barrier, 2048 co-resident workgroups x 256 lanes x 10^4
      rounds of the hash exchange (the headline: microseconds per barrier round);
-  3. mutex: ticket lock, 2048 workgroups x 256 lanes, one lock guarding 16 words,
-     2^20 acquisitions with non-critical delays uniform in [0, 1000] cycles;
+  3. mutex: ticket lock (Algorithm 3), 2048 workgroups x 256 lanes, one lock guarding 16
+     words, 2^20 acquisitions with non-critical delays uniform in [0, 1000] cycles, then
+     the same workload on the library's default mutex for this contention (the XCD-cohort
+     lock);
   4. semaphore: fetch-and-add semaphore (Algorithm 5 with s_sleep polling) with K = 32,
      2048 workgroups, 2^20 wait/post pairs holding uniform [0, 2000] cycles, then the
      same workload on the library's default semaphore for this contention (the adaptive
@@ -125,6 +127,7 @@ def main() -> int:
     # the same barrier for data exchanged with agent-scope accesses: no cache maintenance
     bar_coh = sp.Barrier(ctx, args.barrier, NWG, coherent_cs=1)
     mtx = sp.Mutex(ctx, "ticket", 1, 16)
+    mtx_def = sp.Mutex(ctx, "default", 1, 16)
     sem = sp.Semaphore(ctx, "sleep", SEM_K)
     sem_def = sp.Semaphore(ctx, "default", SEM_K)
     perm1 = ctx.zeros(1)
@@ -143,6 +146,9 @@ def main() -> int:
         r["bar_coh_ms"], r["bar_coh_same"] = st_c["kernel_ms"], bool((chk_c == chk).all())
         words, st, _ = mtx.run(NWG, LANES, MUTEX_TOTAL, 1000, 42)
         r["mtx_ms"], r["mtx_ok"] = st["kernel_ms"], bool((words == MUTEX_TOTAL).all())
+        words_d, st_d, _ = mtx_def.run(NWG, LANES, MUTEX_TOTAL, 1000, 42)
+        r["mtx_def_ms"] = st_d["kernel_ms"]
+        r["mtx_ok"] = r["mtx_ok"] and bool((words_d == MUTEX_TOTAL).all())
         res = sem.run(NWG, LANES, SEM_TOTAL, 2000, 42, track=False)
         r["sem_ms"] = res["stats"]["kernel_ms"]
         r["sem_ok"] = res["state"][3] == SEM_TOTAL and res["state"][0] == 0
@@ -174,6 +180,7 @@ def main() -> int:
     arrivals = NWG * ROUNDS / (bar_ms * 1e-3)
     deterministic = all((r["bar_chk"] == results[0]["bar_chk"]).all() for r in results)
     mtx_rate = float(np.mean([MUTEX_TOTAL / (r["mtx_ms"] * 1e-3) for r in results]))
+    mtx_def_rate = float(np.mean([MUTEX_TOTAL / (r["mtx_def_ms"] * 1e-3) for r in results]))
     sem_rate = float(np.mean([SEM_TOTAL / (r["sem_ms"] * 1e-3) for r in results]))
     sem_def_rate = float(np.mean([SEM_TOTAL / (r["sem_def_ms"] * 1e-3) for r in results]))
 
@@ -222,6 +229,7 @@ def main() -> int:
             "barrier_coherent_checksums_identical": all(r["bar_coh_same"] for r in results),
             "barrier_arrivals_per_s": round(arrivals, 1),
             "mutex_ticket_acq_per_s": round(mtx_rate, 1),
+            "mutex_default_kind_acq_per_s": round(mtx_def_rate, 1),
             "semaphore_k32_pairs_per_s": round(sem_rate, 1),
             "semaphore_k32_default_kind_pairs_per_s": round(sem_def_rate, 1),
             "contended_atomic_ceiling_ops_per_s": round(a1, 1),

@@ -66,6 +66,11 @@ enum sp_mutex_kind {
   SP_MUTEX_ADAPTIVE = 7,     /* ticket mutex whose waiters sleep in proportion to their */
                              /* distance from the head, scaled by a hand-over time each */
                              /* workgroup learns online from its own waits              */
+  SP_MUTEX_COHORT = 8,       /* XCD-cohort lock: a ticket lock per XCD in front of a    */
+                             /* global ticket lock; the holder passes the global lock   */
+                             /* to a waiter of its own XCD (at most cohort_passes       */
+                             /* times in a row) without the L2 writeback, which only a  */
+                             /* hand-over to another XCD needs                          */
   SP_MUTEX_DEFAULT = 15
 };
 
@@ -155,7 +160,10 @@ typedef struct sp_params {
                          /* workgroups of a CU poll copy (XCD + number of XCDs * rank of    */
                          /* the CU in its XCD) mod C, which spreads the polling over C      */
                          /* lines.  Timing only; results are the same.                      */
-  uint32_t reserved[3];
+  uint32_t cohort_passes; /* SP_MUTEX_COHORT: holders of one XCD that may take the lock */
+                           /* in a row before it goes back to the global queue, 1..255    */
+                           /* (0 = 64)                                                    */
+  uint32_t reserved[2];
 } sp_params;
 
 typedef struct sp_stats {
@@ -199,9 +207,8 @@ void sp_params_default(sp_params* p);
  * 64 workgroups per resource, 1 = high).  Used by the autotuner (future-work item of
  * Section 7: tuning backoff per GPU and contention level).  Until a call replaces them,
  * the defaults are a tuning pass's winners on an MI355X: barrier central (low) and
- * per-XCD with 64 stamp copies (high); mutex spin with the paper's backoff, I_max 8
- * (low) and ticket with s_sleep 4 (high); semaphore two counters with s_sleep 16 (low)
- * and adaptive (high).                                                                  */
+ * per-XCD with 64 stamp copies (high); mutex: the XCD-cohort lock (both); semaphore
+ * two counters with s_sleep 16 (low) and adaptive (high).                               */
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p);
 const char* sp_strerror(int code);

@@ -14,9 +14,12 @@ struct MutexState {
   uint32_t* lockw;      // lock words (0 free, 1 held), one line per lock
   uint32_t* ticket;     // ticket mutex: next ticket, one line per lock
   uint32_t* turn;       // ticket mutex: ticket being served; ring: head; one line per lock
-  uint32_t* queue;      // ring / array: qlen slots per lock, qstride words apart
+  uint32_t* queue;      // ring / array: qlen slots per lock, qstride words apart;
+                        // cohort: per lock and XCC id, two lines (local ticket, 64-bit
+                        // grant word), qstride (even) words apart
   uint32_t qlen;        // slots per lock (power of two; the ring needs >= contenders)
   uint32_t qstride;     // words between slots
+  uint32_t cohort_bound;  // cohort: holders of one XCD in a row, at most
   BackoffCfg bo;        // backoff between failed attempts
 };
 
@@ -27,7 +30,24 @@ struct MutexState {
 struct MutexHold {
   uint32_t ticket;
   uint32_t handoff;  // SP_MUTEX_ADAPTIVE: learned wall-clock ticks per hand-over (0 = none yet)
+  uint32_t session;  // SP_MUTEX_COHORT: holders of this XCD before this one since the
+                     // cohort took the global lock (0 = this holder took it)
+  uint32_t global;   // SP_MUTEX_COHORT: the global ticket the cohort holds
 };
+
+// Cohort lock state of `lock` for the XCD with XCC id x (kXccSlots per lock: the XCC id
+// register has four bits, so every XCD has its own cohort whatever the count): line 0 the
+// local ticket counter, line 1 the 64-bit grant word = local turn (bits 0-23, modulo
+// 2^24) | session (bits 24-31) | global ticket of the session (bits 32-63), written only
+// by the local holder, so one store hands over turn, session and global ticket at once.
+constexpr uint32_t kXccSlots = 16;
+constexpr uint32_t kTurnMask = 0xFFFFFFu;
+__device__ __forceinline__ uint32_t* cohort_ticket(const MutexState& s, uint32_t lock, uint32_t x) {
+  return s.queue + ((size_t)lock * kXccSlots + x) * 2 * s.qstride;
+}
+__device__ __forceinline__ uint64_t* cohort_grant(const MutexState& s, uint32_t lock, uint32_t x) {
+  return reinterpret_cast<uint64_t*>(s.queue + (((size_t)lock * kXccSlots + x) * 2 + 1) * s.qstride);
+}
 
 // KIND:
 //   SP_MUTEX_SPIN_CAS     compare-and-swap 0 -> 1 until it succeeds (backoff if configured)
@@ -47,6 +67,21 @@ struct MutexHold {
 //                         line) until it holds t; unlock writes t + 1 into slot t + 1.  A
 //                         grant is overwritten only after its owner entered and left, so
 //                         any number of slots is correct; more slots spread the polling.
+//   SP_MUTEX_COHORT       XCD-cohort lock (lock cohorting, made for per-XCD L2s): a ticket
+//                         lock per XCD in front of a global ticket lock.  The grant word
+//                         a local waiter polls carries the session (0 = the XCD does not
+//                         hold the global lock; k > 0 = it does, k holders of this XCD
+//                         took it in a row) and the session's global ticket.  A local
+//                         holder that reads session 0 takes the global lock.  Unlock
+//                         passes the global lock with the local one (one store of the
+//                         grant word: turn + 1, session k + 1) when a local ticket beyond
+//                         one's own was drawn and k + 1 < cohort_bound; that hand-over
+//                         needs no L2 writeback, since both holders use this XCD's L2
+//                         (the critical section's stores have completed into it).
+//                         Otherwise it releases the global lock (with the writeback), then
+//                         grants the local turn with session 0.  Cohorts are the actual
+//                         XCDs (XCC id), never merged: the local hand-over relies on the
+//                         shared L2.
 //   SP_MUTEX_ADAPTIVE     ticket mutex with proportional waiting tuned online (Section 5's
 //                         aggressive lock that reverts to backoff): a waiter d tickets from
 //                         the head sleeps about (d - 1) / 4 hand-over times before polling
@@ -66,7 +101,8 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
   __shared__ uint32_t s_ok;
   if (is_leader()) {
     uint32_t* m = s.lockw + (size_t)lock * s.stride;
-    Wait w(ctl, (KIND == SP_MUTEX_SLEEP || KIND == SP_MUTEX_RING || KIND == SP_MUTEX_ARRAY)
+    Wait w(ctl, (KIND == SP_MUTEX_SLEEP || KIND == SP_MUTEX_RING || KIND == SP_MUTEX_ARRAY ||
+                 KIND == SP_MUTEX_COHORT)
                     ? s.poll_sleep : 0);
     Backoff bo(s.bo);
     bool ok = true;
@@ -135,6 +171,28 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
         if (!(ok = w.tick())) break;
       }
       if (hold) hold->ticket = t;
+    } else if constexpr (KIND == SP_MUTEX_COHORT) {
+      const uint32_t x = xcc_id();
+      const uint32_t t = add_relaxed(cohort_ticket(s, lock, x), 1);
+      const uint64_t* grant = cohort_grant(s, lock, x);
+      uint64_t v;
+      for (;;) {
+        v = ld_relaxed64(grant);
+        if (((uint32_t)v & kTurnMask) == (t & kTurnMask)) break;
+        if (!(ok = w.tick())) break;
+      }
+      uint32_t k = ((uint32_t)v >> 24) & 0xFF, g = (uint32_t)(v >> 32);
+      if (ok && k == 0) {  // the cohort does not hold the global lock: queue for it
+        g = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
+        const uint32_t* turn = s.turn + (size_t)lock * s.stride;
+        while (ld_relaxed(turn) != g)
+          if (!(ok = w.tick())) break;
+      }
+      if (hold) {
+        hold->ticket = t;
+        hold->session = k;
+        hold->global = g;
+      }
     } else if constexpr (KIND == SP_MUTEX_ARRAY) {
       const uint32_t t = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
       const uint32_t* slot =
@@ -157,10 +215,34 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
 }
 
 // `hold`: the record mutex_lock filled in (leader's copy).  It may be nullptr except for
-// SP_MUTEX_ARRAY: the ticket and ring mutexes then load turn / head to find the value to
-// publish.
+// SP_MUTEX_ARRAY and SP_MUTEX_COHORT: the ticket and ring mutexes then load turn / head
+// to find the value to publish.
 template <int KIND, bool FENCED = true>
 __device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold* hold = nullptr) {
+  if constexpr (KIND == SP_MUTEX_COHORT) {
+    // The local ticket count is loaded first so that its round trip overlaps the wait
+    // for the critical section's stores.
+    const uint32_t x = xcc_id();
+    const uint32_t drawn = is_leader() ? ld_relaxed(cohort_ticket(s, lock, x)) : 0;
+    wave_stores_complete();
+    __syncthreads();
+    if (!is_leader()) return;
+    uint64_t* grant = cohort_grant(s, lock, x);
+    const uint32_t t = hold->ticket, k = hold->session + 1, g = hold->global;
+    const uint64_t next_turn = (t + 1) & kTurnMask;
+    if ((int32_t)(drawn - (t + 1)) > 0 && k < s.cohort_bound) {
+      // The next holder runs on this XCD: pass the global lock with the local one.  The
+      // critical section's stores have completed into this XCD's L2 (waited for above),
+      // which the next holder reads through after its own acquire: no writeback.
+      st_relaxed64(grant, ((uint64_t)g << 32) | ((uint64_t)k << 24) | next_turn);
+    } else {
+      uint32_t* turn = s.turn + (size_t)lock * s.stride;
+      if constexpr (FENCED) st_release(turn, g + 1);  // writes back every local holder's stores
+      else st_relaxed(turn, g + 1);
+      st_relaxed64(grant, next_turn);  // session 0: the next local holder queues globally
+    }
+    return;
+  }
   wave_stores_complete();
   __syncthreads();
   if (is_leader()) {

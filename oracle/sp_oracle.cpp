@@ -356,7 +356,7 @@ int or_barrier_threaded(int kind, uint32_t seed, uint32_t N, uint32_t R, uint32_
 int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uint32_t L,
                       uint32_t W, uint32_t imin, uint32_t imax, uint32_t* words,
                       double* seconds) {
-  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 7) return -1;
+  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 8) return -1;
   std::vector<Word> lockw(L), ticket(L), turn(L), owner(L);
   for (uint32_t l = 0; l < L; ++l) lockw[l] = 0, ticket[l] = 0, turn[l] = 0, owner[l] = 0;
   // kinds 5 (ring) and 6 (array): Q slots per lock, Q a power of two >= agents
@@ -367,9 +367,18 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
   std::vector<Word> cs((size_t)L * W);
   for (auto& w : cs) w.store(0);
   std::atomic<int> bad{0};
+  // kind 8 (cohort): agent b belongs to cohort b mod kCoh; per lock and cohort a local
+  // ticket counter and a grant word = local turn | session << 32 (session 0 = the cohort
+  // does not hold the global lock, k > 0 = it does and k holders passed it on); at most
+  // kPasses holders in a row.
+  constexpr uint32_t kCoh = 8, kPasses = 4;
+  std::vector<Word> lt(kind == 8 ? (size_t)L * kCoh : 0);
+  std::vector<std::atomic<uint64_t>> grant(lt.size());
+  for (size_t i = 0; i < lt.size(); ++i) lt[i] = 0, grant[i] = 0;
 
-  // returns the ticket the lock was taken with (ticket, ring and array kinds)
-  auto lock = [&](uint32_t l, Backoff& bo) -> uint32_t {
+  // returns the ticket the lock was taken with (ticket, ring and array kinds); cohort:
+  // the local ticket, and the session it read in the upper 32 bits
+  auto lock = [&](uint32_t l, uint32_t b, Backoff& bo) -> uint64_t {
     switch (kind) {
       case 0:
         for (;;) {
@@ -417,6 +426,18 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
         while (slot.load(std::memory_order_acquire) != my) relax();
         return my;
       }
+      case 8: {  // cohort: the local ticket lock, then the global one unless inherited
+        const size_t c = (size_t)l * kCoh + b % kCoh;
+        const uint32_t my = lt[c].fetch_add(1, std::memory_order_relaxed);
+        uint64_t v;
+        while ((uint32_t)(v = grant[c].load(std::memory_order_acquire)) != my) relax();
+        const uint32_t k = (uint32_t)(v >> 32);
+        if (k == 0) {
+          const uint32_t g = ticket[l].fetch_add(1, std::memory_order_relaxed);
+          while (turn[l].load(std::memory_order_acquire) != g) relax();
+        }
+        return ((uint64_t)k << 32) | my;
+      }
       default:
         for (;;) {
           while (lockw[l].load(std::memory_order_relaxed) != 0) relax();
@@ -427,7 +448,21 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
         }
     }
   };
-  auto unlock = [&](uint32_t l, uint32_t my) {
+  auto unlock = [&](uint32_t l, uint32_t b, uint64_t held) {
+    const uint32_t my = (uint32_t)held;
+    if (kind == 8) {
+      const size_t c = (size_t)l * kCoh + b % kCoh;
+      const uint32_t k = (uint32_t)(held >> 32) + 1;
+      const bool waiter = (int32_t)(lt[c].load(std::memory_order_relaxed) - (my + 1)) > 0;
+      if (waiter && k < kPasses) {  // pass the global lock with the local one
+        grant[c].store(((uint64_t)k << 32) | (my + 1), std::memory_order_release);
+      } else {
+        const uint32_t t = turn[l].load(std::memory_order_relaxed);  // only the holder writes
+        turn[l].store(t + 1, std::memory_order_release);
+        grant[c].store(my + 1, std::memory_order_release);  // session 0
+      }
+      return;
+    }
     if (kind == 3 || kind == 7) {
       uint32_t t = turn[l].load(std::memory_order_relaxed);  // only the holder writes turn
       turn[l].store(t + 1, std::memory_order_release);
@@ -445,14 +480,14 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
     uint64_t A = or_ops_for_agent(nwg, total, b);
     for (uint64_t j = 0; j < A; ++j) {
       uint32_t l = or_key(seed, b, (uint32_t)j, 1) % L;
-      const uint32_t my = lock(l, bo);
+      const uint64_t my = lock(l, b, bo);
       if (owner[l].exchange(b + 1, std::memory_order_relaxed) != 0) bad.store(1);
       for (uint32_t w = 0; w < W; ++w) {
         Word& x = cs[(size_t)l * W + w];
         x.store(x.load(std::memory_order_relaxed) + 1, std::memory_order_relaxed);
       }
       if (owner[l].exchange(0, std::memory_order_relaxed) != b + 1) bad.store(1);
-      unlock(l, my);
+      unlock(l, b, my);
     }
   });
   for (size_t i = 0; i < cs.size(); ++i) words[i] = cs[i].load();

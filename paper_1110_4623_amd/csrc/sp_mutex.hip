@@ -72,6 +72,7 @@ const void* mutex_kernel_f(uint32_t kind) {
     case SP_MUTEX_RING: return (const void*)k_mutex<SP_MUTEX_RING, FENCED>;
     case SP_MUTEX_ARRAY: return (const void*)k_mutex<SP_MUTEX_ARRAY, FENCED>;
     case SP_MUTEX_ADAPTIVE: return (const void*)k_mutex<SP_MUTEX_ADAPTIVE, FENCED>;
+    case SP_MUTEX_COHORT: return (const void*)k_mutex<SP_MUTEX_COHORT, FENCED>;
     default: return nullptr;
   }
 }
@@ -89,7 +90,7 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
   if (!ctx || !out || nlocks == 0 || words_per_lock == 0 || nlocks > (1u << 20) ||
       words_per_lock > (1u << 16))
     return SP_E_INVAL;
-  if (kind > SP_MUTEX_ADAPTIVE && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_MUTEX_COHORT && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -164,13 +165,17 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
   ms.queue = nullptr;
   ms.qlen = 1;
   ms.qstride = 1;
-  if (kind == SP_MUTEX_RING || kind == SP_MUTEX_ARRAY) {
+  ms.cohort_bound = q.cohort_passes;
+  if (kind == SP_MUTEX_RING || kind == SP_MUTEX_ARRAY || kind == SP_MUTEX_COHORT) {
     // The ring needs a slot per contender (each workgroup has at most one arrival
-    // outstanding); the array lock is correct with any number and polls one line each.
+    // outstanding); the array lock is correct with any number and polls one line each;
+    // the cohort lock keeps three lines per lock and XCC id.
     uint32_t Q = 64;
     while (Q < nwg) Q <<= 1;
+    if (kind == SP_MUTEX_COHORT) Q = 2 * sp::kXccSlots;
     ms.qlen = Q;
-    ms.qstride = kind == SP_MUTEX_RING ? 1 : sw;  // ring entries packed, array slots padded
+    ms.qstride = kind == SP_MUTEX_RING ? 1 : sw;  // ring entries packed, others padded
+    if (kind == SP_MUTEX_COHORT && ms.qstride < 2) ms.qstride = 2;  // 64-bit grant words
     const uint64_t words = (uint64_t)m->nlocks * Q * ms.qstride;
     if (words > (1ull << 28)) return SP_E_INVAL;  // 1 GiB of slots at most
     if (words > m->queue_words) {

@@ -100,6 +100,8 @@ def mutex_candidates():
     out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
     out += [("array", {"poll_sleep": ps}) for ps in (0, 1, 4)]
     out += [("ring", {"poll_sleep": 0}), ("adaptive", {})]
+    out += [("cohort", {"poll_sleep": ps, "cohort_passes": cp}) for ps in (0, 4)
+            for cp in (16, 64)]
     return out
 
 

@@ -3,8 +3,8 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 
 import pytest
 
-from oracle.modelcheck import (BarrierModel, CondModel, FASemModel, MutexModel, QueueLockModel,
-                               SpinSemModel, WeightedSemModel, explore)
+from oracle.modelcheck import (BarrierModel, CohortLockModel, CondModel, FASemModel, MutexModel,
+                               QueueLockModel, SpinSemModel, WeightedSemModel, explore)
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
@@ -165,3 +165,24 @@ def test_catches_predicate_not_rechecked():
 def test_catches_missing_signal():
     r = explore(CondModel(1, 1, 2, 1, mutant="no_signal"))
     assert r.deadlock
+
+
+@pytest.mark.parametrize("n,ops,B", [(4, 1, 2), (3, 2, 2), (3, 1, 3), (3, 2, 3)])
+def test_cohort_lock_correct(n, ops, B):
+    """Mutual exclusion, every acquisition completes, and the global and local locks end
+    released, on all interleavings (two cohorts)."""
+    r = explore(CohortLockModel(n, ops, C=2, B=B))
+    assert r.ok, r.violation
+
+
+@pytest.mark.slow
+def test_cohort_lock_correct_two_per_cohort_twice():
+    r = explore(CohortLockModel(4, 2, C=2, B=2))
+    assert r.ok and r.states > 5 * 10 ** 5, (r.states, r.violation)
+
+
+@pytest.mark.parametrize("mutant,n,ops,B", [("skip_global_wait", 4, 1, 2), ("keep_session", 3, 2, 3),
+                                            ("no_waiter_check", 3, 1, 3)])
+def test_cohort_lock_mutants_fail(mutant, n, ops, B):
+    r = explore(CohortLockModel(n, ops, C=2, B=B, mutant=mutant))
+    assert not r.ok

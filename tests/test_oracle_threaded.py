@@ -23,13 +23,23 @@ def test_barrier_hierarchical_any_grouping(groups):
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep",
-                                  "ring", "array", "adaptive"])
+                                  "ring", "array", "adaptive", "cohort"])
 @pytest.mark.parametrize("L,W", [(1, 1), (1, 16), (3, 4)])
 def test_mutex_threaded_matches_closed(kind, L, W):
     seed, nwg, total = 0xC0FFEE, 8, 3000
     words, rc, _ = oracle.mutex_threaded(kind, seed, nwg, total, L, W)
     assert rc == 0
     assert (words == oracle.mutex_closed(seed, nwg, total, L, W)).all()
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_cohort_mutex_threaded_with_local_passes(L):
+    """32 agents in 8 cohorts of 4: local hand-overs happen; counts stay exact and no two
+    agents are ever inside together (the owner check)."""
+    seed, nwg, total = 11, 32, 6400
+    words, rc, _ = oracle.mutex_threaded("cohort", seed, nwg, total, L, 8)
+    assert rc == 0
+    assert (words == oracle.mutex_closed(seed, nwg, total, L, 8)).all()
 
 
 @pytest.mark.parametrize("kind", ["spin", "spin_backoff", "ticket", "sleep", "counters",
