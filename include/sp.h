@@ -70,7 +70,8 @@ enum sp_mutex_kind {
                              /* global ticket lock; the holder passes the global lock   */
                              /* to a waiter of its own XCD (at most cohort_passes       */
                              /* times in a row) without the L2 writeback, which only a  */
-                             /* hand-over to another XCD needs                          */
+                             /* hand-over to another XCD needs.  State: 32 padded lines */
+                             /* per lock (sp_mutex_run refuses more than 2^28 words)    */
   SP_MUTEX_DEFAULT = 15
 };
 
