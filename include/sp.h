@@ -315,7 +315,7 @@ int sp_sem_run(sp_sem* s, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
  * of `items` values (producer w's j-th value is sm32(seed ^ (w << 16) ^ j); shares split
  * as in sp_mutex_run) into a ring of `capacity` words; the other nwg - producers
  * workgroups take their share.  One mutex of kind mutex_kind (SP_MUTEX_SPIN_CAS, _TICKET,
- * _SLEEP or _ARRAY) guards the ring; producers wait on "not full" while it holds capacity
+ * _SLEEP, _ARRAY or _COHORT) guards the ring; producers wait on "not full" while it holds capacity
  * values, consumers on "not empty" while it is empty, and each signals the other after
  * its put or take.  All nwg workgroups must be co-resident.  out: device, 6 uint64 =
  * {xor of the values taken, their sum, values taken, values put, most values ever in the

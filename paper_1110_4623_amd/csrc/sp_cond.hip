@@ -113,6 +113,7 @@ const void* bb_kernel(uint32_t kind) {
     case SP_MUTEX_TICKET: return (const void*)k_bounded_buffer<SP_MUTEX_TICKET>;
     case SP_MUTEX_SLEEP: return (const void*)k_bounded_buffer<SP_MUTEX_SLEEP>;
     case SP_MUTEX_ARRAY: return (const void*)k_bounded_buffer<SP_MUTEX_ARRAY>;
+    case SP_MUTEX_COHORT: return (const void*)k_bounded_buffer<SP_MUTEX_COHORT>;
     default: return nullptr;
   }
 }
@@ -141,7 +142,13 @@ int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, u
   const uint32_t sw = spi::stride_words(q);
   uint32_t Q = 64;
   while (Q < nwg) Q <<= 1;
-  const uint64_t mutex_words = 5ull * sw + (mutex_kind == SP_MUTEX_ARRAY ? (uint64_t)Q * sw : 0);
+  // the array lock's slots, or the cohort lock's two lines per XCC id (64-bit grant words)
+  const uint32_t qstride = mutex_kind == SP_MUTEX_COHORT ? std::max<uint32_t>(sw, 2) : sw;
+  const uint64_t qwords = mutex_kind == SP_MUTEX_ARRAY    ? (uint64_t)Q * sw
+                          : mutex_kind == SP_MUTEX_COHORT ? 2ull * sp::kXccSlots * qstride
+                                                          : 0;
+  const uint64_t qoff = (5ull * sw + 1) & ~1ull;  // 8-byte aligned for the grant words
+  const uint64_t mutex_words = qoff + qwords;
   const uint64_t cond_words = (uint64_t)C_LINES * kLine;
   const uint64_t bstate_words = (uint64_t)B_LINES * kLine;
   const uint64_t res_words = 8ull * nwg;  // 4 uint64 per workgroup
@@ -156,9 +163,10 @@ int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, u
   ms.ticket = base + sw;
   ms.turn = base + 2ull * sw;
   ms.bo = spi::backoff_cfg(q, base + 3ull * sw);
-  ms.queue = base + 5ull * sw;
+  ms.queue = base + qoff;
   ms.qlen = Q;
-  ms.qstride = sw;
+  ms.qstride = qstride;
+  ms.cohort_bound = q.cohort_passes;
   uint32_t* cond = base + mutex_words;
   sp::CondState nf{cond + C_NF_WAITERS * kLine, cond + C_NF_SIGNALS * kLine, q.poll_sleep};
   sp::CondState ne{cond + C_NE_WAITERS * kLine, cond + C_NE_SIGNALS * kLine, q.poll_sleep};

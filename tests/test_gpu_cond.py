@@ -23,7 +23,7 @@ def _check(r, producers, cap, items, seed):
     assert 1 <= r["max_count"] <= cap
 
 
-@pytest.mark.parametrize("kind", ["ticket", "array", "sleep", "spin_cas"])
+@pytest.mark.parametrize("kind", ["ticket", "array", "sleep", "spin_cas", "cohort"])
 @pytest.mark.parametrize("cap", [1, 16, 1024])
 @pytest.mark.parametrize("nwg,producers", [(2, 1), (9, 4), (64, 32)])
 def test_small(ctx, kind, cap, nwg, producers):
@@ -32,7 +32,7 @@ def test_small(ctx, kind, cap, nwg, producers):
     _check(r, producers, cap, items, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "array"])
+@pytest.mark.parametrize("kind", ["ticket", "array", "cohort"])
 @pytest.mark.parametrize("cap", [1, 64])
 def test_full_width(ctx, kind, cap):
     # 2048 workgroups of 256 lanes: 1024 producers, 1024 consumers
