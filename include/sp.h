@@ -448,7 +448,13 @@ typedef struct sp_serve_cfg {
   uint32_t streams;      /* launch comparator: streams used round robin, 1..4 (0 = 1)      */
   uint32_t batch;        /* launch comparator: requests per launch at most (0 = 1)         */
   uint32_t track;        /* 1: also track the maximum units in use (three more atomics)    */
-  uint32_t reserved[5];
+  uint32_t graph_batch;  /* launch comparator: G in [1, 4096] = replay a HIP graph of G     */
+                         /* one-workgroup kernel nodes (no dependencies between them)     */
+                         /* once G requests have arrived; each node claims the next       */
+                         /* request from a device counter.  A partial batch is launched   */
+                         /* as one kernel when the budget or the ring stalls publishing,  */
+                         /* and at the end.  0 = off; batch must then be 0 or 1           */
+  uint32_t reserved[4];
 } sp_serve_cfg;
 
 typedef struct sp_serve_result {

@@ -126,7 +126,8 @@ class ServeCfg(ctypes.Structure):
         ("streams", ctypes.c_uint32),
         ("batch", ctypes.c_uint32),
         ("track", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 5),
+        ("graph_batch", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 4),
     ]
 
 

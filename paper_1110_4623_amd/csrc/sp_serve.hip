@@ -31,7 +31,7 @@
 namespace {
 
 // Device state lines (each `stride` words apart).
-enum { S_HEAD = 0, S_FRONT, S_READY, S_ISSUED, S_RELEASED, S_INUSE, S_MAXUSE, S_LINES };
+enum { S_HEAD = 0, S_FRONT, S_READY, S_ISSUED, S_RELEASED, S_INUSE, S_MAXUSE, S_CLAIM, S_LINES };
 constexpr uint32_t kStride = 32;            // 128-byte lines
 constexpr uint32_t kMaxSleepUnits = 2048;   // cap of a waiting workgroup's sleep
 constexpr uint64_t kStopBit = 1ull << 63;   // in the host tail word: abandon the run
@@ -160,6 +160,22 @@ __global__ void k_serve_launch(uint32_t r0, uint32_t count, uint32_t L1, const u
   st_sys(h_done + c, 1);
 }
 
+// Comparator, graph-batched: each workgroup (a one-workgroup node of a replayed graph, or
+// one workgroup of a flush launch) claims the next request and reads its descriptor from
+// the ring.  The host launches exactly as many workgroups as it has published requests.
+__global__ void k_serve_claim(const uint64_t* ring, uint32_t mask, uint32_t n, uint32_t seed,
+                              uint32_t* claim, uint32_t* out, uint32_t* h_done, uint32_t* err,
+                              uint64_t timeout) {
+  if (!sp::is_leader()) return;
+  const uint32_t c = sp::add_relaxed(claim, 1);
+  if (c >= n) return;
+  const sp::Ctl ctl{err, sp::wall_clock() + timeout};
+  uint32_t L = 0, u = 0;
+  if (!read_desc(ring, mask, c, &L, &u, ctl)) return;
+  out[c] = chain(seed ^ c, L);
+  st_sys(h_done + c, 1);
+}
+
 // ---- host side ---------------------------------------------------------------------------
 
 inline uint64_t now_ns() {
@@ -178,7 +194,7 @@ inline void wait_until(uint64_t t) {
 }
 
 struct Cfg {
-  uint32_t nwg, lanes, ring_slots, K, seed, poll_sleep, far_sleep, streams, batch, track;
+  uint32_t nwg, lanes, ring_slots, K, seed, poll_sleep, far_sleep, streams, batch, track, graph;
   uint64_t unit_bytes;
   uint64_t timeout_ms;
 };
@@ -197,6 +213,8 @@ int normalize_cfg(const sp_serve_cfg* in, Cfg* c) {
   c->streams = in->streams ? in->streams : 1;
   c->batch = in->batch ? in->batch : 1;
   c->track = in->track ? 1 : 0;
+  c->graph = in->graph_batch;
+  if (c->graph > 4096 || (c->graph && c->batch > 1)) return SP_E_INVAL;
   if (!spi::lanes_ok(c->lanes)) return SP_E_INVAL;
   if (c->ring_slots < 64 || c->ring_slots > (1u << 24) || (c->ring_slots & (c->ring_slots - 1)))
     return SP_E_INVAL;
@@ -216,7 +234,11 @@ struct Buffers {
   uint32_t* d_state = nullptr;
   uint32_t* d_out = nullptr;
   std::vector<hipStream_t> streams;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   ~Buffers() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
     for (hipStream_t s : streams) (void)hipStreamDestroy(s);
     if (h_tail) (void)hipHostFree(h_tail);
     if (h_ring) (void)hipHostFree(h_ring);
@@ -392,6 +414,45 @@ int serve(sp_ctx* ctx, const sp_serve_cfg* cfg_in, uint32_t n, const uint32_t* L
     res->launches = 1;
   }
 
+  // Graph-batched comparator: one graph of G independent one-workgroup claim kernels,
+  // built once and replayed per G published requests.
+  uint32_t* claim = b.d_state + S_CLAIM * kStride;
+  const uint64_t* ring_arg = b.h_ring;
+  uint32_t mask_arg = mask, n_arg = n, seed_arg = c.seed;
+  uint64_t timeout_arg = dev_timeout;
+  void* claim_args[] = {&ring_arg, &mask_arg,  &n_arg,       &seed_arg,   &claim,
+                        &b.d_out,  &b.h_done,  &ctx->d_err, &timeout_arg};
+  if (!persistent && c.graph) {
+    SP_HIP(ctx, hipGraphCreate(&b.graph, 0));
+    hipKernelNodeParams kp{};
+    kp.func = (void*)k_serve_claim;
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(c.lanes);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = claim_args;
+    kp.extra = nullptr;
+    for (uint32_t i = 0; i < c.graph; ++i) {
+      hipGraphNode_t node;
+      SP_HIP(ctx, hipGraphAddKernelNode(&node, b.graph, nullptr, 0, &kp));
+    }
+    SP_HIP(ctx, hipGraphInstantiate(&b.graph_exec, b.graph, nullptr, nullptr, 0));
+  }
+  const bool use_ring = persistent || c.batch > 1 || c.graph;
+  uint32_t covered = 0;  // graph mode: requests the launched workgroups will claim
+  // Graph mode: launch one claim workgroup per published request (below `upto`) that no
+  // launched workgroup covers yet.
+  auto flush = [&](uint32_t upto) -> bool {
+    if (covered >= upto) return true;
+    const uint32_t m = upto - covered;
+    hipLaunchKernelGGL(k_serve_claim, dim3(m), dim3(c.lanes), 0,
+                       b.streams[res->launches % nstreams], ring_arg, mask, n, c.seed, claim,
+                       b.d_out, b.h_done, ctx->d_err, dev_timeout);
+    if (hipGetLastError() != hipSuccess) return false;
+    covered += m;
+    res->launches++;
+    return true;
+  };
+
   const uint64_t t0 = now_ns();
   ob.deadline = t0 + limit_ms * 1000000ull;
   std::thread observer([&ob] { ob.run(); });
@@ -408,9 +469,9 @@ int serve(sp_ctx* ctx, const sp_serve_cfg* cfg_in, uint32_t n, const uint32_t* L
     wait_until(due);
     const uint64_t now = now_ns();
     uint32_t r1 = r;
-    const uint32_t cap = persistent ? n : std::min<uint32_t>(n, r + c.batch);
+    const uint32_t cap = (persistent || c.graph) ? n : std::min<uint32_t>(n, r + c.batch);
     while (r1 < cap && t0 + (uint64_t)(t_arr[r1] * 1e9) <= now) {
-      if (persistent || c.batch > 1) {
+      if (use_ring) {
         if (r1 - ob.lo.load(std::memory_order_acquire) >= c.ring_slots) break;  // ring full
       }
       if (!persistent) {  // host-side admission against the same budget
@@ -418,7 +479,7 @@ int serve(sp_ctx* ctx, const sp_serve_cfg* cfg_in, uint32_t n, const uint32_t* L
         if (held > c.K) break;
         launched_units += units[r1];
       }
-      if (persistent || c.batch > 1) {
+      if (use_ring) {
         uint64_t* slot = b.h_ring + 2 * (size_t)(r1 & mask);
         slot[0] = ((uint64_t)r1 << 32) | L[r1];
         slot[1] = ((uint64_t)r1 << 32) | units[r1];
@@ -426,9 +487,32 @@ int serve(sp_ctx* ctx, const sp_serve_cfg* cfg_in, uint32_t n, const uint32_t* L
       lag_max = std::max(lag_max, (double)(now - (t0 + (uint64_t)(t_arr[r1] * 1e9))) / 1e3);
       ++r1;
     }
-    if (r1 == r) continue;  // ring full or budget exhausted: observe and retry
+    if (r1 == r) {  // ring full or budget exhausted: observe and retry
+      // graph mode: requests waiting for a full batch must run, to free ring and budget
+      if (c.graph && !persistent && !flush(r)) {
+        rc = SP_E_HIP;
+        ob.abort.store(1);
+        break;
+      }
+      continue;
+    }
     if (persistent) {
       __atomic_store_n(b.h_tail, (uint64_t)r1, __ATOMIC_RELEASE);
+    } else if (c.graph) {
+      bool launched_ok = true;
+      while (r1 - covered >= c.graph) {
+        if (hipGraphLaunch(b.graph_exec, b.streams[res->launches % nstreams]) != hipSuccess) {
+          launched_ok = false;
+          break;
+        }
+        covered += c.graph;
+        res->launches++;
+      }
+      if (!launched_ok) {
+        rc = SP_E_HIP;
+        ob.abort.store(1);
+        break;
+      }
     } else {
       hipStream_t s = b.streams[res->launches % nstreams];
       hipLaunchKernelGGL(k_serve_launch, dim3(r1 - r), dim3(c.lanes), 0, s, r, r1 - r, L[r],
@@ -443,6 +527,10 @@ int serve(sp_ctx* ctx, const sp_serve_cfg* cfg_in, uint32_t n, const uint32_t* L
     }
     ob.published.store(r1, std::memory_order_release);
     r = r1;
+  }
+  if (rc == SP_OK && !persistent && c.graph && !flush(r)) {  // the last, partial batch
+    rc = SP_E_HIP;
+    ob.abort.store(1);
   }
   observer.join();
   if (ob.abort.load() && rc == SP_OK) rc = SP_E_TIMEOUT;

@@ -106,6 +106,36 @@ def test_launch_tight_budget(ctx):
     _check(reqs, out, lat, res, seed, 64, tracked=False)
 
 
+@pytest.mark.parametrize("streams,graph", [(1, 1), (1, 8), (4, 8), (4, 64)])
+def test_launch_graph_batched(ctx, streams, graph):
+    """graph_batch: a recorded graph of G one-workgroup nodes is replayed per G arrivals;
+    the partial last batch is flushed; results are the oracle's for every request."""
+    seed = 11
+    reqs = sp_inputs.request_table(1500, 1e5, seed)
+    out, lat, res = _launch(ctx, reqs, seed, streams=streams, graph_batch=graph)
+    _check(reqs, out, lat, res, seed, 16384, tracked=False)
+    assert res["launches"] >= -(-1500 // graph)
+
+
+@pytest.mark.parametrize("budget,ring,graph", [(64, 65536, 16), (16384, 64, 128)])
+def test_launch_graph_batched_flushes_on_stalls(ctx, budget, ring, graph):
+    """A tight budget, or a ring smaller than a batch, stops publishing before a batch is
+    full: the waiting requests are launched as a partial batch instead of deadlocking."""
+    seed = 3
+    reqs = sp_inputs.request_table(700, 1e6, seed, lmax=1024)
+    out, lat, res = _launch(ctx, reqs, seed, budget=budget, streams=2, graph_batch=graph,
+                            ring_slots=ring)
+    _check(reqs, out, lat, res, seed, budget, tracked=False)
+
+
+def test_launch_graph_batched_bad_arguments(ctx):
+    import paper_1110_4623_amd as sp
+    reqs = sp_inputs.request_table(10, 1e5, 1)
+    for kw in (dict(graph_batch=4097), dict(graph_batch=8, batch=4)):
+        with pytest.raises(sp.SpError):
+            _launch(ctx, reqs, 1, **kw)
+
+
 def test_bad_tables_rejected(ctx):
     import paper_1110_4623_amd as sp
     reqs = sp_inputs.request_table(10, 1e5, 42)
