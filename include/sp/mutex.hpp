@@ -46,7 +46,8 @@ __device__ __forceinline__ uint32_t* cohort_ticket(const MutexState& s, uint32_t
   return s.queue + ((size_t)lock * kXccSlots + x) * 2 * s.qstride;
 }
 __device__ __forceinline__ uint64_t* cohort_grant(const MutexState& s, uint32_t lock, uint32_t x) {
-  return reinterpret_cast<uint64_t*>(s.queue + (((size_t)lock * kXccSlots + x) * 2 + 1) * s.qstride);
+  const size_t line = ((size_t)lock * kXccSlots + x) * 2 + 1;
+  return reinterpret_cast<uint64_t*>(s.queue + line * s.qstride);
 }
 
 // KIND:

@@ -169,7 +169,7 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
   if (kind == SP_MUTEX_RING || kind == SP_MUTEX_ARRAY || kind == SP_MUTEX_COHORT) {
     // The ring needs a slot per contender (each workgroup has at most one arrival
     // outstanding); the array lock is correct with any number and polls one line each;
-    // the cohort lock keeps three lines per lock and XCC id.
+    // the cohort lock keeps two lines per lock and XCC id (ticket, 64-bit grant word).
     uint32_t Q = 64;
     while (Q < nwg) Q <<= 1;
     if (kind == SP_MUTEX_COHORT) Q = 2 * sp::kXccSlots;
