@@ -357,6 +357,16 @@ int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, 
  * and counts shader clocks meanwhile (clock64 against wall_clock64).  out: device, 2
  * uint64 scratch; *mhz (host) = the shader clock rate observed.  ms in [1, 10000].      */
 int sp_bench_clock(sp_ctx* ctx, uint32_t ms, uint64_t* out, double* mhz, void* stream);
+/* sp_bench_fence: the cost of agent-scope fences (Section 4's question of what memory
+ * operations cost, asked of gfx950's cache maintenance).  nwg co-resident workgroups of
+ * `lanes` threads; each leader stores to `lines` (<= 1024) 128-byte lines of its own,
+ * waits for all workgroups at a start counter, then issues `reps` (1..1000) fences of
+ * kind 0 = release (write back the XCD's dirty L2 lines) or 1 = acquire (invalidate the
+ * CU's L1 and the XCD's non-coherent L2 lines).  out: device, 4 * nwg uint64: per
+ * workgroup {shader clocks for the reps, wall clock at start, wall clock at end, 0}.
+ * Errors: SP_E_INVAL, SP_E_NORESIDENT, SP_E_TIMEOUT, SP_E_HIP.                           */
+int sp_bench_fence(sp_ctx* ctx, uint32_t kind, uint32_t nwg, uint32_t lanes, uint32_t reps,
+                   uint32_t lines, uint64_t* out, sp_stats* st, void* stream);
 /* sp_bench_copy: copies `bytes` (multiple of 16) from src to dst (device, disjoint) with
  * 16-byte loads and stores, `reps` times; the streaming read+write reference kernel.   */
 int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint32_t reps,

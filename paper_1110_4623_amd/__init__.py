@@ -11,13 +11,14 @@ package is its binding.
 
 from ._native import SpError, SpNotResident, SpTimeout
 from .api import (Barrier, Context, DeviceBuffer, Graph, Mutex, Semaphore,
-                  barrier_hash_launches, bench_atomic, bounded_buffer, copy, litmus,
+                  barrier_hash_launches, bench_atomic, bench_fence, bounded_buffer, copy, litmus,
                   make_params, paper12, pingpong, serve, serve_launch_per_request,
                   shader_clock_mhz, stream_read)
 
 __all__ = [
     "Barrier", "Context", "DeviceBuffer", "Graph", "Mutex", "Semaphore", "SpError",
-    "SpNotResident", "SpTimeout", "barrier_hash_launches", "bench_atomic", "bounded_buffer",
+    "SpNotResident", "SpTimeout", "barrier_hash_launches", "bench_atomic", "bench_fence",
+    "bounded_buffer",
     "copy", "litmus", "make_params", "paper12", "pingpong", "serve",
     "serve_launch_per_request", "shader_clock_mhz", "stream_read",
 ]

@@ -189,6 +189,7 @@ def _load():
         "sp_bench_pingpong": (i32, [vp, u32, vp, vp, P(Stats), vp]),
         "sp_bench_copy": (i32, [vp, vp, vp, u64, u32, P(Stats), vp]),
         "sp_bench_litmus": (i32, [vp, u32, u32, u32, u32, vp, P(Stats), vp]),
+        "sp_bench_fence": (i32, [vp, u32, u32, u32, u32, u32, vp, P(Stats), vp]),
         "sp_bench_clock": (i32, [vp, u32, vp, P(ctypes.c_double), vp]),
         "sp_cond_run_bounded_buffer": (i32, [vp, u32, u32, u32, u32, u32, u64, u32, P(Params),
                                               vp, P(Stats), vp]),

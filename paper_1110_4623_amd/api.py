@@ -447,6 +447,23 @@ def shader_clock_mhz(ctx: Context, ms: int = 20) -> float:
     return mhz.value
 
 
+def bench_fence(ctx: Context, kind: str, nwg: int, lanes: int = 64, reps: int = 1,
+                lines: int = 1) -> dict:
+    """Agent-scope fence cost (sp_bench_fence).  kind: "release" or "acquire".  Returns
+    per-fence shader clocks (mean and max over workgroups) and the wall-clock span from
+    the first workgroup's start to the last one's end."""
+    out = ctx.zeros(4 * nwg, "u64")
+    st = N.Stats()
+    check(lib.sp_bench_fence(ctx.h, {"release": 0, "acquire": 1}[kind], nwg, lanes, reps, lines,
+                             ctx.ptr(out), ctypes.byref(st), ctx.stream()),
+          "sp_bench_fence", ctx.h)
+    v = ctx.read(out, "u64", 4 * nwg).reshape(nwg, 4).astype(np.float64)
+    per = v[:, 0] / reps
+    span_ticks = float(v[:, 2].max() - v[:, 1].min())
+    return {"clk_per_fence_mean": float(per.mean()), "clk_per_fence_max": float(per.max()),
+            "span_us": span_ticks / ctx.info["wall_clock_khz"] * 1e3, "stats": st.as_dict()}
+
+
 def pingpong(ctx: Context, rounds: int):
     words = ctx.zeros(512)
     out = ctx.zeros(4)

@@ -146,6 +146,37 @@ __global__ void k_clock(uint64_t wall_ticks, unsigned long long* out) {
   out[1] = w - w0;
 }
 
+// Fence cost: each workgroup's leader makes `lines` of its own 128-byte lines dirty (plain
+// stores, completed into its XCD's L2), meets the others at a start counter, then times
+// `reps` agent-scope fences of one kind: 0 = release (write back the XCD's dirty L2 lines),
+// 1 = acquire (invalidate the CU's L1 and the XCD's stale L2 lines).  out[4 w + 0] =
+// shader clocks for the reps, out[4 w + 1] / [4 w + 2] = wall clock at start / end.
+__global__ SP_FULL_OCCUPANCY void k_fence(uint32_t kind, uint32_t reps, uint32_t lines,
+                                          uint32_t* scratch, uint32_t* start, uint32_t nwg,
+                                          unsigned long long* out, uint32_t* err,
+                                          uint64_t timeout) {
+  if (!sp::is_leader()) return;
+  const sp::Ctl ctl{err, sp::wall_clock() + timeout};
+  const uint32_t b = blockIdx.x;
+  for (uint32_t i = 0; i < lines; ++i) scratch[((size_t)b * lines + i) * 32] = b + i + 1;
+  sp::wave_stores_complete();
+  sp::add_relaxed(start, 1);
+  sp::Wait w(ctl, 0);
+  while (sp::ld_relaxed(start) < nwg)
+    if (!w.tick()) return;
+  const uint64_t w0 = sp::wall_clock(), c0 = sp::shader_clock();
+  for (uint32_t r = 0; r < reps; ++r) {
+    if (kind == 0) sp::fence_release();
+    else sp::fence_acquire();
+    __asm__ __volatile__("" ::: "memory");
+  }
+  const uint64_t c1 = sp::shader_clock(), w1 = sp::wall_clock();
+  out[4 * (size_t)b + 0] = c1 - c0;
+  out[4 * (size_t)b + 1] = w0;
+  out[4 * (size_t)b + 2] = w1;
+  out[4 * (size_t)b + 3] = 0;
+}
+
 // Streaming copy: 16-byte loads and stores, grid-stride.
 __global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n16) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16;
@@ -288,6 +319,36 @@ int sp_bench_clock(sp_ctx* ctx, uint32_t ms, uint64_t* out, double* mhz, void* s
   SP_HIP(ctx, hipMemcpy(h, out, sizeof(h), hipMemcpyDeviceToHost));
   *mhz = h[1] ? (double)h[0] / (double)h[1] * ctx->wall_khz / 1e3 : 0.0;
   return SP_OK;
+}
+
+int sp_bench_fence(sp_ctx* ctx, uint32_t kind, uint32_t nwg, uint32_t lanes, uint32_t reps,
+                   uint32_t lines, uint64_t* out, sp_stats* st, void* stream) {
+  if (!ctx || !out || kind > 1 || nwg == 0 || nwg > 65536 || !spi::lanes_ok(lanes) ||
+      reps == 0 || reps > 1000 || lines > 1024)
+    return SP_E_INVAL;
+  hipStream_t s = spi::as_stream(stream);
+  SP_HIP(ctx, hipSetDevice(ctx->device));
+  if (spi::capturing(s)) return SP_E_INVAL;  // allocates its buffers
+  // every workgroup waits for all others at the start counter: all must be resident
+  int per_cu = 0;
+  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fence,
+                                                           (int)lanes, 0));
+  if ((uint64_t)per_cu * ctx->cu_count < nwg) return SP_E_NORESIDENT;
+  const uint64_t scratch_words = (uint64_t)nwg * (lines ? lines : 1) * 32;
+  spi::DeviceScratch scratch, start;
+  SP_HIP(ctx, hipMalloc(&scratch.p, scratch_words * sizeof(uint32_t)));
+  SP_HIP(ctx, hipMalloc(&start.p, 64 * sizeof(uint32_t)));
+  SP_CHECK(spi::fill_u32(ctx, start.as<uint32_t>(), 64, 0, s));
+  sp_params q;
+  sp_params_default(&q);
+  const uint64_t timeout = spi::timeout_ticks(ctx, q);
+  SP_CHECK(spi::begin_timed(ctx, s));
+  hipLaunchKernelGGL(k_fence, dim3(nwg), dim3(lanes), 0, s, kind, reps, lines,
+                     scratch.as<uint32_t>(), start.as<uint32_t>(), nwg,
+                     reinterpret_cast<unsigned long long*>(out), ctx->d_err, timeout);
+  const int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, (uint64_t)nwg * reps);
+  SP_HIP(ctx, hipStreamSynchronize(s));  // before the buffers are freed
+  return rc;
 }
 
 int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint32_t reps,

@@ -103,8 +103,23 @@ def micro(ctx, budget_s: float = 0.15, lanes: int = 256, seed: int = 42, quick: 
     return {"rows": rows, "ceilings": ceilings(ctx, rows)}
 
 
+def fence_costs(ctx) -> dict:
+    """Agent-scope fences alone (eight workgroups, one per XCD, one fence each after one
+    dirty line; median of five runs) and when 2048 workgroups issue one each at once (span
+    from the first start to the last end, and the slowest workgroup's fence)."""
+    out = {}
+    for kind in ("release", "acquire"):
+        alone = [api.bench_fence(ctx, kind, 8, 64, reps=1, lines=1)["clk_per_fence_mean"]
+                 for _ in range(5)]
+        together = api.bench_fence(ctx, kind, 2048, 64, reps=1, lines=1)
+        out[f"{kind}_alone_clk"] = float(np.median(alone))
+        out[f"{kind}_2048_span_us"] = together["span_us"]
+        out[f"{kind}_2048_max_clk"] = together["clk_per_fence_max"]
+    return out
+
+
 def ceilings(ctx, rows) -> dict:
-    """A1, A_dist, streaming read bandwidth and coherence latency."""
+    """A1, A_dist, streaming read bandwidth, coherence latency and fence costs."""
     rows = [r for r in rows if "ops_per_s" in r]
     a1 = max((r for r in rows if r["T"] == 1 and r["op"] in ("add", "exch")),
              key=lambda r: r["ops_per_s"], default=None)
@@ -130,7 +145,7 @@ def ceilings(ctx, rows) -> dict:
             {k: ad[k] for k in ("op", "mode", "nwg")},
             "stream_read_GB_per_s": stream, "l2_read_GB_per_s": l2,
             "coherence_latency_ns": lcoh, "shader_clock_mhz": api.shader_clock_mhz(ctx),
-            "pingpong_xcc": out[2:4]}
+            "pingpong_xcc": out[2:4], "fences": fence_costs(ctx)}
 
 
 # ---- mutexes ------------------------------------------------------------------------------

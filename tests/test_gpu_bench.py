@@ -128,3 +128,32 @@ def test_shader_clock_probe(ctx):
     mhz = sp.shader_clock_mhz(ctx, 10)
     print(f"[clock] shader clock {mhz:.0f} MHz", flush=True)
     assert 300 < mhz < 4000
+
+
+@pytest.mark.parametrize("kind", ["release", "acquire"])
+def test_fence_cost_alone_and_together(ctx, kind):
+    """sp_bench_fence: per-fence clocks are positive and bounded; when 2048 workgroups
+    fence at once the span covers at least the slowest workgroup's fence."""
+    import paper_1110_4623_amd as sp
+    announce("bench fence", kind)
+    alone = sp.bench_fence(ctx, kind, 1, 64, reps=50, lines=1)
+    assert 0 < alone["clk_per_fence_mean"] < 1e6
+    together = sp.bench_fence(ctx, kind, 2048, 64, reps=1, lines=4)
+    assert together["clk_per_fence_max"] >= together["clk_per_fence_mean"] > 0
+    mhz = sp.shader_clock_mhz(ctx)
+    assert together["span_us"] * mhz >= 0.5 * together["clk_per_fence_max"]
+    assert together["stats"]["device_error"] == 0
+
+
+def test_fence_bad_arguments(ctx):
+    import ctypes
+    import paper_1110_4623_amd as sp
+    from paper_1110_4623_amd import _native as N
+    out = ctx.zeros(8, "u64")
+    st = N.Stats()
+    for kind, nwg, reps, lines in ((2, 1, 1, 1), (0, 0, 1, 1), (0, 1, 0, 1), (1, 1, 1, 2000)):
+        rc = N.lib.sp_bench_fence(ctx.h, kind, nwg, 64, reps, lines, ctx.ptr(out),
+                                  ctypes.byref(st), ctx.stream())
+        assert rc == N.SP_E_INVAL
+    with pytest.raises(sp.SpError):
+        sp.bench_fence(ctx, "acquire", 1 << 17, 64)
