@@ -171,6 +171,11 @@ def main() -> int:
     ctx.synchronize()
     wall = time.perf_counter() - t0
     clock_after = sp.shader_clock_mhz(ctx)
+    # Cache maintenance the plain-data barrier adds to the coherent-data one (outside the
+    # timed region): one L2 writeback per XCD (8 workgroups, one per XCD) and the
+    # invalidations of 32 CUs per XCD at once (256 workgroups); the slowest of each.
+    rel_us = sp.bench_fence(ctx, "release", 8, 64)["clk_per_fence_max"] / clock_after
+    inv_us = sp.bench_fence(ctx, "acquire", 256, 64)["clk_per_fence_max"] / clock_after
 
     bar_ms = float(np.mean([r["bar_ms"] for r in results]))
     us_round = bar_ms * 1e3 / ROUNDS
@@ -227,6 +232,10 @@ def main() -> int:
             "barrier_coherent_data_us_per_round": round(
                 float(np.mean([r["bar_coh_ms"] for r in results])) * 1e3 / ROUNDS, 4),
             "barrier_coherent_checksums_identical": all(r["bar_coh_same"] for r in results),
+            "barrier_plain_minus_coherent_us": round(
+                us_round - float(np.mean([r["bar_coh_ms"] for r in results])) * 1e3 / ROUNDS, 4),
+            "fence_writeback_per_xcd_us": round(rel_us, 4),
+            "fence_invalidate_32_cus_per_xcd_us": round(inv_us, 4),
             "barrier_arrivals_per_s": round(arrivals, 1),
             "mutex_ticket_acq_per_s": round(mtx_rate, 1),
             "mutex_default_kind_acq_per_s": round(mtx_def_rate, 1),
