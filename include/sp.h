@@ -208,7 +208,8 @@ void sp_params_default(sp_params* p);
  * 64 workgroups per resource, 1 = high).  Used by the autotuner (future-work item of
  * Section 7: tuning backoff per GPU and contention level).  Until a call replaces them,
  * the defaults are a tuning pass's winners on an MI355X: barrier central (low) and
- * per-XCD with 64 stamp copies (high); mutex: the XCD-cohort lock (both); semaphore
+ * per-XCD with 64 stamp copies (high); mutex spin with the paper's backoff, I_max 8
+ * (low) and the XCD-cohort lock (high); semaphore
  * two counters with s_sleep 16 (low) and adaptive (high).                               */
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p);

@@ -178,11 +178,14 @@ int sp_init(int device, sp_ctx** out) {
   ctx->defaults[0][0].p.poll_sleep = 0;
   ctx->defaults[0][1].kind = SP_BARRIER_XCD;      // 6.1 us/round at 1024, 64 stamp copies
   ctx->defaults[0][1].p.poll_sleep = 0;
-  ctx->defaults[1][0].kind = SP_MUTEX_COHORT;  // 0.82 M/s at 16 (paper's backoff: 0.79)
-  ctx->defaults[1][0].p.poll_sleep = 0;
-  ctx->defaults[1][0].p.cohort_passes = 64;
-  ctx->defaults[1][1].kind = SP_MUTEX_COHORT;  // 0.79 M/s at 1024 (ticket: 0.72)
-  ctx->defaults[1][1].p.poll_sleep = 4;
+  // paper's linear backoff, I_max 8: 0.62 / 0.74 M/s at 4 / 32 workgroups on one lock
+  // (cohort lock 0.52 / 0.84, ticket 0.57 / 0.68)
+  ctx->defaults[1][0].kind = SP_MUTEX_SPIN_BACKOFF;
+  ctx->defaults[1][0].p.backoff = SP_BACKOFF_PAPER;
+  ctx->defaults[1][0].p.backoff_max = 8;
+  // XCD-cohort lock: 0.81 M/s on one lock at 1024, 11.0 M/s on 16 locks at 2048 (array 0.68 / 9.2)
+  ctx->defaults[1][1].kind = SP_MUTEX_COHORT;
+  ctx->defaults[1][1].p.poll_sleep = 0;
   ctx->defaults[1][1].p.cohort_passes = 64;
   ctx->defaults[2][0].kind = SP_SEM_COUNTERS;  // 8.7 M pairs/s K = 32 at 256, 7.3 K = 256 at 2048
   ctx->defaults[2][0].p.poll_sleep = 16;

@@ -132,6 +132,16 @@ def tune_mutex(ctx, nwg: int, nlocks: int = 1, words: int = 16, total: int = 409
     return {"nwg": nwg, "nlocks": nlocks, "total": total, "best": best, "candidates": rows}
 
 
+def tune_mutex_points(ctx, points, total: int, **kw) -> dict:
+    """tune_mutex at several (nwg, nlocks) points of one contention bucket; the best
+    geometric mean of acquisitions/s wins (the cohort lock, for one, pays a round trip
+    when uncontended and gains from a few contenders on)."""
+    runs = [tune_mutex(ctx, nwg, nlocks, total=total, **kw) for nwg, nlocks in points]
+    best, rows = _combine_points(runs, "acq_per_s")
+    return {"points": [list(p) for p in points], "total": total, "best": best,
+            "candidates": rows}
+
+
 # ---- semaphores ---------------------------------------------------------------------------
 
 def semaphore_candidates():
@@ -170,11 +180,8 @@ def tune_semaphore(ctx, nwg: int, K: int, total: int = 8192, max_hold: int = 200
     return {"nwg": nwg, "K": K, "total": total, "best": best, "candidates": rows}
 
 
-def tune_semaphore_points(ctx, points, total: int, **kw) -> dict:
-    """Times every candidate at several (nwg, K) points of one contention bucket and keeps
-    the best geometric mean of pairs/s among the candidates correct at every point (a
-    bucket spans many K, and the best waiting policy depends on K)."""
-    runs = [tune_semaphore(ctx, nwg, K, total=total, **kw) for nwg, K in points]
+def _combine_points(runs, key: str) -> tuple:
+    """Candidates correct at every point, ranked by the geometric mean of `key`."""
     keyed = {}
     for run in runs:
         for r in run["candidates"]:
@@ -184,11 +191,19 @@ def tune_semaphore_points(ctx, points, total: int, **kw) -> dict:
         ok = len(rs) == len(runs) and all(r["consistent"] for r in rs)
         row = {"kind": kind, "params": rs[0]["params"], "consistent": ok}
         if ok:
-            row["points_pairs_per_s"] = [r["pairs_per_s"] for r in rs]
-            row["pairs_per_s"] = math.exp(sum(math.log(v) for v in row["points_pairs_per_s"])
-                                          / len(rs))
+            row["points_" + key] = [r[key] for r in rs]
+            row[key] = math.exp(sum(math.log(v) for v in row["points_" + key]) / len(rs))
         rows.append(row)
-    best = max((r for r in rows if r["consistent"]), key=lambda r: r["pairs_per_s"])
+    best = max((r for r in rows if r["consistent"]), key=lambda r: r[key])
+    return best, rows
+
+
+def tune_semaphore_points(ctx, points, total: int, **kw) -> dict:
+    """Times every candidate at several (nwg, K) points of one contention bucket and keeps
+    the best geometric mean of pairs/s among the candidates correct at every point (a
+    bucket spans many K, and the best waiting policy depends on K)."""
+    runs = [tune_semaphore(ctx, nwg, K, total=total, **kw) for nwg, K in points]
+    best, rows = _combine_points(runs, "pairs_per_s")
     return {"points": [list(p) for p in points], "total": total, "best": best,
             "candidates": rows}
 
@@ -222,16 +237,16 @@ def device_key(ctx) -> str:
 
 
 def tune_all(ctx, quick: bool = False) -> dict:
-    """Tunes barriers (16 and 1024 workgroups), one contended lock (16 and 1024
-    workgroups) and semaphores (bucket 0: K = 32 at 256 workgroups and K = 256 at 2048;
-    bucket 1: K = 32 and K = 4 at 2048)."""
+    """Tunes barriers (16 and 1024 workgroups), mutexes (bucket 0: one lock at 4 and 32
+    workgroups; bucket 1: one lock at 1024, 16 locks at 2048) and semaphores (bucket 0:
+    K = 32 at 256 workgroups and K = 256 at 2048; bucket 1: K = 32 and K = 4 at 2048)."""
     rounds = 300 if quick else 1000
     mt = 1024 if quick else 4096
     res = {"device": device_key(ctx), "barrier": {}, "mutex": {}, "semaphore": {}}
     res["barrier"]["0"] = tune_barrier(ctx, 16, rounds=rounds)
     res["barrier"]["1"] = tune_barrier(ctx, 1024, rounds=rounds)
-    res["mutex"]["0"] = tune_mutex(ctx, 16, total=mt)
-    res["mutex"]["1"] = tune_mutex(ctx, 1024, total=mt)
+    res["mutex"]["0"] = tune_mutex_points(ctx, [(4, 1), (32, 1)], mt)
+    res["mutex"]["1"] = tune_mutex_points(ctx, [(1024, 1), (2048, 16)], mt)
     # 32 waits per workgroup at 2048: long enough for the adaptive kind to learn its interval
     res["semaphore"]["0"] = tune_semaphore_points(ctx, [(256, 32), (2048, 256)], 16 * mt)
     res["semaphore"]["1"] = tune_semaphore_points(ctx, [(2048, 32), (2048, 4)], 16 * mt)
