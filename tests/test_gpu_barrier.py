@@ -200,3 +200,44 @@ def test_xcd_stamp_copies_with_small_and_large_padding(ctx, pad):
     """A copy holds every XCD's stamp even when the padding is below 8 words."""
     chk, _ = _run(ctx, "xcd", 1024, 128, 300, 42, xcd_copies=64, pad_bytes=pad)
     assert (chk == oracle.barrier_closed(42, 1024, 300)).all()
+
+
+def _max_resident(ctx, lanes):
+    import paper_1110_4623_amd as sp
+    b = sp.Barrier(ctx, "central", 64)
+    try:
+        _, st = b.run_hash(lanes, 1, 1)
+    finally:
+        b.close()
+    return st["resident_per_cu"] * ctx.info["cu_count"]
+
+
+@pytest.mark.parametrize("kind", ["xcd", "central", "tree", "flag"])
+def test_largest_co_resident_grid(ctx, kind):
+    """The most workgroups that can be resident at once (64-lane workgroups, every wave
+    slot of every CU): each XCD's master scans a full flag block, every CU's member list
+    is full; the checksums are the oracle's."""
+    import paper_1110_4623_amd as sp
+    nwg = _max_resident(ctx, 64)
+    assert nwg >= 4096
+    announce("barrier largest grid", kind, f"nwg={nwg} lanes=64 rounds=200")
+    b = sp.Barrier(ctx, kind, nwg)
+    try:
+        for seed in (42, 7):
+            chk, _ = b.run_hash(64, 200, seed)
+            assert (chk == oracle.barrier_closed(seed, nwg, 200)).all()
+        if kind == "xcd":
+            assert b.info()["xcd_path"]
+    finally:
+        b.close()
+
+
+def test_one_more_than_resident_is_refused(ctx):
+    import paper_1110_4623_amd as sp
+    nwg = _max_resident(ctx, 64) + 1
+    b = sp.Barrier(ctx, "xcd", nwg)
+    try:
+        with pytest.raises(sp.SpNotResident):
+            b.run_hash(64, 1, 1)
+    finally:
+        b.close()
