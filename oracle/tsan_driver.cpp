@@ -48,12 +48,13 @@ int main() {
       expect(got == want, "barrier checksums");
     }
   }
-  {  // mutexes: every kind, two locks of three words
-    const uint32_t nwg = 6, L = 2, W = 3;
+  {  // mutexes: every kind, two locks of three words; 16 agents put two in each of the
+     // cohort lock's eight cohorts, so its local hand-overs run too
+    const uint32_t nwg = 16, L = 2, W = 3;
     const uint64_t total = 300;
     std::vector<uint32_t> want(L * W), got(L * W);
     or_mutex_closed(seed, nwg, total, L, W, want.data());
-    for (int kind = 0; kind <= 7; ++kind) {
+    for (int kind = 0; kind <= 8; ++kind) {
       expect(or_mutex_threaded(kind, seed, nwg, total, L, W, 1, 4, got.data(), nullptr) == 0,
              "mutex rc");
       expect(got == want, "mutex words");
@@ -65,7 +66,7 @@ int main() {
     std::vector<uint32_t> want(nwg), got(nwg);
     uint32_t maxocc = 0, state[4];
     or_sem_closed(seed, nwg, total, want.data());
-    for (int kind = 0; kind <= 4; ++kind) {
+    for (int kind = 0; kind <= 5; ++kind) {
       expect(or_sem_threaded(kind, 2, seed, nwg, total, 1, 4, got.data(), &maxocc, state,
                              nullptr) == 0,
              "semaphore rc");
