@@ -15,7 +15,7 @@ struct sp_mutex {
   uint32_t* d_state = nullptr;  // lock, ticket and turn lines + one private line
   uint64_t state_words = 0;
   uint32_t* d_words = nullptr;  // critical-section words, nlocks x wstride
-  uint32_t* d_queue = nullptr;  // ring / array mutexes: slots, sized per run
+  uint32_t* d_queue = nullptr;  // ring / array: slots, sized per run; cohort: at creation
   uint64_t queue_words = 0;
 };
 
@@ -108,10 +108,26 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
   m->wstride = (words_per_lock + line_words - 1) / line_words * line_words;
   hipError_t e = hipMalloc(&m->d_state, m->state_words * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&m->d_words, (uint64_t)nlocks * m->wstride * sizeof(uint32_t));
+  // The cohort lock's state depends only on the lock count and padding: allocate it now
+  // (for a DEFAULT mutex when a built-in default is the cohort lock), so that even the
+  // first run can be recorded into a graph.
+  uint32_t cohort_sw = 0;
+  if (kind == SP_MUTEX_COHORT) cohort_sw = spi::stride_words(q);
+  for (int b = 0; b < 2 && kind == SP_MUTEX_DEFAULT; ++b)
+    if (ctx->defaults[1][b].kind == SP_MUTEX_COHORT)
+      cohort_sw = std::max(cohort_sw, spi::stride_words(ctx->defaults[1][b].p));
+  if (cohort_sw) {
+    const uint64_t words = (uint64_t)nlocks * 2 * sp::kXccSlots * std::max<uint32_t>(cohort_sw, 2);
+    if (e == hipSuccess && words <= (1ull << 28)) {
+      e = hipMalloc(&m->d_queue, words * sizeof(uint32_t));
+      if (e == hipSuccess) m->queue_words = words;
+    }
+  }
   if (e != hipSuccess) {
     ctx->last_hip = (int)e;
     hipFree(m->d_state);
     hipFree(m->d_words);
+    hipFree(m->d_queue);
     delete m;
     return SP_E_HIP;
   }

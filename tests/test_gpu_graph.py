@@ -109,3 +109,23 @@ def test_cooperative_launch_cannot_be_recorded(ctx):
         assert (chk == oracle.barrier_closed(3, 16, 10)).all()
     finally:
         ok.close()
+
+
+def test_default_mutex_recorded_on_first_use(ctx):
+    """A DEFAULT mutex whose kind resolves to the cohort lock (2048 contenders on one lock)
+    records into a graph on its very first run: its state is allocated at creation."""
+    import paper_1110_4623_amd as sp
+    seed, total = 9, 1 << 14
+    m = sp.Mutex(ctx, "default", 1, 16)
+    try:
+        announce("graph default mutex first use")
+        g = sp.Graph(ctx)
+        with g:
+            m.launch(2048, 256, total, 200, seed)
+        for rep in range(2):
+            st = g.launch(replays=1)
+            assert st["device_error"] == 0
+            assert (m.words() == total).all()
+        g.close()
+    finally:
+        m.close()
