@@ -404,7 +404,10 @@ int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* o
  * records its state resets (fill kernels, never memset nodes) and kernels instead of
  * running them: it returns SP_OK at once, zeroes *st and leaves its outputs unwritten.
  * Cooperative launches (SP_BARRIER_GRID_SYNC, sp_params.cooperative) and the graph mode
- * of sp_barrier_run_hash_launches cannot be recorded (SP_E_INVAL).
+ * of sp_barrier_run_hash_launches cannot be recorded (SP_E_INVAL), nor can calls that
+ * allocate device memory: a ring or array mutex's run with more workgroups than any run
+ * before it (run it once outside the recording), sp_bench_litmus, sp_bench_fence and
+ * sp_cond_run_bounded_buffer (SP_E_INVAL).
  * sp_graph_end: stops recording and instantiates the graph (*out, owned by the caller).
  * sp_graph_launch: clears the watchdog word, replays the graph `replays` times back to
  * back on `stream`, times all replays with HIP events, waits, and reports SP_E_TIMEOUT if
