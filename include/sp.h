@@ -407,7 +407,7 @@ int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* o
  * of sp_barrier_run_hash_launches cannot be recorded (SP_E_INVAL), nor can calls that
  * allocate device memory: a ring or array mutex's run with more workgroups than any run
  * before it (run it once outside the recording), sp_bench_litmus, sp_bench_fence and
- * sp_cond_run_bounded_buffer (SP_E_INVAL).
+ * sp_cond_run_bounded_buffer, or that return a host result (sp_bench_clock).
  * sp_graph_end: stops recording and instantiates the graph (*out, owned by the caller).
  * sp_graph_launch: clears the watchdog word, replays the graph `replays` times back to
  * back on `stream`, times all replays with HIP events, waits, and reports SP_E_TIMEOUT if

@@ -310,6 +310,7 @@ int sp_bench_clock(sp_ctx* ctx, uint32_t ms, uint64_t* out, double* mhz, void* s
   if (!ctx || !out || !mhz || ms == 0 || ms > 10000) return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
+  if (spi::capturing(s)) return SP_E_INVAL;  // waits and reads the result back
   const uint64_t ticks = (uint64_t)ms * ctx->wall_khz;
   hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s, ticks,
                      reinterpret_cast<unsigned long long*>(out));

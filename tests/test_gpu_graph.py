@@ -129,3 +129,26 @@ def test_default_mutex_recorded_on_first_use(ctx):
         g.close()
     finally:
         m.close()
+
+
+def test_calls_that_cannot_be_recorded_are_refused(ctx):
+    """Inside a recording, calls that wait for a host result or allocate raise at once and
+    leave the recording usable: what was recorded before and after still replays."""
+    import paper_1110_4623_amd as sp
+    bar = sp.Barrier(ctx, "central", 64)
+    try:
+        announce("graph refusals")
+        g = sp.Graph(ctx)
+        with g:
+            bar.launch(64, 50, 3)
+            with pytest.raises(sp.SpError):
+                sp.shader_clock_mhz(ctx)
+            with pytest.raises(sp.SpError):
+                sp.bench_fence(ctx, "release", 8)
+            bar.launch(64, 50, 4)
+        st = g.launch(replays=2)
+        assert st["device_error"] == 0
+        assert (bar.checksums() == oracle.barrier_closed(4, 64, 50)).all()
+        g.close()
+    finally:
+        bar.close()
