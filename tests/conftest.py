@@ -31,5 +31,6 @@ def pytest_sessionstart(session):
     """Build the HIP library once if it is not there (tests load what is built)."""
     lib = os.path.join(ROOT, "paper_1110_4623_amd", "libsp.so")
     if not os.path.exists(lib):
-        from paper_1110_4623_amd import build as b
-        b.build()
+        sys.path.insert(0, ROOT)
+        import __graft_entry__
+        __graft_entry__._builder().build()
