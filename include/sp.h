@@ -18,6 +18,10 @@
  *     fill `*st` (may be NULL).  Output buffers hold the results when the call returns.
  *   - Every device wait is bounded by sp_params.timeout_ms (wall clock); on expiry the
  *     kernel stops and the call returns SP_E_TIMEOUT.
+ *   - A context and the objects created from it are used by one host thread at a time:
+ *     all of a context's runs share its watchdog word and its last-error slot (the
+ *     serving calls run their own observer thread inside the call).  Use one context per
+ *     host thread for concurrent work.
  */
 #ifndef SP_H
 #define SP_H
