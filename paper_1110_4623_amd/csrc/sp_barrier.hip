@@ -235,13 +235,14 @@ int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t
   int per_cu = 0;
   SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
   if ((uint64_t)per_cu * ctx->cu_count < b->nwg) return SP_E_NORESIDENT;
+  // cooperative launches are not recorded: refuse before anything joins the capture
+  const bool coop = b->kind == SP_BARRIER_GRID_SYNC || b->p.cooperative;
+  if (coop && spi::capturing(s)) return SP_E_INVAL;
   SP_CHECK(spi::fill_u32(ctx, b->d_state, b->state_words, 0, s));
   SP_CHECK(spi::fill_u32(ctx, b->d_slots, 2ull * b->nwg, 0, s));
   SP_CHECK(spi::begin_timed(ctx, s));
   uint64_t timeout = spi::timeout_ticks(ctx, b->p);
   uint32_t N = b->nwg;
-  const bool coop = b->kind == SP_BARRIER_GRID_SYNC || b->p.cooperative;
-  if (coop && spi::capturing(s)) return SP_E_INVAL;  // cooperative launches are not recorded
   if (b->kind == SP_BARRIER_GRID_SYNC) {  // grid.sync() requires a cooperative launch
     void* args[] = {&N, &rounds, &seed, &b->d_slots, &out_checksums};
     SP_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(N), dim3(lanes), args, 0, s));

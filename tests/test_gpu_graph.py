@@ -92,9 +92,11 @@ def test_replay_overhead_below_call_overhead(ctx):
         bar.close()
 
 
-def test_cooperative_launch_cannot_be_recorded(ctx):
+@pytest.mark.parametrize("kind,params", [("grid_sync", {}), ("central", {"cooperative": 1})])
+def test_cooperative_launch_cannot_be_recorded(ctx, kind, params):
     import paper_1110_4623_amd as sp
-    bar = sp.Barrier(ctx, "grid_sync", 16)
+    announce("graph refuses cooperative", kind, params)
+    bar = sp.Barrier(ctx, kind, 16, **params)
     try:
         g = sp.Graph(ctx)
         with pytest.raises(sp.SpError):
