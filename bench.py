@@ -176,6 +176,12 @@ def main() -> int:
     # invalidations of 32 CUs per XCD at once (256 workgroups); the slowest of each.
     rel_us = sp.bench_fence(ctx, "release", 8, 64)["clk_per_fence_max"] / clock_after
     inv_us = sp.bench_fence(ctx, "acquire", 256, 64)["clk_per_fence_max"] / clock_after
+    # One-way latency of a signal between workgroups on different XCDs, relaxed agent-scope
+    # store and polling (token ping-pong, 2 x 20000 hand-overs), also outside the timed
+    # region.  No barrier round can end sooner than one such hop after its last arrival.
+    sp.pingpong(ctx, 100, fenced=False)
+    pp_xcc, pp_st = sp.pingpong(ctx, 20000, fenced=False)
+    sig_us = pp_st["kernel_ms"] * 1e3 / (2 * 20000)
 
     bar_ms = float(np.mean([r["bar_ms"] for r in results]))
     us_round = bar_ms * 1e3 / ROUNDS
@@ -204,6 +210,14 @@ def main() -> int:
                 "measured_traffic_GB_per_s": (round(traffic / (bar_ms * 1e-3) / 1e9, 2)
                                               if traffic is not None else None)}
 
+    # Latency floor of one plain-data round (any barrier on this chip): the last arriver's
+    # XCD writes its dirty L2 lines back, one cross-XCD signal reaches the other workgroups,
+    # and every CU's L1 is invalidated (32 per XCD, which the XCD serializes) before the
+    # exchanged slot can be read.  The exchange's own slot store and load are left out, so
+    # the floor is a lower bound.  With coherently accessed data only the signal remains.
+    coh_us = float(np.mean([r["bar_coh_ms"] for r in results])) * 1e3 / ROUNDS
+    floor_us = rel_us + sig_us + inv_us
+
     line = {
         "metric": METRIC,
         "value": round(us_round, 4),
@@ -229,13 +243,13 @@ def main() -> int:
             "barrier_us_per_round_min": round(float(per_round.min()), 4),
             "kernel_boundary_graph_us_per_round": round(kb_us, 4),
             "kernel_boundary_checksums_identical": all(r["bar_kb_same"] for r in results),
-            "barrier_coherent_data_us_per_round": round(
-                float(np.mean([r["bar_coh_ms"] for r in results])) * 1e3 / ROUNDS, 4),
+            "barrier_coherent_data_us_per_round": round(coh_us, 4),
             "barrier_coherent_checksums_identical": all(r["bar_coh_same"] for r in results),
-            "barrier_plain_minus_coherent_us": round(
-                us_round - float(np.mean([r["bar_coh_ms"] for r in results])) * 1e3 / ROUNDS, 4),
+            "barrier_plain_minus_coherent_us": round(us_round - coh_us, 4),
             "fence_writeback_per_xcd_us": round(rel_us, 4),
             "fence_invalidate_32_cus_per_xcd_us": round(inv_us, 4),
+            "signal_one_way_cross_xcd_us": round(sig_us, 4),
+            "signal_pingpong_xcc": pp_xcc[2:4],
             "barrier_arrivals_per_s": round(arrivals, 1),
             "mutex_ticket_acq_per_s": round(mtx_rate, 1),
             "mutex_default_kind_acq_per_s": round(mtx_def_rate, 1),
@@ -255,15 +269,25 @@ def main() -> int:
             "shader_clock_mhz_before_after": [round(clock_before, 1), round(clock_after, 1)],
         },
         "roofline": {
-            "bound": "atomic",
+            "bound": "latency",
             "kernel": f"k_barrier_hash<{args.barrier}, plain data>",
-            "achieved": round(arrivals / 1e9, 6),
-            "peak": round(a1 / 1e9, 6),
-            "unit": "G arrivals/s vs contended atomics/s",
-            "frac": round(arrivals / a1, 4),
+            "achieved": round(1.0 / us_round, 6),
+            "peak": round(1.0 / floor_us, 6),
+            "unit": "M barrier rounds/s (peak: 1 / the round's latency floor)",
+            "frac": round(floor_us / us_round, 4),
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-            "peak_source": "measured in this run: contended agent-scope atomic adds to one word",
+            "floor": {"l2_writeback_per_xcd_us": round(rel_us, 4),
+                      "signal_one_way_cross_xcd_us": round(sig_us, 4),
+                      "cu_invalidations_per_xcd_us": round(inv_us, 4),
+                      "floor_us": round(floor_us, 4),
+                      "source": "measured in this run: sp_bench_fence, sp_bench_pingpong"},
+            "coherent_data_view": {"achieved_us": round(coh_us, 4),
+                                   "floor_us": round(sig_us, 4),
+                                   "frac": round(sig_us / coh_us, 4)},
+            "atomic_view": {"achieved": round(arrivals / 1e9, 6), "peak": round(a1 / 1e9, 6),
+                            "unit": "G arrivals/s vs contended atomics/s (one word)",
+                            "frac": round(arrivals / a1, 4)},
             "hbm_view": hbm_view,
         },
         "env": environment(ctx, results[0]["bar_occ"]),

@@ -390,13 +390,22 @@ int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint3
 int sp_bench_litmus(sp_ctx* ctx, uint32_t test, uint32_t variant, uint32_t pairs,
                     uint32_t iters, uint64_t* out, sp_stats* st, void* stream);
 /* sp_bench_pingpong: two workgroups hand a token back and forth `rounds` times through
- * two agent-scope words (release store, relaxed polling, acquire fence), measuring the
- * one-way coherence latency.  words: device, 2048 bytes, zeroed by the call.
- * out: device, 4 uint32 = {word written by workgroup 1 (ends at 2 * rounds), word
- * written by workgroup 0 (ends at 2 * rounds - 1), XCC id of workgroup 0, XCC id of
- * workgroup 1}.  st->kernel_ms / (2 * rounds) is the one-way latency.                   */
-int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* out,
-                      sp_stats* st, void* stream);
+ * two agent-scope words, measuring the one-way coherence latency that bounds every
+ * signal between workgroups (Section 4's latency question; Section 5's flags).
+ * mode: bit 0 (SP_PINGPONG_FENCED) = release store and acquire fence around each hand-over
+ * (a signal that publishes plain data); clear = relaxed agent-scope store and polling
+ * only (a signal that publishes nothing, or coherently accessed data).  Bit 1
+ * (SP_PINGPONG_SAME_XCD) = the partner is workgroup `xcd_count` instead of workgroup 1,
+ * which the dispatcher's round robin over the XCDs places on workgroup 0's XCD (out[2..3]
+ * report where they ran).  Other bits: SP_E_INVAL.
+ * words: device, 2048 bytes, zeroed by the call.  out: device, 4 uint32 = {word written by
+ * the partner (ends at 2 * rounds), word written by workgroup 0 (ends at 2 * rounds - 1),
+ * XCC id of workgroup 0, XCC id of the partner}.  st->kernel_ms / (2 * rounds) is the
+ * one-way latency.  Errors: SP_E_INVAL (rounds == 0, bad mode), SP_E_TIMEOUT, SP_E_HIP.  */
+#define SP_PINGPONG_FENCED 1u
+#define SP_PINGPONG_SAME_XCD 2u
+int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t mode, uint32_t* words,
+                      uint32_t* out, sp_stats* st, void* stream);
 
 /* ---- recorded batches (HIP graphs) ---------------------------------------------------
  * Section 7 leaves the tuning of these primitives per GPU and contention level to future

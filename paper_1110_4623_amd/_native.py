@@ -42,6 +42,8 @@ BACKOFF = {"none": 0, "paper": 1, "exp": 2}
 BACKOFF_UNIT = {"sleep": 0, "load": 1}
 OPS = {"add": 0, "cas": 1, "exch": 2, "ld": 3, "st": 4}
 ISSUE = {"per_lane": 0, "wave_leader": 1}
+PINGPONG_FENCED = 1
+PINGPONG_SAME_XCD = 2
 PAPER12 = {
     "cont_vol_read": 0, "cont_vol_write": 1, "noncont_vol_read": 2, "noncont_vol_write": 3,
     "cont_atom_read": 4, "cont_atom_write": 5, "noncont_atom_read": 6,
@@ -186,7 +188,7 @@ def _load():
                                   P(Stats), vp]),
         "sp_bench_paper12": (i32, [vp, u32, u32, u32, u32, u32, vp, vp, P(Stats), vp]),
         "sp_bench_stream": (i32, [vp, vp, u64, u32, u32, vp, P(Stats), vp]),
-        "sp_bench_pingpong": (i32, [vp, u32, vp, vp, P(Stats), vp]),
+        "sp_bench_pingpong": (i32, [vp, u32, u32, vp, vp, P(Stats), vp]),
         "sp_bench_copy": (i32, [vp, vp, vp, u64, u32, P(Stats), vp]),
         "sp_bench_litmus": (i32, [vp, u32, u32, u32, u32, vp, P(Stats), vp]),
         "sp_bench_fence": (i32, [vp, u32, u32, u32, u32, u32, vp, P(Stats), vp]),

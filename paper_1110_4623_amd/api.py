@@ -464,12 +464,16 @@ def bench_fence(ctx: Context, kind: str, nwg: int, lanes: int = 64, reps: int = 
             "span_us": span_ticks / ctx.info["wall_clock_khz"] * 1e3, "stats": st.as_dict()}
 
 
-def pingpong(ctx: Context, rounds: int):
+def pingpong(ctx: Context, rounds: int, fenced: bool = True, same_xcd: bool = False):
+    """Token ping-pong between two workgroups (`sp_bench_pingpong`): returns ([partner's
+    word, workgroup 0's word, XCC of workgroup 0, XCC of the partner], stats); one-way
+    latency = kernel_ms / (2 * rounds)."""
     words = ctx.zeros(512)
     out = ctx.zeros(4)
     st = N.Stats()
-    check(lib.sp_bench_pingpong(ctx.h, rounds, ctx.ptr(words), ctx.ptr(out), ctypes.byref(st),
-                                ctx.stream()), "sp_bench_pingpong", ctx.h)
+    mode = (N.PINGPONG_FENCED if fenced else 0) | (N.PINGPONG_SAME_XCD if same_xcd else 0)
+    check(lib.sp_bench_pingpong(ctx.h, rounds, mode, ctx.ptr(words), ctx.ptr(out),
+                                ctypes.byref(st), ctx.stream()), "sp_bench_pingpong", ctx.h)
     return [int(x) for x in ctx.read(out, "u32", 4)], st.as_dict()
 
 

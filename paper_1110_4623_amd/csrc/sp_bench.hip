@@ -184,30 +184,38 @@ __global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, u
     dst[i] = src[i];
 }
 
-// Token passing between workgroup 0 and workgroup 1 through two words 1 KiB apart.
-__global__ SP_FULL_OCCUPANCY void k_pingpong(uint32_t rounds, uint32_t* words, uint32_t* out, uint32_t* err,
-                           uint64_t timeout) {
-  if (threadIdx.x != 0 || blockIdx.x > 1) return;
+// Token passing between workgroup 0 and a partner workgroup through two words 1 KiB
+// apart.  FENCED: release store and acquire fence per hand-over; otherwise relaxed
+// agent-scope accesses only.  Workgroups other than 0 and the partner leave at once.
+template <bool FENCED>
+__global__ SP_FULL_OCCUPANCY void k_pingpong(uint32_t rounds, uint32_t partner, uint32_t* words,
+                                             uint32_t* out, uint32_t* err, uint64_t timeout) {
+  if (threadIdx.x != 0 || (blockIdx.x != 0 && blockIdx.x != partner)) return;
   const sp::Ctl ctl{err, sp::wall_clock() + timeout};
   sp::Wait w(ctl, 0);
-  uint32_t* from1 = words;        // written by workgroup 1
+  uint32_t* from1 = words;        // written by the partner
   uint32_t* from0 = words + 256;  // written by workgroup 0
   if (blockIdx.x == 0) {
     for (uint32_t r = 0; r < rounds; ++r) {
-      sp::st_release(from0, 2 * r + 1);
+      if constexpr (FENCED) sp::st_release(from0, 2 * r + 1);
+      else sp::st_relaxed(from0, 2 * r + 1);
       while (!sp::reached(sp::ld_relaxed(from1), 2 * r + 2))
         if (!w.tick()) return;
-      sp::fence_acquire();
+      if constexpr (FENCED) sp::fence_acquire();
     }
   } else {
     for (uint32_t r = 0; r < rounds; ++r) {
       while (!sp::reached(sp::ld_relaxed(from0), 2 * r + 1))
         if (!w.tick()) return;
-      sp::fence_acquire();
-      sp::st_release(from1, 2 * r + 2);
+      if constexpr (FENCED) {
+        sp::fence_acquire();
+        sp::st_release(from1, 2 * r + 2);
+      } else {
+        sp::st_relaxed(from1, 2 * r + 2);
+      }
     }
   }
-  out[2 + blockIdx.x] = sp::xcc_id();
+  out[blockIdx.x == 0 ? 2 : 3] = sp::xcc_id();
   if (blockIdx.x == 0) {
     out[0] = sp::ld_relaxed(from1);
     out[1] = sp::ld_relaxed(from0);
@@ -365,9 +373,11 @@ int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint3
   return spi::end_timed(ctx, s, st, nwg, 256, 0, 2 * bytes * reps);
 }
 
-int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* out,
-                      sp_stats* st, void* stream) {
-  if (!ctx || !words || !out || rounds == 0) return SP_E_INVAL;
+int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t mode, uint32_t* words,
+                      uint32_t* out, sp_stats* st, void* stream) {
+  if (!ctx || !words || !out || rounds == 0 ||
+      (mode & ~(SP_PINGPONG_FENCED | SP_PINGPONG_SAME_XCD)) != 0)
+    return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
   SP_CHECK(spi::fill_u32(ctx, words, 512, 0, s));
@@ -375,10 +385,14 @@ int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t* words, uint32_t* o
   sp_params q;
   sp_params_default(&q);
   uint64_t timeout = spi::timeout_ticks(ctx, q);
+  // Workgroup b goes to XCD b mod xcd_count, so workgroup xcd_count shares workgroup 0's.
+  uint32_t partner = (mode & SP_PINGPONG_SAME_XCD) ? std::max<uint32_t>(1, ctx->xcd_count) : 1;
+  const void* kern = (mode & SP_PINGPONG_FENCED) ? (const void*)k_pingpong<true>
+                                                 : (const void*)k_pingpong<false>;
   SP_CHECK(spi::begin_timed(ctx, s));
-  // Both workgroups must run at once: two one-wave workgroups always fit.
-  void* args[] = {&rounds, &words, &out, &ctx->d_err, &timeout};
-  SP_HIP(ctx, hipLaunchKernel((const void*)k_pingpong, dim3(2), dim3(64), args, 0, s));
+  // Both workgroups must run at once: at most 17 one-wave workgroups always fit.
+  void* args[] = {&rounds, &partner, &words, &out, &ctx->d_err, &timeout};
+  SP_HIP(ctx, hipLaunchKernel(kern, dim3(partner + 1), dim3(64), args, 0, s));
   return spi::end_timed(ctx, s, st, 2, 64, 0, 2ull * rounds);
 }
 

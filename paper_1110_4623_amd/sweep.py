@@ -118,8 +118,23 @@ def fence_costs(ctx) -> dict:
     return out
 
 
+def signal_latencies(ctx, rounds: int = 20000) -> dict:
+    """One-way latency of a signal between two workgroups (ns, token ping-pong): across
+    XCDs and within one, relaxed agent-scope accesses only and with a release store and
+    acquire fence per hand-over; plus where the two workgroups ran."""
+    out = {}
+    for fenced in (False, True):
+        for same in (False, True):
+            api.pingpong(ctx, 100, fenced=fenced, same_xcd=same)
+            xcc, st = api.pingpong(ctx, rounds, fenced=fenced, same_xcd=same)
+            key = ("fenced" if fenced else "relaxed") + ("_same_xcd" if same else "_cross_xcd")
+            out[key + "_ns"] = st["kernel_ms"] * 1e6 / (2 * rounds)
+            out[key + "_xcc"] = xcc[2:4]
+    return out
+
+
 def ceilings(ctx, rows) -> dict:
-    """A1, A_dist, streaming read bandwidth, coherence latency and fence costs."""
+    """A1, A_dist, streaming read bandwidth, signal latencies and fence costs."""
     rows = [r for r in rows if "ops_per_s" in r]
     a1 = max((r for r in rows if r["T"] == 1 and r["op"] in ("add", "exch")),
              key=lambda r: r["ops_per_s"], default=None)
@@ -137,15 +152,15 @@ def ceilings(ctx, rows) -> dict:
     _, st = api.stream_read(ctx, buf, small, 200, nwg=2048)
     l2 = 200 * small / (st["kernel_ms"] * 1e-3) / 1e9
     del buf
-    out, st = api.pingpong(ctx, 20000)
-    lcoh = st["kernel_ms"] * 1e6 / (2 * 20000)
+    sig = signal_latencies(ctx)
     return {"A1_ops_per_s": a1 and a1["ops_per_s"], "A1_setting": a1 and
             {k: a1[k] for k in ("op", "mode", "nwg")},
             "A_dist_ops_per_s": ad and ad["ops_per_s"], "A_dist_setting": ad and
             {k: ad[k] for k in ("op", "mode", "nwg")},
             "stream_read_GB_per_s": stream, "l2_read_GB_per_s": l2,
-            "coherence_latency_ns": lcoh, "shader_clock_mhz": api.shader_clock_mhz(ctx),
-            "pingpong_xcc": out[2:4], "fences": fence_costs(ctx)}
+            "coherence_latency_ns": sig["fenced_cross_xcd_ns"],
+            "shader_clock_mhz": api.shader_clock_mhz(ctx), "signal_latency": sig,
+            "fences": fence_costs(ctx)}
 
 
 # ---- mutexes ------------------------------------------------------------------------------

@@ -127,3 +127,20 @@ def test_kind_tables_match_the_header():
                           ("SP_SEM_", N.SEM_KINDS)):
         for name, value in table.items():
             assert enum[prefix + name.upper()] == value, (prefix, name)
+
+
+def test_pingpong_mode_bits_match_the_header():
+    import re
+    from paper_1110_4623_amd import _native as N
+    text = open(os.path.join(ROOT, "include", "sp.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in
+            re.finditer(r"#define\s+(SP_PINGPONG_\w+)\s+(\d+)u", text)}
+    assert defs == {"SP_PINGPONG_FENCED": N.PINGPONG_FENCED,
+                    "SP_PINGPONG_SAME_XCD": N.PINGPONG_SAME_XCD}
+
+
+def test_pingpong_rejects_bad_arguments_without_gpu():
+    import ctypes
+    from paper_1110_4623_amd import _native as N
+    st = N.Stats()
+    assert N.lib.sp_bench_pingpong(None, 10, 0, None, None, ctypes.byref(st), None) == N.SP_E_INVAL

@@ -84,11 +84,16 @@ def test_stream_sum(ctx):
     assert (ctx.read(dst, "u32", n) == np.arange(n, dtype=np.uint32)).all()
 
 
-def test_pingpong(ctx):
+@pytest.mark.parametrize("fenced", [True, False])
+@pytest.mark.parametrize("same_xcd", [False, True])
+def test_pingpong(ctx, fenced, same_xcd):
     import paper_1110_4623_amd as sp
-    announce("pingpong")
-    out, st = sp.pingpong(ctx, 1000)
+    announce("pingpong", f"fenced={fenced} same_xcd={same_xcd}")
+    out, st = sp.pingpong(ctx, 1000, fenced=fenced, same_xcd=same_xcd)
     assert out[0] == 2000 and out[1] == 1999
+    assert out[2] < 16 and out[3] < 16 and st["kernel_ms"] > 0
+    print(f"[pingpong] xcc {out[2]} / {out[3]}, one way {st['kernel_ms'] * 1e6 / 2000:.0f} ns",
+          flush=True)
 
 
 @pytest.mark.parametrize("nwg", [1, 8, 2048])
