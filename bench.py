@@ -177,11 +177,17 @@ def main() -> int:
     rel_us = sp.bench_fence(ctx, "release", 8, 64)["clk_per_fence_max"] / clock_after
     inv_us = sp.bench_fence(ctx, "acquire", 256, 64)["clk_per_fence_max"] / clock_after
     # One-way latency of a signal between workgroups on different XCDs, relaxed agent-scope
-    # store and polling (token ping-pong, 2 x 20000 hand-overs), also outside the timed
-    # region.  No barrier round can end sooner than one such hop after its last arrival.
+    # store and polling (token ping-pong, 2 x 10^4 hand-overs per run), also outside the
+    # timed region.  It depends on which XCDs the pair runs on and on where the two words
+    # live (0.39-0.65 µs measured): eight runs with the words 4 KiB further on each time,
+    # the fastest is the hop.  No barrier round can end sooner than one such hop after
+    # its last arrival.
     sp.pingpong(ctx, 100, fenced=False)
-    pp_xcc, pp_st = sp.pingpong(ctx, 20000, fenced=False)
-    sig_us = pp_st["kernel_ms"] * 1e3 / (2 * 20000)
+    sig_runs = []
+    for i in range(8):
+        pp_xcc, pp_st = sp.pingpong(ctx, 10000, fenced=False, offset_bytes=4096 * i)
+        sig_runs.append([round(pp_st["kernel_ms"] * 1e3 / (2 * 10000), 4), pp_xcc[2:4]])
+    sig_us = min(v for v, _ in sig_runs)
 
     bar_ms = float(np.mean([r["bar_ms"] for r in results]))
     us_round = bar_ms * 1e3 / ROUNDS
@@ -249,7 +255,7 @@ def main() -> int:
             "fence_writeback_per_xcd_us": round(rel_us, 4),
             "fence_invalidate_32_cus_per_xcd_us": round(inv_us, 4),
             "signal_one_way_cross_xcd_us": round(sig_us, 4),
-            "signal_pingpong_xcc": pp_xcc[2:4],
+            "signal_one_way_runs_us_xcc": sig_runs,
             "barrier_arrivals_per_s": round(arrivals, 1),
             "mutex_ticket_acq_per_s": round(mtx_rate, 1),
             "mutex_default_kind_acq_per_s": round(mtx_def_rate, 1),

@@ -464,15 +464,20 @@ def bench_fence(ctx: Context, kind: str, nwg: int, lanes: int = 64, reps: int = 
             "span_us": span_ticks / ctx.info["wall_clock_khz"] * 1e3, "stats": st.as_dict()}
 
 
-def pingpong(ctx: Context, rounds: int, fenced: bool = True, same_xcd: bool = False):
+def pingpong(ctx: Context, rounds: int, fenced: bool = True, same_xcd: bool = False,
+             offset_bytes: int = 0):
     """Token ping-pong between two workgroups (`sp_bench_pingpong`): returns ([partner's
     word, workgroup 0's word, XCC of workgroup 0, XCC of the partner], stats); one-way
-    latency = kernel_ms / (2 * rounds)."""
-    words = ctx.zeros(512)
+    latency = kernel_ms / (2 * rounds).  offset_bytes (a multiple of 128) places the two
+    words that far into a fresh buffer, to reach other memory channels."""
+    if offset_bytes < 0 or offset_bytes % 128:
+        raise ValueError("offset_bytes must be a non-negative multiple of 128")
+    words = ctx.zeros(512 + offset_bytes // 4)
     out = ctx.zeros(4)
     st = N.Stats()
     mode = (N.PINGPONG_FENCED if fenced else 0) | (N.PINGPONG_SAME_XCD if same_xcd else 0)
-    check(lib.sp_bench_pingpong(ctx.h, rounds, mode, ctx.ptr(words), ctx.ptr(out),
+    base = ctx.ptr(words).value + offset_bytes
+    check(lib.sp_bench_pingpong(ctx.h, rounds, mode, ctypes.c_void_p(base), ctx.ptr(out),
                                 ctypes.byref(st), ctx.stream()), "sp_bench_pingpong", ctx.h)
     return [int(x) for x in ctx.read(out, "u32", 4)], st.as_dict()
 

@@ -162,3 +162,12 @@ def test_fence_bad_arguments(ctx):
         assert rc == N.SP_E_INVAL
     with pytest.raises(sp.SpError):
         sp.bench_fence(ctx, "acquire", 1 << 17, 64)
+
+
+def test_pingpong_words_at_an_offset(ctx):
+    import paper_1110_4623_amd as sp
+    announce("pingpong offset 12288")
+    out, _ = sp.pingpong(ctx, 500, fenced=False, offset_bytes=3 * 4096)
+    assert out[0] == 1000 and out[1] == 999
+    with pytest.raises(ValueError):
+        sp.pingpong(ctx, 10, offset_bytes=100)
