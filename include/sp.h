@@ -168,7 +168,16 @@ typedef struct sp_params {
   uint32_t cohort_passes; /* SP_MUTEX_COHORT: holders of one XCD that may take the lock */
                            /* in a row before it goes back to the global queue, 1..255    */
                            /* (0 = 64)                                                    */
-  uint32_t reserved[2];
+  uint32_t flag_placement; /* SP_BARRIER_XCD: 0 = measured (default).  A signal between    */
+                           /* two workgroups takes 30-40 % less time when its line lives   */
+                           /* in memory close to their XCD, so sp_barrier_create times a   */
+                           /* same-XCD hand-over on each 8 KiB chunk of a 512 KiB area for */
+                           /* every XCD (~2 ms) and gives each XCD its fastest free chunk  */
+                           /* for its arrival flags and then for the stamp copies it polls */
+                           /* (when xcd_copies is a multiple of the XCD count and each     */
+                           /* block fits in a chunk; sp_barrier_info reports the outcome). */
+                           /* 1 = fixed layout (XCD-major blocks).  Timing only.           */
+  uint32_t reserved[1];
 } sp_params;
 
 typedef struct sp_stats {
@@ -263,7 +272,9 @@ typedef struct sp_barrier_info {
   uint32_t xcd_path;
   uint32_t misplaced;
   uint32_t cu_overflow;
-  uint32_t reserved[3];
+  uint32_t near_placed;  /* SP_BARRIER_XCD: 1 = arrival flags in measured chunks, 2 = the */
+                         /* stamp copies too, 0 = fixed layout                             */
+  uint32_t reserved[2];
 } sp_barrier_info;
 int sp_barrier_info_get(sp_barrier* b, sp_barrier_info* out);
 /* Comparator: the same workload with the kernel boundary as the barrier (one launch per

@@ -28,6 +28,13 @@ struct BarrierState {
                         // loads and stores, so the barrier does no cache maintenance
   uint32_t xcopies;     // xcd: copies of the XCD stamps (0 = xarrive, one line per XCD)
   uint32_t xmstride;    // xcd: words between two copies (>= groups, whole lines)
+  // xcd: where each XCD's flags live.  XCD x's block of arrival flags starts xoff[x]
+  // words into larrive; copy c of the stamps starts moff[c mod groups] + (c / groups) *
+  // xmstep words into xmail (with xcopies a multiple of groups, only XCD c mod groups
+  // polls copy c, so each XCD's copies can sit in memory close to it).
+  uint32_t xmstep;
+  uint32_t xoff[16];
+  uint32_t moff[16];
   uint32_t* cnt;        // centralized counter
   uint32_t* gen;        // centralized split: release word
   uint32_t* gcnt;       // tree: per-group counters (groups lines)
@@ -232,7 +239,7 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
   const uint32_t members = __builtin_amdgcn_readfirstlane(L.members);
   const uint32_t xmask = __builtin_amdgcn_readfirstlane(L.xmask);
   const uint32_t slot = __builtin_amdgcn_readfirstlane(L.slot);
-  uint32_t* block = s.larrive + (size_t)x * s.xblock * kArriveWords;
+  uint32_t* block = s.larrive + s.xoff[x];
   uint32_t* rel = s.lrelease + (size_t)x * s.xblock * s.stride;  // member k: rel + k*stride
   Wait w(ctl, s.poll_sleep);
   int ok = 1;
@@ -252,14 +259,15 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
     } else if (threadIdx.x < 64) {
       if (s.fenced) fence_release();
       for (uint32_t c = threadIdx.x; c < C; c += 64)
-        st_relaxed(s.xmail + (size_t)c * s.xmstride + x, stamp);
+        st_relaxed(s.xmail + s.moff[c % X] + (size_t)(c / X) * s.xmstep + x, stamp);
     }
   } else if (is_leader()) {
     st_relaxed(block + (size_t)k * kArriveWords, stamp);
   }
   // The populated XCDs' stamps: one line each, or packed in this CU's copy.
+  const uint32_t mail = __builtin_amdgcn_readfirstlane(L.mail);
   const uint32_t* stamps =
-      C ? s.xmail + (size_t)__builtin_amdgcn_readfirstlane(L.mail) * s.xmstride : s.xarrive;
+      C ? s.xmail + s.moff[mail % X] + (size_t)(mail / X) * s.xmstep : s.xarrive;
   const uint32_t sstride = C ? 1 : s.stride;
   if (!s.fenced) {
     // Coherent data: no cache maintenance, so nothing is shared per CU; every workgroup

@@ -68,7 +68,8 @@ class Params(ctypes.Structure):
         ("coherent_cs", ctypes.c_uint32),
         ("xcd_copies", ctypes.c_uint32),
         ("cohort_passes", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 2),
+        ("flag_placement", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 1),
     ]
 
 
@@ -110,7 +111,8 @@ class BarrierInfo(ctypes.Structure):
         ("xcd_path", ctypes.c_uint32),
         ("misplaced", ctypes.c_uint32),
         ("cu_overflow", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 3),
+        ("near_placed", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 2),
     ]
 
 

@@ -217,7 +217,7 @@ class Barrier(_Handle):
         i = N.BarrierInfo()
         check(lib.sp_barrier_info_get(self.h, ctypes.byref(i)), "sp_barrier_info_get", self.ctx.h)
         return {"xcd_path": bool(i.xcd_path), "misplaced": i.misplaced,
-                "cu_overflow": i.cu_overflow}
+                "cu_overflow": i.cu_overflow, "near_placed": i.near_placed}
 
     def run_hash(self, lanes: int, rounds: int, seed: int):
         """Hash-exchange workload; returns (checksums as uint32 numpy array, stats)."""

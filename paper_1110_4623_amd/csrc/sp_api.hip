@@ -34,6 +34,7 @@ int normalize(const sp_ctx* ctx, const sp_params* in, sp_params* out) {
   if (p.xcd_copies > 256 || (p.xcd_copies & (p.xcd_copies - 1))) return SP_E_INVAL;
   if (p.cohort_passes == 0) p.cohort_passes = 64;
   if (p.cohort_passes > 255) return SP_E_INVAL;  // the grant word's session field
+  if (p.flag_placement > 1) return SP_E_INVAL;
   *out = p;
   return SP_OK;
 }

@@ -3,6 +3,8 @@
 #include <hip/hip_cooperative_groups.h>
 #include <string.h>
 
+#include <vector>
+
 #include "sp/barrier.hpp"
 #include "sp_internal.hpp"
 
@@ -14,6 +16,9 @@ struct sp_barrier {
   uint32_t* d_state = nullptr;  // counters and flags
   uint64_t state_words = 0;
   uint32_t* d_slots = nullptr;  // 2 x nwg exchanged values
+  uint32_t* d_near = nullptr;   // per-XCD blocks in measured chunks (flag_placement 0)
+  uint64_t near_words = 0;
+  uint32_t near_placed = 0;     // 0 fixed layout, 1 arrival blocks, 2 and stamp copies
   sp::BarrierState st{};
 };
 
@@ -98,6 +103,94 @@ const void* barrier_kernel(uint32_t kind, bool coherent) {
   return coherent ? barrier_kernel_c<true>(kind) : barrier_kernel_c<false>(kind);
 }
 
+// Flag placement.  A signal between two workgroups of one XCD takes 640-720 shader clocks
+// one way when its line lives in a chunk of memory close to that XCD and 950-1080 when it
+// does not; which 8 KiB chunks are close changes with the XCD.  The probe measures it:
+// the first two one-wave workgroups that register on an XCD hand a token back and forth
+// `rounds` times through two lines of every chunk in turn (XCD x starting at chunk
+// x * nchunks / groups, so that the pairs work on different chunks), and the first of
+// them stores the mean one-way time per chunk in lat[x * nchunks + chunk].  Every wait
+// ends at the wall-clock deadline; a chunk not measured keeps 0.
+constexpr uint32_t kChunkWords = 2048;  // 8 KiB
+constexpr uint32_t kNearChunks = 64;    // 512 KiB
+constexpr uint32_t kProbeWorkgroups = 64;
+
+__global__ void k_near_probe(uint32_t* area, uint32_t nchunks, uint32_t groups,
+                             uint32_t rounds, uint32_t* claims, uint32_t* lat,
+                             uint64_t deadline_ticks) {
+  if (threadIdx.x != 0) return;
+  const uint64_t end = sp::wall_clock() + deadline_ticks;
+  const uint32_t x = sp::xcc_id() % groups;
+  const uint32_t role = sp::add_relaxed(claims + x, 1);
+  if (role > 1) return;
+  for (uint32_t i = 0; i < nchunks; ++i) {
+    const uint32_t j = (i + x * (nchunks / groups)) % nchunks;
+    uint32_t* ping = area + (size_t)j * kChunkWords + x * 64;  // two lines per XCD
+    uint32_t* pong = ping + 32;
+    const uint64_t t0 = sp::shader_clock();
+    for (uint32_t r = 0; r < rounds; ++r) {
+      if (role == 0) {
+        sp::st_relaxed(ping, 2 * r + 1);
+        while (sp::ld_relaxed(pong) < 2 * r + 2)
+          if (sp::wall_clock() > end) return;
+      } else {
+        while (sp::ld_relaxed(ping) < 2 * r + 1)
+          if (sp::wall_clock() > end) return;
+        sp::st_relaxed(pong, 2 * r + 2);
+      }
+    }
+    if (role == 0) {
+      const uint64_t t = (sp::shader_clock() - t0) / (2ull * rounds);
+      sp::st_relaxed(lat + (size_t)x * nchunks + j, (uint32_t)std::max<uint64_t>(1, t));
+    }
+  }
+}
+
+// Measures the chunks of b->d_near and gives each XCD its fastest free chunk for its
+// arrival block and, when `mail`, then for its stamp copies.  Leaves the fixed layout
+// in place (returns SP_OK) when any XCD could not be measured.
+int place_near(sp_barrier* b, uint32_t G, bool mail) {
+  sp_ctx* ctx = b->ctx;
+  spi::DeviceScratch scratch;
+  const uint64_t words = G + (uint64_t)G * kNearChunks;
+  SP_HIP(ctx, hipMalloc(&scratch.p, words * sizeof(uint32_t)));
+  uint32_t* claims = scratch.as<uint32_t>();
+  uint32_t* lat = claims + G;
+  hipStream_t s = nullptr;
+  SP_CHECK(spi::fill_u32(ctx, claims, words, 0, s));
+  SP_CHECK(spi::fill_u32(ctx, b->d_near, b->near_words, 0, s));
+  const uint64_t deadline = (uint64_t)ctx->wall_khz * 50;  // 50 ms
+  hipLaunchKernelGGL(k_near_probe, dim3(kProbeWorkgroups), dim3(64), 0, s, b->d_near,
+                     kNearChunks, G, 32u, claims, lat, deadline);
+  SP_HIP(ctx, hipGetLastError());
+  SP_HIP(ctx, hipStreamSynchronize(s));
+  std::vector<uint32_t> h((size_t)G * kNearChunks);
+  SP_HIP(ctx, hipMemcpy(h.data(), lat, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  for (uint32_t v : h)
+    if (v == 0) return SP_OK;
+  std::vector<bool> used(kNearChunks, false);
+  auto take = [&](uint32_t x) {
+    uint32_t best = kNearChunks;
+    for (uint32_t j = 0; j < kNearChunks; ++j)
+      if (!used[j] && (best == kNearChunks || h[(size_t)x * kNearChunks + j] <
+                                                   h[(size_t)x * kNearChunks + best]))
+        best = j;
+    used[best] = true;
+    return best * kChunkWords;
+  };
+  sp::BarrierState& st = b->st;
+  for (uint32_t x = 0; x < G; ++x) st.xoff[x] = take(x);
+  st.larrive = b->d_near;
+  b->near_placed = 1;
+  if (mail) {
+    for (uint32_t x = 0; x < G; ++x) st.moff[x] = take(x);
+    st.xmail = b->d_near;
+    st.xmstep = st.xmstride;
+    b->near_placed = 2;
+  }
+  return SP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -113,6 +206,7 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
     sp_params dp = d.p;
     if (p && p->timeout_ms) dp.timeout_ms = p->timeout_ms;  // an explicit timeout applies
     if (p) dp.coherent_cs = p->coherent_cs;  // a property of the caller's data accesses
+    if (p) dp.flag_placement = p->flag_placement;
     SP_CHECK(spi::normalize(ctx, &dp, &q));  // fills fan_in and the other "auto" fields
   } else {
     if (kind > SP_BARRIER_XCD) return SP_E_INVAL;
@@ -191,6 +285,34 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.xcu = s.overflow + 1;                                      // G words
   s.cu_rank = s.xcu + G;                                       // G * 256 words
   s.xmail = s.cu_count + cu_lines * sw;  // xcopies copies of xmstride words
+  // Fixed layout: XCD-major blocks of arrival flags, copies in order.
+  for (uint32_t x = 0; x < G && x < 16; ++x) {
+    s.xoff[x] = x * xblock * sp::kArriveWords;
+    s.moff[x] = x * mstride;
+  }
+  s.xmstep = G * mstride;
+  if (kind == SP_BARRIER_XCD && q.flag_placement == 0 && G >= 2 && G <= 16 &&
+      xblock * sp::kArriveWords <= kChunkWords) {
+    const bool mail = copies >= G && copies % G == 0 && (copies / G) * mstride <= kChunkWords;
+    b->near_words = (uint64_t)kNearChunks * kChunkWords;
+    int rc = SP_OK;
+    e = hipMalloc(&b->d_near, b->near_words * sizeof(uint32_t));
+    if (e != hipSuccess) {
+      ctx->last_hip = (int)e;
+      rc = SP_E_HIP;
+    } else {
+      rc = place_near(b, G, mail);
+    }
+    if (rc != SP_OK) {
+      sp_barrier_destroy(b);
+      return rc;
+    }
+    if (b->near_placed == 0) {  // not measured: keep the fixed layout, drop the area
+      hipFree(b->d_near);
+      b->d_near = nullptr;
+      b->near_words = 0;
+    }
+  }
   *out = b;
   return SP_OK;
 }
@@ -200,6 +322,7 @@ int sp_barrier_destroy(sp_barrier* b) {
   hipSetDevice(b->ctx->device);
   hipFree(b->d_state);
   hipFree(b->d_slots);
+  if (b->d_near) hipFree(b->d_near);
   delete b;
   return SP_OK;
 }
@@ -218,6 +341,7 @@ int sp_barrier_info_get(sp_barrier* b, sp_barrier_info* out) {
     out->misplaced = w[0];
     out->cu_overflow = w[1];
     out->xcd_path = w[1] == 0;
+    out->near_placed = b->near_placed;
   }
   return SP_OK;
 }
@@ -240,6 +364,7 @@ int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t
   if (coop && spi::capturing(s)) return SP_E_INVAL;
   SP_CHECK(spi::fill_u32(ctx, b->d_state, b->state_words, 0, s));
   SP_CHECK(spi::fill_u32(ctx, b->d_slots, 2ull * b->nwg, 0, s));
+  if (b->d_near) SP_CHECK(spi::fill_u32(ctx, b->d_near, b->near_words, 0, s));
   SP_CHECK(spi::begin_timed(ctx, s));
   uint64_t timeout = spi::timeout_ticks(ctx, b->p);
   uint32_t N = b->nwg;

@@ -171,6 +171,61 @@ def test_xcd_stamp_copies(ctx, copies, coherent, nwg, lanes):
         b.close()
 
 
+def _near_expected(ctx, nwg, copies, placement, pad=128):
+    n = ctx.info["xcd_count"]
+    xblock = ((nwg + n - 1) // n + 31) // 32 * 32
+    if placement == 1 or n < 2 or xblock * 4 > 2048:
+        return 0
+    sw = max(1, pad // 4)
+    mstride = (max(sw, n) + sw - 1) // sw * sw
+    return 2 if copies >= n and copies % n == 0 and copies // n * mstride <= 2048 else 1
+
+
+@pytest.mark.parametrize("placement", [0, 1])
+@pytest.mark.parametrize("copies", [0, 4, 8, 64, 256])
+@pytest.mark.parametrize("coherent", [0, 1])
+def test_xcd_flag_placement(ctx, placement, copies, coherent):
+    """flag_placement 0 measures at creation which 8 KiB chunks are close to each XCD and
+    puts the XCD's arrival flags there, and the stamp copies it polls when every copy is
+    polled by one XCD; 1 keeps the fixed layout.  The checksums are the oracle's either
+    way, run after run."""
+    import paper_1110_4623_amd as sp
+    nwg = 2048
+    announce("xcd placement", f"placement={placement} copies={copies} coherent={coherent}")
+    b = sp.Barrier(ctx, "xcd", nwg, xcd_copies=copies, coherent_cs=coherent,
+                   flag_placement=placement)
+    try:
+        assert b.info()["near_placed"] == _near_expected(ctx, nwg, copies, placement)
+        for seed in (42, 7, 42):
+            chk, _ = b.run_hash(256, 500, seed)
+            assert (chk == oracle.barrier_closed(seed, nwg, 500)).all()
+        assert b.info()["xcd_path"]
+    finally:
+        b.close()
+
+
+@pytest.mark.parametrize("nwg,lanes,pad", [(5, 64, 128), (300, 128, 4), (1000, 256, 4096),
+                                           (4096, 64, 128)])
+def test_xcd_flag_placement_shapes(ctx, nwg, lanes, pad):
+    """Ragged grids, tiny and page-sized padding: the measured layout where the blocks
+    fit a chunk, the fixed one where they do not."""
+    import paper_1110_4623_amd as sp
+    announce("xcd placement shapes", f"nwg={nwg} lanes={lanes} pad={pad}")
+    b = sp.Barrier(ctx, "xcd", nwg, xcd_copies=64, pad_bytes=pad)
+    try:
+        assert b.info()["near_placed"] == _near_expected(ctx, nwg, 64, 0, pad)
+        chk, _ = b.run_hash(lanes, 300, 5)
+        assert (chk == oracle.barrier_closed(5, nwg, 300)).all()
+    finally:
+        b.close()
+
+
+def test_xcd_flag_placement_invalid(ctx):
+    import paper_1110_4623_amd as sp
+    with pytest.raises(sp.SpError):
+        sp.Barrier(ctx, "xcd", 64, flag_placement=2)
+
+
 def test_xcd_stamp_copies_after_cooperative_launch(ctx):
     import paper_1110_4623_amd as sp
     announce("grid_sync then xcd copies=8")
@@ -228,6 +283,7 @@ def test_largest_co_resident_grid(ctx, kind):
             assert (chk == oracle.barrier_closed(seed, nwg, 200)).all()
         if kind == "xcd":
             assert b.info()["xcd_path"]
+            assert b.info()["near_placed"] == _near_expected(ctx, nwg, 64, 0)
     finally:
         b.close()
 
