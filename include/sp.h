@@ -173,9 +173,10 @@ typedef struct sp_params {
                            /* in memory close to their XCD, so sp_barrier_create times a   */
                            /* same-XCD hand-over on each 8 KiB chunk of a 512 KiB area for */
                            /* every XCD (~2 ms) and gives each XCD its fastest free chunk  */
-                           /* for its arrival flags and then for the stamp copies it polls */
-                           /* (when xcd_copies is a multiple of the XCD count and each     */
-                           /* block fits in a chunk; sp_barrier_info reports the outcome). */
+                           /* for its arrival flags, the stamp copies it polls (when       */
+                           /* xcd_copies is a multiple of the XCD count) and its CUs'      */
+                           /* release lines, each when it fits in a chunk                  */
+                           /* (sp_barrier_info reports the outcome).                       */
                            /* 1 = fixed layout (XCD-major blocks).  Timing only.           */
   uint32_t reserved[1];
 } sp_params;
@@ -272,8 +273,9 @@ typedef struct sp_barrier_info {
   uint32_t xcd_path;
   uint32_t misplaced;
   uint32_t cu_overflow;
-  uint32_t near_placed;  /* SP_BARRIER_XCD: 1 = arrival flags in measured chunks, 2 = the */
-                         /* stamp copies too, 0 = fixed layout                             */
+  uint32_t near_placed;  /* SP_BARRIER_XCD, what sits in measured chunks: bit 0 arrival */
+                         /* flags, bit 1 stamp copies, bit 2 per-CU release lines; 0 =     */
+                         /* fixed layout                                                   */
   uint32_t reserved[2];
 } sp_barrier_info;
 int sp_barrier_info_get(sp_barrier* b, sp_barrier_info* out);

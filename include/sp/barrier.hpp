@@ -29,12 +29,14 @@ struct BarrierState {
   uint32_t xcopies;     // xcd: copies of the XCD stamps (0 = xarrive, one line per XCD)
   uint32_t xmstride;    // xcd: words between two copies (>= groups, whole lines)
   // xcd: where each XCD's flags live.  XCD x's block of arrival flags starts xoff[x]
-  // words into larrive; copy c of the stamps starts moff[c mod groups] + (c / groups) *
-  // xmstep words into xmail (with xcopies a multiple of groups, only XCD c mod groups
+  // words into larrive, its per-CU release lines roff[x] words into lrelease (the CU of
+  // rank r at + r * stride); copy c of the stamps starts moff[c mod groups] + (c / groups)
+  // * xmstep words into xmail (with xcopies a multiple of groups, only XCD c mod groups
   // polls copy c, so each XCD's copies can sit in memory close to it).
   uint32_t xmstep;
   uint32_t xoff[16];
   uint32_t moff[16];
+  uint32_t roff[16];
   uint32_t* cnt;        // centralized counter
   uint32_t* gen;        // centralized split: release word
   uint32_t* gcnt;       // tree: per-group counters (groups lines)
@@ -46,19 +48,18 @@ struct BarrierState {
   uint32_t* mismatch;   // xcd: workgroups not on XCD (id mod groups), informational
   uint32_t* overflow;   // xcd: registrations that did not fit (nonzero = tree fallback)
   uint32_t* xarrive;    // xcd: per-XCD arrival stamps (groups lines)
-  uint32_t* lrelease;   // xcd: per-workgroup release flags (nwg lines), XCD-major
+  uint32_t* lrelease;   // xcd: per-CU release lines (kCuLines per XCD)
   uint32_t* larrive;    // xcd: arrival flags kArriveWords apart, XCD-major blocks of
                         // xblock flags
   uint32_t* cu_count;   // xcd: workgroups registered per CU key (groups * 256 words)
-  uint32_t* cu_members; // xcd: member indices per CU key (groups * 256 * kCuSlots words)
   uint32_t* xcount;     // xcd: members registered per XCD (groups words)
   uint32_t* xcu;        // xcd: CU leaders registered per XCD (groups words)
   uint32_t* cu_rank;    // xcd: rank of each CU key within its XCD (groups * 256 words)
   uint32_t* xmail;      // xcd: xcopies copies, each holding every XCD's stamp packed
 };
 
-// Workgroups one CU can hold at most (32 wavefront slots).
-constexpr uint32_t kCuSlots = 32;
+// CUs with members per XCD that the per-XCD barrier takes (gfx950 has 32 per XCD).
+constexpr uint32_t kCuLines = 64;
 // Words between two arrival flags of an XCD's block: 16 bytes, eight flags per 128-byte
 // line.  Packed flags put 32 concurrent writers on every line and one line per flag
 // makes the master's scan touch a line per member; eight per line measured fastest.
@@ -197,16 +198,17 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
 //   2. The master writes back the XCD's dirty L2 lines once for all its members (agent
 //      release) and publishes the XCD's stamp.
 //   3. Each CU leader polls the stamps of every XCD that has members; once all are
-//      published it acquires (agent scope) and releases the other workgroups of its CU.
-//      Every flag is its own line.  With xcopies = C > 0 the masters write their stamps
-//      into C lines that each hold all of them packed, and the CUs spread their polls
-//      over the copies by their rank in their XCD (fewer pollers per line).
+//      published it acquires (agent scope) and releases the other workgroups of its CU
+//      with one store to the CU's release line, which they poll.  With xcopies = C > 0
+//      the masters write their stamps into C lines that each hold all of them packed,
+//      and the CUs spread their polls over the copies by their rank in their XCD (fewer
+//      pollers per line).
 // Writebacks and invalidations both serialize at each XCD's L2 controller.  The
 // writeback is shared by the whole XCD.  The invalidation has to reach each CU's L1, and
 // on gfx950 only the agent-scope invalidate does (a workgroup-scope one leaves stale L1
 // lines), so it is shared by the workgroups of one CU: all of them are waiting when
 // their leader invalidates, so nothing stale can re-enter the L1 before they read.
-// If an XCD holds more members than its flag block or a CU more than kCuSlots, every
+// If an XCD holds more members than its flag block or more than kCuLines CUs, every
 // workgroup falls back to the counter tree.  All flags are agent-scope atomics.
 struct XcdLocal {
   uint32_t x;        // the XCD this workgroup runs on
@@ -215,19 +217,9 @@ struct XcdLocal {
   uint32_t xmask;    // XCDs that have members (bit i = XCD i)
   uint32_t key;      // CU key: XCD * 256 + CU id
   uint32_t slot;     // registration order on the CU (0 = CU leader)
-  uint32_t ncu;      // workgroups on this CU
+  uint32_t rank;     // rank of the CU among its XCD's CUs with members
   uint32_t mail;     // the copy of the XCD stamps this workgroup polls (xcopies > 0)
-  uint32_t cu_list[kCuSlots];  // CU leader only: member indices of the CU's workgroups
 };
-
-__device__ __forceinline__ void release_list(const BarrierState& s, const XcdLocal& L,
-                                             uint32_t ncu, uint32_t self, uint32_t stamp,
-                                             uint32_t* rel) {
-  for (uint32_t i = threadIdx.x; i < ncu; i += blockDim.x) {
-    const uint32_t k = L.cu_list[i];
-    if (k != self) st_relaxed(rel + (size_t)k * s.stride, stamp);
-  }
-}
 
 __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, const Ctl& ctl,
                                          const XcdLocal& L) {
@@ -240,7 +232,6 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
   const uint32_t xmask = __builtin_amdgcn_readfirstlane(L.xmask);
   const uint32_t slot = __builtin_amdgcn_readfirstlane(L.slot);
   uint32_t* block = s.larrive + s.xoff[x];
-  uint32_t* rel = s.lrelease + (size_t)x * s.xblock * s.stride;  // member k: rel + k*stride
   Wait w(ctl, s.poll_sleep);
   int ok = 1;
   __syncthreads();
@@ -276,6 +267,9 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
       ok = poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
     return __syncthreads_and(ok);
   }
+  // this CU's release line
+  uint32_t* rel = s.lrelease + s.roff[x] +
+                  (size_t)__builtin_amdgcn_readfirstlane(L.rank) * s.stride;
   if (slot == 0) {
     // CU leader: once every populated XCD has published, invalidate for the CU and
     // release it.  The invalidation has to follow the last XCD's writeback: a line that
@@ -285,13 +279,15 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
       ok = poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
     ok = __syncthreads_and(ok);
     if (!ok) return false;
-    if (is_leader()) fence_acquire();
+    if (is_leader()) {
+      fence_acquire();  // completes before the release store is issued
+      st_relaxed(rel, stamp);
+    }
     __syncthreads();
-    release_list(s, L, __builtin_amdgcn_readfirstlane(L.ncu), k, stamp, rel);
     return true;
   }
   if (is_leader()) {
-    ok = poll_until(rel + (size_t)k * s.stride, stamp, w);
+    ok = poll_until(rel, stamp, w);
     s_ok = ok;
   }
   __syncthreads();
@@ -313,30 +309,24 @@ __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl,
     if (L.k >= s.xblock) add_relaxed(s.overflow, 1);
     L.key = xcc * 256 + cu_in_xcc();
     L.slot = add_relaxed(s.cu_count + L.key, 1);
-    if (L.slot == 0) st_relaxed(s.cu_rank + L.key, add_relaxed(s.xcu + xcc, 1));
-    if (L.slot < kCuSlots)
-      st_relaxed(s.cu_members + (size_t)L.key * kCuSlots + L.slot, L.k);
-    else
-      add_relaxed(s.overflow, 1);
+    if (L.slot == 0) {
+      const uint32_t r = add_relaxed(s.xcu + xcc, 1);
+      st_relaxed(s.cu_rank + L.key, r);
+      if (r >= kCuLines) add_relaxed(s.overflow, 1);
+    }
     // the registration stores are complete before the arrival (with or without fences)
     wave_stores_complete();
     const bool ok = counter_arrive_wait<SP_BARRIER_TREE>(s, 1, ctl);
     fence_acquire();  // round 0 only: always, so the registrations below read fresh
     *use_xcd = ld_relaxed(s.overflow) == 0;
-    L.ncu = ld_relaxed(s.cu_count + L.key);
+    L.rank = ld_relaxed(s.cu_rank + L.key);
     L.members = ld_relaxed(s.xcount + xcc);
     uint32_t mask = 0;
     for (uint32_t i = 0; i < X; ++i)
       if (ld_relaxed(s.xcount + i) != 0) mask |= 1u << i;
     L.xmask = mask;
-    L.mail = s.xcopies ? (xcc + X * ld_relaxed(s.cu_rank + L.key)) % s.xcopies : 0;
+    L.mail = s.xcopies ? (xcc + X * L.rank) % s.xcopies : 0;
     s_ok = ok;
-  }
-  __syncthreads();
-  if (*use_xcd) {
-    if (L.slot == 0)
-      for (uint32_t i = threadIdx.x; i < L.ncu && i < kCuSlots; i += blockDim.x)
-        L.cu_list[i] = ld_relaxed(s.cu_members + (size_t)L.key * kCuSlots + i);
   }
   __syncthreads();
   return s_ok;

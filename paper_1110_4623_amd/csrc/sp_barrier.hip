@@ -18,7 +18,7 @@ struct sp_barrier {
   uint32_t* d_slots = nullptr;  // 2 x nwg exchanged values
   uint32_t* d_near = nullptr;   // per-XCD blocks in measured chunks (flag_placement 0)
   uint64_t near_words = 0;
-  uint32_t near_placed = 0;     // 0 fixed layout, 1 arrival blocks, 2 and stamp copies
+  uint32_t near_placed = 0;     // bits: 1 arrival blocks, 2 stamp copies, 4 release lines
   sp::BarrierState st{};
 };
 
@@ -147,9 +147,10 @@ __global__ void k_near_probe(uint32_t* area, uint32_t nchunks, uint32_t groups,
 }
 
 // Measures the chunks of b->d_near and gives each XCD its fastest free chunk for its
-// arrival block and, when `mail`, then for its stamp copies.  Leaves the fixed layout
-// in place (returns SP_OK) when any XCD could not be measured.
-int place_near(sp_barrier* b, uint32_t G, bool mail) {
+// arrival block, then (`mail`) for its stamp copies and (`rel`) for its per-CU release
+// lines.  Leaves the fixed layout in place (returns SP_OK) when any XCD could not be
+// measured.
+int place_near(sp_barrier* b, uint32_t G, bool mail, bool rel) {
   sp_ctx* ctx = b->ctx;
   spi::DeviceScratch scratch;
   const uint64_t words = G + (uint64_t)G * kNearChunks;
@@ -186,7 +187,12 @@ int place_near(sp_barrier* b, uint32_t G, bool mail) {
     for (uint32_t x = 0; x < G; ++x) st.moff[x] = take(x);
     st.xmail = b->d_near;
     st.xmstep = st.xmstride;
-    b->near_placed = 2;
+    b->near_placed |= 2;
+  }
+  if (rel) {
+    for (uint32_t x = 0; x < G; ++x) st.roff[x] = take(x);
+    st.lrelease = b->d_near;
+    b->near_placed |= 4;
   }
   return SP_OK;
 }
@@ -231,10 +237,10 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   // arrival blocks and the per-XCD blocks of release flags (one line per member)
   const uint64_t flag_lines = ((uint64_t)nwg * fs + sw - 1) / sw;
   const uint64_t local_lines = ((uint64_t)G * xblock * sp::kArriveWords + sw - 1) / sw;
-  const uint64_t lrel_lines = (uint64_t)G * xblock;
-  // per-CU and per-XCD registration (per-XCD barrier): counts and member indices per CU
-  // key, member counts per XCD, the overflow word
-  const uint64_t cu_words = (uint64_t)G * 256 * (2 + sp::kCuSlots) + 2ull * G + 1;
+  const uint64_t lrel_lines = (uint64_t)G * sp::kCuLines;
+  // per-CU and per-XCD registration (per-XCD barrier): counts and ranks per CU key,
+  // member and CU counts per XCD, the overflow word
+  const uint64_t cu_words = (uint64_t)G * 256 * 2 + 2ull * G + 1;
   // copies of the XCD stamps, each one word per XCD, padded to at least a line
   const uint32_t copies = kind == SP_BARRIER_XCD ? q.xcd_copies : 0;
   const uint32_t mstride = (std::max(sw, G) + sw - 1) / sw * sw;
@@ -249,8 +255,8 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   if (e == hipSuccess) e = hipMemset(b->d_slots, 0, 2ull * nwg * sizeof(uint32_t));
   if (e != hipSuccess) {
     ctx->last_hip = (int)e;
-    hipFree(b->d_state);
-    hipFree(b->d_slots);
+    (void)hipFree(b->d_state);
+    (void)hipFree(b->d_slots);
     delete b;
     return SP_E_HIP;
   }
@@ -279,21 +285,22 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.larrive = s.release + flag_lines * sw;
   s.lrelease = s.larrive + local_lines * sw;
   s.cu_count = s.lrelease + lrel_lines * sw;           // G * 256 words
-  s.cu_members = s.cu_count + (uint64_t)G * 256;        // G * 256 * kCuSlots words
-  s.xcount = s.cu_members + (uint64_t)G * 256 * sp::kCuSlots;  // G words
+  s.xcount = s.cu_count + (uint64_t)G * 256;           // G words
   s.overflow = s.xcount + G;                                   // 1 word
   s.xcu = s.overflow + 1;                                      // G words
   s.cu_rank = s.xcu + G;                                       // G * 256 words
   s.xmail = s.cu_count + cu_lines * sw;  // xcopies copies of xmstride words
-  // Fixed layout: XCD-major blocks of arrival flags, copies in order.
+  // Fixed layout: XCD-major blocks of arrival flags and release lines, copies in order.
   for (uint32_t x = 0; x < G && x < 16; ++x) {
     s.xoff[x] = x * xblock * sp::kArriveWords;
+    s.roff[x] = x * sp::kCuLines * sw;
     s.moff[x] = x * mstride;
   }
   s.xmstep = G * mstride;
   if (kind == SP_BARRIER_XCD && q.flag_placement == 0 && G >= 2 && G <= 16 &&
       xblock * sp::kArriveWords <= kChunkWords) {
     const bool mail = copies >= G && copies % G == 0 && (copies / G) * mstride <= kChunkWords;
+    const bool rel = sp::kCuLines * sw <= kChunkWords;
     b->near_words = (uint64_t)kNearChunks * kChunkWords;
     int rc = SP_OK;
     e = hipMalloc(&b->d_near, b->near_words * sizeof(uint32_t));
@@ -301,14 +308,14 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
       ctx->last_hip = (int)e;
       rc = SP_E_HIP;
     } else {
-      rc = place_near(b, G, mail);
+      rc = place_near(b, G, mail, rel);
     }
     if (rc != SP_OK) {
       sp_barrier_destroy(b);
       return rc;
     }
     if (b->near_placed == 0) {  // not measured: keep the fixed layout, drop the area
-      hipFree(b->d_near);
+      (void)hipFree(b->d_near);
       b->d_near = nullptr;
       b->near_words = 0;
     }
@@ -319,10 +326,10 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
 
 int sp_barrier_destroy(sp_barrier* b) {
   if (!b) return SP_E_INVAL;
-  hipSetDevice(b->ctx->device);
-  hipFree(b->d_state);
-  hipFree(b->d_slots);
-  if (b->d_near) hipFree(b->d_near);
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipFree(b->d_state);
+  (void)hipFree(b->d_slots);
+  if (b->d_near) (void)hipFree(b->d_near);
   delete b;
   return SP_OK;
 }
@@ -412,7 +419,7 @@ int sp_barrier_run_hash_launches(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint
   if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     ctx->last_hip = (int)e;
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return SP_E_HIP;
   }
   int rc = spi::begin_timed(ctx, s);
@@ -425,8 +432,8 @@ int sp_barrier_run_hash_launches(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint
       rc = spi::end_timed(ctx, s, st, nwg, lanes, 0, rounds);
     }
   }
-  hipGraphExecDestroy(ge);
-  hipGraphDestroy(g);
+  (void)hipGraphExecDestroy(ge);
+  (void)hipGraphDestroy(g);
   return rc;
 }
 

@@ -172,13 +172,20 @@ def test_xcd_stamp_copies(ctx, copies, coherent, nwg, lanes):
 
 
 def _near_expected(ctx, nwg, copies, placement, pad=128):
+    """Bits of what the measured placement covers: 1 arrival blocks, 2 stamp copies,
+    4 per-CU release lines (each where it fits an 8 KiB chunk)."""
     n = ctx.info["xcd_count"]
     xblock = ((nwg + n - 1) // n + 31) // 32 * 32
     if placement == 1 or n < 2 or xblock * 4 > 2048:
         return 0
     sw = max(1, pad // 4)
     mstride = (max(sw, n) + sw - 1) // sw * sw
-    return 2 if copies >= n and copies % n == 0 and copies // n * mstride <= 2048 else 1
+    bits = 1
+    if copies >= n and copies % n == 0 and copies // n * mstride <= 2048:
+        bits |= 2
+    if 64 * sw <= 2048:
+        bits |= 4
+    return bits
 
 
 @pytest.mark.parametrize("placement", [0, 1])
@@ -270,8 +277,8 @@ def _max_resident(ctx, lanes):
 @pytest.mark.parametrize("kind", ["xcd", "central", "tree", "flag"])
 def test_largest_co_resident_grid(ctx, kind):
     """The most workgroups that can be resident at once (64-lane workgroups, every wave
-    slot of every CU): each XCD's master scans a full flag block, every CU's member list
-    is full; the checksums are the oracle's."""
+    slot of every CU): each XCD's master scans a full flag block, every CU releases 32
+    workgroups through its line; the checksums are the oracle's."""
     import paper_1110_4623_amd as sp
     nwg = _max_resident(ctx, 64)
     assert nwg >= 4096
