@@ -49,8 +49,8 @@ enum sp_barrier_kind {
   SP_BARRIER_TREE = 2,          /* two-level counter tree: fan_in groups, top counter  */
   SP_BARRIER_FLAG = 3,          /* decentralized flag barrier with a master workgroup  */
   SP_BARRIER_GRID_SYNC = 4,     /* comparator: HIP cooperative-groups grid.sync()      */
-  SP_BARRIER_XCD = 5,           /* per-XCD: flags through each XCD's L2, one writeback */
-                                /* and one invalidation per XCD per round              */
+  SP_BARRIER_XCD = 5,           /* per-XCD: one L2 writeback per XCD and one           */
+                                /* invalidation per CU per round                       */
   SP_BARRIER_DEFAULT = 15       /* the tuned default for this GPU                      */
 };
 
@@ -262,9 +262,10 @@ int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t
                         uint32_t* out_checksums, sp_stats* st, void* stream);
 /* sp_barrier_info_get: after a run (call it once the run has returned), how the last
  * run synchronized.  For SP_BARRIER_XCD: xcd_path = 1 if every workgroup's registration
- * fit (at most ceil(nwg / XCDs) rounded up to 32 per XCD, 32 per CU), so the per-XCD
- * protocol was used; otherwise the run fell back to the counter tree (same results) and
- * cu_overflow counts the registrations that did not fit.  misplaced counts workgroups
+ * fit (at most ceil(nwg / XCDs) rounded up to 32 workgroups and 64 CUs with workgroups
+ * per XCD), so the per-XCD protocol was used; otherwise the run fell back to the counter
+ * tree (same results) and cu_overflow counts the registrations that did not fit.
+ * near_placed is known from creation on.  misplaced counts workgroups
  * that did not run on XCD (id mod XCDs), the dispatcher's usual placement: the barrier
  * reads each workgroup's XCD and does not depend on it.                                 */
 typedef struct sp_barrier_info {
