@@ -4,6 +4,8 @@ loading only, no compute calls)."""
 import os
 import re
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -145,3 +147,11 @@ def test_pingpong_rejects_bad_arguments_without_gpu():
     from paper_1110_4623_amd import _native as N
     st = N.Stats()
     assert N.lib.sp_bench_pingpong(None, 10, 0, None, None, ctypes.byref(st), None) == N.SP_E_INVAL
+
+
+def test_pingpong_offset_must_be_whole_lines():
+    """The binding checks the word offset before it touches the device."""
+    import paper_1110_4623_amd as sp
+    for bad in (-128, 100, 4095):
+        with pytest.raises(ValueError):
+            sp.pingpong(None, 10, offset_bytes=bad)
