@@ -178,7 +178,18 @@ typedef struct sp_params {
                            /* release lines, each when it fits in a chunk                  */
                            /* (sp_barrier_info reports the outcome).                       */
                            /* 1 = fixed layout (XCD-major blocks).  Timing only.           */
-  uint32_t reserved[1];
+  uint32_t xcd_release;    /* SP_BARRIER_XCD with plain data (coherent_cs = 0): how the    */
+                           /* workgroups leave a round once every XCD has written its L2    */
+                           /* back.  0 = each CU's first workgroup polls the stamps,        */
+                           /* invalidates the CU's L1 and the XCD's stale L2 lines (agent- */
+                           /* scope acquire) and releases the CU's other workgroups through */
+                           /* one line; 1 = every workgroup polls the stamps and            */
+                           /* invalidates its CU's L1 only (workgroup-scope invalidate).    */
+  uint32_t post_backoff;   /* SP_SEM_SPIN_BACKOFF (Algorithm 4): 0 = post retries at once  */
+                           /* (Section 5's prose: post proceeds aggressively, only wait     */
+                           /* backs off), 1 = post backs off after a failed exchange as     */
+                           /* wait does (the Algorithm 4 listing)                           */
+  uint32_t reserved[2];
 } sp_params;
 
 typedef struct sp_stats {

@@ -61,10 +61,6 @@ __device__ __forceinline__ uint32_t cas_relaxed(uint32_t* p, uint32_t expected, 
 // (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maxima).
 __device__ __forceinline__ void wave_stores_complete() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-#ifndef SP_FENCE_WAITS
-#define SP_FENCE_WAITS 1
-#endif
-
 // Agent-scope fences.  The release fence writes back the XCD's dirty L2 lines and the
 // acquire fence invalidates stale L1/L2 lines; both are asynchronous cache operations.
 // An explicit vmcnt(0) wait follows each one so that the writeback has finished before
@@ -73,11 +69,20 @@ __device__ __forceinline__ void wave_stores_complete() { __builtin_amdgcn_s_wait
 // writeback is elided when no other memory operation is outstanding).
 __device__ __forceinline__ void fence_acquire() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  if (SP_FENCE_WAITS) wave_stores_complete();
+  wave_stores_complete();
 }
 __device__ __forceinline__ void fence_release() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (SP_FENCE_WAITS) wave_stores_complete();
+  wave_stores_complete();
+}
+
+// Invalidate this CU's L1 (vector data cache) only: a workgroup-scope invalidate, which
+// leaves the XCD's L2 alone and is not serialized at the L2 as the agent-scope one is.
+// It makes later plain loads of this CU miss in the L1; whether the L2 then serves fresh
+// data depends on how the L2s keep the lines coherent, which the litmus tests measure.
+__device__ __forceinline__ void invalidate_l1() {
+  __asm__ __volatile__("buffer_inv sc0" ::: "memory");
+  wave_stores_complete();
 }
 
 // Release store / release add: publish everything this wavefront wrote, then the flag.

@@ -15,6 +15,8 @@ struct SemState {
   uint32_t* turn;       // Algorithm 5: number of queued workgroups admitted; counters:
                         // posts made
   BackoffCfg bo;        // SP_SEM_SPIN_BACKOFF
+  uint32_t post_backoff;  // SP_SEM_SPIN_BACKOFF: 1 = post backs off too (Algorithm 4's
+                          // listing); 0 = post retries at once (Section 5's prose)
 };
 
 // Per-workgroup waiting state that persists across waits (SP_SEM_ADAPTIVE).
@@ -132,7 +134,8 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl) {
           exch_relaxed(s.S, v + 1);
           break;
         }
-        if constexpr (KIND == SP_SEM_SPIN_BACKOFF) bo(s.bo);
+        if constexpr (KIND == SP_SEM_SPIN_BACKOFF)
+          if (s.post_backoff) bo(s.bo);
         if (!(ok = w.tick())) break;
       }
     } else if constexpr (KIND == SP_SEM_COUNTERS || KIND == SP_SEM_ADAPTIVE) {

@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sp_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-BARRIER_KINDS = {"central": 0, "xcd": 1, "flag": 2}
+BARRIER_KINDS = {"central": 0, "tree": 1, "flag": 2, "xcd": 3, "split": 4}
 MUTEX_KINDS = {"spin_cas": 0, "spin_exch": 1, "spin_backoff": 2, "ticket": 3, "sleep": 4,
                "ring": 5, "array": 6, "adaptive": 7, "cohort": 8}
 SEM_KINDS = {"spin": 0, "spin_backoff": 1, "ticket": 2, "sleep": 3, "counters": 4,

@@ -664,7 +664,10 @@ class WeightedSemModel:
 class BarrierModel:
     """kind: 'central' -- one counter; an agent arrives with fetch-and-add and waits
                           until the counter reaches N * (r + 1);
-             'xcd'     -- agents split into G groups (b mod G); the last arriver of a
+             'split'   -- the same counter; the agent whose fetch-and-add returns
+                          N * (r + 1) - 1 (the last arriver) stores r + 1 into a separate
+                          release word, which the others poll;
+             'tree'    -- agents split into G groups (b mod G); the last arriver of a
                           group adds one to a top counter; the last group publishes a
                           top generation word; each group's last arriver copies it into
                           its group's generation word, which the others poll;
@@ -672,8 +675,9 @@ class BarrierModel:
                           (master) waits for every arrive flag, then stores r + 1 into
                           every release flag; the others poll their release flag.
        mutant: 'single_buffer' -- one slot array for every round;
-               'no_wait'       -- arrive but never wait (central, flag);
-               'no_top_wait'   -- xcd: a group's last arriver releases its group without
+               'no_wait'       -- arrive but never wait (central, split, flag);
+               'split_off_by_one' -- split: the agent that sees N * (r + 1) - 2 publishes;
+               'no_top_wait'   -- tree: a group's last arriver releases its group without
                                   waiting for the other groups."""
 
     WRITE, ARRIVE, POLL, TOP, TOP_POLL, TOP_REL, GROUP_REL, SCAN, RELEASE, READ, DONE = range(11)
@@ -711,7 +715,14 @@ class BarrierModel:
             if self.kind == "central":
                 sh = (slots, cnt + 1, gcnt, ggen, top, topgen, arrive, release)
                 return sh, (self.READ if self.mutant == "no_wait" else self.POLL, r, 0, bad)
-            if self.kind == "xcd":
+            if self.kind == "split":
+                old = cnt
+                sh = (slots, cnt + 1, gcnt, ggen, top, topgen, arrive, release)
+                last = N * stamp - (2 if self.mutant == "split_off_by_one" else 1)
+                if old == last:
+                    return sh, (self.TOP_REL, r, 0, bad)
+                return sh, (self.READ if self.mutant == "no_wait" else self.POLL, r, 0, bad)
+            if self.kind == "tree":
                 g = a % G
                 old = gcnt[g]
                 sh = (slots, cnt, self._set(gcnt, g, old + 1), ggen, top, topgen, arrive, release)
@@ -725,12 +736,14 @@ class BarrierModel:
         if pc == self.POLL:
             if self.kind == "central":
                 ok = cnt >= N * stamp
-            elif self.kind == "xcd":
+            elif self.kind == "split":
+                ok = topgen >= stamp
+            elif self.kind == "tree":
                 ok = ggen[a % G] >= stamp
             else:
                 ok = release[a] >= stamp
             return sh, ((self.READ if ok else self.POLL), r, i, bad)
-        if pc == self.TOP:  # xcd: last of the group arrives at the top counter
+        if pc == self.TOP:  # tree: last of the group arrives at the top counter
             t = top
             sh = (slots, cnt, gcnt, ggen, top + 1, topgen, arrive, release)
             if self.mutant == "no_top_wait":
@@ -739,7 +752,8 @@ class BarrierModel:
         if pc == self.TOP_POLL:
             return sh, ((self.GROUP_REL if topgen >= stamp else self.TOP_POLL), r, 0, bad)
         if pc == self.TOP_REL:
-            return (slots, cnt, gcnt, ggen, top, stamp, arrive, release), (self.GROUP_REL, r, 0, bad)
+            sh = (slots, cnt, gcnt, ggen, top, stamp, arrive, release)
+            return sh, ((self.READ if self.kind == "split" else self.GROUP_REL), r, 0, bad)
         if pc == self.GROUP_REL:
             ggen = self._set(ggen, a % G, stamp)
             return (slots, cnt, gcnt, ggen, top, topgen, arrive, release), (self.READ, r, 0, bad)
@@ -764,4 +778,359 @@ class BarrierModel:
         return None
 
     def final_check(self, sh, los):
+        return None
+
+
+# ------------------------------------------------------------------------------------
+# The per-XCD barrier as the library runs it, with the caches it has to maintain.
+#
+# Memory model of the data (the exchanged slots; every flag, stamp and counter is an
+# agent-scope atomic and is modelled as a plain shared variable under sequential
+# consistency).  All 2N slots share one cache line, so a read fills every slot:
+#   * each CU has an L1 holding the whole line or nothing; a load hits it if present,
+#     otherwise fills it from its XCD's L2;
+#   * each XCD has an L2 holding, per slot, nothing or (value, dirty); a load or a store
+#     that misses fills the missing slots from memory (write-allocate); a store marks its
+#     slot dirty and updates the storing CU's L1 copy, not the other CUs' copies;
+#   * a release (L2 writeback) copies the XCD's dirty slots to memory and marks them
+#     clean; with l2_coherent it also drops those slots from every other XCD's L2 (the
+#     L2s are then kept coherent by the hardware), otherwise other L2s keep stale copies;
+#   * an agent-scope acquire empties the CU's L1 and drops the clean slots of its XCD's
+#     L2; a workgroup-scope invalidate empties the CU's L1 only;
+#   * a plain store is issued first and completes into the L2 in a later step: the wait
+#     for outstanding stores is the agent's own step sequence.
+# ------------------------------------------------------------------------------------
+
+class XcdBarrierModel:
+    """Per-XCD barrier, hash-exchange workload (round r: agent a stores r into slot
+    (r & 1, a), passes the barrier, reads slot (r & 1, (a + r) mod n), which must hold r).
+
+    placement: per agent (xcd, cu); CU ids are global.  Registration: member k of an XCD
+    in agent order (k = 0 is the XCD's master), CU leader = first agent of its CU, rank of
+    a CU = order of its first agent among its XCD's CUs.  With register=True, round 0
+    computes these with fetch-and-adds exactly as the library does (XCD count, CU count,
+    CU rank of each CU's first agent), then passes a fenced counter barrier (release,
+    arrive, poll, acquire) and reads the registration; an XCD with more than `block`
+    members or more than `cu_lines` CUs makes every agent fall back to the counter barrier
+    in the later rounds.
+
+    Later rounds, mode 'plain' (data with plain accesses; coherent_cs = 0):
+      members: the slot store completes, then the arrival flag is stored;
+      the master: the store completes, it scans its members' flags, writes its XCD's L2
+        back, publishes its XCD's stamp into each of `copies` copies;
+      CU leaders: poll the populated XCDs' stamps in copy (x + X * rank) mod copies,
+        acquire for the CU, store the CU's release line;
+      other agents: poll their CU's release line.
+    mode 'l1only': as 'plain', but every agent polls the stamps and invalidates its CU's
+      L1 only (no release line).
+    mode 'coherent': slots are stored and loaded with atomics (no caches); every agent
+      polls the stamps; no writeback, no acquire.
+
+    mutant: 'early_publish' -- the master skips its last member's flag;
+            'early_release' -- a CU leader polls only its own XCD's stamp;
+            'skip_copy'     -- XCD 0's master does not write the last copy;
+            'no_writeback'  -- masters do not write the L2 back;
+            'no_invalidate' -- CU leaders do not acquire;
+            'no_cu_wait'    -- agents that are not CU leaders poll the stamps themselves and
+                               read without their CU's invalidation;
+            'flag_before_store' -- a member stores its arrival flag before its slot store
+                               has completed into the L2;
+            'rank_after_arrival' -- (register=True) a CU's first agent stores its CU's rank
+                               after arriving at the registration barrier, so another agent
+                               of the CU can read the rank before it is written (and poll
+                               another CU's release line).
+    The release lines are indexed by (XCD, rank of the CU), as in the library."""
+
+    (WRITE, COMPLETE, ARRIVE, SCAN, WB, PUB, POLL, ACQ, REL, WAIT_REL, INV_L1, READ,
+     REG_X, REG_CU, REG_RANK, REG_RANKST, REG_WB, REG_ARRIVE, REG_POLL, REG_ACQ, REG_READ,
+     FB_WB, FB_ARRIVE, FB_POLL, FB_ACQ, LATE, DONE) = range(27)
+
+    def __init__(self, placement, rounds: int = 3, copies: int = 2, mode: str = "plain",
+                 register: bool = False, block: int = 8, cu_lines: int = 8,
+                 l2_coherent: bool = False, mutant: str | None = None):
+        self.pl = tuple(placement)
+        self.n = len(self.pl)
+        self.R, self.C, self.mode, self.register = rounds, copies, mode, register
+        self.block, self.cu_lines, self.l2c, self.mutant = block, cu_lines, l2_coherent, mutant
+        self.X = 1 + max(x for x, _ in self.pl)
+        self.ncu = 1 + max(c for _, c in self.pl)
+        # static registration (also what register=True must reproduce when it fits)
+        self.k, self.slot, self.rank = [], [], []
+        ranks, cus_of = {}, {}
+        for a, (x, c) in enumerate(self.pl):
+            self.k.append(sum(1 for b in range(a) if self.pl[b][0] == x))
+            self.slot.append(sum(1 for b in range(a) if self.pl[b][1] == c))
+            if c not in ranks:
+                ranks[c] = cus_of.get(x, 0)
+                cus_of[x] = ranks[c] + 1
+            self.rank.append(ranks[c])
+        self.members = [sum(1 for x2, _ in self.pl if x2 == x) for x in range(self.X)]
+        self.xmask = tuple(x for x in range(self.X) if self.members[x])
+
+    # shared = (mem, l1, l2, arrive, mail, rel, reg) where reg = (xcount, cucount, xcu,
+    #          curank, overflow, cnt)
+    # local  = (pc, r, i, bad, pend, k, slot, rank, use)
+    def init(self):
+        S = 2 * self.n
+        reg = ((0,) * self.X, (0,) * self.ncu, (0,) * self.X, (0,) * self.ncu, 0, 0)
+        sh = ((-1,) * S, (None,) * self.ncu, (None,) * self.X, (0,) * self.n,
+              tuple((0,) * self.X for _ in range(self.C)), (0,) * (self.X * self.cu_lines), reg)
+        los = []
+        for a in range(self.n):
+            if self.register:
+                los.append((self.WRITE, 0, 0, False, None, -1, -1, -1, True))
+            else:
+                los.append((self.WRITE, 0, 0, False, None, self.k[a], self.slot[a],
+                            self.rank[a], True))
+        return sh, tuple(los)
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    @staticmethod
+    def _set(t, i, v):
+        return t[:i] + (v,) + t[i + 1:]
+
+    # ---- caches --------------------------------------------------------------------
+    def _fill(self, mem, line2):
+        return tuple((mem[j], False) if line2 is None or line2[j] is None else line2[j]
+                     for j in range(len(mem)))
+
+    def _load(self, sh, a, i):
+        mem, l1, l2 = sh[0], sh[1], sh[2]
+        x, c = self.pl[a]
+        if self.mode == "coherent":
+            return sh, mem[i]
+        if l1[c] is not None:
+            return sh, l1[c][i]
+        line2 = self._fill(mem, l2[x])
+        vals = tuple(v for v, _ in line2)
+        sh = (mem, self._set(l1, c, vals), self._set(l2, x, line2)) + sh[3:]
+        return sh, vals[i]
+
+    def _store_complete(self, sh, a, i, v):
+        mem, l1, l2 = sh[0], sh[1], sh[2]
+        x, c = self.pl[a]
+        line2 = self._set(self._fill(mem, l2[x]), i, (v, True))
+        if l1[c] is not None:
+            l1 = self._set(l1, c, self._set(l1[c], i, v))
+        return (mem, l1, self._set(l2, x, line2)) + sh[3:]
+
+    def _writeback(self, sh, x):
+        mem, l1, l2 = sh[0], sh[1], sh[2]
+        line2 = l2[x]
+        if line2 is None:
+            return sh
+        dirty = [j for j, e in enumerate(line2) if e is not None and e[1]]
+        for j in dirty:
+            mem = self._set(mem, j, line2[j][0])
+        l2 = self._set(l2, x, tuple(None if e is None else (e[0], False) for e in line2))
+        if self.l2c:
+            for y in range(self.X):
+                if y != x and l2[y] is not None:
+                    l2 = self._set(l2, y, tuple(None if j in dirty else e
+                                                for j, e in enumerate(l2[y])))
+        return (mem, l1, l2) + sh[3:]
+
+    def _acquire(self, sh, a):
+        mem, l1, l2 = sh[0], sh[1], sh[2]
+        x, c = self.pl[a]
+        l1 = self._set(l1, c, None)
+        if l2[x] is not None:
+            l2 = self._set(l2, x, tuple(e if e is not None and e[1] else None for e in l2[x]))
+        return (mem, l1, l2) + sh[3:]
+
+    def _inv_l1(self, sh, a):
+        return (sh[0], self._set(sh[1], self.pl[a][1], None)) + sh[2:]
+
+    # ---- protocol ----------------------------------------------------------------------
+    def _slot_index(self, r, b):
+        return (r & 1) * self.n + b
+
+    def _scan_list(self, a):
+        x = self.pl[a][0]
+        mem = [b for b in range(self.n) if self.pl[b][0] == x and b != a]
+        if self.mutant == "early_publish" and mem:
+            mem = mem[:-1]
+        return mem
+
+    def _poll_list(self, a):
+        if self.mutant == "early_release":
+            return [self.pl[a][0]]
+        return list(self.xmask)
+
+    def _after_arrival(self, lo):
+        pc, r, i, bad, pend, k, slot, rank, use = lo
+        if self.mode == "plain" and slot != 0 and self.mutant != "no_cu_wait":
+            return (self.WAIT_REL, r, 0, bad, pend, k, slot, rank, use)
+        return (self.POLL, r, 0, bad, pend, k, slot, rank, use)
+
+    def step(self, a, sh, lo):
+        pc, r, i, bad, pend, k, slot, rank, use = lo
+        mem, l1, l2, arrive, mail, rel, reg = sh
+        x, c = self.pl[a]
+        stamp = r + 1
+        if pc == self.WRITE:
+            idx = self._slot_index(r, a)
+            if self.mode == "coherent":
+                sh = (self._set(mem, idx, r),) + sh[1:]
+                nxt = self.REG_X if (self.register and r == 0) else (
+                    self.FB_WB if not use else (self.SCAN if k == 0 else self.ARRIVE))
+                return sh, (nxt, r, 0, bad, None, k, slot, rank, use)
+            nxt = self.COMPLETE
+            if (self.mutant == "flag_before_store" and use and k != 0
+                    and not (self.register and r == 0)):
+                nxt = self.ARRIVE
+            return sh, (nxt, r, 0, bad, (idx, r), k, slot, rank, use)
+        if pc == self.COMPLETE:
+            sh = self._store_complete(sh, a, pend[0], pend[1])
+            lo = (pc, r, 0, bad, None, k, slot, rank, use)
+            if self.register and r == 0:
+                return sh, (self.REG_X,) + lo[1:]
+            if not use:
+                return sh, (self.FB_WB,) + lo[1:]
+            if self.mutant == "flag_before_store" and k != 0:  # flag already stored
+                return sh, self._after_arrival(lo)
+            return sh, ((self.SCAN if k == 0 else self.ARRIVE),) + lo[1:]
+        if pc == self.ARRIVE:
+            sh = (mem, l1, l2, self._set(arrive, a, stamp), mail, rel, reg)
+            lo2 = (pc, r, 0, bad, pend, k, slot, rank, use)
+            if pend is not None:  # flag_before_store: the slot store completes later
+                return sh, (self.COMPLETE,) + lo2[1:]
+            return sh, self._after_arrival(lo2)
+        if pc == self.SCAN:
+            lst = self._scan_list(a)
+            if i < len(lst):
+                if arrive[lst[i]] >= stamp:
+                    return sh, (self.SCAN, r, i + 1, bad, pend, k, slot, rank, use)
+                return sh, lo
+            nxt = self.PUB if (self.mode == "coherent" or self.mutant == "no_writeback") else self.WB
+            return sh, (nxt, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.WB:
+            return self._writeback(sh, x), (self.PUB, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.PUB:
+            if not (self.mutant == "skip_copy" and x == 0 and i == self.C - 1):
+                mail = self._set(mail, i, self._set(mail[i], x, stamp))
+            sh = (mem, l1, l2, arrive, mail, rel, reg)
+            if i + 1 < self.C:
+                return sh, (self.PUB, r, i + 1, bad, pend, k, slot, rank, use)
+            return sh, self._after_arrival(lo)
+        if pc == self.POLL:
+            lst = self._poll_list(a)
+            copy = (x + self.X * rank) % self.C
+            if i < len(lst):
+                if mail[copy][lst[i]] >= stamp:
+                    return sh, (self.POLL, r, i + 1, bad, pend, k, slot, rank, use)
+                return sh, lo
+            if self.mode == "coherent" or (self.mutant == "no_cu_wait" and slot != 0):
+                nxt = self.READ
+            elif self.mode == "l1only":
+                nxt = self.INV_L1
+            else:
+                nxt = self.REL if self.mutant == "no_invalidate" else self.ACQ
+            return sh, (nxt, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.ACQ:
+            return self._acquire(sh, a), (self.REL, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.REL:
+            sh = (mem, l1, l2, arrive, mail, self._set(rel, x * self.cu_lines + rank, stamp), reg)
+            return sh, (self.READ, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.WAIT_REL:
+            if rel[x * self.cu_lines + rank] >= stamp:
+                return sh, (self.READ, r, 0, bad, pend, k, slot, rank, use)
+            return sh, lo
+        if pc == self.INV_L1:
+            return self._inv_l1(sh, a), (self.READ, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.READ:
+            sh, v = self._load(sh, a, self._slot_index(r, (a + r) % self.n))
+            bad = bad or v != r
+            nxt = self.WRITE if r + 1 < self.R else self.DONE
+            return sh, (nxt, r + 1, 0, bad, pend, k, slot, rank, use)
+        # ---- round 0 with registration -------------------------------------------------
+        xcount, cucount, xcu, curank, overflow, cnt = reg
+        if pc == self.REG_X:
+            k = xcount[x]
+            overflow += 1 if k >= self.block else 0
+            reg = (self._set(xcount, x, k + 1), cucount, xcu, curank, overflow, cnt)
+            return (mem, l1, l2, arrive, mail, rel, reg), (self.REG_CU, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.REG_CU:
+            slot = cucount[c]
+            reg = (xcount, self._set(cucount, c, slot + 1), xcu, curank, overflow, cnt)
+            nxt = self.REG_RANK if slot == 0 else self.REG_WB
+            return (mem, l1, l2, arrive, mail, rel, reg), (nxt, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.LATE:  # rank_after_arrival: the CU leader stores its rank only now
+            reg = (xcount, cucount, xcu, self._set(curank, c, i), overflow, cnt)
+            return (mem, l1, l2, arrive, mail, rel, reg), (self.REG_POLL, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.REG_RANK:
+            rk = xcu[x]
+            overflow += 1 if rk >= self.cu_lines else 0
+            reg = (xcount, cucount, self._set(xcu, x, rk + 1), curank, overflow, cnt)
+            return (mem, l1, l2, arrive, mail, rel, reg), (self.REG_RANKST, r, rk, bad, pend, k, slot, rank, use)
+        if pc == self.REG_RANKST:
+            if self.mutant == "rank_after_arrival":
+                return sh, (self.REG_WB, r, i, bad, pend, k, slot, rank, use)
+            reg = (xcount, cucount, xcu, self._set(curank, c, i), overflow, cnt)
+            return (mem, l1, l2, arrive, mail, rel, reg), (self.REG_WB, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.REG_WB:
+            sh = sh if self.mode == "coherent" else self._writeback(sh, x)
+            return sh, (self.REG_ARRIVE, r, i, bad, pend, k, slot, rank, use)
+        if pc == self.REG_ARRIVE:
+            reg = (xcount, cucount, xcu, curank, overflow, cnt + 1)
+            late = self.mutant == "rank_after_arrival" and slot == 0
+            return (mem, l1, l2, arrive, mail, rel, reg), (
+                (self.LATE if late else self.REG_POLL), r, i if late else 0, bad, pend, k, slot,
+                rank, use)
+        if pc == self.REG_POLL:
+            if cnt >= self.n:
+                return sh, (self.REG_ACQ, r, 0, bad, pend, k, slot, rank, use)
+            return sh, lo
+        if pc == self.REG_ACQ:
+            sh = sh if self.mode == "coherent" else self._acquire(sh, a)
+            return sh, (self.REG_READ, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.REG_READ:
+            rank = curank[c]
+            use = overflow == 0
+            return sh, (self.READ, r, 0, bad, pend, k, slot, rank, use)
+        # ---- fallback: a fenced counter barrier (round r's target is n * r; round 0's
+        # registration barrier counted n) ----------------------------------------------------
+        if pc == self.FB_WB:
+            sh = sh if self.mode == "coherent" else self._writeback(sh, x)
+            return sh, (self.FB_ARRIVE, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.FB_ARRIVE:
+            reg = (xcount, cucount, xcu, curank, overflow, cnt + 1)
+            return (mem, l1, l2, arrive, mail, rel, reg), (self.FB_POLL, r, 0, bad, pend, k, slot, rank, use)
+        if pc == self.FB_POLL:
+            if cnt >= self.n * (r + 1):
+                return sh, (self.FB_ACQ, r, 0, bad, pend, k, slot, rank, use)
+            return sh, lo
+        if pc == self.FB_ACQ:
+            sh = sh if self.mode == "coherent" else self._acquire(sh, a)
+            return sh, (self.READ, r, 0, bad, pend, k, slot, rank, use)
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        for b, lo in enumerate(los):
+            if lo[3]:
+                return f"phase violated: agent {b} read stale or overwritten data"
+        return None
+
+    def final_check(self, sh, los):
+        if not self.register:
+            return None
+        fits = all(m <= self.block for m in self.members) and all(
+            len({c for x2, c in self.pl if x2 == x}) <= self.cu_lines for x in range(self.X))
+        if any(lo[8] != fits for lo in los):
+            return f"per-XCD path taken {[lo[8] for lo in los]}, registration fits: {fits}"
+        for x in self.xmask:
+            on = [a for a in range(self.n) if self.pl[a][0] == x]
+            if sorted(los[a][5] for a in on) != list(range(len(on))):
+                return f"XCD {x}: member numbers {[los[a][5] for a in on]}"
+            cus = sorted({self.pl[a][1] for a in on})
+            if sorted({los[a][7] for a in on}) != list(range(len(cus))) or any(
+                    los[a][7] != los[b][7] for a in on for b in on
+                    if self.pl[a][1] == self.pl[b][1]):
+                return f"XCD {x}: CU ranks {[los[a][7] for a in on]}"
+            for cu in cus:
+                if sorted(los[a][6] for a in on if self.pl[a][1] == cu) != list(
+                        range(sum(1 for a in on if self.pl[a][1] == cu))):
+                    return f"CU {cu}: registration order {[los[a][6] for a in on]}"
         return None

@@ -272,14 +272,26 @@ extern "C" {
 
 // Barrier kinds: 0 centralized counter, 1 hierarchical (groups of agents, then a top
 // counter), 2 decentralized flag barrier with a master agent (the "XF" barrier of
-// Section 5).  The workload is the hash exchange of or_barrier_closed; the published
-// values live in two slot arrays selected by round parity, so that a round-(r+1) store
-// can never overwrite a round-r value that has not been read yet.
+// Section 5), 3 the per-XCD flag protocol (below), 4 centralized counter whose last
+// arriver publishes a separate release word.  The workload is the hash exchange of
+// or_barrier_closed; the published values live in two slot arrays selected by round
+// parity, so that a round-(r+1) store can never overwrite a round-r value that has not
+// been read yet.
+//
+// Kind 3 groups the agents as a GPU groups workgroups: agent b sits in group (XCD)
+// b mod G and in "CU" (b / G) mod 4 of that group.  Round 0 registers every agent with
+// fetch-and-adds -- its member number in its group (member 0 is the group's master), its
+// order on its CU (0 = the CU's leader), and for a CU's leader the rank of the CU among
+// its group's CUs -- then passes a counter barrier and reads the registration.  Later
+// rounds: a member stores its arrival stamp in its group's flag block; the master checks
+// every member's flag, then stores the group's stamp into each of 2G copies; each CU
+// leader waits until every populated group's stamp is in copy (group + G * rank) mod 2G,
+// then stores its CU's release line; the other agents of the CU wait on that line.
 // Returns 0, or -2 if the phase check failed (an agent read a slot that did not hold
 // the value of the round it is in).
 int or_barrier_threaded(int kind, uint32_t seed, uint32_t N, uint32_t R, uint32_t groups,
                         uint32_t* chk, double* seconds) {
-  if (N == 0 || kind < 0 || kind > 2) return -1;
+  if (N == 0 || kind < 0 || kind > 4) return -1;
   if (groups == 0) groups = 1;
   std::vector<Word> slot(2 * (size_t)N);
   for (auto& s : slot) s.store(0);
@@ -293,12 +305,77 @@ int or_barrier_threaded(int kind, uint32_t seed, uint32_t N, uint32_t R, uint32_
   std::vector<Word> arrive(N), release(N);
   for (uint32_t b = 0; b < N; ++b) arrive[b].store(0), release[b].store(0);
   std::atomic<int> bad{0};
+  // split state
+  Word gen{0};
+  // per-XCD state (kind 3): G groups, kCus CUs per group, C = 2G copies of the stamps
+  constexpr uint32_t kCus = 4;
+  const uint32_t C = 2 * G;
+  const uint32_t block = (N + G - 1) / G;
+  std::vector<Word> xcount(G), xcu(G), cucount((size_t)G * kCus), currank((size_t)G * kCus);
+  std::vector<Word> larrive((size_t)G * block), mail((size_t)C * G), rel((size_t)G * kCus);
+  for (auto* v : {&xcount, &xcu, &cucount, &currank, &larrive, &mail, &rel})
+    for (auto& w : *v) w.store(0);
+  struct Reg {
+    uint32_t x, k, members, slot, rank, copy;
+    uint32_t xmask;
+  };
+  std::vector<Reg> reg(N);
 
   auto members = [&](uint32_t g) { return (N - g + G - 1) / G; };  // agents b with b%G==g
 
+  auto wait_reached = [&](const Word& w, uint32_t stamp) {
+    while (!reached(w.load(std::memory_order_acquire), stamp)) relax();
+  };
+
+  // Round 0 of kind 3: registration, then a counter barrier, then read it back.
+  auto xcd_register = [&](uint32_t b) {
+    Reg& g = reg[b];
+    g.x = b % G;
+    const uint32_t cu = g.x * kCus + (b / G) % kCus;
+    g.k = xcount[g.x].fetch_add(1, std::memory_order_relaxed);
+    g.slot = cucount[cu].fetch_add(1, std::memory_order_relaxed);
+    if (g.slot == 0)
+      currank[cu].store(xcu[g.x].fetch_add(1, std::memory_order_relaxed),
+                        std::memory_order_relaxed);
+    cnt.fetch_add(1, std::memory_order_acq_rel);
+    wait_reached(cnt, N);
+    g.members = xcount[g.x].load(std::memory_order_relaxed);
+    g.rank = currank[cu].load(std::memory_order_relaxed);
+    g.copy = (g.x + G * g.rank) % C;
+    g.xmask = 0;
+    for (uint32_t i = 0; i < G; ++i)
+      if (xcount[i].load(std::memory_order_relaxed) != 0) g.xmask |= 1u << i;
+  };
+  auto xcd_round = [&](uint32_t b, uint32_t stamp) {
+    const Reg& g = reg[b];
+    Word* blk = &larrive[(size_t)g.x * block];
+    if (g.k == 0) {
+      for (uint32_t m = 1; m < g.members; ++m) wait_reached(blk[m], stamp);
+      for (uint32_t c = 0; c < C; ++c)
+        mail[(size_t)c * G + g.x].store(stamp, std::memory_order_release);
+    } else {
+      blk[g.k].store(stamp, std::memory_order_release);
+    }
+    Word& line = rel[(size_t)g.x * kCus + g.rank];
+    if (g.slot == 0) {
+      for (uint32_t i = 0; i < G; ++i)
+        if ((g.xmask >> i) & 1) wait_reached(mail[(size_t)g.copy * G + i], stamp);
+      line.store(stamp, std::memory_order_release);
+    } else {
+      wait_reached(line, stamp);
+    }
+  };
+
   auto barrier = [&](uint32_t b, uint32_t r) {
     const uint32_t stamp = r + 1;
-    if (kind == 0) {
+    if (kind == 3) {
+      if (r == 0) xcd_register(b);
+      else xcd_round(b, stamp);
+    } else if (kind == 4) {
+      const uint32_t old = cnt.fetch_add(1, std::memory_order_acq_rel);
+      if (old == N * stamp - 1) gen.store(stamp, std::memory_order_release);
+      else wait_reached(gen, stamp);
+    } else if (kind == 0) {
       cnt.fetch_add(1, std::memory_order_acq_rel);
       const uint32_t target = N * stamp;
       while (!reached(cnt.load(std::memory_order_acquire), target)) relax();

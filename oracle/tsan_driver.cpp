@@ -39,11 +39,11 @@ static void expect(bool ok, const char* what) {
 
 int main() {
   const uint32_t seed = 42;
-  {  // barriers: central, hierarchical, flag
+  {  // barriers: central, counter tree, flag, per-XCD flag protocol, split central
     const uint32_t N = 6, R = 40;
     std::vector<uint32_t> want(N), got(N);
     or_barrier_closed(seed, N, R, want.data());
-    for (int kind = 0; kind < 3; ++kind) {
+    for (int kind = 0; kind <= 4; ++kind) {
       expect(or_barrier_threaded(kind, seed, N, R, 2, got.data(), nullptr) == 0, "barrier rc");
       expect(got == want, "barrier checksums");
     }

@@ -69,7 +69,9 @@ class Params(ctypes.Structure):
         ("xcd_copies", ctypes.c_uint32),
         ("cohort_passes", ctypes.c_uint32),
         ("flag_placement", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 1),
+        ("xcd_release", ctypes.c_uint32),
+        ("post_backoff", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 2),
     ]
 
 

@@ -423,7 +423,8 @@ def copy(ctx: Context, dst, src, nbytes: int, reps: int = 1):
     return st.as_dict()
 
 
-LITMUS = {"mp": (0, {"fenced": 0, "no_acquire": 1, "no_release": 2, "none": 3}),
+LITMUS = {"mp": (0, {"fenced": 0, "no_acquire": 1, "no_release": 2, "none": 3,
+                    "release_l1_invalidate": 4}),
           "sb": (1, {"fenced": 0, "none": 1})}
 
 
@@ -449,12 +450,13 @@ def shader_clock_mhz(ctx: Context, ms: int = 20) -> float:
 
 def bench_fence(ctx: Context, kind: str, nwg: int, lanes: int = 64, reps: int = 1,
                 lines: int = 1) -> dict:
-    """Agent-scope fence cost (sp_bench_fence).  kind: "release" or "acquire".  Returns
+    """Fence cost (sp_bench_fence).  kind: "release" or "acquire" (agent scope) or
+    "l1_invalidate" (workgroup-scope invalidate of the CU's L1).  Returns
     per-fence shader clocks (mean and max over workgroups) and the wall-clock span from
     the first workgroup's start to the last one's end."""
     out = ctx.zeros(4 * nwg, "u64")
     st = N.Stats()
-    check(lib.sp_bench_fence(ctx.h, {"release": 0, "acquire": 1}[kind], nwg, lanes, reps, lines,
+    check(lib.sp_bench_fence(ctx.h, {"release": 0, "acquire": 1, "l1_invalidate": 2}[kind], nwg, lanes, reps, lines,
                              ctx.ptr(out), ctypes.byref(st), ctx.stream()),
           "sp_bench_fence", ctx.h)
     v = ctx.read(out, "u64", 4 * nwg).reshape(nwg, 4).astype(np.float64)

@@ -35,6 +35,7 @@ int normalize(const sp_ctx* ctx, const sp_params* in, sp_params* out) {
   if (p.cohort_passes == 0) p.cohort_passes = 64;
   if (p.cohort_passes > 255) return SP_E_INVAL;  // the grant word's session field
   if (p.flag_placement > 1) return SP_E_INVAL;
+  if (p.xcd_release > 1 || p.post_backoff > 1) return SP_E_INVAL;
   *out = p;
   return SP_OK;
 }

@@ -267,6 +267,7 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.groups = G;
   s.tgroups = std::min(G, nwg);
   s.fenced = q.coherent_cs ? 0u : 1u;
+  s.l1only = kind == SP_BARRIER_XCD && s.fenced && q.xcd_release == 1;
   s.xcopies = copies;
   s.xmstride = mstride;
   s.flag_stride = fs;

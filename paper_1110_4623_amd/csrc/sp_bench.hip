@@ -148,8 +148,9 @@ __global__ void k_clock(uint64_t wall_ticks, unsigned long long* out) {
 
 // Fence cost: each workgroup's leader makes `lines` of its own 128-byte lines dirty (plain
 // stores, completed into its XCD's L2), meets the others at a start counter, then times
-// `reps` agent-scope fences of one kind: 0 = release (write back the XCD's dirty L2 lines),
-// 1 = acquire (invalidate the CU's L1 and the XCD's stale L2 lines).  out[4 w + 0] =
+// `reps` fences of one kind: 0 = agent-scope release (write back the XCD's dirty L2 lines),
+// 1 = agent-scope acquire (invalidate the CU's L1 and the XCD's stale L2 lines),
+// 2 = workgroup-scope invalidate (the CU's L1 only).  out[4 w + 0] =
 // shader clocks for the reps, out[4 w + 1] / [4 w + 2] = wall clock at start / end.
 __global__ SP_FULL_OCCUPANCY void k_fence(uint32_t kind, uint32_t reps, uint32_t lines,
                                           uint32_t* scratch, uint32_t* start, uint32_t nwg,
@@ -167,7 +168,8 @@ __global__ SP_FULL_OCCUPANCY void k_fence(uint32_t kind, uint32_t reps, uint32_t
   const uint64_t w0 = sp::wall_clock(), c0 = sp::shader_clock();
   for (uint32_t r = 0; r < reps; ++r) {
     if (kind == 0) sp::fence_release();
-    else sp::fence_acquire();
+    else if (kind == 1) sp::fence_acquire();
+    else sp::invalidate_l1();
     __asm__ __volatile__("" ::: "memory");
   }
   const uint64_t c1 = sp::shader_clock(), w1 = sp::wall_clock();
@@ -332,7 +334,7 @@ int sp_bench_clock(sp_ctx* ctx, uint32_t ms, uint64_t* out, double* mhz, void* s
 
 int sp_bench_fence(sp_ctx* ctx, uint32_t kind, uint32_t nwg, uint32_t lanes, uint32_t reps,
                    uint32_t lines, uint64_t* out, sp_stats* st, void* stream) {
-  if (!ctx || !out || kind > 1 || nwg == 0 || nwg > 65536 || !spi::lanes_ok(lanes) ||
+  if (!ctx || !out || kind > 2 || nwg == 0 || nwg > 65536 || !spi::lanes_ok(lanes) ||
       reps == 0 || reps > 1000 || lines > 1024)
     return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);

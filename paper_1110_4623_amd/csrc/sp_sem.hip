@@ -149,6 +149,7 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   ss.ticket = base + L_TICKET * sw;
   ss.turn = base + L_TURN * sw;
   ss.bo = spi::backoff_cfg(q, base + L_PRIVATE * sw);
+  ss.post_backoff = q.post_backoff;
   SP_CHECK(spi::fill_u32(ctx, base, sem->state_words, 0, s));
   if (kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF)
     SP_CHECK(spi::fill_u32(ctx, ss.S, 1, sem->K + 1, s));  // Algorithm 4: S = K + 1

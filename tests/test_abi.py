@@ -45,7 +45,7 @@ def test_params_default_roundtrip():
     assert (p.backoff, p.backoff_min, p.backoff_max, p.poll_sleep) == (1, 2, 64, 3)
     assert p.pad_bytes == 128 and p.timeout_ms == 20000 and p.xcd_copies == 64
     assert p.flag_placement == 0 and p.cohort_passes in (0, 64)
-    assert ctypes.sizeof(_native.Params) == 64
+    assert ctypes.sizeof(_native.Params) == 76
     assert ctypes.sizeof(_native.Stats) == 64
 
 

@@ -4,7 +4,8 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 import pytest
 
 from oracle.modelcheck import (BarrierModel, CohortLockModel, CondModel, FASemModel, MutexModel,
-                               QueueLockModel, SpinSemModel, WeightedSemModel, explore)
+                               QueueLockModel, SpinSemModel, WeightedSemModel, XcdBarrierModel,
+                               explore)
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
@@ -28,7 +29,7 @@ def test_fa_semaphore_correct(K, n, ops):
     assert r.ok, r.violation
 
 
-@pytest.mark.parametrize("kind", ["central", "xcd", "flag"])
+@pytest.mark.parametrize("kind", ["central", "split", "tree", "flag"])
 @pytest.mark.parametrize("n,rounds,groups", [(2, 3, 2), (3, 3, 2), (4, 3, 2), (3, 4, 3)])
 def test_barrier_correct(kind, n, rounds, groups):
     r = explore(BarrierModel(kind, n, rounds, groups))
@@ -63,20 +64,25 @@ def test_catches_spin_semaphore_off_by_one():
     assert r.violation and "occupancy" in r.violation
 
 
-@pytest.mark.parametrize("kind", ["central", "xcd", "flag"])
+@pytest.mark.parametrize("kind", ["central", "split", "tree", "flag"])
 def test_catches_single_buffered_exchange(kind):
     r = explore(BarrierModel(kind, 2, 3, 2, mutant="single_buffer"))
     assert r.violation and "phase" in r.violation
 
 
-@pytest.mark.parametrize("kind", ["central", "flag"])
+@pytest.mark.parametrize("kind", ["central", "split", "flag"])
 def test_catches_barrier_that_does_not_wait(kind):
     r = explore(BarrierModel(kind, 2, 2, mutant="no_wait"))
     assert r.violation and "phase" in r.violation
 
 
 def test_catches_hierarchical_group_released_early():
-    r = explore(BarrierModel("xcd", 4, 2, 2, mutant="no_top_wait"))
+    r = explore(BarrierModel("tree", 4, 2, 2, mutant="no_top_wait"))
+    assert r.violation and "phase" in r.violation
+
+
+def test_catches_split_barrier_published_one_arrival_early():
+    r = explore(BarrierModel("split", 3, 3, mutant="split_off_by_one"))
     assert r.violation and "phase" in r.violation
 
 
@@ -186,3 +192,62 @@ def test_cohort_lock_correct_two_per_cohort_twice():
 def test_cohort_lock_mutants_fail(mutant, n, ops, B):
     r = explore(CohortLockModel(n, ops, C=2, B=B, mutant=mutant))
     assert not r.ok
+
+
+# ---- the per-XCD barrier as the library runs it, with its caches ----------------------
+
+# (xcd, cu) per agent.  TWO_XCDS: XCD 0 holds agents 0 and 2 on one CU (agent 0 is the
+# master and the CU leader, agent 2 waits on the CU's release line), XCD 1 holds agent 1.
+TWO_XCDS = ((0, 0), (1, 1), (0, 0))
+# FOUR: XCD 0 has two CUs (agents 0 and 3 share CU 0; agent 1 is alone on CU 1, a CU
+# leader that is not the master), XCD 1 has agent 2.
+FOUR = ((0, 0), (0, 1), (1, 2), (0, 0))
+
+
+@pytest.mark.parametrize("placement,rounds", [(TWO_XCDS, 3), (TWO_XCDS, 4), (FOUR, 3)])
+@pytest.mark.parametrize("copies", [1, 2])
+@pytest.mark.parametrize("mode", ["plain", "coherent"])
+def test_xcd_barrier_correct(placement, rounds, copies, mode):
+    r = explore(XcdBarrierModel(placement, rounds, copies, mode))
+    assert r.ok, r.violation
+
+
+def test_xcd_barrier_registration_round():
+    """Round 0 numbers the members and CUs with fetch-and-adds, as the library does."""
+    r = explore(XcdBarrierModel(TWO_XCDS, 3, 2, register=True))
+    assert r.ok, r.violation
+    r = explore(XcdBarrierModel(TWO_XCDS, 3, 2, "coherent", register=True))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("block,cu_lines", [(1, 8), (8, 0)])
+def test_xcd_barrier_falls_back_when_registration_overflows(block, cu_lines):
+    r = explore(XcdBarrierModel(TWO_XCDS, 3, 2, register=True, block=block, cu_lines=cu_lines))
+    assert r.ok, r.violation
+
+
+def test_xcd_barrier_l1_invalidation_needs_coherent_l2s():
+    """Every workgroup dropping only its CU's L1 is enough if a writeback removes the other
+    XCDs' copies of the lines, and not otherwise."""
+    r = explore(XcdBarrierModel(TWO_XCDS, 3, 2, "l1only", l2_coherent=True))
+    assert r.ok, r.violation
+    r = explore(XcdBarrierModel(TWO_XCDS, 3, 2, "l1only", l2_coherent=False))
+    assert r.violation and "phase" in r.violation
+
+
+@pytest.mark.parametrize("mutant", ["early_publish", "early_release", "no_writeback",
+                                    "no_invalidate", "no_cu_wait", "flag_before_store"])
+def test_xcd_barrier_mutants_read_stale_data(mutant):
+    r = explore(XcdBarrierModel(TWO_XCDS, 3, 2, mutant=mutant))
+    assert r.violation and "phase" in r.violation
+
+
+def test_xcd_barrier_missing_stamp_copy_deadlocks():
+    r = explore(XcdBarrierModel(TWO_XCDS, 3, 2, mutant="skip_copy"))
+    assert r.deadlock
+
+
+def test_xcd_barrier_rank_stored_late_is_caught():
+    r = explore(XcdBarrierModel(((0, 0), (0, 1), (0, 0)), 2, 2, register=True,
+                                mutant="rank_after_arrival"))
+    assert r.violation

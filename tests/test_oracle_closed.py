@@ -120,6 +120,38 @@ def test_sem_single_agent_checksum():
     assert int(oracle.sem_closed(seed, 1, A)[0]) == c
 
 
+def test_sem_closed_hand_assembled_vectors():
+    """Several workgroups and a ragged split: pins the per-workgroup (b << 16) term and the
+    operation index j of the checksum against values assembled by hand from pinned hashes."""
+    rows = [r for r in _rows("workload_vectors.txt") if r[0] == "sem"]
+    assert len(rows) >= 2
+    for row in rows:
+        seed, nwg, total = int(row[1]), int(row[2]), int(row[3])
+        expect = [int(v, 16) for v in row[4:]]
+        assert [int(x) for x in oracle.sem_closed(seed, nwg, total)] == expect
+
+
+def test_bounded_buffer_closed_hand_assembled_vectors():
+    rows = [r for r in _rows("workload_vectors.txt") if r[0] == "bb"]
+    assert len(rows) >= 2
+    for row in rows:
+        seed, producers, items = int(row[1]), int(row[2]), int(row[3])
+        assert oracle.bb_closed(seed, producers, items) == (int(row[4], 16), int(row[5], 16))
+
+
+def test_key_hand_assembled_vectors():
+    """key chains three splitmix32 calls; each vector's inputs cancel the previous hash so
+    that every stage lands on a pinned splitmix32 value (and a swap of b and j, or of the
+    seed and the stream, would not)."""
+    rows = [r for r in _rows("workload_vectors.txt") if r[0] == "key"]
+    assert len(rows) >= 3
+    for row in rows:
+        seed, b, j, s = int(row[1]), int(row[2], 16), int(row[3], 16), int(row[4])
+        assert oracle.key(seed, b, j, s) == int(row[5], 16)
+        if b != j:
+            assert oracle.key(seed, j, b, s) != int(row[5], 16)
+
+
 # ---- microbenchmarks -----------------------------------------------------------------
 
 @pytest.mark.parametrize("U,n,T", [(1, 1, 1), (5, 3, 7), (64, 100, 32), (8, 1000, 1024), (3, 5, 1)])

@@ -7,7 +7,7 @@ import pytest
 import oracle
 
 
-@pytest.mark.parametrize("kind", ["central", "xcd", "flag"])
+@pytest.mark.parametrize("kind", ["central", "split", "tree", "flag", "xcd"])
 @pytest.mark.parametrize("N,R", [(1, 20), (2, 50), (5, 40), (16, 200), (64, 20)])
 def test_barrier_threaded_matches_closed(kind, N, R):
     seed = 42
@@ -16,10 +16,18 @@ def test_barrier_threaded_matches_closed(kind, N, R):
     assert (chk == oracle.barrier_closed(seed, N, R)).all()
 
 
+@pytest.mark.parametrize("kind", ["tree", "xcd"])
 @pytest.mark.parametrize("groups", [1, 2, 8, 100])
-def test_barrier_hierarchical_any_grouping(groups):
-    chk, rc, _ = oracle.barrier_threaded("xcd", 7, 24, 30, groups=groups)
+def test_barrier_hierarchical_any_grouping(kind, groups):
+    chk, rc, _ = oracle.barrier_threaded(kind, 7, 24, 30, groups=groups)
     assert rc == 0 and (chk == oracle.barrier_closed(7, 24, 30)).all()
+
+
+def test_barrier_per_xcd_protocol_at_full_grid():
+    """The per-XCD flag protocol with 2048 agents in 8 groups of 4 CUs each (256 members
+    per group, 64 agents per CU), as on the GPU's largest co-resident grid."""
+    chk, rc, _ = oracle.barrier_threaded("xcd", 42, 2048, 20, groups=8)
+    assert rc == 0 and (chk == oracle.barrier_closed(42, 2048, 20)).all()
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep",
