@@ -178,18 +178,11 @@ typedef struct sp_params {
                            /* release lines, each when it fits in a chunk                  */
                            /* (sp_barrier_info reports the outcome).                       */
                            /* 1 = fixed layout (XCD-major blocks).  Timing only.           */
-  uint32_t xcd_release;    /* SP_BARRIER_XCD with plain data (coherent_cs = 0): how the    */
-                           /* workgroups leave a round once every XCD has written its L2    */
-                           /* back.  0 = each CU's first workgroup polls the stamps,        */
-                           /* invalidates the CU's L1 and the XCD's stale L2 lines (agent- */
-                           /* scope acquire) and releases the CU's other workgroups through */
-                           /* one line; 1 = every workgroup polls the stamps and            */
-                           /* invalidates its CU's L1 only (workgroup-scope invalidate).    */
   uint32_t post_backoff;   /* SP_SEM_SPIN_BACKOFF (Algorithm 4): 0 = post retries at once  */
                            /* (Section 5's prose: post proceeds aggressively, only wait     */
                            /* backs off), 1 = post backs off after a failed exchange as     */
                            /* wait does (the Algorithm 4 listing)                           */
-  uint32_t reserved[2];
+  uint32_t reserved[3];
 } sp_params;
 
 typedef struct sp_stats {
@@ -243,6 +236,27 @@ int sp_last_hip_error(const sp_ctx* ctx);
 /* Writes the XCC id of every workgroup of a plain launch of nwg x lanes into
  * out (device, nwg uint32).                                                             */
 int sp_probe_xcc(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t* out, void* stream);
+
+/* ---- co-residency ----------------------------------------------------------------------
+ * A barrier (and every workload whose workgroups wait for each other) needs all of its
+ * workgroups resident at once (Section 5: the barrier is the primitive that needs
+ * persistent threads).  Every such run refuses with SP_E_NORESIDENT when
+ * sp_resident_per_cu(occupancy of its kernel) * CUs < workgroups.
+ * sp_resident_per_cu: workgroups of one kernel that fit on one CU at once -- the smaller
+ * of the runtime's figure (runtime_per_cu) and the budget that the kernel's own resource
+ * use leaves on gfx950: 8 wavefronts per SIMD and 4 SIMDs per CU, 512 VGPRs per lane per
+ * SIMD allocated in granules of 8, 160 KiB of LDS per CU allocated in 512-byte granules.
+ * A kernel whose registers the runtime under-counts therefore cannot pass the check and
+ * then wait forever for a workgroup that never became resident.  Pure host arithmetic
+ * (no GPU call); returns 0 for lanes == 0 or a NULL argument.                            */
+typedef struct sp_occupancy {
+  uint32_t runtime_per_cu; /* hipOccupancyMaxActiveBlocksPerMultiprocessor                 */
+  uint32_t vgprs;          /* VGPRs per lane (hipFuncAttributes.numRegs)                     */
+  uint32_t lds_bytes;      /* LDS per workgroup (hipFuncAttributes.sharedSizeBytes + dynamic) */
+  uint32_t lanes;          /* threads per workgroup                                          */
+  uint32_t reserved[4];
+} sp_occupancy;
+uint32_t sp_resident_per_cu(const sp_occupancy* occ);
 
 /* ---- device memory for callers without their own allocator ------------------------
  * sp_buffer_alloc: `bytes` of device memory on the context's GPU, zero-filled; the
@@ -333,10 +347,17 @@ int sp_sem_destroy(sp_sem* s);
  * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, 0, 0, 0}
  * (SP_SEM_COUNTERS, SP_SEM_ADAPTIVE: count stays 0, ticket = tickets drawn, turn = posts
  * made).
+ * out_data: device, K uint32 (zeroed by the call), or NULL; K <= 4096.  Guarded data:
+ * each admission adds one to a word with a plain load and store made by the workgroup's
+ * last thread -- for K = 1 to the one word, ordered only by the semaphore's acquire and
+ * release; for K > 1 to the word of a slot of a pool of K that the holder claims with a
+ * compare-and-swap (first try at key(w, j, 4) mod K) and returns with a release before it
+ * posts.  The words sum to total_pairs (K = 1: the word equals it); which slot each
+ * admission took is not unique.
  * Errors: SP_E_INVAL, SP_E_TIMEOUT, SP_E_HIP.                                           */
 int sp_sem_run(sp_sem* s, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
                uint32_t max_hold_cyc, uint32_t seed, uint32_t track, uint32_t* out_chk,
-               uint32_t* out_state, sp_stats* st, void* stream);
+               uint32_t* out_state, uint32_t* out_data, sp_stats* st, void* stream);
 
 /* ---- condition variables (Section 7's future work) ------------------------------------
  * Device API in include/sp/cond.hpp: cond_wait (register, unlock, wait, relock; Mesa
@@ -349,11 +370,15 @@ int sp_sem_run(sp_sem* s, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
  * values, consumers on "not empty" while it is empty, and each signals the other after
  * its put or take.  All nwg workgroups must be co-resident.  out: device, 6 uint64 =
  * {xor of the values taken, their sum, values taken, values put, most values ever in the
- * ring (<= capacity), values left (0)}.  p: poll_sleep, pad_bytes, timeout_ms are used.
+ * ring (<= capacity), values left (0)}.  out_taken: device, items uint32, or NULL: every
+ * value taken, consumer i's in order at the start of its share (consumer shares split as
+ * the producers' are), so the values taken can be compared one by one, as a multiset, with
+ * the values put.  p: poll_sleep, pad_bytes, timeout_ms are used.
  * Errors: SP_E_INVAL, SP_E_NORESIDENT, SP_E_TIMEOUT, SP_E_HIP.                          */
 int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, uint32_t producers,
                                uint32_t lanes, uint32_t capacity, uint64_t items, uint32_t seed,
-                               const sp_params* p, uint64_t* out, sp_stats* st, void* stream);
+                               const sp_params* p, uint64_t* out, uint32_t* out_taken,
+                               sp_stats* st, void* stream);
 
 /* ---- memory-system microbenchmarks (Section 3; Tables 1-3) ------------------------------
  * sp_bench_atomic: issuer u (a lane, or a wavefront's lane 0) performs ops_per_issuer

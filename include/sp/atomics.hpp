@@ -76,11 +76,12 @@ __device__ __forceinline__ void fence_release() {
   wave_stores_complete();
 }
 
-// Invalidate this CU's L1 (vector data cache) only: a workgroup-scope invalidate, which
-// leaves the XCD's L2 alone and is not serialized at the L2 as the agent-scope one is.
-// It makes later plain loads of this CU miss in the L1; whether the L2 then serves fresh
-// data depends on how the L2s keep the lines coherent, which the litmus tests measure.
-__device__ __forceinline__ void invalidate_l1() {
+// A workgroup-scope invalidate (buffer_inv sc0).  It costs ~310 shader clocks and is not
+// serialized at the L2, unlike the agent-scope one; but it does not make another XCD's
+// written-back data visible: after it, a plain load returned the old value in 28 % of
+// 4.1 M message-passing trials, as many as with no invalidate at all.  Measurements only
+// (sp_bench_fence kind 2, litmus variant 4); no primitive relies on it.
+__device__ __forceinline__ void invalidate_workgroup_scope() {
   __asm__ __volatile__("buffer_inv sc0" ::: "memory");
   wave_stores_complete();
 }

@@ -26,9 +26,6 @@ struct BarrierState {
   uint32_t fenced;      // 1: order plain memory (release / acquire fences); 0: the data
                         // exchanged across the barrier is accessed with agent-scope
                         // loads and stores, so the barrier does no cache maintenance
-  uint32_t l1only;      // xcd, fenced: every workgroup polls the stamps and invalidates its
-                        // CU's L1 only, instead of a CU leader's agent-scope acquire and
-                        // per-CU release line
   uint32_t xcopies;     // xcd: copies of the XCD stamps (0 = xarrive, one line per XCD)
   uint32_t xmstride;    // xcd: words between two copies (>= groups, whole lines)
   // xcd: where each XCD's flags live.  XCD x's block of arrival flags starts xoff[x]
@@ -263,19 +260,12 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
   const uint32_t* stamps =
       C ? s.xmail + s.moff[mail % X] + (size_t)(mail / X) * s.xmstep : s.xarrive;
   const uint32_t sstride = C ? 1 : s.stride;
-  if (!s.fenced || s.l1only) {
+  if (!s.fenced) {
     // Coherent data: no cache maintenance, so nothing is shared per CU; every workgroup
-    // polls the populated XCDs' stamps itself (two flag hops per round).  With l1only the
-    // data is plain: every XCD has written its L2 back before it published its stamp, and
-    // each workgroup then drops its CU's L1 lines itself.
+    // polls the populated XCDs' stamps itself (two flag hops per round).
     if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
       ok = poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
-    ok = __syncthreads_and(ok);
-    if (s.fenced) {
-      if (is_leader()) invalidate_l1();
-      __syncthreads();
-    }
-    return ok;
+    return __syncthreads_and(ok);
   }
   // this CU's release line
   uint32_t* rel = s.lrelease + s.roff[x] +

@@ -31,7 +31,7 @@ BARRIER_KINDS = {"central": 0, "tree": 1, "flag": 2, "xcd": 3, "split": 4}
 MUTEX_KINDS = {"spin_cas": 0, "spin_exch": 1, "spin_backoff": 2, "ticket": 3, "sleep": 4,
                "ring": 5, "array": 6, "adaptive": 7, "cohort": 8}
 SEM_KINDS = {"spin": 0, "spin_backoff": 1, "ticket": 2, "sleep": 3, "counters": 4,
-             "adaptive": 5}
+             "adaptive": 5, "spin_backoff_wait_only": 6}
 BENCH_OPS = {"add": 0, "cas": 1, "exch": 2, "ld": 3, "st": 4}
 
 
@@ -81,6 +81,8 @@ def lib():
             "or_bench_threaded": (i32, [i32, u32, u32, u64, u32, p32, u32, p32, p64, pd]),
             "or_serve_threaded": (i32, [u32, p32, p32, u32, u32, u32, p32, p32, p64, pd]),
             "or_bb_closed": (None, [u32, u32, u64, p64]),
+            "or_bb_values": (None, [u32, u32, u64, p32]),
+            "or_exch_finals_invalid": (u64, [u32, u32, u64, u32, p32, p32]),
             "or_bb_threaded": (i32, [u32, u32, u32, u64, u32, p64, pd]),
         }
         for name, (res, args) in sig.items():
@@ -184,6 +186,22 @@ def bench_closed(op: str, seed: int, U: int, n: int, perm: np.ndarray):
     if rc != 0:
         raise ValueError(f"or_bench_closed({op}) failed: {rc}")
     return finals, s.value
+
+
+def exch_finals_invalid(seed: int, U: int, n: int, perm: np.ndarray, finals: np.ndarray) -> int:
+    """Words whose final value after the exchange benchmark is neither their initial value
+    nor a value some exchange wrote to them (0 for a valid outcome)."""
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    finals = np.ascontiguousarray(finals, dtype=np.uint32)
+    return lib().or_exch_finals_invalid(seed & 0xFFFFFFFF, U, n, len(perm), _p32(perm),
+                                        _p32(finals))
+
+
+def bb_values(seed: int, producers: int, items: int) -> np.ndarray:
+    """Every value the bounded buffer's producers put (uint32, producer order)."""
+    out = np.zeros(items, dtype=np.uint32)
+    lib().or_bb_values(seed & 0xFFFFFFFF, producers, items, _p32(out))
+    return out
 
 
 # ---- threaded reference ----------------------------------------------------------------

@@ -21,6 +21,7 @@
 //
 // Every function returns 0 on success or a negative code on a detected violation.
 
+#include <algorithm>
 #include <atomic>
 #include <condition_variable>
 #include <mutex>
@@ -205,6 +206,33 @@ int or_bench_closed(int op, uint32_t seed, uint32_t U, uint64_t n, uint32_t T,
   }
   *sum = s;
   return 0;
+}
+
+// Exchange finals are not unique (last writer wins), but each final word must be its
+// initial value sm32(seed ^ t) or one of the values written to that word.  Returns the
+// number of words for which neither holds (0 for a valid outcome).
+uint64_t or_exch_finals_invalid(uint32_t seed, uint32_t U, uint64_t n, uint32_t T,
+                                const uint32_t* perm, const uint32_t* finals) {
+  std::vector<char> ok(T, 0);
+  for (uint32_t t = 0; t < T; ++t) ok[t] = finals[t] == or_prefill(seed, t);
+  for (uint32_t u = 0; u < U; ++u)
+    for (uint64_t i = 0; i < n; ++i) {
+      const uint32_t t = perm[(u + i) % T];
+      if (!ok[t] && finals[t] == or_exch_value(seed, u, (uint32_t)i)) ok[t] = 1;
+    }
+  uint64_t bad = 0;
+  for (uint32_t t = 0; t < T; ++t) bad += ok[t] ? 0 : 1;
+  return bad;
+}
+
+// Multiset of the values the bounded buffer's producers put, in producer order: producer
+// w's j-th value is sm32(seed ^ (w << 16) ^ j); shares split as or_ops_for_agent.
+void or_bb_values(uint32_t seed, uint32_t P, uint64_t items, uint32_t* out) {
+  uint64_t k = 0;
+  for (uint32_t w = 0; w < P; ++w) {
+    const uint64_t A = or_ops_for_agent(P, items, w);
+    for (uint64_t j = 0; j < A; ++j) out[k++] = or_sm32(seed ^ (w << 16) ^ (uint32_t)j);
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -578,19 +606,24 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 // Initial value K.  Algorithm 4 keeps S = K + 1 (zero means "held"); Algorithm 5 keeps
 // count, ticket and turn starting at 0, and a queued waiter proceeds once turn is
 // strictly greater than the ticket it drew (0-based).
-// kind: 0 Algorithm 4, 1 Algorithm 4 with backoff, 2 Algorithm 5, 3 Algorithm 5 with
-// yielding polls, 4 two monotone counters (ticket t enters once posts + K > t), 5 the same
-// admission rule with proportional waiting (a waiter d posts short of admission yields
-// (d - 1) / 4 extra times per poll).
+// kind: 0 Algorithm 4, 1 Algorithm 4 with backoff in both loops (the listing), 2
+// Algorithm 5, 3 Algorithm 5 with yielding polls, 4 two monotone counters (ticket t
+// enters once posts + K > t), 5 the same admission rule with proportional waiting (a
+// waiter d posts short of admission yields (d - 1) / 4 extra times per poll), 6 Algorithm
+// 4 with backoff in wait only (Section 5's prose: post proceeds aggressively).
 // Each pair: wait, occupancy tracking, checksum update, admission count, post.
-// out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}.
+// out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}; for the
+// Algorithm 4 kinds ticket and turn are unused and state[1] / state[2] report instead the
+// failed exchanges of wait / of post (attempts that found S held or the semaphore full).
 // Returns 0, -2 if occupancy ever exceeded K.
 int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t total,
                     uint32_t imin, uint32_t imax, uint32_t* chk, uint32_t* maxocc,
                     uint32_t* state, double* seconds) {
-  if (nwg == 0 || K == 0 || kind < 0 || kind > 5) return -1;
+  if (nwg == 0 || K == 0 || kind < 0 || kind > 6) return -1;
   Word S{K + 1}, count{0}, ticket{0}, turn{0}, occ{0}, maxo{0}, adm{0};
-  const bool alg4 = kind <= 1, backoff = kind == 1;
+  const bool alg4 = kind <= 1 || kind == 6, backoff = kind == 1 || kind == 6;
+  const bool post_backoff = kind == 1;
+  std::atomic<uint64_t> wait_fail{0}, post_fail{0};
 
   auto wait = [&](Backoff& bo) {
     if (alg4) {
@@ -602,6 +635,7 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
           return;
         }
         if (v == 1) S.exchange(1, std::memory_order_release);
+        wait_fail.fetch_add(1, std::memory_order_relaxed);
         if (backoff) bo(); else relax();
       }
     } else if (kind == 4 || kind == 5) {
@@ -630,7 +664,8 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
           S.exchange(v + 1, std::memory_order_release);
           return;
         }
-        if (backoff) bo(); else relax();
+        post_fail.fetch_add(1, std::memory_order_relaxed);
+        if (post_backoff) bo(); else relax();
       }
     } else if (kind == 4 || kind == 5) {
       turn.fetch_add(1, std::memory_order_acq_rel);
@@ -659,8 +694,8 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   });
   *maxocc = maxo.load();
   state[0] = alg4 ? S.load() : count.load();
-  state[1] = ticket.load();
-  state[2] = turn.load();
+  state[1] = alg4 ? (uint32_t)std::min<uint64_t>(wait_fail.load(), 0xFFFFFFFFu) : ticket.load();
+  state[2] = alg4 ? (uint32_t)std::min<uint64_t>(post_fail.load(), 0xFFFFFFFFu) : turn.load();
   state[3] = adm.load();
   if (seconds) *seconds = t;
   return *maxocc > K ? -2 : 0;

@@ -69,9 +69,8 @@ class Params(ctypes.Structure):
         ("xcd_copies", ctypes.c_uint32),
         ("cohort_passes", ctypes.c_uint32),
         ("flag_placement", ctypes.c_uint32),
-        ("xcd_release", ctypes.c_uint32),
         ("post_backoff", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 2),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 
@@ -156,6 +155,16 @@ class ServeResult(ctypes.Structure):
     ]
 
 
+class Occupancy(ctypes.Structure):
+    _fields_ = [
+        ("runtime_per_cu", ctypes.c_uint32),
+        ("vgprs", ctypes.c_uint32),
+        ("lds_bytes", ctypes.c_uint32),
+        ("lanes", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 4),
+    ]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -173,6 +182,7 @@ def _load():
         "sp_strerror": (ctypes.c_char_p, [i32]),
         "sp_last_hip_error": (i32, [vp]),
         "sp_probe_xcc": (i32, [vp, u32, u32, vp, vp]),
+        "sp_resident_per_cu": (u32, [P(Occupancy)]),
         "sp_buffer_alloc": (i32, [vp, u64, P(vp)]),
         "sp_buffer_free": (i32, [vp, vp]),
         "sp_buffer_read": (i32, [vp, vp, vp, u64]),
@@ -187,7 +197,7 @@ def _load():
         "sp_mutex_run": (i32, [vp, u32, u32, u64, u32, u32, vp, vp, P(Stats), vp]),
         "sp_sem_create": (i32, [vp, u32, u32, P(Params), P(vp)]),
         "sp_sem_destroy": (i32, [vp]),
-        "sp_sem_run": (i32, [vp, u32, u32, u64, u32, u32, u32, vp, vp, P(Stats), vp]),
+        "sp_sem_run": (i32, [vp, u32, u32, u64, u32, u32, u32, vp, vp, vp, P(Stats), vp]),
         "sp_bench_atomic": (i32, [vp, u32, u32, u32, u32, u32, u32, u64, u32, vp, vp, vp,
                                   P(Stats), vp]),
         "sp_bench_paper12": (i32, [vp, u32, u32, u32, u32, u32, vp, vp, P(Stats), vp]),
@@ -198,7 +208,7 @@ def _load():
         "sp_bench_fence": (i32, [vp, u32, u32, u32, u32, u32, vp, P(Stats), vp]),
         "sp_bench_clock": (i32, [vp, u32, vp, P(ctypes.c_double), vp]),
         "sp_cond_run_bounded_buffer": (i32, [vp, u32, u32, u32, u32, u32, u64, u32, P(Params),
-                                              vp, P(Stats), vp]),
+                                              vp, vp, P(Stats), vp]),
         "sp_graph_begin": (i32, [vp, vp, P(vp)]),
         "sp_graph_end": (i32, [vp, vp, P(vp)]),
         "sp_graph_launch": (i32, [vp, u32, P(Stats), vp]),

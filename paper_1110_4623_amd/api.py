@@ -11,7 +11,9 @@ when torch is in the process, otherwise from the library's own sp_buffer_alloc
 
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 
 import numpy as np
 
@@ -26,9 +28,11 @@ class DeviceBuffer:
 
     def __init__(self, ctx: "Context", nbytes: int):
         self.ctx, self.nbytes = ctx, nbytes
+        self.p = None
         p = ctypes.c_void_p()
         check(lib.sp_buffer_alloc(ctx.h, nbytes, ctypes.byref(p)), "sp_buffer_alloc", ctx.h)
         self.p = p
+        ctx._own(self)
 
     def ptr(self) -> ctypes.c_void_p:
         return self.p
@@ -46,7 +50,8 @@ class DeviceBuffer:
 
     def close(self):
         if self.p:
-            lib.sp_buffer_free(self.ctx.h, self.p)
+            if self.ctx.h:
+                lib.sp_buffer_free(self.ctx.h, self.p)
             self.p = None
 
     def __del__(self):
@@ -54,6 +59,18 @@ class DeviceBuffer:
             self.close()
         except Exception:
             pass
+
+
+# Contexts still open; closed before the interpreter tears down its objects (and before
+# the HIP runtime and any profiler attached to it finalize), so that no device memory or
+# state object is released in the middle of process exit.
+_LIVE: "weakref.WeakSet[Context]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for c in list(_LIVE):
+        c.close()
 
 
 class Context:
@@ -70,9 +87,13 @@ class Context:
             torch.cuda.set_device(device)
             torch.cuda.init()
         self.device = 0 if device is None else device
+        self.h = None
+        # buffers and state objects made from this context: closed before sp_fini
+        self._owned = weakref.WeakSet()
         h = ctypes.c_void_p()
         check(lib.sp_init(self.device, ctypes.byref(h)), "sp_init")
         self.h = h
+        _LIVE.add(self)
         info = N.DeviceInfo()
         check(lib.sp_device_info_get(self.h, ctypes.byref(info)), "sp_device_info_get", self.h)
         self.info = {
@@ -132,10 +153,18 @@ class Context:
             self.torch.cuda.synchronize()
 
     # ---- lifetime ------------------------------------------------------------------
+    def _own(self, obj) -> None:
+        self._owned.add(obj)
+
     def close(self):
+        """Releases every buffer, state object and graph made from this context, waits for
+        the device, then the context itself.  Idempotent."""
         if self.h:
+            for obj in list(self._owned):
+                obj.close()
             lib.sp_fini(self.h)
             self.h = None
+        _LIVE.discard(self)
 
     def __del__(self):
         try:
@@ -198,6 +227,7 @@ class Barrier(_Handle):
         check(lib.sp_barrier_create(ctx.h, N.BARRIER_KINDS[kind], nwg, ctypes.byref(p),
                                     ctypes.byref(h)), "sp_barrier_create", ctx.h)
         self.h = h
+        ctx._own(self)
         self._out = ctx.zeros(nwg)
 
     def launch(self, lanes: int, rounds: int, seed: int) -> dict:
@@ -250,6 +280,7 @@ class Mutex(_Handle):
         check(lib.sp_mutex_create(ctx.h, N.MUTEX_KINDS[kind], nlocks, words_per_lock,
                                   ctypes.byref(p), ctypes.byref(h)), "sp_mutex_create", ctx.h)
         self.h = h
+        ctx._own(self)
         self._words = ctx.zeros(nlocks * words_per_lock)
 
     def launch(self, nwg: int, lanes: int, total: int, max_delay: int, seed: int,
@@ -285,44 +316,59 @@ class Semaphore(_Handle):
         check(lib.sp_sem_create(ctx.h, N.SEM_KINDS[kind], K, ctypes.byref(p), ctypes.byref(h)),
               "sp_sem_create", ctx.h)
         self.h = h
+        ctx._own(self)
         self._state = ctx.zeros(8)
 
     def launch(self, nwg: int, lanes: int, total: int, max_hold: int, seed: int,
-               track: bool = True) -> dict:
+               track: bool = True, data: bool = False) -> dict:
         """Runs (or records) the wait/post workload; results stay on the device until
-        `result()`.  Returns the stats."""
+        `result()`.  data=True also updates the guarded data words.  Returns the stats."""
         if getattr(self, "_chk_n", None) != nwg:
             self._chk, self._chk_n = self.ctx.zeros(nwg), nwg
+        if data and getattr(self, "_data", None) is None:
+            self._data = self.ctx.zeros(self.K)
+        self._with_data = data
         st = N.Stats()
         check(lib.sp_sem_run(self.h, nwg, lanes, total, max_hold, seed & 0xFFFFFFFF, int(track),
-                             self.ctx.ptr(self._chk), self.ctx.ptr(self._state), ctypes.byref(st),
+                             self.ctx.ptr(self._chk), self.ctx.ptr(self._state),
+                             self.ctx.ptr(self._data if data else None), ctypes.byref(st),
                              self.ctx.stream()), "sp_sem_run", self.ctx.h)
         return st.as_dict()
 
     def result(self) -> dict:
         s = [int(x) for x in self.ctx.read(self._state, "u32", 8)]
-        return {"chk": self.ctx.read(self._chk, "u32", self._chk_n), "maxocc": s[0],
-                "state": (s[1], s[2], s[3], s[4]), "count": s[5], "occ": s[6]}
+        r = {"chk": self.ctx.read(self._chk, "u32", self._chk_n), "maxocc": s[0],
+             "state": (s[1], s[2], s[3], s[4]), "count": s[5], "occ": s[6]}
+        if getattr(self, "_with_data", False):
+            r["data"] = self.ctx.read(self._data, "u32", self.K)
+        return r
 
-    def run(self, nwg: int, lanes: int, total: int, max_hold: int, seed: int, track: bool = True):
-        st = self.launch(nwg, lanes, total, max_hold, seed, track)
+    def run(self, nwg: int, lanes: int, total: int, max_hold: int, seed: int, track: bool = True,
+            data: bool = False):
+        st = self.launch(nwg, lanes, total, max_hold, seed, track, data)
         return dict(self.result(), stats=st)
 
 
 def bounded_buffer(ctx: Context, mutex_kind: str, nwg: int, producers: int, capacity: int,
-                   items: int, seed: int, lanes: int = 64, **params) -> dict:
+                   items: int, seed: int, lanes: int = 64, values: bool = False,
+                   **params) -> dict:
     """Producer/consumer ring on a mutex and two condition variables
-    (sp_cond_run_bounded_buffer)."""
+    (sp_cond_run_bounded_buffer).  values=True also returns every value taken."""
     out = ctx.zeros(6, "u64")
+    taken = ctx.zeros(items) if values else None
     p = make_params(**params)
     st = N.Stats()
     check(lib.sp_cond_run_bounded_buffer(ctx.h, N.MUTEX_KINDS[mutex_kind], nwg, producers, lanes,
                                          capacity, items, seed & 0xFFFFFFFF, ctypes.byref(p),
-                                         ctx.ptr(out), ctypes.byref(st), ctx.stream()),
+                                         ctx.ptr(out), ctx.ptr(taken), ctypes.byref(st),
+                                         ctx.stream()),
           "sp_cond_run_bounded_buffer", ctx.h)
     v = [int(x) for x in ctx.read(out, "u64", 6)]
-    return {"xor": v[0], "sum": v[1], "taken": v[2], "put": v[3], "max_count": v[4],
-            "left": v[5], "stats": st.as_dict()}
+    r = {"xor": v[0], "sum": v[1], "taken": v[2], "put": v[3], "max_count": v[4],
+         "left": v[5], "stats": st.as_dict()}
+    if values:
+        r["values"] = ctx.read(taken, "u32", items)
+    return r
 
 
 class Graph:
@@ -351,6 +397,7 @@ class Graph:
         if exc_type is None:
             check(rc, "sp_graph_end", self.ctx.h)
             self.h = g
+            self.ctx._own(self)
         elif rc == 0:
             lib.sp_graph_destroy(g)
         return False
@@ -424,7 +471,7 @@ def copy(ctx: Context, dst, src, nbytes: int, reps: int = 1):
 
 
 LITMUS = {"mp": (0, {"fenced": 0, "no_acquire": 1, "no_release": 2, "none": 3,
-                    "release_l1_invalidate": 4}),
+                    "release_wg_invalidate": 4}),
           "sb": (1, {"fenced": 0, "none": 1})}
 
 
@@ -451,12 +498,12 @@ def shader_clock_mhz(ctx: Context, ms: int = 20) -> float:
 def bench_fence(ctx: Context, kind: str, nwg: int, lanes: int = 64, reps: int = 1,
                 lines: int = 1) -> dict:
     """Fence cost (sp_bench_fence).  kind: "release" or "acquire" (agent scope) or
-    "l1_invalidate" (workgroup-scope invalidate of the CU's L1).  Returns
+    "wg_invalidate" (a workgroup-scope invalidate).  Returns
     per-fence shader clocks (mean and max over workgroups) and the wall-clock span from
     the first workgroup's start to the last one's end."""
     out = ctx.zeros(4 * nwg, "u64")
     st = N.Stats()
-    check(lib.sp_bench_fence(ctx.h, {"release": 0, "acquire": 1, "l1_invalidate": 2}[kind], nwg, lanes, reps, lines,
+    check(lib.sp_bench_fence(ctx.h, {"release": 0, "acquire": 1, "wg_invalidate": 2}[kind], nwg, lanes, reps, lines,
                              ctx.ptr(out), ctypes.byref(st), ctx.stream()),
           "sp_bench_fence", ctx.h)
     v = ctx.read(out, "u64", 4 * nwg).reshape(nwg, 4).astype(np.float64)

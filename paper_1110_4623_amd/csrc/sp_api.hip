@@ -35,7 +35,7 @@ int normalize(const sp_ctx* ctx, const sp_params* in, sp_params* out) {
   if (p.cohort_passes == 0) p.cohort_passes = 64;
   if (p.cohort_passes > 255) return SP_E_INVAL;  // the grant word's session field
   if (p.flag_placement > 1) return SP_E_INVAL;
-  if (p.xcd_release > 1 || p.post_backoff > 1) return SP_E_INVAL;
+  if (p.post_backoff > 1) return SP_E_INVAL;
   *out = p;
   return SP_OK;
 }
@@ -45,6 +45,20 @@ int fill_u32(sp_ctx* ctx, uint32_t* d, uint64_t words, uint32_t value, hipStream
   uint64_t blocks = std::min<uint64_t>((words + 255) / 256, 4096);
   hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, d, words, value);
   SP_HIP(ctx, hipGetLastError());
+  return SP_OK;
+}
+
+int resident_per_cu(sp_ctx* ctx, const void* kern, uint32_t lanes, uint32_t* per_cu) {
+  int rt = 0;
+  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&rt, kern, (int)lanes, 0));
+  hipFuncAttributes fa{};
+  SP_HIP(ctx, hipFuncGetAttributes(&fa, kern));
+  sp_occupancy occ{};
+  occ.runtime_per_cu = rt > 0 ? (uint32_t)rt : 0u;
+  occ.vgprs = fa.numRegs > 0 ? (uint32_t)fa.numRegs : 0u;
+  occ.lds_bytes = (uint32_t)fa.sharedSizeBytes;
+  occ.lanes = lanes;
+  *per_cu = sp_resident_per_cu(&occ);
   return SP_OK;
 }
 
@@ -60,6 +74,7 @@ int sync_unless_capturing(sp_ctx* ctx, hipStream_t s) {
 }
 
 int begin_timed(sp_ctx* ctx, hipStream_t s) {
+  if (!usable(ctx)) return SP_E_INVAL;
   // Under capture the graph's launcher clears the watchdog word once per replay and
   // times the replays; the recorded call adds only its own kernels.
   if (capturing(s)) return SP_OK;
@@ -97,6 +112,8 @@ int end_timed(sp_ctx* ctx, hipStream_t s, sp_stats* st, uint32_t nwg, uint32_t l
 
 }  // namespace spi
 
+using spi::usable;
+
 extern "C" {
 
 void sp_params_default(sp_params* p) {
@@ -111,6 +128,24 @@ void sp_params_default(sp_params* p) {
   p->flags_packed = 0;
   p->timeout_ms = 20000;
   p->xcd_copies = 64;
+}
+
+uint32_t sp_resident_per_cu(const sp_occupancy* occ) {
+  if (!occ || occ->lanes == 0) return 0;
+  constexpr uint32_t kSimds = 4, kWavesPerSimd = 8, kVgprsPerSimd = 512, kVgprGranule = 8;
+  constexpr uint32_t kLdsBytes = 160 * 1024, kLdsGranule = 512;
+  const uint32_t waves = (occ->lanes + 63) / 64;
+  uint32_t per_simd = kWavesPerSimd;
+  if (occ->vgprs > 0) {
+    const uint32_t v = (occ->vgprs + kVgprGranule - 1) / kVgprGranule * kVgprGranule;
+    per_simd = std::min(per_simd, kVgprsPerSimd / v);
+  }
+  uint32_t wgs = kSimds * per_simd / waves;
+  if (occ->lds_bytes > 0) {
+    const uint32_t l = (occ->lds_bytes + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+    wgs = std::min(wgs, kLdsBytes / l);
+  }
+  return std::min(wgs, occ->runtime_per_cu);
 }
 
 const char* sp_strerror(int code) {
@@ -203,19 +238,26 @@ int sp_init(int device, sp_ctx** out) {
 }
 
 int sp_fini(sp_ctx* ctx) {
-  if (!ctx) return SP_E_INVAL;
-  hipSetDevice(ctx->device);
-  hipFree(ctx->d_err);
-  hipFree(ctx->d_scratch);
-  hipEventDestroy(ctx->ev0);
-  hipEventDestroy(ctx->ev1);
-  hipStreamDestroy(ctx->capture_stream);
-  delete ctx;
+  if (!usable(ctx)) return SP_E_INVAL;
+  // Nothing of this context may still run when its memory goes: wait for the device,
+  // then release in the reverse order of sp_init.
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipStreamDestroy(ctx->capture_stream);
+  (void)hipEventDestroy(ctx->ev1);
+  (void)hipEventDestroy(ctx->ev0);
+  (void)hipFree(ctx->d_scratch);
+  (void)hipFree(ctx->d_err);
+  ctx->capture_stream = nullptr;
+  ctx->ev0 = ctx->ev1 = nullptr;
+  ctx->d_err = ctx->d_scratch = nullptr;
+  ctx->closed = true;
+  if (ctx->refs == 0) delete ctx;
   return SP_OK;
 }
 
 int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
-  if (!ctx || !out) return SP_E_INVAL;
+  if (!usable(ctx) || !out) return SP_E_INVAL;
   memset(out, 0, sizeof(*out));
   strncpy(out->name, ctx->prop.name, sizeof(out->name) - 1);
   strncpy(out->arch, ctx->prop.gcnArchName, sizeof(out->arch) - 1);
@@ -230,7 +272,7 @@ int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
 
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p) {
-  if (!ctx || primitive > 2 || bucket > 1) return SP_E_INVAL;
+  if (!usable(ctx) || primitive > 2 || bucket > 1) return SP_E_INVAL;
   const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_COHORT, SP_SEM_ADAPTIVE};
   if (kind > max_kind[primitive]) return SP_E_INVAL;
   sp_params q;
@@ -241,7 +283,7 @@ int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t ki
 }
 
 int sp_probe_xcc(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t* out, void* stream) {
-  if (!ctx || !out || nwg == 0 || !spi::lanes_ok(lanes)) return SP_E_INVAL;
+  if (!usable(ctx) || !out || nwg == 0 || !spi::lanes_ok(lanes)) return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   hipLaunchKernelGGL(k_probe_xcc, dim3(nwg), dim3(lanes), 0, s, out);
   SP_HIP(ctx, hipGetLastError());
@@ -250,7 +292,7 @@ int sp_probe_xcc(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t* out, void*
 }
 
 int sp_buffer_alloc(sp_ctx* ctx, uint64_t bytes, void** out) {
-  if (!ctx || !out || bytes == 0) return SP_E_INVAL;
+  if (!usable(ctx) || !out || bytes == 0) return SP_E_INVAL;
   *out = nullptr;
   SP_HIP(ctx, hipSetDevice(ctx->device));
   void* p = nullptr;
@@ -267,21 +309,21 @@ int sp_buffer_alloc(sp_ctx* ctx, uint64_t bytes, void** out) {
 }
 
 int sp_buffer_free(sp_ctx* ctx, void* p) {
-  if (!ctx || !p) return SP_E_INVAL;
+  if (!usable(ctx) || !p) return SP_E_INVAL;
   SP_HIP(ctx, hipSetDevice(ctx->device));
   SP_HIP(ctx, hipFree(p));
   return SP_OK;
 }
 
 int sp_buffer_read(sp_ctx* ctx, void* host_dst, const void* dev_src, uint64_t bytes) {
-  if (!ctx || !host_dst || !dev_src) return SP_E_INVAL;
+  if (!usable(ctx) || !host_dst || !dev_src) return SP_E_INVAL;
   SP_HIP(ctx, hipSetDevice(ctx->device));
   SP_HIP(ctx, hipMemcpy(host_dst, dev_src, bytes, hipMemcpyDeviceToHost));
   return SP_OK;
 }
 
 int sp_buffer_write(sp_ctx* ctx, void* dev_dst, const void* host_src, uint64_t bytes) {
-  if (!ctx || !dev_dst || !host_src) return SP_E_INVAL;
+  if (!usable(ctx) || !dev_dst || !host_src) return SP_E_INVAL;
   SP_HIP(ctx, hipSetDevice(ctx->device));
   SP_HIP(ctx, hipMemcpy(dev_dst, host_src, bytes, hipMemcpyHostToDevice));
   return SP_OK;
@@ -296,7 +338,7 @@ struct sp_graph {
 };
 
 int sp_graph_begin(sp_ctx* ctx, void* stream, void** capture_stream) {
-  if (!ctx || !capture_stream) return SP_E_INVAL;
+  if (!usable(ctx) || !capture_stream) return SP_E_INVAL;
   SP_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = stream ? spi::as_stream(stream) : ctx->capture_stream;
   if (spi::capturing(s)) return SP_E_INVAL;
@@ -306,7 +348,7 @@ int sp_graph_begin(sp_ctx* ctx, void* stream, void** capture_stream) {
 }
 
 int sp_graph_end(sp_ctx* ctx, void* capture_stream, sp_graph** out) {
-  if (!ctx || !capture_stream || !out) return SP_E_INVAL;
+  if (!usable(ctx) || !capture_stream || !out) return SP_E_INVAL;
   *out = nullptr;
   hipStream_t s = spi::as_stream(capture_stream);
   hipGraph_t g = nullptr;
@@ -320,6 +362,7 @@ int sp_graph_end(sp_ctx* ctx, void* capture_stream, sp_graph** out) {
   }
   sp_graph* gr = new sp_graph();
   gr->ctx = ctx;
+  spi::ctx_ref(ctx);
   gr->g = g;
   gr->ge = ge;
   *out = gr;
@@ -339,10 +382,12 @@ int sp_graph_launch(sp_graph* gr, uint32_t replays, sp_stats* st, void* stream) 
 
 int sp_graph_destroy(sp_graph* gr) {
   if (!gr) return SP_E_INVAL;
-  (void)hipSetDevice(gr->ctx->device);
+  sp_ctx* ctx = gr->ctx;
+  (void)hipSetDevice(ctx->device);
   (void)hipGraphExecDestroy(gr->ge);
   (void)hipGraphDestroy(gr->g);
   delete gr;
+  spi::ctx_unref(ctx);
   return SP_OK;
 }
 

@@ -19,6 +19,7 @@ struct sp_barrier {
   uint32_t* d_near = nullptr;   // per-XCD blocks in measured chunks (flag_placement 0)
   uint64_t near_words = 0;
   uint32_t near_placed = 0;     // bits: 1 arrival blocks, 2 stamp copies, 4 release lines
+  bool counted = false;         // holds a reference on ctx (set once creation succeeded)
   sp::BarrierState st{};
 };
 
@@ -203,7 +204,7 @@ extern "C" {
 
 int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params* p,
                       sp_barrier** out) {
-  if (!ctx || !out || nwg == 0 || nwg > (1u << 16)) return SP_E_INVAL;
+  if (!spi::usable(ctx) || !out || nwg == 0 || nwg > (1u << 16)) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   if (kind == SP_BARRIER_DEFAULT) {
@@ -267,7 +268,6 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   s.groups = G;
   s.tgroups = std::min(G, nwg);
   s.fenced = q.coherent_cs ? 0u : 1u;
-  s.l1only = kind == SP_BARRIER_XCD && s.fenced && q.xcd_release == 1;
   s.xcopies = copies;
   s.xmstride = mstride;
   s.flag_stride = fs;
@@ -321,22 +321,27 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
       b->near_words = 0;
     }
   }
+  spi::ctx_ref(ctx);
+  b->counted = true;
   *out = b;
   return SP_OK;
 }
 
 int sp_barrier_destroy(sp_barrier* b) {
   if (!b) return SP_E_INVAL;
-  (void)hipSetDevice(b->ctx->device);
+  sp_ctx* ctx = b->ctx;
+  const bool counted = b->counted;
+  (void)hipSetDevice(ctx->device);
   (void)hipFree(b->d_state);
   (void)hipFree(b->d_slots);
   if (b->d_near) (void)hipFree(b->d_near);
   delete b;
+  if (counted) spi::ctx_unref(ctx);
   return SP_OK;
 }
 
 int sp_barrier_info_get(sp_barrier* b, sp_barrier_info* out) {
-  if (!b || !out) return SP_E_INVAL;
+  if (!b || !out || !spi::usable(b->ctx)) return SP_E_INVAL;
   sp_ctx* ctx = b->ctx;
   SP_HIP(ctx, hipSetDevice(ctx->device));
   memset(out, 0, sizeof(*out));
@@ -364,8 +369,8 @@ int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t
   if (!kern) return SP_E_INVAL;
   // Every workgroup must be resident at once (the barrier's persistent-threads
   // requirement, Section 5); refuse instead of hanging.
-  int per_cu = 0;
-  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  uint32_t per_cu = 0;
+  SP_CHECK(spi::resident_per_cu(ctx, kern, lanes, &per_cu));
   if ((uint64_t)per_cu * ctx->cu_count < b->nwg) return SP_E_NORESIDENT;
   // cooperative launches are not recorded: refuse before anything joins the capture
   const bool coop = b->kind == SP_BARRIER_GRID_SYNC || b->p.cooperative;
@@ -393,7 +398,8 @@ int sp_barrier_run_hash(sp_barrier* b, uint32_t lanes, uint32_t rounds, uint32_t
 int sp_barrier_run_hash_launches(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t rounds,
                                  uint32_t seed, uint32_t graph, uint32_t* slots,
                                  uint32_t* out_checksums, sp_stats* st, void* stream) {
-  if (!ctx || !slots || !out_checksums || nwg == 0 || nwg > (1u << 16) || !spi::lanes_ok(lanes))
+  if (!spi::usable(ctx) || !slots || !out_checksums || nwg == 0 || nwg > (1u << 16) ||
+      !spi::lanes_ok(lanes))
     return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));

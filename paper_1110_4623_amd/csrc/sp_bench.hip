@@ -150,7 +150,7 @@ __global__ void k_clock(uint64_t wall_ticks, unsigned long long* out) {
 // stores, completed into its XCD's L2), meets the others at a start counter, then times
 // `reps` fences of one kind: 0 = agent-scope release (write back the XCD's dirty L2 lines),
 // 1 = agent-scope acquire (invalidate the CU's L1 and the XCD's stale L2 lines),
-// 2 = workgroup-scope invalidate (the CU's L1 only).  out[4 w + 0] =
+// 2 = workgroup-scope invalidate.  out[4 w + 0] =
 // shader clocks for the reps, out[4 w + 1] / [4 w + 2] = wall clock at start / end.
 __global__ SP_FULL_OCCUPANCY void k_fence(uint32_t kind, uint32_t reps, uint32_t lines,
                                           uint32_t* scratch, uint32_t* start, uint32_t nwg,
@@ -169,7 +169,7 @@ __global__ SP_FULL_OCCUPANCY void k_fence(uint32_t kind, uint32_t reps, uint32_t
   for (uint32_t r = 0; r < reps; ++r) {
     if (kind == 0) sp::fence_release();
     else if (kind == 1) sp::fence_acquire();
-    else sp::invalidate_l1();
+    else sp::invalidate_workgroup_scope();
     __asm__ __volatile__("" ::: "memory");
   }
   const uint64_t c1 = sp::shader_clock(), w1 = sp::wall_clock();
@@ -249,7 +249,7 @@ int sp_bench_atomic(sp_ctx* ctx, uint32_t op, uint32_t nwg, uint32_t lanes, uint
                     uint32_t stride_bytes, uint32_t mode, uint64_t ops_per_issuer,
                     uint32_t seed, const uint32_t* perm, uint32_t* buf, uint64_t* out_sum,
                     sp_stats* st, void* stream) {
-  if (!ctx || !perm || !buf || !out_sum || nwg == 0 || T == 0 || !spi::lanes_ok(lanes) ||
+  if (!spi::usable(ctx) || !perm || !buf || !out_sum || nwg == 0 || T == 0 || !spi::lanes_ok(lanes) ||
       stride_bytes == 0 || stride_bytes % 4 || op > SP_OP_ST || mode > SP_ISSUE_WAVE_LEADER)
     return SP_E_INVAL;
   if ((uint64_t)nwg * lanes > 0xFFFFFFFFull) return SP_E_INVAL;
@@ -261,8 +261,8 @@ int sp_bench_atomic(sp_ctx* ctx, uint32_t op, uint32_t nwg, uint32_t lanes, uint
                      buf, T, sw, seed, hashed);
   SP_CHECK(spi::fill_u32(ctx, reinterpret_cast<uint32_t*>(out_sum), 2, 0, s));
   const void* kern = bench_kernel(op, mode);
-  int per_cu = 0;
-  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  uint32_t per_cu = 0;
+  SP_CHECK(spi::resident_per_cu(ctx, kern, lanes, &per_cu));
   SP_CHECK(spi::begin_timed(ctx, s));
   uint64_t n = ops_per_issuer;
   unsigned long long* sum = reinterpret_cast<unsigned long long*>(out_sum);
@@ -286,7 +286,7 @@ int sp_bench_atomic(sp_ctx* ctx, uint32_t op, uint32_t nwg, uint32_t lanes, uint
 int sp_bench_paper12(sp_ctx* ctx, uint32_t test, uint32_t nwg, uint32_t lanes, uint32_t n_ops,
                      uint32_t stride_bytes, uint32_t* buf, uint64_t* out_sum, sp_stats* st,
                      void* stream) {
-  if (!ctx || !buf || !out_sum || nwg == 0 || test > SP_P12_NONCONT_VOL_WRITE_AFTER_ATOM ||
+  if (!spi::usable(ctx) || !buf || !out_sum || nwg == 0 || test > SP_P12_NONCONT_VOL_WRITE_AFTER_ATOM ||
       !spi::lanes_ok(lanes) || stride_bytes == 0 || stride_bytes % 4)
     return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
@@ -294,9 +294,8 @@ int sp_bench_paper12(sp_ctx* ctx, uint32_t test, uint32_t nwg, uint32_t lanes, u
   const uint32_t sw = stride_bytes / 4;
   SP_CHECK(spi::fill_u32(ctx, buf, (uint64_t)nwg * sw, 0, s));
   SP_CHECK(spi::fill_u32(ctx, reinterpret_cast<uint32_t*>(out_sum), 2, 0, s));
-  int per_cu = 0;
-  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_paper12,
-                                                           (int)lanes, 0));
+  uint32_t per_cu = 0;
+  SP_CHECK(spi::resident_per_cu(ctx, (const void*)k_paper12, lanes, &per_cu));
   SP_CHECK(spi::begin_timed(ctx, s));
   hipLaunchKernelGGL(k_paper12, dim3(nwg), dim3(lanes), 0, s, test, n_ops, sw, 0u, buf,
                      reinterpret_cast<unsigned long long*>(out_sum));
@@ -305,7 +304,7 @@ int sp_bench_paper12(sp_ctx* ctx, uint32_t test, uint32_t nwg, uint32_t lanes, u
 
 int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, uint32_t reps,
                     uint64_t* out_sum, sp_stats* st, void* stream) {
-  if (!ctx || !buf || !out_sum || bytes == 0 || bytes % 16 || reps == 0) return SP_E_INVAL;
+  if (!spi::usable(ctx) || !buf || !out_sum || bytes == 0 || bytes % 16 || reps == 0) return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
   if (nwg == 0) nwg = ctx->cu_count * 8;
@@ -317,7 +316,7 @@ int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, 
 }
 
 int sp_bench_clock(sp_ctx* ctx, uint32_t ms, uint64_t* out, double* mhz, void* stream) {
-  if (!ctx || !out || !mhz || ms == 0 || ms > 10000) return SP_E_INVAL;
+  if (!spi::usable(ctx) || !out || !mhz || ms == 0 || ms > 10000) return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
   if (spi::capturing(s)) return SP_E_INVAL;  // waits and reads the result back
@@ -334,16 +333,15 @@ int sp_bench_clock(sp_ctx* ctx, uint32_t ms, uint64_t* out, double* mhz, void* s
 
 int sp_bench_fence(sp_ctx* ctx, uint32_t kind, uint32_t nwg, uint32_t lanes, uint32_t reps,
                    uint32_t lines, uint64_t* out, sp_stats* st, void* stream) {
-  if (!ctx || !out || kind > 2 || nwg == 0 || nwg > 65536 || !spi::lanes_ok(lanes) ||
+  if (!spi::usable(ctx) || !out || kind > 2 || nwg == 0 || nwg > 65536 || !spi::lanes_ok(lanes) ||
       reps == 0 || reps > 1000 || lines > 1024)
     return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
   if (spi::capturing(s)) return SP_E_INVAL;  // allocates its buffers
   // every workgroup waits for all others at the start counter: all must be resident
-  int per_cu = 0;
-  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fence,
-                                                           (int)lanes, 0));
+  uint32_t per_cu = 0;
+  SP_CHECK(spi::resident_per_cu(ctx, (const void*)k_fence, lanes, &per_cu));
   if ((uint64_t)per_cu * ctx->cu_count < nwg) return SP_E_NORESIDENT;
   const uint64_t scratch_words = (uint64_t)nwg * (lines ? lines : 1) * 32;
   spi::DeviceScratch scratch, start;
@@ -364,7 +362,7 @@ int sp_bench_fence(sp_ctx* ctx, uint32_t kind, uint32_t nwg, uint32_t lanes, uin
 
 int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint32_t reps,
                   sp_stats* st, void* stream) {
-  if (!ctx || !dst || !src || bytes == 0 || bytes % 16 || reps == 0) return SP_E_INVAL;
+  if (!spi::usable(ctx) || !dst || !src || bytes == 0 || bytes % 16 || reps == 0) return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
   const uint32_t nwg = ctx->cu_count * 8;
@@ -377,7 +375,7 @@ int sp_bench_copy(sp_ctx* ctx, void* dst, const void* src, uint64_t bytes, uint3
 
 int sp_bench_pingpong(sp_ctx* ctx, uint32_t rounds, uint32_t mode, uint32_t* words,
                       uint32_t* out, sp_stats* st, void* stream) {
-  if (!ctx || !words || !out || rounds == 0 ||
+  if (!spi::usable(ctx) || !words || !out || rounds == 0 ||
       (mode & ~(SP_PINGPONG_FENCED | SP_PINGPONG_SAME_XCD)) != 0)
     return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);

@@ -18,14 +18,16 @@ constexpr uint32_t kLine = 32;  // words per 128-byte line
 // into a ring of `capacity` words; the others take their share.  Only the leader touches
 // the buffer (plain loads and stores, ordered by the mutex); the whole workgroup takes
 // part in every mutex and condition-variable call.  res: 4 uint64 per workgroup = {xor of
-// values taken, sum of values taken, values taken or put, 0}.
+// values taken, sum of values taken, values taken or put, 0}.  taken (optional): consumer
+// i's j-th value goes to taken[first_i + j], first_i the start of its share.
 template <int MKIND>
 __global__ SP_FULL_OCCUPANCY void k_bounded_buffer(sp::MutexState m, sp::CondState not_full,
                                                    sp::CondState not_empty, uint32_t* bstate,
                                                    uint32_t* buf, uint32_t capacity,
                                                    uint32_t producers, uint64_t items,
                                                    uint32_t seed, unsigned long long* res,
-                                                   uint32_t* err, uint64_t timeout) {
+                                                   uint32_t* taken, uint32_t* err,
+                                                   uint64_t timeout) {
   const sp::Ctl ctl{err, sp::wall_clock() + timeout};
   __shared__ uint32_t s_blocked;
   const uint32_t b = blockIdx.x;
@@ -34,6 +36,8 @@ __global__ SP_FULL_OCCUPANCY void k_bounded_buffer(sp::MutexState m, sp::CondSta
   const uint32_t parts = prod ? producers : consumers;
   const uint32_t idx = prod ? b : b - producers;
   const uint64_t A = items / parts + (idx < items % parts ? 1 : 0);
+  // where this consumer records the values it takes: its share's place in [0, items)
+  const uint64_t first = (uint64_t)idx * (items / parts) + (idx < items % parts ? idx : items % parts);
   uint32_t* count = bstate + B_COUNT * kLine;
   uint32_t* head = bstate + B_HEAD * kLine;
   uint32_t* tail = bstate + B_TAIL * kLine;
@@ -70,6 +74,7 @@ __global__ SP_FULL_OCCUPANCY void k_bounded_buffer(sp::MutexState m, sp::CondSta
         *count = *count - 1;
         x ^= v;
         sum += v;
+        if (taken) taken[first + j] = v;
       }
       sp::cond_signal_leader(other);
     }
@@ -124,8 +129,9 @@ extern "C" {
 
 int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, uint32_t producers,
                                uint32_t lanes, uint32_t capacity, uint64_t items, uint32_t seed,
-                               const sp_params* p, uint64_t* out, sp_stats* st, void* stream) {
-  if (!ctx || !out || nwg < 2 || producers == 0 || producers >= nwg || !spi::lanes_ok(lanes) ||
+                               const sp_params* p, uint64_t* out, uint32_t* out_taken,
+                               sp_stats* st, void* stream) {
+  if (!spi::usable(ctx) || !out || nwg < 2 || producers == 0 || producers >= nwg || !spi::lanes_ok(lanes) ||
       capacity == 0 || capacity > (1u << 24) || items == 0 || items >= (1ull << 32))
     return SP_E_INVAL;
   const void* kern = bb_kernel(mutex_kind);
@@ -136,8 +142,8 @@ int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, u
   SP_HIP(ctx, hipSetDevice(ctx->device));
   if (spi::capturing(s)) return SP_E_INVAL;  // allocates its buffers
   // Producers and consumers wait for each other: all must be resident at once.
-  int per_cu = 0;
-  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  uint32_t per_cu = 0;
+  SP_CHECK(spi::resident_per_cu(ctx, kern, lanes, &per_cu));
   if ((uint64_t)per_cu * ctx->cu_count < nwg) return SP_E_NORESIDENT;
   const uint32_t sw = spi::stride_words(q);
   uint32_t Q = 64;
@@ -181,7 +187,7 @@ int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, u
   uint64_t timeout = spi::timeout_ticks(ctx, q);
   unsigned long long* resp = res;
   void* args[] = {&ms, &nf, &ne, &bstate, &buf, &capacity, &producers, &items, &seed, &resp,
-                  &ctx->d_err, &timeout};
+                  &out_taken, &ctx->d_err, &timeout};
   SP_HIP(ctx, hipLaunchKernel(kern, dim3(nwg), dim3(lanes), args, 0, s));
   int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, items);
   hipLaunchKernelGGL(k_bb_reduce, dim3(1), dim3(64), 0, s, res, nwg, producers, bstate,

@@ -15,6 +15,12 @@ struct sp_default_entry {
 };
 
 struct sp_ctx {
+  // Objects created from the context (barriers, mutexes, semaphores, graphs) hold a
+  // reference: sp_fini releases the context's device resources at once, but the struct
+  // itself lives until the last object is destroyed, so an object destroyed after
+  // sp_fini (as a garbage-collecting caller may do at exit) touches no freed memory.
+  int refs = 0;
+  bool closed = false;
   int device = 0;
   hipDeviceProp_t prop{};
   int last_hip = 0;
@@ -47,6 +53,15 @@ namespace spi {
   } while (0)
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// A context that can still run work (not NULL, not finalized).
+inline bool usable(const sp_ctx* ctx) { return ctx && !ctx->closed; }
+// Object lifetime: every create that succeeds takes a reference, every destroy drops it;
+// the last drop after sp_fini deletes the context.
+inline void ctx_ref(sp_ctx* ctx) { ++ctx->refs; }
+inline void ctx_unref(sp_ctx* ctx) {
+  if (--ctx->refs == 0 && ctx->closed) delete ctx;
+}
 
 // Normalized parameters (defaults filled, ranges clamped); returns SP_E_INVAL on bad
 // values.
@@ -83,6 +98,11 @@ int begin_timed(sp_ctx* ctx, hipStream_t s);
 // zeroes st and returns SP_OK).
 int end_timed(sp_ctx* ctx, hipStream_t s, sp_stats* st, uint32_t nwg, uint32_t lanes,
               uint32_t resident_per_cu, uint64_t ops);
+
+// Workgroups of `kern` (launched with `lanes` threads) that fit on one CU at once: the
+// runtime's occupancy figure checked against the kernel's own VGPR and LDS use
+// (sp_resident_per_cu).
+int resident_per_cu(sp_ctx* ctx, const void* kern, uint32_t lanes, uint32_t* per_cu);
 
 inline bool lanes_ok(uint32_t lanes) { return lanes >= 64 && lanes <= 1024 && lanes % 64 == 0; }
 

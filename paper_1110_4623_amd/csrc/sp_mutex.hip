@@ -87,7 +87,7 @@ extern "C" {
 
 int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_per_lock,
                     const sp_params* p, sp_mutex** out) {
-  if (!ctx || !out || nlocks == 0 || words_per_lock == 0 || nlocks > (1u << 20) ||
+  if (!spi::usable(ctx) || !out || nlocks == 0 || words_per_lock == 0 || nlocks > (1u << 20) ||
       words_per_lock > (1u << 16))
     return SP_E_INVAL;
   if (kind > SP_MUTEX_COHORT && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
@@ -131,17 +131,20 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
     delete m;
     return SP_E_HIP;
   }
+  spi::ctx_ref(ctx);
   *out = m;
   return SP_OK;
 }
 
 int sp_mutex_destroy(sp_mutex* m) {
   if (!m) return SP_E_INVAL;
-  hipSetDevice(m->ctx->device);
-  hipFree(m->d_state);
-  hipFree(m->d_words);
-  if (m->d_queue) hipFree(m->d_queue);
+  sp_ctx* ctx = m->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipFree(m->d_state);
+  (void)hipFree(m->d_words);
+  if (m->d_queue) (void)hipFree(m->d_queue);
   delete m;
+  spi::ctx_unref(ctx);
   return SP_OK;
 }
 
@@ -208,8 +211,8 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
   }
   SP_CHECK(spi::fill_u32(ctx, m->d_state, m->state_words, 0, s));
   SP_CHECK(spi::fill_u32(ctx, m->d_words, (uint64_t)m->nlocks * m->wstride, 0, s));
-  int per_cu = 0;
-  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  uint32_t per_cu = 0;
+  SP_CHECK(spi::resident_per_cu(ctx, kern, lanes, &per_cu));
   SP_CHECK(spi::begin_timed(ctx, s));
   uint64_t timeout = spi::timeout_ticks(ctx, q);
   uint32_t nlocks = m->nlocks, W = m->W, wstride = m->wstride;

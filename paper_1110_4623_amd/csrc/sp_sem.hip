@@ -12,22 +12,36 @@ struct sp_sem {
   sp_params p{};
   uint32_t* d_state = nullptr;
   uint64_t state_words = 0;
+  uint32_t* d_owner = nullptr;  // K <= kMaxPool: owner word of each pool slot, kOwnerWords apart
 };
 
 namespace {
 
 // Line indices of the semaphore state (each line `stride` words).
 enum { L_S = 0, L_COUNT, L_TICKET, L_TURN, L_OCC, L_MAXOCC, L_ADM, L_PRIVATE, L_LINES };
+// Guarded data: a pool of K slots for K <= kMaxPool, owner words 32 bytes apart.
+constexpr uint32_t kMaxPool = 4096;
+constexpr uint32_t kOwnerWords = 8;
 
+// The wait/hold/post workload.  With `data` (K uint32 words, packed, plain memory) every
+// holder also updates guarded data: for K = 1 the semaphore is a mutex and the data is
+// the one word, ordered by the semaphore's own acquire and release; for K > 1 the holder
+// claims a free slot of a pool of K (compare-and-swap on the slot's owner word, then the
+// acquire the hand-over of the slot needs), and returns it with a release before it posts.
+// The update is a plain load and store by the workgroup's last thread (another wavefront
+// than the leader's when lanes > 64), so the totals are exact only if the fences order it.
 template <int KIND, bool FENCED>
 __global__ SP_FULL_OCCUPANCY void k_sem(sp::SemState s, uint32_t stride, uint32_t* state, uint32_t nwg,
                       uint64_t total, uint32_t max_hold, uint32_t seed, uint32_t track,
-                      uint32_t* chk, uint32_t* err, uint64_t timeout) {
+                      uint32_t* chk, uint32_t* data, uint32_t* owner, uint32_t* err,
+                      uint64_t timeout) {
   const sp::Ctl ctl{err, sp::wall_clock() + timeout};
+  __shared__ uint32_t s_slot;
   const uint32_t b = blockIdx.x;
   const uint64_t A = total / nwg + (b < total % nwg ? 1 : 0);
   uint32_t* occ = state + L_OCC * stride;
   uint32_t* maxocc = state + L_MAXOCC * stride;
+  const bool pool = data && s.K > 1;
   uint32_t c = 0;
   sp::SemHold sh{0};  // the adaptive kind's learned post interval, kept across waits
   for (uint64_t j = 0; j < A; ++j) {
@@ -36,8 +50,40 @@ __global__ SP_FULL_OCCUPANCY void k_sem(sp::SemState s, uint32_t stride, uint32_
     if (sp::is_leader()) {
       if (track) sp::max_relaxed(maxocc, sp::add_relaxed(occ, 1) + 1);
       c ^= sp::sm32(seed ^ (b << 16) ^ (uint32_t)j);
+      uint32_t slot = 0;
+      if (pool) {
+        // at most K holders, so some slot is free; start where the schedule says
+        sp::Wait w(ctl, 0);
+        slot = sp::sched_key(seed, b, (uint32_t)j, 4) % s.K;
+        while (sp::cas_relaxed(owner + (size_t)slot * kOwnerWords, 0, b + 1) != 0) {
+          slot = slot + 1 == s.K ? 0 : slot + 1;
+          if (!w.tick()) {
+            slot = s.K;
+            break;
+          }
+        }
+        if constexpr (FENCED) sp::fence_acquire();
+      }
+      s_slot = slot;
+    }
+    __syncthreads();
+    const uint32_t slot = s_slot;
+    if (slot >= s.K) return;  // the watchdog ended the run
+    if (data && threadIdx.x == blockDim.x - 1) {
+      if constexpr (FENCED) data[slot] = data[slot] + 1;
+      else sp::st_relaxed(data + slot, sp::ld_relaxed(data + slot) + 1);
+    }
+    if (sp::is_leader()) {
       sp::spin_cycles(hold);
       if (track) sp::add_relaxed(occ, 0xFFFFFFFFu);
+    }
+    if (pool) {
+      sp::wave_stores_complete();
+      __syncthreads();
+      if (sp::is_leader()) {
+        if constexpr (FENCED) sp::st_release(owner + (size_t)slot * kOwnerWords, 0);
+        else sp::st_relaxed(owner + (size_t)slot * kOwnerWords, 0);
+      }
     }
     if (!sp::sem_post<KIND, FENCED>(s, ctl)) return;
   }
@@ -60,9 +106,8 @@ __global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg
   }
 }
 
-// The critical section of this workload touches only registers and agent-scope atomics,
-// so it is correct with or without the fences; FENCED = false is the variant for
-// critical sections that access their data coherently.
+// FENCED = false is the variant for critical sections that access their data coherently
+// (agent-scope loads and stores of the guarded data).
 template <bool FENCED>
 const void* sem_kernel_f(uint32_t kind) {
   switch (kind) {
@@ -85,7 +130,7 @@ const void* sem_kernel(uint32_t kind, bool coherent_cs) {
 extern "C" {
 
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out) {
-  if (!ctx || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
+  if (!spi::usable(ctx) || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
   if (kind > SP_SEM_ADAPTIVE && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
@@ -98,29 +143,37 @@ int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp
   s->p = q;
   s->state_words = (uint64_t)L_LINES * 1024;  // room for the widest padding
   hipError_t e = hipMalloc(&s->d_state, s->state_words * sizeof(uint32_t));
+  if (e == hipSuccess && K <= kMaxPool)
+    e = hipMalloc(&s->d_owner, (size_t)K * kOwnerWords * sizeof(uint32_t));
   if (e != hipSuccess) {
     ctx->last_hip = (int)e;
+    (void)hipFree(s->d_state);
     delete s;
     return SP_E_HIP;
   }
+  spi::ctx_ref(ctx);
   *out = s;
   return SP_OK;
 }
 
 int sp_sem_destroy(sp_sem* s) {
   if (!s) return SP_E_INVAL;
-  hipSetDevice(s->ctx->device);
-  hipFree(s->d_state);
+  sp_ctx* ctx = s->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipFree(s->d_state);
+  if (s->d_owner) (void)hipFree(s->d_owner);
   delete s;
+  spi::ctx_unref(ctx);
   return SP_OK;
 }
 
 int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
                uint32_t max_hold_cyc, uint32_t seed, uint32_t track, uint32_t* out_chk,
-               uint32_t* out_state, sp_stats* st, void* stream) {
+               uint32_t* out_state, uint32_t* out_data, sp_stats* st, void* stream) {
   if (!sem || !out_chk || !out_state || nwg == 0 || !spi::lanes_ok(lanes) ||
       max_hold_cyc == 0xFFFFFFFFu || total_pairs >= (1ull << 32))
     return SP_E_INVAL;
+  if (out_data && sem->K > kMaxPool) return SP_E_INVAL;
   sp_ctx* ctx = sem->ctx;
   hipStream_t s = spi::as_stream(stream);
   SP_HIP(ctx, hipSetDevice(ctx->device));
@@ -151,15 +204,20 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   ss.bo = spi::backoff_cfg(q, base + L_PRIVATE * sw);
   ss.post_backoff = q.post_backoff;
   SP_CHECK(spi::fill_u32(ctx, base, sem->state_words, 0, s));
+  if (out_data) {
+    SP_CHECK(spi::fill_u32(ctx, out_data, sem->K, 0, s));
+    if (sem->K > 1) SP_CHECK(spi::fill_u32(ctx, sem->d_owner, (uint64_t)sem->K * kOwnerWords, 0, s));
+  }
+  uint32_t* owner = sem->d_owner;
   if (kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF)
     SP_CHECK(spi::fill_u32(ctx, ss.S, 1, sem->K + 1, s));  // Algorithm 4: S = K + 1
-  int per_cu = 0;
-  SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)lanes, 0));
+  uint32_t per_cu = 0;
+  SP_CHECK(spi::resident_per_cu(ctx, kern, lanes, &per_cu));
   SP_CHECK(spi::begin_timed(ctx, s));
   uint64_t timeout = spi::timeout_ticks(ctx, q);
   uint32_t stride = sw;
   void* args[] = {&ss, &stride, &base, &nwg, &total_pairs, &max_hold_cyc, &seed, &track,
-                  &out_chk, &ctx->d_err, &timeout};
+                  &out_chk, &out_data, &owner, &ctx->d_err, &timeout};
   SP_HIP(ctx, hipLaunchKernel(kern, dim3(nwg), dim3(lanes), args, 0, s));
   int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, total_pairs);
   const uint32_t alg4 = kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF;

@@ -324,7 +324,7 @@ void summarize(const Observer& ob, uint64_t t0, const double* t_arr, uint32_t n,
 int serve(sp_ctx* ctx, const sp_serve_cfg* cfg_in, uint32_t n, const uint32_t* L,
           const uint64_t* nbytes, const double* t_arr, uint32_t* out, double* lat_us,
           sp_serve_result* res, bool persistent) {
-  if (!ctx || !L || !nbytes || !t_arr || !out || !res) return SP_E_INVAL;
+  if (!spi::usable(ctx) || !L || !nbytes || !t_arr || !out || !res) return SP_E_INVAL;
   if (n == 0 || n >= (1u << 31)) return SP_E_INVAL;
   Cfg c;
   SP_CHECK(normalize_cfg(cfg_in, &c));
@@ -381,9 +381,8 @@ int serve(sp_ctx* ctx, const sp_serve_cfg* cfg_in, uint32_t n, const uint32_t* L
   ob.t_done.assign(n, 0);
 
   if (persistent) {
-    int per_cu = 0;
-    SP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_serve,
-                                                             (int)c.lanes, 0));
+    uint32_t per_cu = 0;
+    SP_CHECK(spi::resident_per_cu(ctx, (const void*)k_serve, c.lanes, &per_cu));
     if ((uint64_t)per_cu * ctx->cu_count < c.nwg) return SP_E_NORESIDENT;
     ServeArgs a;
     a.st = b.d_state;

@@ -14,7 +14,8 @@ def _declared():
     for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
         if h.endswith(".h"):
             text = open(os.path.join(ROOT, "include", h)).read()
-            names += re.findall(r"^(?:int|void|const char\*)\s+(sp_\w+)\(", text, re.M)
+            names += re.findall(r"^(?:int|void|uint32_t|const char\*)\s+(sp_\w+)\(", text,
+                                re.M)
     return names
 
 
@@ -70,7 +71,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     from paper_1110_4623_amd import _native as N
     structs = {"sp_params": N.Params, "sp_stats": N.Stats, "sp_device_info": N.DeviceInfo,
                "sp_serve_cfg": N.ServeCfg, "sp_serve_result": N.ServeResult,
-               "sp_barrier_info": N.BarrierInfo}
+               "sp_barrier_info": N.BarrierInfo, "sp_occupancy": N.Occupancy}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "sp.h"', "int main(void) {"]
     for cname, py in structs.items():
         src.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
@@ -110,7 +111,7 @@ def test_newer_entry_points_reject_bad_arguments_without_gpu():
     lib.sp_params_default(ctypes.byref(p))
     # no context / no output / no consumers: argument errors before any HIP call
     assert lib.sp_cond_run_bounded_buffer(None, 3, 4, 2, 64, 8, 100, 1, ctypes.byref(p), None,
-                                          ctypes.byref(st), None) == N.SP_E_INVAL
+                                          None, ctypes.byref(st), None) == N.SP_E_INVAL
     g = ctypes.c_void_p()
     assert lib.sp_graph_begin(None, None, ctypes.byref(g)) == N.SP_E_INVAL
     assert lib.sp_graph_end(None, None, ctypes.byref(g)) == N.SP_E_INVAL
@@ -155,3 +156,37 @@ def test_pingpong_offset_must_be_whole_lines():
     for bad in (-128, 100, 4095):
         with pytest.raises(ValueError):
             sp.pingpong(None, 10, offset_bytes=bad)
+
+
+def _resident(runtime, vgprs, lds, lanes):
+    import ctypes
+    from paper_1110_4623_amd import _native as N
+    o = N.Occupancy(runtime_per_cu=runtime, vgprs=vgprs, lds_bytes=lds, lanes=lanes)
+    return N.lib.sp_resident_per_cu(ctypes.byref(o))
+
+
+def test_residency_takes_the_smaller_of_runtime_and_own_budget():
+    """A fake occupancy provider: the runtime's figure is trusted only as far as the
+    kernel's own VGPR and LDS use allows (8 waves and 512 VGPRs per SIMD, 4 SIMDs,
+    160 KiB of LDS per CU)."""
+    import ctypes
+    from paper_1110_4623_amd import _native as N
+    # 256 lanes = 4 wavefronts, one per SIMD: 8 workgroups per CU when registers allow
+    assert _resident(8, 64, 0, 256) == 8
+    # the runtime over-reports: 72 VGPRs leave 512 // 72 = 7 waves per SIMD
+    assert _resident(8, 72, 0, 256) == 7
+    # 2048 workgroups of 256 lanes then do not fit 256 CUs: a run refuses
+    assert _resident(8, 72, 0, 256) * 256 < 2048
+    # VGPRs round up to granules of 8: 65 counts as 72
+    assert _resident(8, 65, 0, 256) == 7
+    # LDS: 48 KiB per workgroup leaves 3 per CU; 40000 B rounds up to 40448 -> 4
+    assert _resident(8, 32, 48 * 1024, 256) == 3
+    assert _resident(8, 32, 40000, 256) == 4
+    # one-wave workgroups: 4 SIMDs x 8 waves, capped by the runtime
+    assert _resident(32, 32, 0, 64) == 32
+    assert _resident(20, 32, 0, 64) == 20
+    # 1024 lanes = 16 wavefronts: 2 per CU at 8 waves per SIMD
+    assert _resident(2, 32, 0, 1024) == 2
+    assert _resident(0, 32, 0, 256) == 0
+    assert _resident(8, 32, 0, 0) == 0
+    assert N.lib.sp_resident_per_cu(None) == 0

@@ -47,5 +47,37 @@ def test_one_step_prints_the_contract_line():
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in r, k
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-2)
+    assert r["bound"] == "latency" and r["bound_terms"]["hops"] == 3
+    assert r["peak"] == pytest.approx(1.0 / r["bound_terms"]["floor_us"], rel=1e-3)
+    assert r["kernel_boundary_us_per_round"] > 0
+    card = m["machine_card_2048wg"]
+    for name in ("atomic_to_volatile_contentious", "contentious_to_noncontentious_volatile",
+                 "volatile_after_atomic_to_volatile"):
+        assert card[name]["read"] > 0 and card[name]["write"] > 0, name
+    for k in ("A1_contended_atomics_per_s", "A_dist_atomics_per_s_2p20_words",
+              "B_stream_read_GB_per_s", "L_coh_one_way_us"):
+        assert m["ceilings"][k] > 0, k
+    assert m["central_barrier_16wg_x64_1000_rounds_us_per_round"] > 0
+    assert m["central_barrier_16wg_checksums_deterministic"] is True
     assert d["env"]["arch"].startswith("gfx950")
     assert "packed-fp32-ops" in d["env"]["hipcc_flags"]
+
+
+def test_cpu_baseline_leg_checks_checksums_against_the_oracle():
+    """The oracle leg of bench.py (CPU only): it times the threaded per-XCD protocol and
+    compares the run's checksums with the closed form, element by element."""
+    import importlib.util
+    import numpy as np
+    import oracle
+    spec = importlib.util.spec_from_file_location("_bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    ref = oracle.barrier_closed(42, bench.NWG, bench.ROUNDS)
+    ref1 = oracle.barrier_closed(42, bench.C1_NWG, bench.C1_ROUNDS)
+    d = bench.cpu_baseline(ref, ref1, budget_s=0.5)
+    assert d["ok"] and d["kind"] == "oracle" and d["cores"] >= 1 and d["value"] > 0
+    assert d["headline_checksums_match_oracle"] and d["config1_checksums_match_oracle"]
+    bad = ref.copy()
+    bad[7] ^= 1
+    d = bench.cpu_baseline(bad, ref1, budget_s=0.5)
+    assert not d["headline_checksums_match_oracle"]

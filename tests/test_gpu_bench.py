@@ -39,6 +39,8 @@ def test_exchange_conservation(ctx, mode, T):
     U = nwg * lanes if mode == "per_lane" else nwg * (lanes // 64)
     _, conserved = oracle.bench_closed("exch", seed, U, n, perm_np)
     assert s == conserved
+    # every final word is its initial value or a value written to it
+    assert oracle.exch_finals_invalid(seed, U, n, perm_np, finals) == 0
 
 
 def test_full_size_add_sampled(ctx):
@@ -122,6 +124,7 @@ def test_config_grid_at_full_width(ctx, op, mode, nwg):
                                            buf)
             if op == "exch":
                 assert s == es  # conservation: returned + final = initial + written
+                assert oracle.exch_finals_invalid(seed, U, n, perm_np, finals) == 0
             else:
                 assert (finals == ef).all(), (T, stride)
                 if op != "st":
@@ -156,7 +159,7 @@ def test_fence_bad_arguments(ctx):
     from paper_1110_4623_amd import _native as N
     out = ctx.zeros(8, "u64")
     st = N.Stats()
-    for kind, nwg, reps, lines in ((2, 1, 1, 1), (0, 0, 1, 1), (0, 1, 0, 1), (1, 1, 1, 2000)):
+    for kind, nwg, reps, lines in ((3, 1, 1, 1), (0, 0, 1, 1), (0, 1, 0, 1), (1, 1, 1, 2000)):
         rc = N.lib.sp_bench_fence(ctx.h, kind, nwg, 64, reps, lines, ctx.ptr(out),
                                   ctypes.byref(st), ctx.stream())
         assert rc == N.SP_E_INVAL

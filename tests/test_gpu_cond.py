@@ -2,6 +2,7 @@
 producers put (xor and sum against the oracle's closed form), the ring never holds more
 than its capacity, and it ends empty."""
 
+import numpy as np
 import pytest
 
 import oracle
@@ -14,13 +15,17 @@ def _run(ctx, kind, nwg, producers, cap, items, seed, lanes=64, **params):
     import paper_1110_4623_amd as sp
     announce("bounded buffer", kind, f"nwg={nwg} producers={producers} cap={cap} items={items}",
              params)
-    return sp.bounded_buffer(ctx, kind, nwg, producers, cap, items, seed, lanes=lanes, **params)
+    return sp.bounded_buffer(ctx, kind, nwg, producers, cap, items, seed, lanes=lanes,
+                             values=True, **params)
 
 
 def _check(r, producers, cap, items, seed):
     assert (r["xor"], r["sum"]) == oracle.bb_closed(seed, producers, items)
     assert r["taken"] == r["put"] == items and r["left"] == 0
     assert 1 <= r["max_count"] <= cap
+    # value by value: the multiset taken is exactly the multiset put (which consumer took
+    # which value is not unique, so both sides are compared sorted)
+    assert (np.sort(r["values"]) == np.sort(oracle.bb_values(seed, producers, items))).all()
 
 
 @pytest.mark.parametrize("kind", ["ticket", "array", "sleep", "spin_cas", "cohort"])

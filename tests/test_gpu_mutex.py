@@ -53,11 +53,12 @@ def test_full_size_single_lock(ctx, kind):
     assert (words == total).all()
 
 
-@pytest.mark.parametrize("kind", ["spin_backoff", "ticket", "array", "ring", "cohort"])
+@pytest.mark.parametrize("kind", ["spin_cas", "spin_backoff", "sleep", "ticket", "array", "ring",
+                                  "cohort"])
 @pytest.mark.parametrize("L,W", [(16, 256), (256, 16)])
 def test_full_size_many_locks(ctx, kind, L, W):
     total, seed = 1 << 20, 42
-    words, _, _ = _run(ctx, kind, 2048, 256, total, L, W, 1000, seed)
+    words, _, _ = _run(ctx, kind, 2048, 256, total, L, W, 1000, seed, timeout_ms=60000)
     assert (words == oracle.mutex_closed(seed, 2048, total, L, W)).all()
 
 

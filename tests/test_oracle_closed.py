@@ -226,3 +226,30 @@ def test_bench_exch_conservation_threaded(T):
     for t in range(T):
         if int(tf[t]) != oracle.prefill(42, t):
             assert int(tf[t]) in written
+
+
+@pytest.mark.parametrize("T", [1, 32, 1000])
+def test_exchange_finals_validity(T):
+    """Threaded exchanges leave every word at its initial value or at a value written to
+    it; a planted foreign value is caught."""
+    perm = sp_inputs.permutation(T, 42)
+    U, n = 64, 300
+    tf, _, _ = oracle.bench_threaded("exch", 42, U, n, perm, threads=8)
+    assert oracle.exch_finals_invalid(42, U, n, perm, tf) == 0
+    bad = tf.copy()
+    bad[0] ^= 0x5A5A5A5A
+    assert oracle.exch_finals_invalid(42, U, n, perm, bad) == 1
+    # untouched words must keep their initial value
+    assert oracle.exch_finals_invalid(42, 1, 1, perm, np.array(
+        [oracle.prefill(42, t) for t in range(T)], dtype=np.uint32)) == 0
+
+
+def test_bounded_buffer_values_match_the_closed_form():
+    v = oracle.bb_values(3, 5, 1001)
+    x = 0
+    for a in map(int, v):
+        x ^= a
+    assert (x, int(v.astype(np.uint64).sum())) == oracle.bb_closed(3, 5, 1001)
+    rows = [r for r in _rows("workload_vectors.txt") if r[0] == "bb"]
+    v = oracle.bb_values(0, 2, 3)
+    assert sorted(map(int, v)) == sorted([0x92ca2f0e, 0x96a0f96b, 0x5032e8f1])

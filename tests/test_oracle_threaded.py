@@ -50,8 +50,8 @@ def test_cohort_mutex_threaded_with_local_passes(L):
     assert (words == oracle.mutex_closed(seed, nwg, total, L, 8)).all()
 
 
-@pytest.mark.parametrize("kind", ["spin", "spin_backoff", "ticket", "sleep", "counters",
-                                  "adaptive"])
+@pytest.mark.parametrize("kind", ["spin", "spin_backoff", "spin_backoff_wait_only", "ticket",
+                                  "sleep", "counters", "adaptive"])
 @pytest.mark.parametrize("K", [1, 2, 4, 32])
 def test_sem_threaded_invariants(kind, K):
     seed, nwg, total = 7, 12, 2400
@@ -69,6 +69,20 @@ def test_sem_threaded_invariants(kind, K):
         assert s_or_count == 0 and ticket == turn
         if K >= nwg:
             assert ticket == 0  # nobody ever queues
+
+
+@pytest.mark.parametrize("K", [1, 32])
+def test_spin_semaphore_posts_do_not_starve_at_2048_agents(K):
+    """Algorithm 4 with 2048 agents: with backoff in wait only (Section 5's prose) every
+    pair completes, and a post fails far less often per pair than a wait does -- posts are
+    not starved by the waiters' exchanges on the one word S."""
+    seed, nwg, total = 42, 2048, 1 << 13
+    r = oracle.sem_threaded("spin_backoff_wait_only", K, seed, nwg, total, imin=1, imax=64)
+    assert r["rc"] == 0 and r["maxocc"] <= K
+    assert (r["chk"] == oracle.sem_closed(seed, nwg, total)).all()
+    s, wait_fails, post_fails, admissions = r["state"]
+    assert s == K + 1 and admissions == total
+    assert post_fails <= max(wait_fails, 1)
 
 
 def test_hardware_threads_reported():
