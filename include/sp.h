@@ -76,13 +76,18 @@ enum sp_mutex_kind {
                              /* times in a row) without the L2 writeback, which only a  */
                              /* hand-over to another XCD needs.  State: 32 padded lines */
                              /* per lock (sp_mutex_run refuses more than 2^28 words)    */
+  SP_MUTEX_MCS = 9,          /* MCS queue lock: a linked queue of per-workgroup nodes;  */
+                             /* each waiter polls only its own node; unlock hands over  */
+                             /* to the successor or frees the tail with a CAS.  State:  */
+                             /* one padded node per lock and workgroup of the run       */
   SP_MUTEX_DEFAULT = 15
 };
 
 /* Semaphores (Section 5, Semaphore; Algorithms 4-5).                                   */
 enum sp_sem_kind {
   SP_SEM_SPIN = 0,         /* exchange-based spin semaphore (Algorithm 4)              */
-  SP_SEM_SPIN_BACKOFF = 1, /* Algorithm 4 with backoff                                  */
+  SP_SEM_SPIN_BACKOFF = 1, /* Algorithm 4 with backoff (sp_params.backoff NONE: exponential */
+                           /* up to max(backoff_max, 8192) units); post_backoff below     */
   SP_SEM_TICKET = 2,       /* fetch-and-add semaphore, plain polling (Algorithm 5)      */
   SP_SEM_SLEEP = 3,        /* Algorithm 5, queued waiters s_sleep between polls         */
   SP_SEM_COUNTERS = 4,     /* two monotone counters: wait draws a ticket t (fetch-and-  */

@@ -50,6 +50,12 @@ __device__ __forceinline__ uint64_t* cohort_grant(const MutexState& s, uint32_t 
   return reinterpret_cast<uint64_t*>(s.queue + line * s.qstride);
 }
 
+// MCS lock node of workgroup w for `lock`: word 0 = next (workgroup + 1, 0 = none), word 1
+// = locked; qlen nodes per lock (one per workgroup of the launch), qstride words apart.
+__device__ __forceinline__ uint32_t* mcs_node(const MutexState& s, uint32_t lock, uint32_t w) {
+  return s.queue + ((size_t)lock * s.qlen + w) * s.qstride;
+}
+
 // KIND:
 //   SP_MUTEX_SPIN_CAS     compare-and-swap 0 -> 1 until it succeeds (backoff if configured)
 //   SP_MUTEX_SPIN_EXCH    exchange with 1 until the old value is 0 (Algorithm 1; with a
@@ -83,6 +89,14 @@ __device__ __forceinline__ uint64_t* cohort_grant(const MutexState& s, uint32_t 
 //                         grants the local turn with session 0.  Cohorts are the actual
 //                         XCDs (XCC id), never merged: the local hand-over relies on the
 //                         shared L2.
+//   SP_MUTEX_MCS          MCS queue lock: each workgroup has a node per lock (next, locked)
+//                         in its own line; lock stores next = none and locked = 1, then
+//                         exchanges the lock word (the queue's tail) with its node id;
+//                         behind a predecessor it links in (predecessor.next = me) and
+//                         polls only its own locked word.  Unlock hands the lock to the
+//                         successor (its locked = 0), or, when none has linked in,
+//                         swings the tail back to free with a compare-and-swap (waiting
+//                         for a successor whose exchange came first to link in).
 //   SP_MUTEX_ADAPTIVE     ticket mutex with proportional waiting tuned online (Section 5's
 //                         aggressive lock that reverts to backoff): a waiter d tickets from
 //                         the head sleeps about (d - 1) / 4 hand-over times before polling
@@ -103,7 +117,7 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
   if (is_leader()) {
     uint32_t* m = s.lockw + (size_t)lock * s.stride;
     Wait w(ctl, (KIND == SP_MUTEX_SLEEP || KIND == SP_MUTEX_RING || KIND == SP_MUTEX_ARRAY ||
-                 KIND == SP_MUTEX_COHORT)
+                 KIND == SP_MUTEX_COHORT || KIND == SP_MUTEX_MCS)
                     ? s.poll_sleep : 0);
     Backoff bo(s.bo);
     bool ok = true;
@@ -194,6 +208,17 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
         hold->session = k;
         hold->global = g;
       }
+    } else if constexpr (KIND == SP_MUTEX_MCS) {
+      uint32_t* node = mcs_node(s, lock, blockIdx.x);
+      st_relaxed(node, 0);      // next: none
+      st_relaxed(node + 1, 1);  // locked
+      wave_stores_complete();   // both land before the exchange makes the node reachable
+      const uint32_t prev = exch_relaxed(m, blockIdx.x + 1);
+      if (prev != 0) {
+        st_relaxed(mcs_node(s, lock, prev - 1), blockIdx.x + 1);  // predecessor.next = me
+        while (ld_relaxed(node + 1) != 0)
+          if (!(ok = w.tick())) break;
+      }
     } else if constexpr (KIND == SP_MUTEX_ARRAY) {
       const uint32_t t = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
       const uint32_t* slot =
@@ -217,9 +242,29 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
 
 // `hold`: the record mutex_lock filled in (leader's copy).  It may be nullptr except for
 // SP_MUTEX_ARRAY and SP_MUTEX_COHORT: the ticket and ring mutexes then load turn / head
-// to find the value to publish.
+// to find the value to publish.  `ctl` bounds SP_MUTEX_MCS's wait for a successor that
+// has taken the tail but not linked in yet (no other kind waits in unlock).
 template <int KIND, bool FENCED = true>
-__device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold* hold = nullptr) {
+__device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold* hold = nullptr,
+                             const Ctl* ctl = nullptr) {
+  if constexpr (KIND == SP_MUTEX_MCS) {
+    wave_stores_complete();
+    __syncthreads();
+    if (!is_leader()) return;
+    uint32_t* node = mcs_node(s, lock, blockIdx.x);
+    uint32_t* tail = s.lockw + (size_t)lock * s.stride;
+    if constexpr (FENCED) fence_release();  // before either hand-over
+    uint32_t next = ld_relaxed(node);
+    if (next == 0) {
+      if (cas_relaxed(tail, blockIdx.x + 1, 0) == blockIdx.x + 1) return;  // nobody queued
+      // a successor took the tail after us: it links in within a round trip
+      Wait w(ctl ? *ctl : Ctl{nullptr, 0}, 0);
+      while ((next = ld_relaxed(node)) == 0)
+        if (ctl && !w.tick()) return;
+    }
+    st_relaxed(mcs_node(s, lock, next - 1) + 1, 0);  // successor.locked = 0
+    return;
+  }
   if constexpr (KIND == SP_MUTEX_COHORT) {
     // The local ticket count is loaded first so that its round trip overlaps the wait
     // for the critical section's stores.

@@ -373,6 +373,104 @@ class CohortLockModel:
         return None
 
 
+class MCSLockModel:
+    """MCS queue lock (a linked queue of per-waiter nodes; each waiter polls a word of its
+    own node).  Node a+1 belongs to agent a; 0 is "none".  tail is the lock word.
+    lock:   my.next = 0; my.locked = 1; prev = exchange(tail, me);
+            if prev: prev.next = me, then poll my.locked until 0.
+    unlock: if my.next == 0: if compare-and-swap(tail, me -> 0) succeeds, done;
+            otherwise poll my.next until it is set; then successor.locked = 0.
+    mutant 'no_wait_for_next': a failed compare-and-swap returns without handing over;
+    mutant 'link_before_init': my.locked = 1 is stored after linking into prev.next;
+    mutant 'store_tail': unlock clears tail with a plain store instead of the
+    compare-and-swap when next reads 0;
+    mutant 'no_spin': a waiter with a predecessor enters once it has linked in."""
+
+    (INIT_N, INIT_L, XCHG, LINK, SPIN, CS_IN, CS_LD, CS_ST, CS_OUT, REL_RD, REL_CAS,
+     REL_WAIT, REL_GO, LATE_L, DONE) = range(15)
+
+    def __init__(self, n: int = 3, ops: int = 2, mutant: str | None = None):
+        self.n, self.ops, self.mutant = n, ops, mutant
+
+    def init(self):
+        # shared = (tail, next (n), locked (n), data, inside, entries); local = (pc, j, tmp, prev)
+        n = self.n
+        return (0, (0,) * n, (0,) * n, 0, 0, 0), tuple((self.INIT_N, 0, 0, 0) for _ in range(n))
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    @staticmethod
+    def _set(tup, i, v):
+        return tup[:i] + (v,) + tup[i + 1:]
+
+    def step(self, a, sh, lo):
+        tail, nxt, locked, data, inside, entries = sh
+        pc, j, tmp, prev = lo
+        me = a + 1
+        fin = self.INIT_N if j + 1 < self.ops else self.DONE
+        if pc == self.INIT_N:
+            after = self.XCHG if self.mutant == "link_before_init" else self.INIT_L
+            return (tail, self._set(nxt, a, 0), locked, data, inside, entries), (after, j, tmp, prev)
+        if pc == self.INIT_L:
+            return (tail, nxt, self._set(locked, a, 1), data, inside, entries), (self.XCHG, j, tmp, prev)
+        if pc == self.XCHG:
+            sh = (me, nxt, locked, data, inside, entries)
+            if tail == 0:
+                return sh, (self.CS_IN, j, tmp, 0)
+            return sh, (self.LINK, j, tmp, tail)
+        if pc == self.LINK:
+            sh = (tail, self._set(nxt, prev - 1, me), locked, data, inside, entries)
+            after = self.LATE_L if self.mutant == "link_before_init" else self.SPIN
+            if self.mutant == "no_spin":
+                after = self.CS_IN
+            return sh, (after, j, tmp, prev)
+        if pc == self.LATE_L:
+            return (tail, nxt, self._set(locked, a, 1), data, inside, entries), (self.SPIN, j, tmp, prev)
+        if pc == self.SPIN:
+            return sh, ((self.CS_IN if locked[a] == 0 else self.SPIN), j, tmp, prev)
+        if pc == self.CS_IN:
+            return (tail, nxt, locked, data, inside + 1, entries), (self.CS_LD, j, tmp, prev)
+        if pc == self.CS_LD:
+            return sh, (self.CS_ST, j, data, prev)
+        if pc == self.CS_ST:
+            return (tail, nxt, locked, tmp + 1, inside, entries), (self.CS_OUT, j, tmp, prev)
+        if pc == self.CS_OUT:
+            return (tail, nxt, locked, data, inside - 1, entries + 1), (self.REL_RD, j, tmp, prev)
+        if pc == self.REL_RD:
+            if nxt[a] != 0:
+                return sh, (self.REL_GO, j, nxt[a], prev)
+            return sh, (self.REL_CAS, j, tmp, prev)
+        if pc == self.REL_CAS:
+            if self.mutant == "store_tail":
+                return (0, nxt, locked, data, inside, entries), (fin, j + 1, tmp, prev)
+            if tail == me:
+                return (0, nxt, locked, data, inside, entries), (fin, j + 1, tmp, prev)
+            if self.mutant == "no_wait_for_next":
+                return sh, (fin, j + 1, tmp, prev)
+            return sh, (self.REL_WAIT, j, tmp, prev)
+        if pc == self.REL_WAIT:
+            if nxt[a] != 0:
+                return sh, (self.REL_GO, j, nxt[a], prev)
+            return sh, lo
+        if pc == self.REL_GO:
+            return (tail, nxt, self._set(locked, tmp - 1, 0), data, inside, entries), (fin, j + 1, tmp, prev)
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        if sh[4] > 1:
+            return f"mutual exclusion violated: {sh[4]} inside"
+        return None
+
+    def final_check(self, sh, los):
+        total = self.n * self.ops
+        if sh[3] != total or sh[5] != total:
+            return f"final data {sh[3]} entries {sh[5]} != {total}"
+        if sh[0] != 0:
+            return f"lock left with tail {sh[0]}"
+        return None
+
+
 class CondModel:
     """Bounded buffer on a mutex and two condition variables (Mesa semantics).
     The mutex is one atomic test-and-set word.  A condition variable is two counters:

@@ -455,13 +455,16 @@ int or_barrier_threaded(int kind, uint32_t seed, uint32_t N, uint32_t R, uint32_
 // the word reads free, then one compare-and-swap, 5 ring-buffer mutex (Section 5's design
 // alternative: enqueue one's id, wait until the head's entry is one's own), 6 array queue
 // lock (wait on one's own slot, unlock grants the next), 7 ticket mutex waiting in
-// proportion to the distance from the head.
+// proportion to the distance from the head, 8 cohort lock, 9 MCS queue lock (a linked
+// queue of per-agent nodes: lock exchanges the tail with one's node and, behind a
+// predecessor, links in and waits on one's own node; unlock hands over to the successor
+// or, when none has linked in, swings the tail back to empty with a compare-and-swap).
 // Workload: see or_mutex_closed.  An owner word checks mutual exclusion inside every
 // critical section.  Returns 0, or -2 on a mutual-exclusion violation.
 int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uint32_t L,
                       uint32_t W, uint32_t imin, uint32_t imax, uint32_t* words,
                       double* seconds) {
-  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 8) return -1;
+  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 9) return -1;
   std::vector<Word> lockw(L), ticket(L), turn(L), owner(L);
   for (uint32_t l = 0; l < L; ++l) lockw[l] = 0, ticket[l] = 0, turn[l] = 0, owner[l] = 0;
   // kinds 5 (ring) and 6 (array): Q slots per lock, Q a power of two >= agents
@@ -477,6 +480,10 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
   // does not hold the global lock, k > 0 = it does and k holders passed it on); at most
   // kPasses holders in a row.
   constexpr uint32_t kCoh = 8, kPasses = 4;
+  // kind 9 (MCS): per lock and agent a node {next (agent + 1, 0 = none), locked}; the
+  // lock's tail is lockw (agent + 1, 0 = free)
+  std::vector<Word> mnext(kind == 9 ? (size_t)L * nwg : 0), mlocked(mnext.size());
+  for (size_t i = 0; i < mnext.size(); ++i) mnext[i] = 0, mlocked[i] = 0;
   std::vector<Word> lt(kind == 8 ? (size_t)L * kCoh : 0);
   std::vector<std::atomic<uint64_t>> grant(lt.size());
   for (size_t i = 0; i < lt.size(); ++i) lt[i] = 0, grant[i] = 0;
@@ -531,6 +538,17 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
         while (slot.load(std::memory_order_acquire) != my) relax();
         return my;
       }
+      case 9: {  // MCS
+        const size_t me = (size_t)l * nwg + b;
+        mnext[me].store(0, std::memory_order_relaxed);
+        mlocked[me].store(1, std::memory_order_relaxed);
+        const uint32_t prev = lockw[l].exchange(b + 1, std::memory_order_acq_rel);
+        if (prev != 0) {
+          mnext[(size_t)l * nwg + (prev - 1)].store(b + 1, std::memory_order_release);
+          while (mlocked[me].load(std::memory_order_acquire) != 0) relax();
+        }
+        return 0;
+      }
       case 8: {  // cohort: the local ticket lock, then the global one unless inherited
         const size_t c = (size_t)l * kCoh + b % kCoh;
         const uint32_t my = lt[c].fetch_add(1, std::memory_order_relaxed);
@@ -555,6 +573,19 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
   };
   auto unlock = [&](uint32_t l, uint32_t b, uint64_t held) {
     const uint32_t my = (uint32_t)held;
+    if (kind == 9) {
+      const size_t me = (size_t)l * nwg + b;
+      uint32_t nx = mnext[me].load(std::memory_order_acquire);
+      if (nx == 0) {
+        uint32_t expect = b + 1;
+        if (lockw[l].compare_exchange_strong(expect, 0, std::memory_order_acq_rel,
+                                             std::memory_order_relaxed))
+          return;
+        while ((nx = mnext[me].load(std::memory_order_acquire)) == 0) relax();
+      }
+      mlocked[(size_t)l * nwg + (nx - 1)].store(0, std::memory_order_release);
+      return;
+    }
     if (kind == 8) {
       const size_t c = (size_t)l * kCoh + b % kCoh;
       const uint32_t k = (uint32_t)(held >> 32) + 1;

@@ -54,7 +54,7 @@ int main() {
     const uint64_t total = 300;
     std::vector<uint32_t> want(L * W), got(L * W);
     or_mutex_closed(seed, nwg, total, L, W, want.data());
-    for (int kind = 0; kind <= 8; ++kind) {
+    for (int kind = 0; kind <= 9; ++kind) {
       expect(or_mutex_threaded(kind, seed, nwg, total, L, W, 1, 4, got.data(), nullptr) == 0,
              "mutex rc");
       expect(got == want, "mutex words");

@@ -48,7 +48,7 @@ __global__ SP_FULL_OCCUPANCY void k_mutex(sp::MutexState s, uint32_t nlocks, uin
     }
     if (own && sp::is_leader() && sp::exch_relaxed(own, 0) != b + 1)
       sp::cas_relaxed(err, sp::DEV_OK, sp::DEV_PARITY);
-    sp::mutex_unlock<KIND, FENCED>(s, lock, &hold);
+    sp::mutex_unlock<KIND, FENCED>(s, lock, &hold, &ctl);
   }
   if (sp::is_leader() && finish) finish[b] = sp::wall_clock();
 }
@@ -73,6 +73,7 @@ const void* mutex_kernel_f(uint32_t kind) {
     case SP_MUTEX_ARRAY: return (const void*)k_mutex<SP_MUTEX_ARRAY, FENCED>;
     case SP_MUTEX_ADAPTIVE: return (const void*)k_mutex<SP_MUTEX_ADAPTIVE, FENCED>;
     case SP_MUTEX_COHORT: return (const void*)k_mutex<SP_MUTEX_COHORT, FENCED>;
+    case SP_MUTEX_MCS: return (const void*)k_mutex<SP_MUTEX_MCS, FENCED>;
     default: return nullptr;
   }
 }
@@ -90,7 +91,7 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
   if (!spi::usable(ctx) || !out || nlocks == 0 || words_per_lock == 0 || nlocks > (1u << 20) ||
       words_per_lock > (1u << 16))
     return SP_E_INVAL;
-  if (kind > SP_MUTEX_COHORT && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_MUTEX_MCS && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -167,7 +168,8 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
     q.coherent_cs = m->p.coherent_cs;  // a property of the caller's critical sections
   }
   if (kind == SP_MUTEX_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) q.backoff = SP_BACKOFF_EXP;
-  if (kind == SP_MUTEX_SPIN_CAS || kind == SP_MUTEX_SLEEP || kind == SP_MUTEX_ADAPTIVE)
+  if (kind == SP_MUTEX_SPIN_CAS || kind == SP_MUTEX_SLEEP || kind == SP_MUTEX_ADAPTIVE ||
+      kind == SP_MUTEX_MCS)
     q.backoff = SP_BACKOFF_NONE;
   const void* kern = mutex_kernel(kind, q.coherent_cs != 0);
   if (!kern) return SP_E_INVAL;
@@ -185,16 +187,20 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
   ms.qlen = 1;
   ms.qstride = 1;
   ms.cohort_bound = q.cohort_passes;
-  if (kind == SP_MUTEX_RING || kind == SP_MUTEX_ARRAY || kind == SP_MUTEX_COHORT) {
+  if (kind == SP_MUTEX_RING || kind == SP_MUTEX_ARRAY || kind == SP_MUTEX_COHORT ||
+      kind == SP_MUTEX_MCS) {
     // The ring needs a slot per contender (each workgroup has at most one arrival
     // outstanding); the array lock is correct with any number and polls one line each;
-    // the cohort lock keeps two lines per lock and XCC id (ticket, 64-bit grant word).
+    // the cohort lock keeps two lines per lock and XCC id (ticket, 64-bit grant word);
+    // the MCS lock one node (next, locked) per lock and workgroup.
     uint32_t Q = 64;
     while (Q < nwg) Q <<= 1;
     if (kind == SP_MUTEX_COHORT) Q = 2 * sp::kXccSlots;
+    if (kind == SP_MUTEX_MCS) Q = nwg;
     ms.qlen = Q;
     ms.qstride = kind == SP_MUTEX_RING ? 1 : sw;  // ring entries packed, others padded
-    if (kind == SP_MUTEX_COHORT && ms.qstride < 2) ms.qstride = 2;  // 64-bit grant words
+    if ((kind == SP_MUTEX_COHORT || kind == SP_MUTEX_MCS) && ms.qstride < 2)
+      ms.qstride = 2;  // 64-bit grant words; an MCS node's two words
     const uint64_t words = (uint64_t)m->nlocks * Q * ms.qstride;
     if (words > (1ull << 28)) return SP_E_INVAL;  // 1 GiB of slots at most
     if (words > m->queue_words) {

@@ -22,6 +22,8 @@ enum { L_S = 0, L_COUNT, L_TICKET, L_TURN, L_OCC, L_MAXOCC, L_ADM, L_PRIVATE, L_
 // Guarded data: a pool of K slots for K <= kMaxPool, owner words 32 bytes apart.
 constexpr uint32_t kMaxPool = 4096;
 constexpr uint32_t kOwnerWords = 8;
+// Algorithm 4's waiter backoff cap when the caller names no backoff policy (s_sleep units).
+constexpr uint32_t kAlg4BackoffCap = 8192;
 
 // The wait/hold/post workload.  With `data` (K uint32 words, packed, plain memory) every
 // holder also updates guarded data: for K = 1 the semaphore is a mutex and the data is
@@ -188,7 +190,12 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
     q.timeout_ms = t;
     q.coherent_cs = coherent;
   }
-  if (kind == SP_SEM_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) q.backoff = SP_BACKOFF_EXP;
+  if (kind == SP_SEM_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) {
+    // No policy chosen: exponential, capped at 8192 units.  With posts retrying at once,
+    // a 32-unit cap lets 256-2048 waiters keep S busy until the watchdog (measured).
+    q.backoff = SP_BACKOFF_EXP;
+    q.backoff_max = std::max<uint32_t>(q.backoff_max, kAlg4BackoffCap);
+  }
   if (kind != SP_SEM_SPIN_BACKOFF) q.backoff = SP_BACKOFF_NONE;
   const void* kern = sem_kernel(kind, q.coherent_cs != 0);
   if (!kern) return SP_E_INVAL;

@@ -100,6 +100,7 @@ def mutex_candidates():
     out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
     out += [("array", {"poll_sleep": ps}) for ps in (0, 1, 4)]
     out += [("ring", {"poll_sleep": 0}), ("adaptive", {})]
+    out += [("mcs", {"poll_sleep": ps}) for ps in (0, 1)]
     out += [("cohort", {"poll_sleep": ps, "cohort_passes": cp}) for ps in (0, 4)
             for cp in (16, 64)]
     return out
@@ -146,9 +147,15 @@ def tune_mutex_points(ctx, points, total: int, **kw) -> dict:
 
 def semaphore_candidates():
     out = [("spin", {})]
-    for policy in ("exp", "paper"):
-        for imax in (8, 32):
-            out.append(("spin_backoff", {"backoff": policy, "backoff_min": 1, "backoff_max": imax}))
+    # Algorithm 4: the waiters' backoff cap, and whether post backs off too (the listing)
+    # or retries at once (Section 5's prose); caps up to 8192 units keep 2048 waiters
+    # from holding the word S busy
+    for imax in (32, 1024, 8192):
+        for pb in (0, 1):
+            out.append(("spin_backoff", {"backoff": "exp", "backoff_min": 1, "backoff_max": imax,
+                                         "post_backoff": pb}))
+    out.append(("spin_backoff", {"backoff": "paper", "backoff_min": 1, "backoff_max": 32,
+                                 "post_backoff": 0}))
     out += [("ticket", {"poll_sleep": 0})]
     out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
     out += [("counters", {"poll_sleep": ps}) for ps in (0, 1, 4, 16, 64)]

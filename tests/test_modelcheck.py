@@ -3,9 +3,9 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 
 import pytest
 
-from oracle.modelcheck import (BarrierModel, CohortLockModel, CondModel, FASemModel, MutexModel,
-                               QueueLockModel, SpinSemModel, WeightedSemModel, XcdBarrierModel,
-                               explore)
+from oracle.modelcheck import (BarrierModel, CohortLockModel, CondModel, FASemModel,
+                               MCSLockModel, MutexModel, QueueLockModel, SpinSemModel,
+                               WeightedSemModel, XcdBarrierModel, explore)
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
@@ -251,3 +251,22 @@ def test_xcd_barrier_rank_stored_late_is_caught():
     r = explore(XcdBarrierModel(((0, 0), (0, 1), (0, 0)), 2, 2, register=True,
                                 mutant="rank_after_arrival"))
     assert r.violation
+
+
+# ---- MCS queue lock --------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,ops", [(2, 2), (2, 3), (3, 2)])
+def test_mcs_lock_correct(n, ops):
+    r = explore(MCSLockModel(n, ops))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("mutant", ["no_wait_for_next", "link_before_init", "store_tail"])
+def test_mcs_lock_mutants_deadlock(mutant):
+    r = explore(MCSLockModel(3, 2, mutant=mutant))
+    assert not r.ok
+
+
+def test_mcs_lock_entering_without_spinning_breaks_exclusion():
+    r = explore(MCSLockModel(2, 2, mutant="no_spin"))
+    assert r.violation and "mutual exclusion" in r.violation

@@ -31,7 +31,7 @@ def test_barrier_per_xcd_protocol_at_full_grid():
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep",
-                                  "ring", "array", "adaptive", "cohort"])
+                                  "ring", "array", "adaptive", "cohort", "mcs"])
 @pytest.mark.parametrize("L,W", [(1, 1), (1, 16), (3, 4)])
 def test_mutex_threaded_matches_closed(kind, L, W):
     seed, nwg, total = 0xC0FFEE, 8, 3000

@@ -45,9 +45,12 @@ def test_candidate_lists_cover_every_kind():
                                                           "flag", "tree"}
     assert {k for k, _ in tune.mutex_candidates()} == {"spin_cas", "spin_exch", "spin_backoff",
                                                         "ticket", "sleep", "ring", "array",
-                                                        "adaptive", "cohort"}
+                                                        "adaptive", "cohort", "mcs"}
     assert {k for k, _ in tune.semaphore_candidates()} == {"spin", "spin_backoff", "ticket",
                                                             "sleep", "counters", "adaptive"}
+    # Algorithm 4's post backoff is searched both ways
+    assert {p.get("post_backoff") for k, p in tune.semaphore_candidates()
+            if k == "spin_backoff"} == {0, 1}
 
 
 def test_semaphore_points_rank_by_geometric_mean(monkeypatch):
