@@ -40,6 +40,8 @@ extern "C" {
 #define SP_E_NORESIDENT (-3) /* a barrier needs more co-resident workgroups than fit   */
 #define SP_E_TIMEOUT (-4)    /* the device watchdog expired                            */
 #define SP_E_PARITY (-5)     /* a kernel's own consistency check failed                */
+#define SP_E_RANGE (-6)      /* an allocation-free call's input exceeds its fixed        */
+                             /* workspace (see sp_cond_run_bounded_buffer_noalloc)      */
 
 /* ---- kinds -------------------------------------------------------------------------- */
 /* Barriers (Section 5, Barrier; Section 2 for the centralized and tree barriers).      */
@@ -384,6 +386,26 @@ int sp_cond_run_bounded_buffer(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, u
                                uint32_t lanes, uint32_t capacity, uint64_t items, uint32_t seed,
                                const sp_params* p, uint64_t* out, uint32_t* out_taken,
                                sp_stats* st, void* stream);
+/* sp_cond_run_bounded_buffer_noalloc: for callers that cannot allocate device memory --
+ * code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same workload, arguments, outputs and errors as sp_cond_run_bounded_buffer, but the
+ * mutex, condition-variable and ring state live in a fixed workspace of 1 MiB (262144
+ * uint32 words) in device memory that the library holds on each GPU it runs on until the
+ * process ends; the call allocates and frees nothing (and so, unlike
+ * sp_cond_run_bounded_buffer, may be recorded into a graph).  The workspace takes the
+ * mutex state (6 lines, plus Q lines for SP_MUTEX_ARRAY with Q = nwg rounded up to a power
+ * of two >= 64, or 32 lines for SP_MUTEX_COHORT; a line is pad_bytes), 8 lines of 128
+ * bytes, the ring (capacity words) and 8 words per workgroup; a request that needs more
+ * returns SP_E_RANGE (with the default 128-byte padding any nwg <= 2048 fits with a
+ * capacity of up to 179000 words).  The call clears the part it uses before its kernel
+ * runs.  Every call on
+ * one GPU uses the same workspace: calls that overlap on one GPU (on different streams,
+ * or from different host threads) race and their results are undefined.               */
+int sp_cond_run_bounded_buffer_noalloc(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg,
+                                       uint32_t producers, uint32_t lanes, uint32_t capacity,
+                                       uint64_t items, uint32_t seed, const sp_params* p,
+                                       uint64_t* out, uint32_t* out_taken, sp_stats* st,
+                                       void* stream);
 
 /* ---- memory-system microbenchmarks (Section 3; Tables 1-3) ------------------------------
  * sp_bench_atomic: issuer u (a lane, or a wavefront's lane 0) performs ops_per_issuer

@@ -31,6 +31,7 @@ SP_E_HIP = -2
 SP_E_NORESIDENT = -3
 SP_E_TIMEOUT = -4
 SP_E_PARITY = -5
+SP_E_RANGE = -6
 
 BARRIER_KINDS = {"central": 0, "central_split": 1, "tree": 2, "flag": 3, "grid_sync": 4,
                  "xcd": 5, "default": 15}
@@ -209,6 +210,8 @@ def _load():
         "sp_bench_clock": (i32, [vp, u32, vp, P(ctypes.c_double), vp]),
         "sp_cond_run_bounded_buffer": (i32, [vp, u32, u32, u32, u32, u32, u64, u32, P(Params),
                                               vp, vp, P(Stats), vp]),
+        "sp_cond_run_bounded_buffer_noalloc": (i32, [vp, u32, u32, u32, u32, u32, u64, u32,
+                                                      P(Params), vp, vp, P(Stats), vp]),
         "sp_graph_begin": (i32, [vp, vp, P(vp)]),
         "sp_graph_end": (i32, [vp, vp, P(vp)]),
         "sp_graph_launch": (i32, [vp, u32, P(Stats), vp]),

@@ -351,18 +351,18 @@ class Semaphore(_Handle):
 
 def bounded_buffer(ctx: Context, mutex_kind: str, nwg: int, producers: int, capacity: int,
                    items: int, seed: int, lanes: int = 64, values: bool = False,
-                   **params) -> dict:
+                   noalloc: bool = False, **params) -> dict:
     """Producer/consumer ring on a mutex and two condition variables
-    (sp_cond_run_bounded_buffer).  values=True also returns every value taken."""
+    (sp_cond_run_bounded_buffer, or with noalloc=True the allocation-free
+    sp_cond_run_bounded_buffer_noalloc).  values=True also returns every value taken."""
     out = ctx.zeros(6, "u64")
     taken = ctx.zeros(items) if values else None
     p = make_params(**params)
     st = N.Stats()
-    check(lib.sp_cond_run_bounded_buffer(ctx.h, N.MUTEX_KINDS[mutex_kind], nwg, producers, lanes,
-                                         capacity, items, seed & 0xFFFFFFFF, ctypes.byref(p),
-                                         ctx.ptr(out), ctx.ptr(taken), ctypes.byref(st),
-                                         ctx.stream()),
-          "sp_cond_run_bounded_buffer", ctx.h)
+    name = "sp_cond_run_bounded_buffer_noalloc" if noalloc else "sp_cond_run_bounded_buffer"
+    check(getattr(lib, name)(ctx.h, N.MUTEX_KINDS[mutex_kind], nwg, producers, lanes, capacity,
+                             items, seed & 0xFFFFFFFF, ctypes.byref(p), ctx.ptr(out),
+                             ctx.ptr(taken), ctypes.byref(st), ctx.stream()), name, ctx.h)
     v = [int(x) for x in ctx.read(out, "u64", 6)]
     r = {"xor": v[0], "sum": v[1], "taken": v[2], "put": v[3], "max_count": v[4],
          "left": v[5], "stats": st.as_dict()}

@@ -156,6 +156,7 @@ const char* sp_strerror(int code) {
     case SP_E_NORESIDENT: return "not enough co-resident workgroups for a global barrier";
     case SP_E_TIMEOUT: return "device watchdog expired";
     case SP_E_PARITY: return "device consistency check failed";
+    case SP_E_RANGE: return "request exceeds the fixed workspace of an allocation-free call";
     default: return "unknown error";
   }
 }
@@ -185,6 +186,7 @@ int sp_init(int device, sp_ctx** out) {
   if ((e = hipEventCreate(&ctx->ev1)) != hipSuccess) return fail(e);
   if ((e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
     return fail(e);
+  if (spi::static_scratch_setup(ctx) != SP_OK) return fail(hipErrorInvalidSymbol);
   // Count XCDs: launch 8 workgroups per CU and collect the distinct XCC ids.
   {
     uint32_t n = ctx->cu_count * 8;
@@ -301,7 +303,7 @@ int sp_buffer_alloc(sp_ctx* ctx, uint64_t bytes, void** out) {
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     ctx->last_hip = (int)e;
-    hipFree(p);
+    (void)hipFree(p);
     return SP_E_HIP;
   }
   *out = p;

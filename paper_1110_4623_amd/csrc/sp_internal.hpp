@@ -29,12 +29,21 @@ struct sp_ctx {
   uint32_t wall_khz = 100000;
   uint32_t* d_err = nullptr;   // watchdog word, own 256-byte block
   uint32_t* d_scratch = nullptr;  // small staging area (4 KiB) for state readback
+  // the allocation-free entry point's fixed workspace on this device (a file-scope device
+  // array; its address is looked up once per device at sp_init)
+  uint32_t* static_scratch = nullptr;
+  uint64_t static_scratch_words = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t capture_stream = nullptr;
   sp_default_entry defaults[3][2];
 };
 
 namespace spi {
+
+// Looks up (once per device) the address of the allocation-free entry point's fixed
+// workspace and records it in the context.  The context's device must be current.
+int static_scratch_setup(sp_ctx* ctx);
+
 
 // Records a failing HIP call in the context and returns SP_E_HIP from the caller.
 #define SP_HIP(ctx, call)                                      \
