@@ -102,6 +102,11 @@ enum sp_sem_kind {
                            /* interval learned per workgroup from the rate at which the */
                            /* posts counter advanced while it waited, so the queue's    */
                            /* far end stops loading the counter's line                  */
+  SP_SEM_COHORT = 6,       /* Algorithm 5's count with a queue per XCD: a post hands its */
+                           /* unit to the oldest waiter of its own XCD without an L2     */
+                           /* writeback (at most cohort_passes times in a row), else    */
+                           /* writes back and hands it to another XCD's waiter; each    */
+                           /* waiter polls its own slot                                  */
   SP_SEM_DEFAULT = 15
 };
 
@@ -174,7 +179,8 @@ typedef struct sp_params {
                          /* lines.  Timing only; results are the same.                      */
   uint32_t cohort_passes; /* SP_MUTEX_COHORT: holders of one XCD that may take the lock */
                            /* in a row before it goes back to the global queue, 1..255    */
-                           /* (0 = 64)                                                    */
+                           /* (0 = 64); SP_SEM_COHORT: local hand-overs of one unit in a  */
+                           /* row before it goes to another XCD                           */
   uint32_t flag_placement; /* SP_BARRIER_XCD: 0 = measured (default).  A signal between    */
                            /* two workgroups takes 30-40 % less time when its line lives   */
                            /* in memory close to their XCD, so sp_barrier_create times a   */
@@ -351,9 +357,10 @@ int sp_sem_destroy(sp_sem* s);
  * maximum, counts the admission, XORs sm32(seed ^ (w << 16) ^ j) into the workgroup's
  * checksum, holds key(w, j, 3) mod (max_hold_cyc + 1) shader clocks and decrements the
  * occupancy.  out_chk: device, nwg uint32.  out_state: device, 8 uint32 =
- * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, 0, 0, 0}
- * (SP_SEM_COUNTERS, SP_SEM_ADAPTIVE: count stays 0, ticket = tickets drawn, turn = posts
- * made).
+ * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, count,
+ * occupancy, unserved} (SP_SEM_COUNTERS, SP_SEM_ADAPTIVE: count stays 0, ticket = tickets
+ * drawn, turn = posts made; SP_SEM_COHORT: ticket and turn stay 0, unserved = local
+ * tickets drawn and not served, over every XCD's queue, 0 at rest).
  * out_data: device, K uint32 (zeroed by the call), or NULL; K <= 4096.  Guarded data:
  * each admission adds one to a word with a plain load and store made by the workgroup's
  * last thread -- for K = 1 to the one word, ordered only by the semaphore's acquire and

@@ -219,10 +219,18 @@ struct XcdLocal {
   uint32_t slot;     // registration order on the CU (0 = CU leader)
   uint32_t rank;     // rank of the CU among its XCD's CUs with members
   uint32_t mail;     // the copy of the XCD stamps this workgroup polls (xcopies > 0)
+  // word offsets, resolved once in round 0 from the placement tables, so that later
+  // rounds keep no table in registers: this XCD's arrival block in larrive, the stamps
+  // this workgroup polls in xmail, this CU's release line in lrelease
+  uint32_t block_off;
+  uint32_t stamps_off;
+  uint32_t rel_off;
 };
+// The master's stores of its stamp: copy c at pub[c] + the XCD's index in xmail.
+constexpr uint32_t kMaxCopies = 256;
 
 __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, const Ctl& ctl,
-                                         const XcdLocal& L) {
+                                         const XcdLocal& L, const uint32_t* pub) {
   __shared__ uint32_t s_ok;
   const uint32_t X = s.groups;
   // The registration is the same for the whole workgroup: keep it in scalar registers.
@@ -231,7 +239,7 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
   const uint32_t members = __builtin_amdgcn_readfirstlane(L.members);
   const uint32_t xmask = __builtin_amdgcn_readfirstlane(L.xmask);
   const uint32_t slot = __builtin_amdgcn_readfirstlane(L.slot);
-  uint32_t* block = s.larrive + s.xoff[x];
+  uint32_t* block = s.larrive + __builtin_amdgcn_readfirstlane(L.block_off);
   Wait w(ctl, s.poll_sleep);
   int ok = 1;
   __syncthreads();
@@ -249,16 +257,13 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
       }
     } else if (threadIdx.x < 64) {
       if (s.fenced) fence_release();
-      for (uint32_t c = threadIdx.x; c < C; c += 64)
-        st_relaxed(s.xmail + s.moff[c % X] + (size_t)(c / X) * s.xmstep + x, stamp);
+      for (uint32_t c = threadIdx.x; c < C; c += 64) st_relaxed(s.xmail + pub[c] + x, stamp);
     }
   } else if (is_leader()) {
     st_relaxed(block + (size_t)k * kArriveWords, stamp);
   }
   // The populated XCDs' stamps: one line each, or packed in this CU's copy.
-  const uint32_t mail = __builtin_amdgcn_readfirstlane(L.mail);
-  const uint32_t* stamps =
-      C ? s.xmail + s.moff[mail % X] + (size_t)(mail / X) * s.xmstep : s.xarrive;
+  const uint32_t* stamps = C ? s.xmail + __builtin_amdgcn_readfirstlane(L.stamps_off) : s.xarrive;
   const uint32_t sstride = C ? 1 : s.stride;
   if (!s.fenced) {
     // Coherent data: no cache maintenance, so nothing is shared per CU; every workgroup
@@ -268,8 +273,7 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
     return __syncthreads_and(ok);
   }
   // this CU's release line
-  uint32_t* rel = s.lrelease + s.roff[x] +
-                  (size_t)__builtin_amdgcn_readfirstlane(L.rank) * s.stride;
+  uint32_t* rel = s.lrelease + __builtin_amdgcn_readfirstlane(L.rel_off);
   if (slot == 0) {
     // CU leader: once every populated XCD has published, invalidate for the CU and
     // release it.  The invalidation has to follow the last XCD's writeback: a line that
@@ -297,7 +301,7 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
 // Round 0 of the per-XCD barrier: register per XCD and per CU, run the counter tree
 // with per-workgroup fences, then load what the later rounds use.
 __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl, XcdLocal& L,
-                                          uint32_t* use_xcd) {
+                                          uint32_t* pub, uint32_t* use_xcd) {
   __shared__ uint32_t s_ok;
   const uint32_t X = s.groups;
   __syncthreads();  // every wavefront's stores have completed (barrier_wait's entry wait)
@@ -326,8 +330,13 @@ __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl,
       if (ld_relaxed(s.xcount + i) != 0) mask |= 1u << i;
     L.xmask = mask;
     L.mail = s.xcopies ? (xcc + X * L.rank) % s.xcopies : 0;
+    L.block_off = s.xoff[xcc];
+    L.stamps_off = s.xcopies ? s.moff[L.mail % X] + (L.mail / X) * s.xmstep : 0;
+    L.rel_off = s.roff[xcc] + L.rank * s.stride;
     s_ok = ok;
   }
+  for (uint32_t c = threadIdx.x; c < s.xcopies && c < kMaxCopies; c += blockDim.x)
+    pub[c] = s.moff[c % X] + (c / X) * s.xmstep;
   __syncthreads();
   return s_ok;
 }
@@ -347,8 +356,9 @@ __device__ bool barrier_wait(const BarrierState& s, uint32_t round, const Ctl& c
     // protocol unless a registration did not fit, the counter tree otherwise.
     __shared__ detail::XcdLocal s_local;
     __shared__ uint32_t s_use;
-    if (round == 0) return detail::xcd_setup(s, ctl, s_local, &s_use);
-    if (s_use) return detail::xcd_wait(s, stamp, ctl, s_local);
+    __shared__ uint32_t s_pub[detail::kMaxCopies];
+    if (round == 0) return detail::xcd_setup(s, ctl, s_local, s_pub, &s_use);
+    if (s_use) return detail::xcd_wait(s, stamp, ctl, s_local, s_pub);
     __syncthreads();
     if (is_leader()) {
       const bool ok = detail::counter_arrive_wait<SP_BARRIER_TREE>(s, stamp, ctl);

@@ -17,12 +17,98 @@ struct SemState {
   BackoffCfg bo;        // SP_SEM_SPIN_BACKOFF
   uint32_t post_backoff;  // SP_SEM_SPIN_BACKOFF: 1 = post backs off too (Algorithm 4's
                           // listing); 0 = post retries at once (Section 5's prose)
+  // SP_SEM_COHORT: per XCC id (kXccQueues of them) a queue of cq_len 64-bit grant slots,
+  // after two lines (local tickets drawn, local tickets served); lines cq_stride words
+  // apart (even, so the 64-bit slots are aligned)
+  uint32_t* cq;
+  uint32_t cq_stride;
+  uint32_t cq_len;       // power of two
+  uint32_t cohort_bound; // local hand-overs of one unit in a row, at most
 };
 
-// Per-workgroup waiting state that persists across waits (SP_SEM_ADAPTIVE).
+// Per-workgroup waiting state that persists across waits (SP_SEM_ADAPTIVE), or from a
+// wait to its post (SP_SEM_COHORT).
 struct SemHold {
   uint32_t interval;  // learned wall-clock ticks between two posts (0 = none yet)
+  uint32_t pass;      // SP_SEM_COHORT: local hand-overs of the unit held, in a row
 };
+
+// ---- cohort semaphore queues -------------------------------------------------------------
+constexpr uint32_t kXccQueues = 16;  // the XCC id register has four bits
+__device__ __forceinline__ uint32_t* cq_base(const SemState& s, uint32_t x) {
+  return s.cq + (size_t)x * (2 + s.cq_len) * s.cq_stride;
+}
+__device__ __forceinline__ uint32_t* cq_drawn(const SemState& s, uint32_t x) { return cq_base(s, x); }
+__device__ __forceinline__ uint32_t* cq_served(const SemState& s, uint32_t x) {
+  return cq_base(s, x) + s.cq_stride;
+}
+__device__ __forceinline__ uint64_t* cq_slot(const SemState& s, uint32_t x, uint32_t t) {
+  return reinterpret_cast<uint64_t*>(cq_base(s, x) +
+                                     (size_t)(2 + (t & (s.cq_len - 1))) * s.cq_stride);
+}
+
+namespace detail {
+
+// Claims XCD x's oldest unserved local ticket (compare-and-swap on its served counter),
+// starting from the counters `served` and `drawn` already loaded; false when every ticket
+// drawn so far is served.  The grant slot of the ticket being claimed is loaded together
+// with the compare-and-swap, so a successful claim also knows whether the slot is free.
+__device__ __forceinline__ bool cq_claim_at(const SemState& s, uint32_t x, uint32_t served,
+                                            uint32_t drawn, uint32_t* t, uint64_t* slot_v) {
+  uint32_t* sp = cq_served(s, x);
+  uint32_t v = served;
+  while ((int32_t)(drawn - v) > 0) {
+    const uint64_t sv = ld_relaxed64(cq_slot(s, x, v));
+    const uint32_t seen = cas_relaxed(sp, v, v + 1);
+    if (seen == v) {
+      *t = v;
+      *slot_v = sv;
+      return true;
+    }
+    v = seen;
+    drawn = ld_relaxed(cq_drawn(s, x));
+  }
+  return false;
+}
+
+__device__ __forceinline__ bool cq_claim(const SemState& s, uint32_t x, uint32_t* t,
+                                         uint64_t* slot_v) {
+  const uint32_t served = ld_relaxed(cq_served(s, x));
+  const uint32_t drawn = ld_relaxed(cq_drawn(s, x));
+  return cq_claim_at(s, x, served, drawn, t, slot_v);
+}
+
+// Claims a ticket on the first XCD (in the order first, first + 1, ...) that has one;
+// retries until one is found (a waiter counted in `count` draws its ticket within a round
+// trip).  Returns false when the watchdog fired.
+__device__ __forceinline__ bool cq_claim_from(const SemState& s, uint32_t first, uint32_t* y,
+                                              uint32_t* t, uint64_t* slot_v, Wait& w) {
+  for (;;) {
+    for (uint32_t d = 0; d < kXccQueues; ++d) {
+      const uint32_t x = (first + d) % kXccQueues;
+      if (cq_claim(s, x, t, slot_v)) {
+        *y = x;
+        return true;
+      }
+    }
+    if (!w.tick()) return false;
+  }
+}
+
+// Grants ticket t of XCD y with pass count k, once the slot's previous ticket (t - cq_len)
+// has taken its grant (slot_v: the slot as loaded while claiming; reloaded until empty).
+__device__ __forceinline__ bool cq_grant(const SemState& s, uint32_t y, uint32_t t, uint32_t k,
+                                         uint64_t slot_v, Wait& w) {
+  uint64_t* slot = cq_slot(s, y, t);
+  while ((uint32_t)slot_v != 0) {
+    if (!w.tick()) return false;
+    slot_v = ld_relaxed64(slot);
+  }
+  st_relaxed64(slot, ((uint64_t)k << 32) | (uint64_t)(t + 1));
+  return true;
+}
+
+}  // namespace detail
 
 // KIND: SP_SEM_SPIN / SP_SEM_SPIN_BACKOFF (Algorithm 4), SP_SEM_TICKET / SP_SEM_SLEEP
 // (Algorithm 5, the queued waiter proceeds once turn is strictly greater than the
@@ -93,6 +179,28 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
           hold->interval = avg < 100000 ? avg : 100000;  // at most 1 ms of wall clock
         }
       }
+    } else if constexpr (KIND == SP_SEM_COHORT) {
+      // Algorithm 5's count; a waiter beyond capacity queues on its own XCD and takes the
+      // unit a poster grants it (with the unit's count of local hand-overs in a row)
+      Wait w(ctl, s.poll_sleep);
+      uint32_t k = 0;
+      const uint32_t old = add_relaxed(s.count, 1);
+      if (old >= s.K) {
+        const uint32_t x = xcc_id();
+        const uint32_t t = add_relaxed(cq_drawn(s, x), 1);
+        uint64_t* slot = cq_slot(s, x, t);
+        uint64_t v = 0;
+        for (;;) {
+          v = ld_relaxed64(slot);
+          if ((uint32_t)v == t + 1) break;
+          if (!(ok = w.tick())) break;
+        }
+        if (ok) {
+          k = (uint32_t)(v >> 32);
+          st_relaxed64(slot, 0);  // taken: the slot may carry the grant of ticket t + len
+        }
+      }
+      if (hold) hold->pass = k;
     } else if constexpr (KIND == SP_SEM_COUNTERS) {
       Wait w(ctl, s.poll_sleep);
       const uint32_t t = add_relaxed(s.ticket, 1);
@@ -117,11 +225,58 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
   return s_ok;
 }
 
+// `hold`: SP_SEM_COHORT needs the record its sem_wait filled in (the unit's local
+// hand-overs); other kinds ignore it.
 template <int KIND, bool FENCED = true>
-__device__ bool sem_post(const SemState& s, const Ctl& ctl) {
+__device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold = nullptr) {
   __shared__ uint32_t s_ok;
   wave_stores_complete();
   __syncthreads();
+  if constexpr (KIND == SP_SEM_COHORT) {
+    // Hand the unit on.  count > 2K: at least K + 1 workgroups wait or are inside and at
+    // most K - 1 other posts can decrement count first, so a waiter is sure to exist:
+    // decrement, then grant the oldest waiter of this XCD without an L2 writeback (it
+    // reads through the same L2) unless the unit has passed cohort_bound times in a row
+    // here, else write back and grant the first other XCD with a waiter.  Otherwise write
+    // back first, then decrement (Algorithm 5's post); a waiter beyond capacity then gets
+    // the unit, else it returns to the free count.
+    if (is_leader()) {
+      bool ok = true;
+      Wait w(ctl, 0);
+      const uint32_t x = xcc_id();
+      const uint32_t k = hold ? hold->pass : s.cohort_bound;
+      const bool stay = k + 1 < s.cohort_bound;
+      uint32_t y = 0, t = 0, kk = 0;
+      uint64_t slot_v = 0;
+      bool grant = true;
+      // one round trip: the count and this XCD's queue counters, loaded together
+      const uint32_t c = ld_relaxed(s.count);
+      const uint32_t served = ld_relaxed(cq_served(s, x));
+      const uint32_t drawn = ld_relaxed(cq_drawn(s, x));
+      if (c > 2 * s.K) {
+        add_relaxed(s.count, 0xFFFFFFFFu);
+        if (stay && detail::cq_claim_at(s, x, served, drawn, &t, &slot_v)) {
+          y = x;
+          kk = k + 1;
+        } else {
+          if constexpr (FENCED) fence_release();
+          ok = detail::cq_claim_from(s, x + 1, &y, &t, &slot_v, w);
+        }
+      } else {
+        if constexpr (FENCED) fence_release();
+        const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);
+        grant = old > s.K;
+        if (grant) {
+          ok = detail::cq_claim_from(s, stay ? x : x + 1, &y, &t, &slot_v, w);
+          kk = y == x ? k + 1 : 0;
+        }
+      }
+      if (ok && grant) ok = detail::cq_grant(s, y, t, kk, slot_v, w);
+      s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok;
+  }
   if (is_leader()) {
     bool ok = true;
     if constexpr (FENCED) fence_release();

@@ -686,6 +686,162 @@ class FASemModel:
         return None
 
 
+class CohortSemModel:
+    """Algorithm 5 with per-XCD queues and local hand-over of units.
+
+    count (global) counts workgroups inside or waiting, as in Algorithm 5.  wait:
+    old = fetch-and-add(count, 1); old < K: enter with a fresh unit; otherwise draw a
+    local ticket lt of one's own XCD's queue and poll grant slot lt mod Q of that queue
+    until it holds lt + 1, with the number of local passes k of the unit it receives.
+    post: c = load(count).  If c > 2K at least K + 1 workgroups wait or are inside, and at
+    most K - 1 other posts can decrement count before this one, so this post is sure to
+    find a waiter ("hand-over mode"): decrement count, then, if k + 1 < B and one's own XCD
+    has an unserved ticket (claimed with a compare-and-swap on its served counter), grant
+    it with k + 1 and no L2 writeback (both workgroups use the same L2); otherwise write
+    the L2 back and grant the first XCD after one's own that has an unserved ticket, with
+    k = 0.  If c <= 2K: write back first, then decrement; old > K: grant a waiter of any
+    XCD (preferring one's own); else the unit returns to the free count.
+    Units: free (K - inside - waiting, when positive) + held + in transit = K throughout;
+    the B bound sends every unit to another XCD after at most B local hand-overs.
+
+    placement: XCD of each agent.  Data: one word updated in every critical section with
+    a plain load and store through the agent's XCD's L2 (per XCD: empty, or (value,
+    dirty)); a writeback copies a dirty value to memory; the waiter's acquire drops a
+    clean copy.  With K = 1 the final value must count every admission.  A grant slot is
+    reused (Q slots per XCD): a post writes a grant only into an empty slot, and the
+    admitted waiter empties its slot as it takes the grant.
+    small_q: Q = 1 slot per XCD (the reuse path on every grant).
+    mutant 'no_remote_writeback': a hand-over to another XCD skips the writeback;
+    mutant 'no_acquire': the admitted waiter does not invalidate;
+    mutant 'claim_unchecked': a post claims the next local slot even when no ticket for
+    it has been drawn."""
+
+    (W_CNT, W_LT, W_POLL, ACQ, CS_LD, CS_ST, P_PRED, P_DEC_H, P_LOCAL, P_WB_R, P_REMOTE,
+     P_WB_S, P_DEC_S, P_ANY, P_GRANT, DONE) = range(16)
+
+    def __init__(self, K: int, placement: tuple, ops: int = 2, B: int = 2,
+                 mutant: str | None = None, small_q: bool = False):
+        self.K, self.pl, self.ops, self.B, self.mutant = K, tuple(placement), ops, B, mutant
+        self.n = len(self.pl)
+        self.X = 1 + max(self.pl)
+        self.Q = 1 if small_q else self.n
+
+    # shared = (count, ltick, lserved, grant (X tuples of Q (ticket+1, k)), l2 (X), mem,
+    #           inside)
+    # local  = (pc, j, lt, k, tmp, gx, gs)
+    def init(self):
+        X, Q = self.X, self.Q
+        sh = (0, (0,) * X, (0,) * X, tuple(((0, 0),) * Q for _ in range(X)), (None,) * X, 0, 0)
+        return sh, tuple((self.W_CNT, 0, 0, 0, 0, 0, 0) for _ in range(self.n))
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    @staticmethod
+    def _set(t, i, v):
+        return t[:i] + (v,) + t[i + 1:]
+
+    def _wb(self, l2, mem, x):
+        if l2[x] is not None and l2[x][1]:
+            return self._set(l2, x, (l2[x][0], False)), l2[x][0]
+        return l2, mem
+
+    def _claim(self, ltick, lserved, y):
+        """Compare-and-swap claim of XCD y's next unserved ticket; None if none."""
+        if lserved[y] < ltick[y] or self.mutant == "claim_unchecked":
+            return self._set(lserved, y, lserved[y] + 1), lserved[y]
+        return None
+
+    def step(self, a, sh, lo):
+        count, ltick, lserved, grant, l2, mem, inside = sh
+        pc, j, lt, k, tmp, gx, gs = lo
+        x, K, X, Q = self.pl[a], self.K, self.X, self.Q
+        fin = self.W_CNT if j + 1 < self.ops else self.DONE
+
+        def S(**kw):
+            d = dict(count=count, ltick=ltick, lserved=lserved, grant=grant, l2=l2, mem=mem,
+                     inside=inside)
+            d.update(kw)
+            return (d["count"], d["ltick"], d["lserved"], d["grant"], d["l2"], d["mem"],
+                    d["inside"])
+
+        if pc == self.W_CNT:
+            if count < K:
+                return S(count=count + 1), (self.ACQ, j, 0, 0, tmp, gx, gs)
+            return S(count=count + 1), (self.W_LT, j, 0, 0, tmp, gx, gs)
+        if pc == self.W_LT:
+            return S(ltick=self._set(ltick, x, ltick[x] + 1)), (self.W_POLL, j, ltick[x], 0, tmp, gx, gs)
+        if pc == self.W_POLL:  # take the grant and empty the slot in one step
+            t1, kk = grant[x][lt % Q]
+            if t1 == lt + 1:
+                g = self._set(grant, x, self._set(grant[x], lt % Q, (0, 0)))
+                return S(grant=g), (self.ACQ, j, lt, kk, tmp, gx, gs)
+            return sh, lo
+        if pc == self.ACQ:
+            if self.mutant != "no_acquire" and l2[x] is not None and not l2[x][1]:
+                l2 = self._set(l2, x, None)
+            return S(l2=l2, inside=inside + 1), (self.CS_LD, j, lt, k, tmp, gx, gs)
+        if pc == self.CS_LD:
+            if l2[x] is None:
+                l2 = self._set(l2, x, (mem, False))
+            return S(l2=l2), (self.CS_ST, j, lt, k, l2[x][0], gx, gs)
+        if pc == self.CS_ST:
+            return S(l2=self._set(l2, x, (tmp + 1, True))), (self.P_PRED, j, lt, k, tmp, gx, gs)
+        if pc == self.P_PRED:  # leaving the critical section; predict from count
+            nxt = self.P_DEC_H if count > 2 * K else self.P_WB_S
+            return S(inside=inside - 1), (nxt, j, lt, k, tmp, gx, gs)
+        if pc == self.P_DEC_H:
+            nxt = self.P_LOCAL if k + 1 < self.B else self.P_WB_R
+            return S(count=count - 1), (nxt, j, lt, k, tmp, gx, gs)
+        if pc == self.P_LOCAL:
+            c = self._claim(ltick, lserved, x)
+            if c is None:
+                return sh, (self.P_WB_R, j, lt, k, tmp, gx, gs)
+            return S(lserved=c[0]), (self.P_GRANT, j, lt, k + 1, tmp, x, c[1])
+        if pc == self.P_WB_R:
+            if self.mutant != "no_remote_writeback":
+                l2, mem = self._wb(l2, mem, x)
+            return S(l2=l2, mem=mem), (self.P_REMOTE, j, lt, k, tmp, gx, gs)
+        if pc in (self.P_REMOTE, self.P_ANY):
+            first = x if (pc == self.P_ANY and k + 1 < self.B) else x + 1
+            for y in [(first + d) % X for d in range(X)]:
+                c = self._claim(ltick, lserved, y)
+                if c is not None:
+                    kk = k + 1 if (pc == self.P_ANY and y == x) else 0
+                    return S(lserved=c[0]), (self.P_GRANT, j, lt, kk, tmp, y, c[1])
+            return sh, lo  # the waiter that counted itself has not drawn its ticket yet
+        if pc == self.P_WB_S:
+            l2, mem = self._wb(l2, mem, x)
+            return S(l2=l2, mem=mem), (self.P_DEC_S, j, lt, k, tmp, gx, gs)
+        if pc == self.P_DEC_S:
+            if count > K:
+                return S(count=count - 1), (self.P_ANY, j, lt, k, tmp, gx, gs)
+            return S(count=count - 1), (fin, j + 1, 0, 0, tmp, gx, gs)
+        if pc == self.P_GRANT:  # once the slot's previous ticket has taken its grant
+            if grant[gx][gs % Q][0] != 0:
+                return sh, lo
+            g = self._set(grant, gx, self._set(grant[gx], gs % Q, (gs + 1, k)))
+            return S(grant=g), (fin, j + 1, 0, 0, tmp, gx, gs)
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        if sh[6] > self.K:
+            return f"occupancy {sh[6]} > K={self.K}"
+        return None
+
+    def final_check(self, sh, los):
+        count, ltick, lserved, grant, l2, mem, inside = sh
+        if count != 0 or inside != 0 or ltick != lserved:
+            return f"final count={count} inside={inside} tickets={ltick} served={lserved}"
+        if self.K == 1:
+            total = self.n * self.ops
+            vals = [e[0] for e in l2 if e is not None and e[1]]
+            final = vals[0] if vals else mem
+            if final != total:
+                return f"lost update: data {final} != {total}"
+        return None
+
+
 class WeightedSemModel:
     """Fetch-and-add semaphore with weighted requests, the admission rule of the serving
     queue (Algorithm 5 with u tickets drawn at once).  issued and released start at 0.

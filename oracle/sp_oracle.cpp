@@ -641,7 +641,11 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 // Algorithm 5, 3 Algorithm 5 with yielding polls, 4 two monotone counters (ticket t
 // enters once posts + K > t), 5 the same admission rule with proportional waiting (a
 // waiter d posts short of admission yields (d - 1) / 4 extra times per poll), 6 Algorithm
-// 4 with backoff in wait only (Section 5's prose: post proceeds aggressively).
+// 4 with backoff in wait only (Section 5's prose: post proceeds aggressively), 7 Algorithm
+// 5's count with a queue per group of agents (agent b in group b mod 8): a post that
+// finds more than 2K agents counted hands its unit to the oldest waiter of its own group
+// (at most 4 times in a row for one unit), else to the first other group with a waiter;
+// otherwise it decrements first and hands over only if a waiter is counted beyond K.
 // Each pair: wait, occupancy tracking, checksum update, admission count, post.
 // out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}; for the
 // Algorithm 4 kinds ticket and turn are unused and state[1] / state[2] report instead the
@@ -650,13 +654,60 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t total,
                     uint32_t imin, uint32_t imax, uint32_t* chk, uint32_t* maxocc,
                     uint32_t* state, double* seconds) {
-  if (nwg == 0 || K == 0 || kind < 0 || kind > 6) return -1;
+  if (nwg == 0 || K == 0 || kind < 0 || kind > 7) return -1;
   Word S{K + 1}, count{0}, ticket{0}, turn{0}, occ{0}, maxo{0}, adm{0};
+  // kind 7: per group a queue of Q slots {ticket + 1, passes} after (drawn, served)
+  constexpr uint32_t kGroups = 8, kBound = 4;
+  uint32_t Q = 1;
+  while (Q < nwg) Q <<= 1;
+  std::vector<Word> drawn(kind == 7 ? kGroups : 0), served(drawn.size());
+  std::vector<std::atomic<uint64_t>> slots(kind == 7 ? (size_t)kGroups * Q : 0);
+  for (size_t i = 0; i < drawn.size(); ++i) drawn[i] = 0, served[i] = 0;
+  for (auto& w : slots) w.store(0);
+  auto claim = [&](uint32_t g, uint32_t* t) {
+    uint32_t v = served[g].load(std::memory_order_relaxed);
+    while ((int32_t)(drawn[g].load(std::memory_order_relaxed) - v) > 0)
+      if (served[g].compare_exchange_weak(v, v + 1, std::memory_order_acq_rel)) {
+        *t = v;
+        return true;
+      }
+    return false;
+  };
+  auto grant = [&](uint32_t g, uint32_t t, uint32_t k) {
+    auto& slot = slots[(size_t)g * Q + (t & (Q - 1))];
+    while ((uint32_t)slot.load(std::memory_order_acquire) != 0) relax();
+    slot.store(((uint64_t)k << 32) | (t + 1), std::memory_order_release);
+  };
+  auto claim_from = [&](uint32_t first, uint32_t* g, uint32_t* t) {
+    for (;;) {
+      for (uint32_t d = 0; d < kGroups; ++d)
+        if (claim((first + d) % kGroups, t)) {
+          *g = (first + d) % kGroups;
+          return;
+        }
+      relax();
+    }
+  };
+  std::vector<uint32_t> pass(kind == 7 ? nwg : 0, 0);
   const bool alg4 = kind <= 1 || kind == 6, backoff = kind == 1 || kind == 6;
   const bool post_backoff = kind == 1;
   std::atomic<uint64_t> wait_fail{0}, post_fail{0};
 
-  auto wait = [&](Backoff& bo) {
+  auto wait = [&](Backoff& bo, uint32_t b) {
+    if (kind == 7) {
+      uint32_t k = 0;
+      if (count.fetch_add(1, std::memory_order_acq_rel) >= K) {
+        const uint32_t g = b % kGroups;
+        const uint32_t t = drawn[g].fetch_add(1, std::memory_order_acq_rel);
+        auto& slot = slots[(size_t)g * Q + (t & (Q - 1))];
+        uint64_t v;
+        while ((uint32_t)(v = slot.load(std::memory_order_acquire)) != t + 1) relax();
+        k = (uint32_t)(v >> 32);
+        slot.store(0, std::memory_order_release);
+      }
+      pass[b] = k;
+      return;
+    }
     if (alg4) {
       bo.i = bo.imin;
       for (;;) {
@@ -686,7 +737,25 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
       while (!((int32_t)(turn.load(std::memory_order_acquire) - idx) > 0)) relax();
     }
   };
-  auto post = [&](Backoff& bo) {
+  auto post = [&](Backoff& bo, uint32_t b) {
+    if (kind == 7) {
+      const uint32_t g = b % kGroups, k = pass[b];
+      const bool stay = k + 1 < kBound;
+      uint32_t y = 0, t = 0;
+      if (count.load(std::memory_order_acquire) > 2 * K) {
+        count.fetch_sub(1, std::memory_order_acq_rel);
+        if (stay && claim(g, &t)) {
+          grant(g, t, k + 1);
+        } else {
+          claim_from(g + 1, &y, &t);
+          grant(y, t, 0);
+        }
+      } else if (count.fetch_sub(1, std::memory_order_acq_rel) > K) {
+        claim_from(stay ? g : g + 1, &y, &t);
+        grant(y, t, y == g ? k + 1 : 0);
+      }
+      return;
+    }
     if (alg4) {
       bo.i = bo.imin;
       for (;;) {
@@ -711,7 +780,7 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
     uint64_t A = or_ops_for_agent(nwg, total, b);
     uint32_t c = 0;
     for (uint64_t j = 0; j < A; ++j) {
-      wait(bo);
+      wait(bo, b);
       uint32_t o = occ.fetch_add(1) + 1;
       uint32_t m = maxo.load();
       while (o > m && !maxo.compare_exchange_weak(m, o)) {
@@ -719,11 +788,17 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
       c ^= or_sm32(seed ^ (b << 16) ^ (uint32_t)j);
       adm.fetch_add(1);
       occ.fetch_sub(1);
-      post(bo);
+      post(bo, b);
     }
     chk[b] = c;
   });
   *maxocc = maxo.load();
+  if (kind == 7) {  // every local ticket served, every slot taken
+    for (uint32_t g = 0; g < kGroups; ++g)
+      if (drawn[g].load() != served[g].load()) return -3;
+    for (auto& w : slots)
+      if (w.load() != 0) return -3;
+  }
   state[0] = alg4 ? S.load() : count.load();
   state[1] = alg4 ? (uint32_t)std::min<uint64_t>(wait_fail.load(), 0xFFFFFFFFu) : ticket.load();
   state[2] = alg4 ? (uint32_t)std::min<uint64_t>(post_fail.load(), 0xFFFFFFFFu) : turn.load();

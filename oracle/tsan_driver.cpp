@@ -66,7 +66,7 @@ int main() {
     std::vector<uint32_t> want(nwg), got(nwg);
     uint32_t maxocc = 0, state[4];
     or_sem_closed(seed, nwg, total, want.data());
-    for (int kind = 0; kind <= 5; ++kind) {
+    for (int kind = 0; kind <= 7; ++kind) {
       expect(or_sem_threaded(kind, 2, seed, nwg, total, 1, 4, got.data(), &maxocc, state,
                              nullptr) == 0,
              "semaphore rc");

@@ -338,7 +338,7 @@ class Semaphore(_Handle):
     def result(self) -> dict:
         s = [int(x) for x in self.ctx.read(self._state, "u32", 8)]
         r = {"chk": self.ctx.read(self._chk, "u32", self._chk_n), "maxocc": s[0],
-             "state": (s[1], s[2], s[3], s[4]), "count": s[5], "occ": s[6]}
+             "state": (s[1], s[2], s[3], s[4]), "count": s[5], "occ": s[6], "unserved": s[7]}
         if getattr(self, "_with_data", False):
             r["data"] = self.ctx.read(self._data, "u32", self.K)
         return r

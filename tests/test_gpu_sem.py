@@ -9,7 +9,7 @@ from conftest import announce
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive"]
+KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive", "cohort"]
 
 
 def _run(ctx, kind, K, nwg, lanes, total, hold, seed, data=True, **params):
@@ -35,6 +35,8 @@ def _check(r, kind, K, nwg, total, seed):
     s_or_count, ticket, turn, adm = r["state"]
     assert adm == total
     assert r["occ"] == 0
+    if kind == "cohort":
+        assert r["unserved"] == 0  # every local ticket served
     if kind.startswith("spin"):
         assert s_or_count == K + 1
     elif kind in ("counters", "adaptive"):
@@ -53,7 +55,7 @@ def test_small(ctx, kind, K):
     _check(r, kind, K, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort"])
 @pytest.mark.parametrize("K", [1, 4, 32, 256])
 def test_full_size(ctx, kind, K):
     # 2048 workgroups, 2^20 wait/post pairs, holds uniform in [0, 2000] cycles
@@ -98,13 +100,14 @@ def test_spin_as_mutex(ctx, kind):
     _check(r, kind, 1, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "cohort"])
 def test_capacity_above_agents_never_queues(ctx, kind):
     r = _run(ctx, kind, 64, 16, 64, 4000, 50, 7)
     _check(r, kind, 64, 16, 4000, 7)
 
 
-@pytest.mark.parametrize("kind", ["spin_backoff", "ticket", "sleep", "counters", "adaptive"])
+@pytest.mark.parametrize("kind", ["spin_backoff", "ticket", "sleep", "counters", "adaptive",
+                                  "cohort"])
 @pytest.mark.parametrize("K", [1, 32, 256])
 def test_coherent_critical_sections(ctx, kind, K):
     """coherent_cs: wait and post skip the cache maintenance (the workload's critical
@@ -112,3 +115,13 @@ def test_coherent_critical_sections(ctx, kind, K):
     nwg, total, seed = (256, 1 << 13, 7) if kind == "spin_backoff" else (2048, 1 << 18, 7)
     r = _run(ctx, kind, K, nwg, 256, total, 2000, seed, coherent_cs=1)
     _check(r, kind, K, nwg, total, seed)
+
+
+@pytest.mark.parametrize("passes", [1, 2, 64, 255])
+def test_cohort_pass_bounds(ctx, passes):
+    """The cohort semaphore with every pass bound (1: every hand-over goes to another XCD
+    with a writeback) keeps the guarded data exact at K = 1 and K = 32."""
+    for K in (1, 32):
+        nwg, total, seed = 2048, 1 << 16, 11
+        r = _run(ctx, "cohort", K, nwg, 256, total, 500, seed, cohort_passes=passes)
+        _check(r, "cohort", K, nwg, total, seed)

@@ -3,9 +3,9 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 
 import pytest
 
-from oracle.modelcheck import (BarrierModel, CohortLockModel, CondModel, FASemModel,
-                               MCSLockModel, MutexModel, QueueLockModel, SpinSemModel,
-                               WeightedSemModel, XcdBarrierModel, explore)
+from oracle.modelcheck import (BarrierModel, CohortLockModel, CohortSemModel, CondModel,
+                               FASemModel, MCSLockModel, MutexModel, QueueLockModel,
+                               SpinSemModel, WeightedSemModel, XcdBarrierModel, explore)
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
@@ -270,3 +270,28 @@ def test_mcs_lock_mutants_deadlock(mutant):
 def test_mcs_lock_entering_without_spinning_breaks_exclusion():
     r = explore(MCSLockModel(2, 2, mutant="no_spin"))
     assert r.violation and "mutual exclusion" in r.violation
+
+
+# ---- cohort semaphore (Algorithm 5's count, a queue per XCD, local hand-over) -------------
+
+@pytest.mark.parametrize("K,placement,B,small_q", [(1, (0, 1, 0), 2, False),
+                                                   (1, (0, 1, 0), 3, False),
+                                                   (1, (0, 1, 0), 2, True),
+                                                   (1, (0, 0, 0), 2, False),
+                                                   (2, (0, 1, 0), 2, True)])
+def test_cohort_semaphore_correct(K, placement, B, small_q):
+    """Occupancy never above K, final state quiescent, and with K = 1 no update of the
+    guarded word lost through the L2s (local hand-overs skip the writeback)."""
+    r = explore(CohortSemModel(K, placement, 2, B, small_q=small_q))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("mutant", ["no_remote_writeback", "no_acquire"])
+def test_cohort_semaphore_mutants_lose_updates(mutant):
+    r = explore(CohortSemModel(1, (0, 1, 0), 2, 2, mutant=mutant))
+    assert r.violation and "lost update" in r.violation
+
+
+def test_cohort_semaphore_unchecked_claim_deadlocks():
+    r = explore(CohortSemModel(1, (0, 1, 0), 2, 2, mutant="claim_unchecked"))
+    assert r.deadlock

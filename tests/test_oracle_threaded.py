@@ -51,7 +51,7 @@ def test_cohort_mutex_threaded_with_local_passes(L):
 
 
 @pytest.mark.parametrize("kind", ["spin", "spin_backoff", "spin_backoff_wait_only", "ticket",
-                                  "sleep", "counters", "adaptive"])
+                                  "sleep", "counters", "adaptive", "cohort"])
 @pytest.mark.parametrize("K", [1, 2, 4, 32])
 def test_sem_threaded_invariants(kind, K):
     seed, nwg, total = 7, 12, 2400
@@ -83,6 +83,17 @@ def test_spin_semaphore_posts_do_not_starve_at_2048_agents(K):
     s, wait_fails, post_fails, admissions = r["state"]
     assert s == K + 1 and admissions == total
     assert post_fails <= max(wait_fails, 1)
+
+
+@pytest.mark.parametrize("K", [1, 4, 32, 256])
+def test_cohort_semaphore_at_2048_agents(K):
+    """Algorithm 5's count with a queue per group: every pair completes, the bound holds,
+    every local ticket is served and every grant slot taken (rc -3 otherwise)."""
+    seed, nwg, total = 0xC0FFEE, 2048, 1 << 14
+    r = oracle.sem_threaded("cohort", K, seed, nwg, total)
+    assert r["rc"] == 0 and 1 <= r["maxocc"] <= K
+    assert (r["chk"] == oracle.sem_closed(seed, nwg, total)).all()
+    assert r["state"] == (0, 0, 0, total)
 
 
 def test_hardware_threads_reported():
