@@ -102,11 +102,12 @@ enum sp_sem_kind {
                            /* interval learned per workgroup from the rate at which the */
                            /* posts counter advanced while it waited, so the queue's    */
                            /* far end stops loading the counter's line                  */
-  SP_SEM_COHORT = 6,       /* Algorithm 5's count with a queue per XCD: a post hands its */
-                           /* unit to the oldest waiter of its own XCD without an L2     */
-                           /* writeback (at most cohort_passes times in a row), else    */
-                           /* writes back and hands it to another XCD's waiter; each    */
-                           /* waiter polls its own slot                                  */
+  SP_SEM_COHORT = 6,       /* Algorithm 5's count with a queue per XCD: a post writes    */
+                           /* back, decrements, and hands its unit to the oldest waiter  */
+                           /* of its own XCD (at most cohort_passes times in a row), else */
+                           /* to another XCD's waiter; each waiter polls its own slot.   */
+                           /* K = 1: a post that sees a waiter counted skips the writeback */
+                           /* for a waiter of its own XCD (same L2)                      */
   SP_SEM_DEFAULT = 15
 };
 

@@ -233,13 +233,16 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
   wave_stores_complete();
   __syncthreads();
   if constexpr (KIND == SP_SEM_COHORT) {
-    // Hand the unit on.  count > 2K: at least K + 1 workgroups wait or are inside and at
-    // most K - 1 other posts can decrement count first, so a waiter is sure to exist:
-    // decrement, then grant the oldest waiter of this XCD without an L2 writeback (it
-    // reads through the same L2) unless the unit has passed cohort_bound times in a row
-    // here, else write back and grant the first other XCD with a waiter.  Otherwise write
-    // back first, then decrement (Algorithm 5's post); a waiter beyond capacity then gets
-    // the unit, else it returns to the free count.
+    // Hand the unit on.  Algorithm 5's post: write back, then decrement count; if a waiter
+    // is beyond capacity the unit goes to the oldest waiter of this XCD while the unit has
+    // passed fewer than cohort_bound times in a row here, else to the first other XCD with
+    // a waiter.  K = 1 and count > 1 (loaded): the poster holds the only unit, so no other
+    // post can lower count before its own decrement, which therefore returns more than 1:
+    // a waiter exists, and one of this XCD's (it reads through the same L2) takes the unit
+    // without the writeback.  The decrement has completed before the grant is written, so
+    // the next holder's load of count already includes it.  For K >= 2 a loaded count
+    // proves nothing -- the other K - 1 units can change hands any number of times before
+    // the decrement lands -- so every post writes back first.
     if (is_leader()) {
       bool ok = true;
       Wait w(ctl, 0);
@@ -253,9 +256,10 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
       const uint32_t c = ld_relaxed(s.count);
       const uint32_t served = ld_relaxed(cq_served(s, x));
       const uint32_t drawn = ld_relaxed(cq_drawn(s, x));
-      if (c > 2 * s.K) {
+      if (s.K == 1 && c > 1) {
         add_relaxed(s.count, 0xFFFFFFFFu);
         if (stay && detail::cq_claim_at(s, x, served, drawn, &t, &slot_v)) {
+          wave_stores_complete();  // the decrement is done before the grant store
           y = x;
           kk = k + 1;
         } else {

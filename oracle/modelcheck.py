@@ -693,14 +693,15 @@ class CohortSemModel:
     old = fetch-and-add(count, 1); old < K: enter with a fresh unit; otherwise draw a
     local ticket lt of one's own XCD's queue and poll grant slot lt mod Q of that queue
     until it holds lt + 1, with the number of local passes k of the unit it receives.
-    post: c = load(count).  If c > 2K at least K + 1 workgroups wait or are inside, and at
-    most K - 1 other posts can decrement count before this one, so this post is sure to
-    find a waiter ("hand-over mode"): decrement count, then, if k + 1 < B and one's own XCD
-    has an unserved ticket (claimed with a compare-and-swap on its served counter), grant
-    it with k + 1 and no L2 writeback (both workgroups use the same L2); otherwise write
-    the L2 back and grant the first XCD after one's own that has an unserved ticket, with
-    k = 0.  If c <= 2K: write back first, then decrement; old > K: grant a waiter of any
-    XCD (preferring one's own); else the unit returns to the free count.
+    post: c = load(count).  K = 1 and c > 1: the poster holds the only unit, so no other
+    post lowers count before its own decrement, which is sure to find a waiter
+    ("hand-over mode"): decrement count, then, if k + 1 < B and one's own XCD has an
+    unserved ticket (claimed with a compare-and-swap on its served counter), grant it
+    with k + 1 and no L2 writeback (both workgroups use the same L2); otherwise write the
+    L2 back and grant the first XCD after one's own that has an unserved ticket, with
+    k = 0.  Otherwise (and always for K >= 2): write back first, then decrement;
+    old > K: grant a waiter of any XCD (preferring one's own); else the unit returns to
+    the free count.
     Units: free (K - inside - waiting, when positive) + held + in transit = K throughout;
     the B bound sends every unit to another XCD after at most B local hand-overs.
 
@@ -714,7 +715,10 @@ class CohortSemModel:
     mutant 'no_remote_writeback': a hand-over to another XCD skips the writeback;
     mutant 'no_acquire': the admitted waiter does not invalidate;
     mutant 'claim_unchecked': a post claims the next local slot even when no ticket for
-    it has been drawn."""
+    it has been drawn;
+    mutant 'predict_2k': hand-over mode for any K whenever the loaded count exceeds 2K
+    (the other K - 1 units can change hands before the decrement lands, so the post may
+    find no waiter left: reported as a deadlock)."""
 
     (W_CNT, W_LT, W_POLL, ACQ, CS_LD, CS_ST, P_PRED, P_DEC_H, P_LOCAL, P_WB_R, P_REMOTE,
      P_WB_S, P_DEC_S, P_ANY, P_GRANT, DONE) = range(16)
@@ -788,7 +792,10 @@ class CohortSemModel:
         if pc == self.CS_ST:
             return S(l2=self._set(l2, x, (tmp + 1, True))), (self.P_PRED, j, lt, k, tmp, gx, gs)
         if pc == self.P_PRED:  # leaving the critical section; predict from count
-            nxt = self.P_DEC_H if count > 2 * K else self.P_WB_S
+            if self.mutant == "predict_2k":
+                nxt = self.P_DEC_H if count > 2 * K else self.P_WB_S
+            else:
+                nxt = self.P_DEC_H if (K == 1 and count > 1) else self.P_WB_S
             return S(inside=inside - 1), (nxt, j, lt, k, tmp, gx, gs)
         if pc == self.P_DEC_H:
             nxt = self.P_LOCAL if k + 1 < self.B else self.P_WB_R

@@ -642,10 +642,11 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 // enters once posts + K > t), 5 the same admission rule with proportional waiting (a
 // waiter d posts short of admission yields (d - 1) / 4 extra times per poll), 6 Algorithm
 // 4 with backoff in wait only (Section 5's prose: post proceeds aggressively), 7 Algorithm
-// 5's count with a queue per group of agents (agent b in group b mod 8): a post that
-// finds more than 2K agents counted hands its unit to the oldest waiter of its own group
-// (at most 4 times in a row for one unit), else to the first other group with a waiter;
-// otherwise it decrements first and hands over only if a waiter is counted beyond K.
+// 5's count with a queue per group of agents (agent b in group b mod 8): a post
+// decrements count and hands its unit over only if a waiter is counted beyond K, to the
+// oldest waiter of its own group (at most 4 times in a row for one unit), else to the
+// first other group with a waiter; for K = 1 a post that reads count above 1 knows
+// before its decrement that a waiter exists.
 // Each pair: wait, occupancy tracking, checksum update, admission count, post.
 // out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}; for the
 // Algorithm 4 kinds ticket and turn are unused and state[1] / state[2] report instead the
@@ -742,7 +743,9 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
       const uint32_t g = b % kGroups, k = pass[b];
       const bool stay = k + 1 < kBound;
       uint32_t y = 0, t = 0;
-      if (count.load(std::memory_order_acquire) > 2 * K) {
+      // K = 1 only: the poster holds the only unit, so a loaded count above 1 is still
+      // above 1 when its own decrement lands (a waiter exists)
+      if (K == 1 && count.load(std::memory_order_acquire) > 1) {
         count.fetch_sub(1, std::memory_order_acq_rel);
         if (stay && claim(g, &t)) {
           grant(g, t, k + 1);

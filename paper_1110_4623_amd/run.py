@@ -5,7 +5,7 @@
   python -m paper_1110_4623_amd.run sem --kind sleep --K 32 --nwg 2048
   python -m paper_1110_4623_amd.run serve --rate 1e5 --n 200000
   python -m paper_1110_4623_amd.run copy --bytes 1073741824
-  python -m paper_1110_4623_amd.run micro --op ld --T 1048576 --stride 128 --n 16
+  python -m paper_1110_4623_amd.run micro --op ld --T 1048576 --stride 128 --ops 16
 
 Meant for profilers (one workload per process) and quick checks.  The package decides
 at import whether to use PyTorch's HIP runtime: run with SP_NO_TORCH=1 in the environment
@@ -29,7 +29,7 @@ def main(argv=None) -> int:
     ap.add_argument("--T", type=int, default=1 << 20)
     ap.add_argument("--stride", type=int, default=128)
     ap.add_argument("--mode", default="per_lane")
-    ap.add_argument("--n", type=int, default=16)
+    ap.add_argument("--ops", type=int, default=16)
     ap.add_argument("--kind", default=None)
     ap.add_argument("--nwg", type=int, default=2048)
     ap.add_argument("--lanes", type=int, default=256)
@@ -89,9 +89,9 @@ def main(argv=None) -> int:
             import sp_inputs
             perm = sp_inputs.permutation(a.T, a.seed)
             finals, total, st = api.bench_atomic(ctx, a.op, a.nwg, a.lanes, a.T, a.stride,
-                                                 a.mode, a.n, a.seed, perm)
+                                                 a.mode, a.ops, a.seed, perm)
             out.update(op=a.op, nwg=a.nwg, lanes=a.lanes, T=a.T, stride=a.stride, mode=a.mode,
-                       n=a.n, accesses=int(st["ops"]), ms=st["kernel_ms"])
+                       ops=a.ops, accesses=int(st["ops"]), ms=st["kernel_ms"])
         else:
             src, dst = ctx.zeros(a.bytes // 4), ctx.zeros(a.bytes // 4)
             st = api.copy(ctx, dst, src, a.bytes, reps=3)

@@ -295,3 +295,50 @@ def test_cohort_semaphore_mutants_lose_updates(mutant):
 def test_cohort_semaphore_unchecked_claim_deadlocks():
     r = explore(CohortSemModel(1, (0, 1, 0), 2, 2, mutant="claim_unchecked"))
     assert r.deadlock
+
+
+def _advance(model, sh, los, a, until, limit=64):
+    """Step agent `a` alone until its program counter is `until` (or it is done)."""
+    for _ in range(limit):
+        if los[a][0] == until or model.done(los[a]):
+            return sh, los
+        sh, lo = model.step(a, sh, los[a])
+        los = los[:a] + (lo,) + los[a + 1:]
+    raise AssertionError(f"agent {a} did not reach {until}")
+
+
+def _predict_schedule(model):
+    """K = 2, five workgroups on one XCD: 0 and 1 enter, 2-4 queue; 0 leaves its critical
+    section and predicts from count = 5 > 2K; then 1, 2, 3, 4 pass the other unit along
+    and finish; only then does 0's decrement land."""
+    M = CohortSemModel
+    sh, los = model.init()
+    for a in range(5):
+        sh, los = _advance(model, sh, los, a, M.ACQ if a < 2 else M.W_POLL)
+    sh, los = _advance(model, sh, los, 0, M.P_PRED)
+    sh, lo = model.step(0, sh, los[0])  # the prediction
+    los = (lo,) + los[1:]
+    for a in range(1, 5):
+        sh, los = _advance(model, sh, los, a, M.DONE, limit=256)
+    return sh, los
+
+
+def test_cohort_semaphore_count_prediction_unsafe_for_k2():
+    """A post that decides from a loaded count > 2K that a waiter exists (and skips the
+    writeback) can find none left: the other unit served all three waiters first."""
+    model = CohortSemModel(2, (0, 0, 0, 0, 0), 1, 2, mutant="predict_2k")
+    sh, los = _predict_schedule(model)
+    assert all(model.done(lo) for lo in los[1:])
+    for _ in range(8):  # workgroup 0 decrements, then searches every queue forever
+        sh2, lo = model.step(0, sh, los[0])
+        sh, los = sh2, (lo,) + los[1:]
+    assert los[0][0] == CohortSemModel.P_REMOTE and sh[0] == 0
+    assert model.step(0, sh, los[0]) == (sh, los[0])  # no ticket to claim: stuck
+
+
+def test_cohort_semaphore_no_prediction_for_k2():
+    """The shipped rule (hand-over mode only for K = 1) finishes the same schedule."""
+    model = CohortSemModel(2, (0, 0, 0, 0, 0), 1, 2)
+    sh, los = _predict_schedule(model)
+    sh, los = _advance(model, sh, los, 0, CohortSemModel.DONE, limit=256)
+    assert all(model.done(lo) for lo in los) and sh[0] == 0 and sh[6] == 0
