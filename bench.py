@@ -311,6 +311,18 @@ def main() -> int:
                          "A_dist_atomics_per_s_2p20_words": round(a_dist, 1),
                          "B_stream_read_GB_per_s": round(b_stream / 1e9, 1),
                          "L_coh_one_way_us": round(sig_us, 4)},
+            # The mutex and semaphore against their own bounds: a contended semaphore
+            # pair makes two read-modify-writes on contended words (one per wait, one per
+            # post, in every kind here), so at most A1 / 2 pairs per second; a lock
+            # hand-over moves ownership at least one one-way hop, so at most 1 / L_coh
+            # acquisitions per second (the critical section's own time left out).
+            "bounds": {
+                "semaphore_k32_pairs_bound_per_s": round(a1 / 2, 1),
+                "semaphore_k32_default_kind_frac": round(sem_def_rate / (a1 / 2), 4),
+                "semaphore_k32_alg5_frac": round(sem_rate / (a1 / 2), 4),
+                "mutex_acq_bound_per_s": round(1e6 / sig_us, 1),
+                "mutex_default_kind_frac": round(mtx_def_rate * sig_us * 1e-6, 4),
+                "mutex_ticket_frac": round(mtx_rate * sig_us * 1e-6, 4)},
             # other views of the headline kernel (not bounds)
             "barrier_arrivals_vs_A1": round(arrivals / a1, 4),
             "barrier_hbm_view": {"algorithmic_bytes_per_launch": alg_bytes,

@@ -186,6 +186,8 @@ int sp_init(int device, sp_ctx** out) {
   if ((e = hipEventCreate(&ctx->ev1)) != hipSuccess) return fail(e);
   if ((e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
     return fail(e);
+  if ((e = hipStreamCreateWithFlags(&ctx->setup_stream, hipStreamNonBlocking)) != hipSuccess)
+    return fail(e);
   if (spi::static_scratch_setup(ctx) != SP_OK) return fail(hipErrorInvalidSymbol);
   // Count XCDs: launch 8 workgroups per CU and collect the distinct XCC ids.
   {
@@ -245,12 +247,13 @@ int sp_fini(sp_ctx* ctx) {
   // then release in the reverse order of sp_init.
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  (void)hipStreamDestroy(ctx->setup_stream);
   (void)hipStreamDestroy(ctx->capture_stream);
   (void)hipEventDestroy(ctx->ev1);
   (void)hipEventDestroy(ctx->ev0);
   (void)hipFree(ctx->d_scratch);
   (void)hipFree(ctx->d_err);
-  ctx->capture_stream = nullptr;
+  ctx->capture_stream = ctx->setup_stream = nullptr;
   ctx->ev0 = ctx->ev1 = nullptr;
   ctx->d_err = ctx->d_scratch = nullptr;
   ctx->closed = true;

@@ -158,7 +158,8 @@ int place_near(sp_barrier* b, uint32_t G, bool mail, bool rel) {
   SP_HIP(ctx, hipMalloc(&scratch.p, words * sizeof(uint32_t)));
   uint32_t* claims = scratch.as<uint32_t>();
   uint32_t* lat = claims + G;
-  hipStream_t s = nullptr;
+  // the library's own stream: the probe neither joins nor waits for the caller's work
+  hipStream_t s = ctx->setup_stream;
   SP_CHECK(spi::fill_u32(ctx, claims, words, 0, s));
   SP_CHECK(spi::fill_u32(ctx, b->d_near, b->near_words, 0, s));
   const uint64_t deadline = (uint64_t)ctx->wall_khz * 50;  // 50 ms
@@ -167,7 +168,8 @@ int place_near(sp_barrier* b, uint32_t G, bool mail, bool rel) {
   SP_HIP(ctx, hipGetLastError());
   SP_HIP(ctx, hipStreamSynchronize(s));
   std::vector<uint32_t> h((size_t)G * kNearChunks);
-  SP_HIP(ctx, hipMemcpy(h.data(), lat, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  SP_HIP(ctx, hipMemcpyAsync(h.data(), lat, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  SP_HIP(ctx, hipStreamSynchronize(s));
   for (uint32_t v : h)
     if (v == 0) return SP_OK;
   std::vector<bool> used(kNearChunks, false);

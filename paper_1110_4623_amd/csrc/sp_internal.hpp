@@ -35,6 +35,7 @@ struct sp_ctx {
   uint64_t static_scratch_words = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t capture_stream = nullptr;
+  hipStream_t setup_stream = nullptr;  // work done while creating objects (not the caller's)
   sp_default_entry defaults[3][2];
 };
 

@@ -58,6 +58,9 @@ def test_one_step_prints_the_contract_line():
               "B_stream_read_GB_per_s", "L_coh_one_way_us"):
         assert m["ceilings"][k] > 0, k
     assert m["central_barrier_16wg_x64_1000_rounds_us_per_round"] > 0
+    for k in ("semaphore_k32_default_kind_frac", "semaphore_k32_alg5_frac",
+              "mutex_default_kind_frac", "mutex_ticket_frac"):
+        assert 0 < m["bounds"][k] < 1, k
     assert m["central_barrier_16wg_checksums_deterministic"] is True
     assert d["env"]["arch"].startswith("gfx950")
     assert "packed-fp32-ops" in d["env"]["hipcc_flags"]
