@@ -160,6 +160,8 @@ def semaphore_candidates():
     out += [("sleep", {"poll_sleep": ps}) for ps in (1, 4, 16)]
     out += [("counters", {"poll_sleep": ps}) for ps in (0, 1, 4, 16, 64)]
     out += [("adaptive", {"poll_sleep": ps}) for ps in (0, 1, 4)]
+    out += [("cohort", {"poll_sleep": ps, "cohort_passes": cp}) for ps in (0, 4)
+            for cp in (16, 64)]
     return out
 
 
