@@ -48,6 +48,7 @@ METRIC = "µs/barrier round, mutex & semaphore ops/s vs #WGs; persistent-queue p
 NWG, LANES, ROUNDS = 2048, 256, 10_000
 C1_NWG, C1_LANES, C1_ROUNDS = 16, 64, 1000
 MUTEX_TOTAL, SEM_TOTAL, SEM_K = 1 << 20, 1 << 20, 32
+CURVE_NWG, CURVE_OPS = (64, 256, 1024), 1 << 18
 SERVE_RATE, SERVE_N, SERVE_NWG = 1e5, 200_000, 1024
 
 
@@ -69,7 +70,7 @@ def measured_traffic(kernel_sources_dir: str) -> float | None:
         return None
 
 
-def cpu_baseline(headline_chk, config1_chk, budget_s: float = 20.0) -> dict:
+def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20.0) -> dict:
     """The CPU oracle on this host, and the check of this run's barrier checksums against
     it (both outside the timed region).
 
@@ -77,7 +78,9 @@ def cpu_baseline(headline_chk, config1_chk, budget_s: float = 20.0) -> dict:
     protocol with 2048 agents in 8 groups on the same hash exchange -- all the rounds of
     the workload when they fit the time budget, else the number that does.  Check: the
     closed form of the hash exchange for the headline configuration (2048 x 10^4, seed 42)
-    and for the 16-workgroup, 1000-round configuration, element by element."""
+    and for the 16-workgroup, 1000-round configuration, element by element; and every
+    result of the curves against #WGs (barrier checksums, mutex words, semaphore
+    admission checksums) against its closed form."""
     import oracle
     oracle.lib()
     probe_rounds = 256
@@ -90,13 +93,21 @@ def cpu_baseline(headline_chk, config1_chk, budget_s: float = 20.0) -> dict:
         cores = os.cpu_count() or 1
     ref = oracle.barrier_closed(42, NWG, ROUNDS)
     ref1 = oracle.barrier_closed(42, C1_NWG, C1_ROUNDS)
+    curves_ok = None
+    if curve_out is not None:
+        curves_ok = True
+        for nwg, (bchk, words, schk) in curve_out.items():
+            curves_ok &= bool((bchk == oracle.barrier_closed(42, nwg, ROUNDS)).all())
+            curves_ok &= bool((words == oracle.mutex_closed(42, nwg, CURVE_OPS, 1, 16)).all())
+            curves_ok &= bool((schk == oracle.sem_closed(42, nwg, CURVE_OPS)).all())
     return {"value": secs2 * 1e6 / rounds, "unit": "µs/round", "cores": cores,
             "kind": "oracle", "threads": NWG,
             "sample": f"per-XCD flag protocol, {NWG} std::thread agents (8 groups of 4 CUs), "
                       f"{rounds} of the {ROUNDS} rounds of the hash exchange; {secs2:.1f} s",
             "ok": rc == 0 and rc2 == 0,
             "headline_checksums_match_oracle": bool((headline_chk == ref).all()),
-            "config1_checksums_match_oracle": bool((config1_chk == ref1).all())}
+            "config1_checksums_match_oracle": bool((config1_chk == ref1).all()),
+            "curves_match_oracle": curves_ok}
 
 
 def environment(ctx, resident_per_cu: int) -> dict:
@@ -219,6 +230,27 @@ def main() -> int:
     _, st_s = sp.stream_read(ctx, sbuf, 1 << 30, reps=3)
     b_stream = 3 * (1 << 30) / (st_s["kernel_ms"] * 1e-3)
     sbuf.close()
+    # The metric's "vs #WGs": the library's default barrier, mutex and semaphore at fewer
+    # workgroups (the barrier's 10^4 rounds of the hash exchange; one lock x 16 words and
+    # K = 32 with 2^18 operations), each result kept for the check against the oracle.
+    curves = {"barrier_default_us_per_round": {}, "mutex_default_acq_per_s": {},
+              "semaphore_k32_default_pairs_per_s": {}}
+    curve_out = {}
+    for n in CURVE_NWG:
+        b = sp.Barrier(ctx, "default", n)
+        bchk, bst = b.run_hash(LANES, ROUNDS, 42)
+        b.close()
+        m = sp.Mutex(ctx, "default", 1, 16)
+        words, mst, _ = m.run(n, LANES, CURVE_OPS, 1000, 42)
+        m.close()
+        s = sp.Semaphore(ctx, "default", SEM_K)
+        sres = s.run(n, LANES, CURVE_OPS, 2000, 42, track=False)
+        s.close()
+        curves["barrier_default_us_per_round"][n] = round(bst["kernel_ms"] * 1e3 / ROUNDS, 4)
+        curves["mutex_default_acq_per_s"][n] = round(CURVE_OPS / (mst["kernel_ms"] * 1e-3), 1)
+        curves["semaphore_k32_default_pairs_per_s"][n] = round(
+            CURVE_OPS / (sres["stats"]["kernel_ms"] * 1e-3), 1)
+        curve_out[n] = (bchk, words, sres["chk"])
 
     bar_ms = float(np.mean([r["bar_ms"] for r in results]))
     us_round = bar_ms * 1e3 / ROUNDS
@@ -300,6 +332,7 @@ def main() -> int:
             "serve_launch_per_request_req_per_s": med("serve_launch", "req_per_s"),
             "serve_results_identical": all(r["serve_same"] for r in results),
             "shader_clock_mhz_before_after": [round(clock_before, 1), round(clock_after, 1)],
+            "curves_vs_nwg": curves,
             # Section 4's card and the ceilings the primitives are compared with
             "machine_card_2048wg": {
                 "atomic_to_volatile_contentious": mcard["atomic_to_volatile"],
@@ -349,7 +382,7 @@ def main() -> int:
         "env": environment(ctx, results[0]["bar_occ"]),
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(results[0]["bar_chk"], c1_chk)
+        line["cpu_baseline"] = cpu_baseline(results[0]["bar_chk"], c1_chk, curve_out)
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0

@@ -62,6 +62,9 @@ def test_one_step_prints_the_contract_line():
               "mutex_default_kind_frac", "mutex_ticket_frac"):
         assert 0 < m["bounds"][k] < 1, k
     assert m["central_barrier_16wg_checksums_deterministic"] is True
+    for name in ("barrier_default_us_per_round", "mutex_default_acq_per_s",
+                 "semaphore_k32_default_pairs_per_s"):
+        assert len(m["curves_vs_nwg"][name]) == 3 and min(m["curves_vs_nwg"][name].values()) > 0
     assert d["env"]["arch"].startswith("gfx950")
     assert "packed-fp32-ops" in d["env"]["hipcc_flags"]
 
@@ -84,3 +87,13 @@ def test_cpu_baseline_leg_checks_checksums_against_the_oracle():
     bad[7] ^= 1
     d = bench.cpu_baseline(bad, ref1, budget_s=0.5)
     assert not d["headline_checksums_match_oracle"]
+    # the curves against #WGs: every result checked, one wrong word is caught
+    n = 64
+    good = {n: (oracle.barrier_closed(42, n, bench.ROUNDS),
+                oracle.mutex_closed(42, n, bench.CURVE_OPS, 1, 16),
+                oracle.sem_closed(42, n, bench.CURVE_OPS))}
+    assert bench.cpu_baseline(ref, ref1, good, budget_s=0.5)["curves_match_oracle"] is True
+    words = good[n][1].copy()
+    words[0, 3] += 1
+    bad_curve = {n: (good[n][0], words, good[n][2])}
+    assert bench.cpu_baseline(ref, ref1, bad_curve, budget_s=0.5)["curves_match_oracle"] is False
