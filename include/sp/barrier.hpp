@@ -219,31 +219,43 @@ struct XcdLocal {
   uint32_t slot;     // registration order on the CU (0 = CU leader)
   uint32_t rank;     // rank of the CU among its XCD's CUs with members
   uint32_t mail;     // the copy of the XCD stamps this workgroup polls (xcopies > 0)
-  // word offsets, resolved once in round 0 from the placement tables, so that later
-  // rounds keep no table in registers: this XCD's arrival block in larrive, the stamps
-  // this workgroup polls in xmail, this CU's release line in lrelease
-  uint32_t block_off;
-  uint32_t stamps_off;
-  uint32_t rel_off;
+  // Resolved once in round 0 from the barrier's state and its placement tables, so that
+  // later rounds read nothing from the kernel's arguments (reloading those fields inside
+  // the round, or indexing the tables there, was measured to cost ~10 % of a round):
+  uint32_t* block;         // this XCD's block of arrival flags
+  const uint32_t* stamps;  // the stamps this workgroup polls: its copy, or xarrive
+  uint32_t* rel;           // this CU's release line
+  uint32_t* mail_x;        // xmail + x: the master stores copy c at mail_x + pub[c]
+  uint32_t* xarrive_x;     // the XCD's stamp line when there are no copies
+  uint32_t groups, copies, sstride, fenced, poll_sleep;
 };
+
+// A pointer that is the same for the whole workgroup, in scalar registers.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
 // The master's stores of its stamp: copy c at pub[c] + the XCD's index in xmail.
 constexpr uint32_t kMaxCopies = 256;
 
-__device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, const Ctl& ctl,
-                                         const XcdLocal& L, const uint32_t* pub) {
+__device__ __forceinline__ bool xcd_wait(uint32_t stamp, const Ctl& ctl, const XcdLocal& L,
+                                         const uint32_t* pub) {
   __shared__ uint32_t s_ok;
-  const uint32_t X = s.groups;
   // The registration is the same for the whole workgroup: keep it in scalar registers.
-  const uint32_t x = __builtin_amdgcn_readfirstlane(L.x);
+  const uint32_t X = __builtin_amdgcn_readfirstlane(L.groups);
   const uint32_t k = __builtin_amdgcn_readfirstlane(L.k);
   const uint32_t members = __builtin_amdgcn_readfirstlane(L.members);
   const uint32_t xmask = __builtin_amdgcn_readfirstlane(L.xmask);
   const uint32_t slot = __builtin_amdgcn_readfirstlane(L.slot);
-  uint32_t* block = s.larrive + __builtin_amdgcn_readfirstlane(L.block_off);
-  Wait w(ctl, s.poll_sleep);
+  const uint32_t fenced = __builtin_amdgcn_readfirstlane(L.fenced);
+  uint32_t* block = uniform_ptr(L.block);
+  Wait w(ctl, __builtin_amdgcn_readfirstlane(L.poll_sleep));
   int ok = 1;
   __syncthreads();
-  const uint32_t C = s.xcopies;
+  const uint32_t C = __builtin_amdgcn_readfirstlane(L.copies);
   if (k == 0) {
     // XCD master: gather the XCD's arrivals, write the XCD's L2 back once, publish (in
     // every copy of the stamps, by the first wavefront after its writeback).
@@ -252,20 +264,21 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
     if (!ok) return false;
     if (C == 0) {
       if (is_leader()) {
-        if (s.fenced) fence_release();
-        st_relaxed(s.xarrive + (size_t)x * s.stride, stamp);
+        if (fenced) fence_release();
+        st_relaxed(uniform_ptr(L.xarrive_x), stamp);
       }
     } else if (threadIdx.x < 64) {
-      if (s.fenced) fence_release();
-      for (uint32_t c = threadIdx.x; c < C; c += 64) st_relaxed(s.xmail + pub[c] + x, stamp);
+      if (fenced) fence_release();
+      uint32_t* mail_x = uniform_ptr(L.mail_x);
+      for (uint32_t c = threadIdx.x; c < C; c += 64) st_relaxed(mail_x + pub[c], stamp);
     }
   } else if (is_leader()) {
     st_relaxed(block + (size_t)k * kArriveWords, stamp);
   }
   // The populated XCDs' stamps: one line each, or packed in this CU's copy.
-  const uint32_t* stamps = C ? s.xmail + __builtin_amdgcn_readfirstlane(L.stamps_off) : s.xarrive;
-  const uint32_t sstride = C ? 1 : s.stride;
-  if (!s.fenced) {
+  const uint32_t* stamps = uniform_ptr(L.stamps);
+  const uint32_t sstride = __builtin_amdgcn_readfirstlane(L.sstride);
+  if (!fenced) {
     // Coherent data: no cache maintenance, so nothing is shared per CU; every workgroup
     // polls the populated XCDs' stamps itself (two flag hops per round).
     if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
@@ -273,7 +286,7 @@ __device__ __forceinline__ bool xcd_wait(const BarrierState& s, uint32_t stamp, 
     return __syncthreads_and(ok);
   }
   // this CU's release line
-  uint32_t* rel = s.lrelease + __builtin_amdgcn_readfirstlane(L.rel_off);
+  uint32_t* rel = uniform_ptr(L.rel);
   if (slot == 0) {
     // CU leader: once every populated XCD has published, invalidate for the CU and
     // release it.  The invalidation has to follow the last XCD's writeback: a line that
@@ -330,9 +343,17 @@ __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl,
       if (ld_relaxed(s.xcount + i) != 0) mask |= 1u << i;
     L.xmask = mask;
     L.mail = s.xcopies ? (xcc + X * L.rank) % s.xcopies : 0;
-    L.block_off = s.xoff[xcc];
-    L.stamps_off = s.xcopies ? s.moff[L.mail % X] + (L.mail / X) * s.xmstep : 0;
-    L.rel_off = s.roff[xcc] + L.rank * s.stride;
+    L.block = s.larrive + s.xoff[xcc];
+    L.stamps = s.xcopies ? s.xmail + s.moff[L.mail % X] + (size_t)(L.mail / X) * s.xmstep
+                         : s.xarrive;
+    L.sstride = s.xcopies ? 1 : s.stride;
+    L.rel = s.lrelease + s.roff[xcc] + (size_t)L.rank * s.stride;
+    L.mail_x = s.xmail + xcc;
+    L.xarrive_x = s.xarrive + (size_t)xcc * s.stride;
+    L.groups = X;
+    L.copies = s.xcopies;
+    L.fenced = s.fenced;
+    L.poll_sleep = s.poll_sleep;
     s_ok = ok;
   }
   for (uint32_t c = threadIdx.x; c < s.xcopies && c < kMaxCopies; c += blockDim.x)
@@ -358,7 +379,7 @@ __device__ bool barrier_wait(const BarrierState& s, uint32_t round, const Ctl& c
     __shared__ uint32_t s_use;
     __shared__ uint32_t s_pub[detail::kMaxCopies];
     if (round == 0) return detail::xcd_setup(s, ctl, s_local, s_pub, &s_use);
-    if (s_use) return detail::xcd_wait(s, stamp, ctl, s_local, s_pub);
+    if (s_use) return detail::xcd_wait(stamp, ctl, s_local, s_pub);
     __syncthreads();
     if (is_leader()) {
       const bool ok = detail::counter_arrive_wait<SP_BARRIER_TREE>(s, stamp, ctl);
