@@ -256,9 +256,11 @@ def tune_all(ctx, quick: bool = False) -> dict:
     res["barrier"]["1"] = tune_barrier(ctx, 1024, rounds=rounds)
     res["mutex"]["0"] = tune_mutex_points(ctx, [(4, 1), (32, 1)], mt)
     res["mutex"]["1"] = tune_mutex_points(ctx, [(1024, 1), (2048, 16)], mt)
-    # 32 waits per workgroup at 2048: long enough for the adaptive kind to learn its interval
-    res["semaphore"]["0"] = tune_semaphore_points(ctx, [(256, 32), (2048, 256)], 16 * mt)
-    res["semaphore"]["1"] = tune_semaphore_points(ctx, [(2048, 32), (2048, 4)], 16 * mt)
+    # 128 waits per workgroup at 2048: the queues reach their steady state (with 32 the
+    # cohort semaphore measured 9.6 M pairs/s at K = 256 and 2048 workgroups, with 128
+    # 4.8) and the adaptive kind has learned its interval
+    res["semaphore"]["0"] = tune_semaphore_points(ctx, [(256, 32), (2048, 256)], 64 * mt)
+    res["semaphore"]["1"] = tune_semaphore_points(ctx, [(2048, 32), (2048, 4)], 64 * mt)
     return res
 
 
