@@ -49,20 +49,24 @@ __device__ __forceinline__ uint64_t* cq_slot(const SemState& s, uint32_t x, uint
 
 namespace detail {
 
+__device__ __forceinline__ uint64_t cas_relaxed64(uint64_t* p, uint64_t expected,
+                                                  uint64_t desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return expected;  // the value found
+}
+
 // Claims XCD x's oldest unserved local ticket (compare-and-swap on its served counter),
 // starting from the counters `served` and `drawn` already loaded; false when every ticket
-// drawn so far is served.  The grant slot of the ticket being claimed is loaded together
-// with the compare-and-swap, so a successful claim also knows whether the slot is free.
+// drawn so far is served.
 __device__ __forceinline__ bool cq_claim_at(const SemState& s, uint32_t x, uint32_t served,
-                                            uint32_t drawn, uint32_t* t, uint64_t* slot_v) {
+                                            uint32_t drawn, uint32_t* t) {
   uint32_t* sp = cq_served(s, x);
   uint32_t v = served;
   while ((int32_t)(drawn - v) > 0) {
-    const uint64_t sv = ld_relaxed64(cq_slot(s, x, v));
     const uint32_t seen = cas_relaxed(sp, v, v + 1);
     if (seen == v) {
       *t = v;
-      *slot_v = sv;
       return true;
     }
     v = seen;
@@ -71,22 +75,21 @@ __device__ __forceinline__ bool cq_claim_at(const SemState& s, uint32_t x, uint3
   return false;
 }
 
-__device__ __forceinline__ bool cq_claim(const SemState& s, uint32_t x, uint32_t* t,
-                                         uint64_t* slot_v) {
+__device__ __forceinline__ bool cq_claim(const SemState& s, uint32_t x, uint32_t* t) {
   const uint32_t served = ld_relaxed(cq_served(s, x));
   const uint32_t drawn = ld_relaxed(cq_drawn(s, x));
-  return cq_claim_at(s, x, served, drawn, t, slot_v);
+  return cq_claim_at(s, x, served, drawn, t);
 }
 
 // Claims a ticket on the first XCD (in the order first, first + 1, ...) that has one;
 // retries until one is found (a waiter counted in `count` draws its ticket within a round
 // trip).  Returns false when the watchdog fired.
 __device__ __forceinline__ bool cq_claim_from(const SemState& s, uint32_t first, uint32_t* y,
-                                              uint32_t* t, uint64_t* slot_v, Wait& w) {
+                                              uint32_t* t, Wait& w) {
   for (;;) {
     for (uint32_t d = 0; d < kXccQueues; ++d) {
       const uint32_t x = (first + d) % kXccQueues;
-      if (cq_claim(s, x, t, slot_v)) {
+      if (cq_claim(s, x, t)) {
         *y = x;
         return true;
       }
@@ -96,15 +99,15 @@ __device__ __forceinline__ bool cq_claim_from(const SemState& s, uint32_t first,
 }
 
 // Grants ticket t of XCD y with pass count k, once the slot's previous ticket (t - cq_len)
-// has taken its grant (slot_v: the slot as loaded while claiming; reloaded until empty).
+// has taken its grant.  A compare-and-swap from empty, not a check then a store: the
+// previous ticket's own grant may still be on its way from another poster, and a store
+// after a check could overwrite it.
 __device__ __forceinline__ bool cq_grant(const SemState& s, uint32_t y, uint32_t t, uint32_t k,
-                                         uint64_t slot_v, Wait& w) {
+                                         Wait& w) {
   uint64_t* slot = cq_slot(s, y, t);
-  while ((uint32_t)slot_v != 0) {
+  const uint64_t g = ((uint64_t)k << 32) | (uint64_t)(t + 1);
+  while (cas_relaxed64(slot, 0, g) != 0)
     if (!w.tick()) return false;
-    slot_v = ld_relaxed64(slot);
-  }
-  st_relaxed64(slot, ((uint64_t)k << 32) | (uint64_t)(t + 1));
   return true;
 }
 
@@ -250,7 +253,6 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
       const uint32_t k = hold ? hold->pass : s.cohort_bound;
       const bool stay = k + 1 < s.cohort_bound;
       uint32_t y = 0, t = 0, kk = 0;
-      uint64_t slot_v = 0;
       bool grant = true;
       // one round trip: the count and this XCD's queue counters, loaded together
       const uint32_t c = ld_relaxed(s.count);
@@ -258,24 +260,24 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
       const uint32_t drawn = ld_relaxed(cq_drawn(s, x));
       if (s.K == 1 && c > 1) {
         add_relaxed(s.count, 0xFFFFFFFFu);
-        if (stay && detail::cq_claim_at(s, x, served, drawn, &t, &slot_v)) {
+        if (stay && detail::cq_claim_at(s, x, served, drawn, &t)) {
           wave_stores_complete();  // the decrement is done before the grant store
           y = x;
           kk = k + 1;
         } else {
           if constexpr (FENCED) fence_release();
-          ok = detail::cq_claim_from(s, x + 1, &y, &t, &slot_v, w);
+          ok = detail::cq_claim_from(s, x + 1, &y, &t, w);
         }
       } else {
         if constexpr (FENCED) fence_release();
         const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);
         grant = old > s.K;
         if (grant) {
-          ok = detail::cq_claim_from(s, stay ? x : x + 1, &y, &t, &slot_v, w);
+          ok = detail::cq_claim_from(s, stay ? x : x + 1, &y, &t, w);
           kk = y == x ? k + 1 : 0;
         }
       }
-      if (ok && grant) ok = detail::cq_grant(s, y, t, kk, slot_v, w);
+      if (ok && grant) ok = detail::cq_grant(s, y, t, kk, w);
       s_ok = ok;
     }
     __syncthreads();

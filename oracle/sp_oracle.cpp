@@ -675,9 +675,12 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
     return false;
   };
   auto grant = [&](uint32_t g, uint32_t t, uint32_t k) {
+    // into an empty slot only, atomically: the slot's previous ticket (t - Q) may be
+    // granted by another poster at the same moment
     auto& slot = slots[(size_t)g * Q + (t & (Q - 1))];
-    while ((uint32_t)slot.load(std::memory_order_acquire) != 0) relax();
-    slot.store(((uint64_t)k << 32) | (t + 1), std::memory_order_release);
+    const uint64_t v = ((uint64_t)k << 32) | (t + 1);
+    for (uint64_t e = 0; !slot.compare_exchange_weak(e, v, std::memory_order_acq_rel); e = 0)
+      relax();
   };
   auto claim_from = [&](uint32_t first, uint32_t* g, uint32_t* t) {
     for (;;) {
