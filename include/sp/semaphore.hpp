@@ -17,10 +17,11 @@ struct SemState {
   BackoffCfg bo;        // SP_SEM_SPIN_BACKOFF
   uint32_t post_backoff;  // SP_SEM_SPIN_BACKOFF: 1 = post backs off too (Algorithm 4's
                           // listing); 0 = post retries at once (Section 5's prose)
-  // SP_SEM_COHORT: per XCC id (kXccQueues of them) a queue of cq_len 64-bit grant slots,
-  // after two lines (local tickets drawn, local tickets served); lines cq_stride words
-  // apart (even, so the 64-bit slots are aligned)
+  // SP_SEM_COHORT: per XCD (cq_n of them; a workgroup queues on XCC id mod cq_n) a queue
+  // of cq_len 64-bit grant slots, after two lines (local tickets drawn, local tickets
+  // served); lines cq_stride words apart (even, so the 64-bit slots are aligned)
   uint32_t* cq;
+  uint32_t cq_n;         // queues in use, 1..kXccQueues
   uint32_t cq_stride;
   uint32_t cq_len;       // power of two
   uint32_t cohort_bound; // local hand-overs of one unit in a row, at most
@@ -83,16 +84,21 @@ __device__ __forceinline__ bool cq_claim(const SemState& s, uint32_t x, uint32_t
 
 // Claims a ticket on the first XCD (in the order first, first + 1, ...) that has one;
 // retries until one is found (a waiter counted in `count` draws its ticket within a round
-// trip).  Returns false when the watchdog fired.
+// trip).  One round trip per queue tried: the preferred queue usually has a waiter, and
+// loading every queue's counters first was measured slower (an extra round trip before
+// every claim).  Returns false when the watchdog fired.
 __device__ __forceinline__ bool cq_claim_from(const SemState& s, uint32_t first, uint32_t* y,
                                               uint32_t* t, Wait& w) {
+  const uint32_t n = s.cq_n;
+  if (first >= n) first -= n;
   for (;;) {
-    for (uint32_t d = 0; d < kXccQueues; ++d) {
-      const uint32_t x = (first + d) % kXccQueues;
+    uint32_t x = first;
+    for (uint32_t d = 0; d < n; ++d) {
       if (cq_claim(s, x, t)) {
         *y = x;
         return true;
       }
+      if (++x == n) x = 0;
     }
     if (!w.tick()) return false;
   }
@@ -189,7 +195,7 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
       uint32_t k = 0;
       const uint32_t old = add_relaxed(s.count, 1);
       if (old >= s.K) {
-        const uint32_t x = xcc_id();
+        const uint32_t x = xcc_id() % s.cq_n;
         const uint32_t t = add_relaxed(cq_drawn(s, x), 1);
         uint64_t* slot = cq_slot(s, x, t);
         uint64_t v = 0;
@@ -249,7 +255,7 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
     if (is_leader()) {
       bool ok = true;
       Wait w(ctl, 0);
-      const uint32_t x = xcc_id();
+      const uint32_t x = xcc_id() % s.cq_n;
       const uint32_t k = hold ? hold->pass : s.cohort_bound;
       const bool stay = k + 1 < s.cohort_bound;
       uint32_t y = 0, t = 0, kk = 0;
