@@ -279,7 +279,12 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
         const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);
         grant = old > s.K;
         if (grant) {
-          ok = detail::cq_claim_from(s, stay ? x : x + 1, &y, &t, w);
+          // first with the counters loaded beside count: while they are current, one
+          // compare-and-swap claims this XCD's oldest waiter
+          if (stay && detail::cq_claim_at(s, x, served, drawn, &t))
+            y = x;
+          else
+            ok = detail::cq_claim_from(s, stay ? x : x + 1, &y, &t, w);
           kk = y == x ? k + 1 : 0;
         }
       }
