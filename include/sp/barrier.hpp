@@ -319,7 +319,11 @@ __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl,
   const uint32_t X = s.groups;
   __syncthreads();  // every wavefront's stores have completed (barrier_wait's entry wait)
   if (is_leader()) {
-    const uint32_t xcc = xcc_id() % X;
+    // XCDs are told apart by their XCC id modulo the XCD count.  An id at or above the
+    // count would share a group, and its one writeback, with another XCD: fall back.
+    const uint32_t raw = xcc_id();
+    const uint32_t xcc = raw % X;
+    if (raw >= X) add_relaxed(s.overflow, 1);
     if (xcc != blockIdx.x % X) add_relaxed(s.mismatch, 1);
     L.x = xcc;
     L.k = add_relaxed(s.xcount + xcc, 1);

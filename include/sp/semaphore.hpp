@@ -22,6 +22,8 @@ struct SemState {
   // served); lines cq_stride words apart (even, so the 64-bit slots are aligned)
   uint32_t* cq;
   uint32_t cq_n;         // queues in use, 1..kXccQueues
+  uint32_t cq_local;     // 1: every XCC id is below cq_n, so queue x holds XCD x's
+                         // workgroups only (the K = 1 writeback skip relies on it)
   uint32_t cq_stride;
   uint32_t cq_len;       // power of two
   uint32_t cohort_bound; // local hand-overs of one unit in a row, at most
@@ -245,13 +247,14 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
     // Hand the unit on.  Algorithm 5's post: write back, then decrement count; if a waiter
     // is beyond capacity the unit goes to the oldest waiter of this XCD while the unit has
     // passed fewer than cohort_bound times in a row here, else to the first other XCD with
-    // a waiter.  K = 1 and count > 1 (loaded): the poster holds the only unit, so no other
-    // post can lower count before its own decrement, which therefore returns more than 1:
-    // a waiter exists, and one of this XCD's (it reads through the same L2) takes the unit
-    // without the writeback.  The decrement has completed before the grant is written, so
-    // the next holder's load of count already includes it.  For K >= 2 a loaded count
-    // proves nothing -- the other K - 1 units can change hands any number of times before
-    // the decrement lands -- so every post writes back first.
+    // a waiter.  K = 1, one XCD per queue (cq_local) and count > 1 (loaded): the poster
+    // holds the only unit, so no other post can lower count before its own decrement,
+    // which therefore returns more than 1: a waiter exists, and one of this XCD's (it
+    // reads through the same L2) takes the unit without the writeback.  The decrement has
+    // completed before the grant is written, so the next holder's load of count already
+    // includes it.  For K >= 2 a loaded count proves nothing -- the other K - 1 units can
+    // change hands any number of times before the decrement lands -- so every post writes
+    // back first.
     if (is_leader()) {
       bool ok = true;
       Wait w(ctl, 0);
@@ -264,7 +267,7 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
       const uint32_t c = ld_relaxed(s.count);
       const uint32_t served = ld_relaxed(cq_served(s, x));
       const uint32_t drawn = ld_relaxed(cq_drawn(s, x));
-      if (s.K == 1 && c > 1) {
+      if (s.K == 1 && s.cq_local && c > 1) {
         add_relaxed(s.count, 0xFFFFFFFFu);
         if (stay && detail::cq_claim_at(s, x, served, drawn, &t)) {
           wave_stores_complete();  // the decrement is done before the grant store

@@ -206,6 +206,7 @@ int sp_init(int device, sp_ctx** out) {
     for (uint32_t i = 0; i < n; ++i) seen |= 1u << (h[i] & 15);
     delete[] h;
     ctx->xcd_count = (uint32_t)__builtin_popcount(seen);
+    ctx->xcc_mask = seen;
   }
   // Built-in defaults: the winners of a full tuning pass on an MI355X (fewer than 64 /
   // at least 64 workgroups per resource); a tuner run installs its own with

@@ -26,6 +26,7 @@ struct sp_ctx {
   int last_hip = 0;
   uint32_t cu_count = 0;
   uint32_t xcd_count = 0;
+  uint32_t xcc_mask = 0;  // XCC ids seen at sp_init (bit i = id i)
   uint32_t wall_khz = 100000;
   uint32_t* d_err = nullptr;   // watchdog word, own 256-byte block
   uint32_t* d_scratch = nullptr;  // small staging area (4 KiB) for state readback

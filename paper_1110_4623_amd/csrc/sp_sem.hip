@@ -238,6 +238,7 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   ss.cq = sem->d_cq;
   // one queue per XCD (every XCC id the dispatcher uses lands in one of them)
   ss.cq_n = std::min<uint32_t>(std::max<uint32_t>(ctx->xcd_count, 1), sp::kXccQueues);
+  ss.cq_local = ctx->xcc_mask == (1u << ss.cq_n) - 1;
   ss.cq_stride = sem->cq_stride;
   ss.cq_len = kCohortSlots;
   ss.cohort_bound = q.cohort_passes;
