@@ -91,7 +91,9 @@ def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
+    t_closed = time.perf_counter()
     ref = oracle.barrier_closed(42, NWG, ROUNDS)
+    t_closed = time.perf_counter() - t_closed  # the closed form: ground truth, not a baseline
     ref1 = oracle.barrier_closed(42, C1_NWG, C1_ROUNDS)
     curves_ok = None
     if curve_out is not None:
@@ -105,6 +107,7 @@ def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20
             "sample": f"per-XCD flag protocol, {NWG} std::thread agents (8 groups of 4 CUs), "
                       f"{rounds} of the {ROUNDS} rounds of the hash exchange; {secs2:.1f} s",
             "ok": rc == 0 and rc2 == 0,
+            "closed_form_seconds": round(t_closed, 4),
             "headline_checksums_match_oracle": bool((headline_chk == ref).all()),
             "config1_checksums_match_oracle": bool((config1_chk == ref1).all()),
             "curves_match_oracle": curves_ok}
