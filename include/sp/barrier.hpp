@@ -137,15 +137,18 @@ __device__ __forceinline__ bool counter_arrive_wait(const BarrierState& s, uint3
 
 // Master side of a flag scan: every lane checks flags i = lane, lane + lanes, ... of
 // `n` flags (skipping index `skip`) and all of a lane's flags are loaded together each
-// poll, so a scan costs one memory round trip rather than one per flag.
+// poll, so a scan costs one memory round trip rather than one per flag.  `lanes` is the
+// workgroup size (the per-XCD barrier passes the value it saved in round 0: reading
+// blockDim.x is a load from the dispatch packet).
 __device__ __forceinline__ int scan_flags(const uint32_t* flags, uint32_t fs, uint32_t n,
-                                          uint32_t skip, uint32_t stamp, Wait& w) {
-  for (uint32_t base = threadIdx.x; base < n; base += 8 * blockDim.x) {
+                                          uint32_t skip, uint32_t stamp, Wait& w,
+                                          uint32_t lanes) {
+  for (uint32_t base = threadIdx.x; base < n; base += 8 * lanes) {
     for (;;) {
       bool all = true;
 #pragma unroll
       for (uint32_t k = 0; k < 8; ++k) {
-        const uint32_t i = base + k * blockDim.x;
+        const uint32_t i = base + k * lanes;
         if (i < n && i != skip) all &= reached(ld_relaxed(flags + (size_t)i * fs), stamp);
       }
       if (all) break;
@@ -163,7 +166,7 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
   if (blockIdx.x == 0) {
     __syncthreads();
     Wait w(ctl, s.poll_sleep);
-    int ok = scan_flags(s.arrive, fs, s.nwg, 0, stamp, w);
+    int ok = scan_flags(s.arrive, fs, s.nwg, 0, stamp, w, blockDim.x);
     if (s.fenced) fence_acquire();
     ok = __syncthreads_and(ok);
     if (ok) {
@@ -227,7 +230,7 @@ struct XcdLocal {
   uint32_t* rel;           // this CU's release line
   uint32_t* mail_x;        // xmail + x: the master stores copy c at mail_x + pub[c]
   uint32_t* xarrive_x;     // the XCD's stamp line when there are no copies
-  uint32_t groups, copies, sstride, fenced, poll_sleep;
+  uint32_t groups, copies, sstride, fenced, poll_sleep, lanes;
 };
 
 // A pointer that is the same for the whole workgroup, in scalar registers.
@@ -238,11 +241,23 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
   return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
+
+// Workgroup AND of `ok` with one workgroup barrier, for the per-XCD barrier's rounds.
+// HIP's __syncthreads_and loads the workgroup size from the kernel's arguments (a memory
+// round trip) and runs three barriers around an LDS reduction; here a wavefront writes
+// only when one of its lanes failed (the watchdog fired).  fail[stamp & 1] was cleared
+// in the previous round, after every thread had read it (xcd_wait clears the other entry
+// after its first barrier); round 0 clears both.  Every thread of the workgroup calls.
+__device__ __forceinline__ int and_sync(int ok, uint32_t stamp, uint32_t* fail) {
+  if (__builtin_amdgcn_ballot_w64(!ok) != 0 && (threadIdx.x & 63) == 0) fail[stamp & 1] = 1;
+  __syncthreads();
+  return fail[stamp & 1] == 0;
+}
 // The master's stores of its stamp: copy c at pub[c] + the XCD's index in xmail.
 constexpr uint32_t kMaxCopies = 256;
 
 __device__ __forceinline__ bool xcd_wait(uint32_t stamp, const Ctl& ctl, const XcdLocal& L,
-                                         const uint32_t* pub) {
+                                         const uint32_t* pub, uint32_t* fail) {
   __shared__ uint32_t s_ok;
   // The registration is the same for the whole workgroup: keep it in scalar registers.
   const uint32_t X = __builtin_amdgcn_readfirstlane(L.groups);
@@ -255,12 +270,14 @@ __device__ __forceinline__ bool xcd_wait(uint32_t stamp, const Ctl& ctl, const X
   Wait w(ctl, __builtin_amdgcn_readfirstlane(L.poll_sleep));
   int ok = 1;
   __syncthreads();
+  if (threadIdx.x == 0) fail[(stamp + 1) & 1] = 0;  // for the next round's and_sync
   const uint32_t C = __builtin_amdgcn_readfirstlane(L.copies);
   if (k == 0) {
     // XCD master: gather the XCD's arrivals, write the XCD's L2 back once, publish (in
     // every copy of the stamps, by the first wavefront after its writeback).
-    ok = scan_flags(block, kArriveWords, members, 0, stamp, w);
-    ok = __syncthreads_and(ok);
+    ok = scan_flags(block, kArriveWords, members, 0, stamp, w,
+                    __builtin_amdgcn_readfirstlane(L.lanes));
+    ok = and_sync(ok, stamp, fail);
     if (!ok) return false;
     if (C == 0) {
       if (is_leader()) {
@@ -283,7 +300,7 @@ __device__ __forceinline__ bool xcd_wait(uint32_t stamp, const Ctl& ctl, const X
     // polls the populated XCDs' stamps itself (two flag hops per round).
     if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
       ok = poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
-    return __syncthreads_and(ok);
+    return and_sync(ok, stamp, fail);
   }
   // this CU's release line
   uint32_t* rel = uniform_ptr(L.rel);
@@ -294,7 +311,7 @@ __device__ __forceinline__ bool xcd_wait(uint32_t stamp, const Ctl& ctl, const X
     // line that participants elsewhere write) would otherwise stay stale in the L2.
     if (threadIdx.x < X && ((xmask >> threadIdx.x) & 1))
       ok = poll_until(stamps + (size_t)threadIdx.x * sstride, stamp, w);
-    ok = __syncthreads_and(ok);
+    ok = and_sync(ok, stamp, fail);
     if (!ok) return false;
     if (is_leader()) {
       fence_acquire();  // completes before the release store is issued
@@ -314,7 +331,7 @@ __device__ __forceinline__ bool xcd_wait(uint32_t stamp, const Ctl& ctl, const X
 // Round 0 of the per-XCD barrier: register per XCD and per CU, run the counter tree
 // with per-workgroup fences, then load what the later rounds use.
 __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl, XcdLocal& L,
-                                          uint32_t* pub, uint32_t* use_xcd) {
+                                          uint32_t* pub, uint32_t* fail, uint32_t* use_xcd) {
   __shared__ uint32_t s_ok;
   const uint32_t X = s.groups;
   __syncthreads();  // every wavefront's stores have completed (barrier_wait's entry wait)
@@ -358,6 +375,8 @@ __device__ __forceinline__ bool xcd_setup(const BarrierState& s, const Ctl& ctl,
     L.copies = s.xcopies;
     L.fenced = s.fenced;
     L.poll_sleep = s.poll_sleep;
+    L.lanes = blockDim.x;
+    fail[0] = fail[1] = 0;
     s_ok = ok;
   }
   for (uint32_t c = threadIdx.x; c < s.xcopies && c < kMaxCopies; c += blockDim.x)
@@ -382,8 +401,9 @@ __device__ bool barrier_wait(const BarrierState& s, uint32_t round, const Ctl& c
     __shared__ detail::XcdLocal s_local;
     __shared__ uint32_t s_use;
     __shared__ uint32_t s_pub[detail::kMaxCopies];
-    if (round == 0) return detail::xcd_setup(s, ctl, s_local, s_pub, &s_use);
-    if (s_use) return detail::xcd_wait(stamp, ctl, s_local, s_pub);
+    __shared__ uint32_t s_fail[2];
+    if (round == 0) return detail::xcd_setup(s, ctl, s_local, s_pub, s_fail, &s_use);
+    if (s_use) return detail::xcd_wait(stamp, ctl, s_local, s_pub, s_fail);
     __syncthreads();
     if (is_leader()) {
       const bool ok = detail::counter_arrive_wait<SP_BARRIER_TREE>(s, stamp, ctl);
