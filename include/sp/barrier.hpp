@@ -158,17 +158,33 @@ __device__ __forceinline__ int scan_flags(const uint32_t* flags, uint32_t fs, ui
   return 1;
 }
 
+// Workgroup AND of `ok` with one workgroup barrier, for the rounds of the flag and
+// per-XCD barriers.  HIP's __syncthreads_and loads the workgroup size from the kernel's
+// arguments (a memory round trip) and runs three barriers around an LDS reduction; here
+// a wavefront writes only when one of its lanes failed (the watchdog fired).
+// fail[stamp & 1] is zero on entry: the caller cleared it at least one workgroup barrier
+// earlier, after every thread had read it two rounds before.  Every thread of the
+// workgroup calls.
+__device__ __forceinline__ int and_sync(int ok, uint32_t stamp, uint32_t* fail) {
+  if (__builtin_amdgcn_ballot_w64(!ok) != 0 && (threadIdx.x & 63) == 0) fail[stamp & 1] = 1;
+  __syncthreads();
+  return fail[stamp & 1] == 0;
+}
+
 // Decentralized flag barrier (the "XF" barrier of Section 5): no read-modify-writes.
 __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
                                           const Ctl& ctl) {
   __shared__ uint32_t s_ok;
+  __shared__ uint32_t s_fail[2];
   const uint32_t fs = s.flag_stride;
   if (blockIdx.x == 0) {
+    // this round's entry; the other one may still be read for the previous round
+    if (threadIdx.x == 0) s_fail[stamp & 1] = 0;
     __syncthreads();
     Wait w(ctl, s.poll_sleep);
     int ok = scan_flags(s.arrive, fs, s.nwg, 0, stamp, w, blockDim.x);
     if (s.fenced) fence_acquire();
-    ok = __syncthreads_and(ok);
+    ok = and_sync(ok, stamp, s_fail);
     if (ok) {
       if (s.fenced) fence_release();
       for (uint32_t i = threadIdx.x; i < s.nwg; i += blockDim.x)
@@ -242,17 +258,6 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
   return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
-// Workgroup AND of `ok` with one workgroup barrier, for the per-XCD barrier's rounds.
-// HIP's __syncthreads_and loads the workgroup size from the kernel's arguments (a memory
-// round trip) and runs three barriers around an LDS reduction; here a wavefront writes
-// only when one of its lanes failed (the watchdog fired).  fail[stamp & 1] was cleared
-// in the previous round, after every thread had read it (xcd_wait clears the other entry
-// after its first barrier); round 0 clears both.  Every thread of the workgroup calls.
-__device__ __forceinline__ int and_sync(int ok, uint32_t stamp, uint32_t* fail) {
-  if (__builtin_amdgcn_ballot_w64(!ok) != 0 && (threadIdx.x & 63) == 0) fail[stamp & 1] = 1;
-  __syncthreads();
-  return fail[stamp & 1] == 0;
-}
 // The master's stores of its stamp: copy c at pub[c] + the XCD's index in xmail.
 constexpr uint32_t kMaxCopies = 256;
 
