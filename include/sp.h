@@ -108,6 +108,11 @@ enum sp_sem_kind {
                            /* to another XCD's waiter; each waiter polls its own slot.   */
                            /* K = 1: a post that sees a waiter counted skips the writeback */
                            /* for a waiter of its own XCD (same L2)                      */
+  SP_SEM_ARRAY = 7,        /* SP_SEM_COUNTERS' admission rule with a grant slot per      */
+                           /* ticket (64-bit counters): ticket t >= K polls slot t mod  */
+                           /* 4096 (its own line) until it holds at least t + 1; the    */
+                           /* post that draws p raises slot (p + K) mod 4096 to p + K + 1 */
+                           /* with an atomic max, so no line is polled by the queue     */
   SP_SEM_DEFAULT = 15
 };
 
@@ -360,8 +365,9 @@ int sp_sem_destroy(sp_sem* s);
  * occupancy.  out_chk: device, nwg uint32.  out_state: device, 8 uint32 =
  * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, count,
  * occupancy, unserved} (SP_SEM_COUNTERS, SP_SEM_ADAPTIVE: count stays 0, ticket = tickets
- * drawn, turn = posts made; SP_SEM_COHORT: ticket and turn stay 0, unserved = local
- * tickets drawn and not served, over every XCD's queue, 0 at rest).
+ * drawn, turn = posts made; SP_SEM_ARRAY: the same, the low 32 bits of its 64-bit
+ * counters; SP_SEM_COHORT: ticket and turn stay 0, unserved = local tickets drawn and not
+ * served, over every XCD's queue, 0 at rest).
  * out_data: device, K uint32 (zeroed by the call), or NULL; K <= 4096.  Guarded data:
  * each admission adds one to a word with a plain load and store made by the workgroup's
  * last thread -- for K = 1 to the one word, ordered only by the semaphore's acquire and

@@ -27,6 +27,8 @@ struct SemState {
   uint32_t cq_stride;
   uint32_t cq_len;       // power of two
   uint32_t cohort_bound; // local hand-overs of one unit in a row, at most
+  // SP_SEM_ARRAY uses queue 0's memory: line 0 the tickets drawn, line 1 the posts made
+  // (64-bit counters), then the cq_len 64-bit grant slots.
 };
 
 // Per-workgroup waiting state that persists across waits (SP_SEM_ADAPTIVE), or from a
@@ -47,6 +49,24 @@ __device__ __forceinline__ uint32_t* cq_served(const SemState& s, uint32_t x) {
 }
 __device__ __forceinline__ uint64_t* cq_slot(const SemState& s, uint32_t x, uint32_t t) {
   return reinterpret_cast<uint64_t*>(cq_base(s, x) +
+                                     (size_t)(2 + (t & (s.cq_len - 1))) * s.cq_stride);
+}
+
+// ---- array semaphore (ticket-indexed grant slots) ----------------------------------------
+__device__ __forceinline__ uint64_t add_relaxed64(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t max_relaxed64(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t* as_tickets(const SemState& s) {
+  return reinterpret_cast<uint64_t*>(cq_base(s, 0));
+}
+__device__ __forceinline__ uint64_t* as_posts(const SemState& s) {
+  return reinterpret_cast<uint64_t*>(cq_base(s, 0) + s.cq_stride);
+}
+__device__ __forceinline__ uint64_t* as_slot(const SemState& s, uint64_t t) {
+  return reinterpret_cast<uint64_t*>(cq_base(s, 0) +
                                      (size_t)(2 + (t & (s.cq_len - 1))) * s.cq_stride);
 }
 
@@ -135,6 +155,22 @@ __device__ __forceinline__ bool cq_grant(const SemState& s, uint32_t y, uint32_t
 // 2048 workgroups queued on K = 32 the polling of one line otherwise slows the posts'
 // atomics on that line (measured: a uniform s_sleep of 64 units between polls alone
 // gives +47 %).
+// SP_SEM_ARRAY has SP_SEM_COUNTERS' admission rule with the admitting post telling the
+// waiter directly: the post that draws p (0-based, from the posts counter) raises grant
+// slot (p + K) mod len to p + K + 1 with an atomic max, and ticket t >= K waits until its
+// slot holds at least t + 1.  Each waiter polls a line of its own, so the posts counter's
+// line carries only the posts' atomics (with ~2000 waiters on the counter's line the
+// polling, not the cache maintenance, limits the other two-counter kinds).
+//   At most K inside: a slot value v >= t + 1 is some post's p + K + 1 with p + K >= t,
+//   so that post has drawn p >= t - K, and posts > t - K when t enters -- the
+//   two-counter rule; every entered ticket is below posts + K, so at most posts + K
+//   tickets have entered and at most K of them have not posted.
+//   Every waiter enters: tickets below t enter and post (induction), the post that draws
+//   t - K then raises slot t mod len to at least t + 1, and a maximum never decreases.
+//   The slots may be reused in any order (len any power of two): a grant for a later
+//   ticket of the same slot is larger, so it admits the earlier one too, which the rule
+//   already allows; an earlier grant landing late cannot lower it.  64-bit counters and
+//   slots do not wrap.
 // FENCED = false: the data the semaphore guards is accessed with agent-scope loads and
 // stores, which every XCD sees without cache maintenance, so wait skips the acquire
 // invalidation and post the release writeback.
@@ -212,6 +248,14 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
         }
       }
       if (hold) hold->pass = k;
+    } else if constexpr (KIND == SP_SEM_ARRAY) {
+      Wait w(ctl, s.poll_sleep);
+      const uint64_t t = add_relaxed64(as_tickets(s), 1);
+      if (t >= s.K) {
+        const uint64_t* g = as_slot(s, t);
+        while (ld_relaxed64(g) <= t)
+          if (!(ok = w.tick())) break;
+      }
     } else if constexpr (KIND == SP_SEM_COUNTERS) {
       Wait w(ctl, s.poll_sleep);
       const uint32_t t = add_relaxed(s.ticket, 1);
@@ -315,6 +359,9 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
       }
     } else if constexpr (KIND == SP_SEM_COUNTERS || KIND == SP_SEM_ADAPTIVE) {
       add_relaxed(s.turn, 1);
+    } else if constexpr (KIND == SP_SEM_ARRAY) {
+      const uint64_t q = add_relaxed64(as_posts(s), 1) + s.K;  // the ticket this post admits
+      max_relaxed64(as_slot(s, q), q + 1);
     } else {
       const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);  // count -= 1
       if (old > s.K) add_relaxed(s.turn, 1);                   // admit one queued waiter

@@ -849,6 +849,114 @@ class CohortSemModel:
         return None
 
 
+class ArraySemModel:
+    """Two monotone counters with a grant slot per ticket (the array semaphore).
+
+    tickets, posts and the M grant slots start at 0.  wait: t = fetch-and-add(tickets,
+    1); t < K: enter; otherwise poll slot t mod M until it holds at least t + 1.  post:
+    write the L2 back, p = fetch-and-add(posts, 1), then raise slot (p + K) mod M to
+    p + K + 1 with an atomic maximum.  The admission rule is the two-counter one (enter
+    once posts + K > t); the slots only tell each waiter when.  M below the number of
+    tickets makes several tickets share a slot, and grants for one slot may land in any
+    order.
+
+    placement: XCD of each agent.  Data as in CohortSemModel: one word updated in every
+    critical section with a plain load and store through the agent's XCD's L2 (per XCD:
+    empty, or (value, dirty)); a writeback copies a dirty value to memory; the admitted
+    waiter's acquire drops a clean copy.  With K = 1 every load must see every earlier
+    update and the final value must count every admission.
+    mutant 'enter_at_k': tickets t <= K enter at once (an off-by-one);
+    mutant 'poll_eq': the waiter enters only on exactly t + 1 (a later grant of the same
+    slot hides its own);
+    mutant 'grant_next': the post grants ticket p + K + 1;
+    mutant 'store': the grant is a plain store (a late earlier grant can lower a slot);
+    mutant 'no_writeback': the post skips the writeback;
+    mutant 'no_acquire': the admitted waiter does not invalidate."""
+
+    W_TICKET, W_POLL, ACQ, CS_LD, CS_ST, P_WB, P_DRAW, P_GRANT, DONE = range(9)
+
+    def __init__(self, K: int, placement: tuple, M: int, ops: int = 2,
+                 mutant: str | None = None):
+        self.K, self.pl, self.M, self.ops, self.mutant = K, tuple(placement), M, ops, mutant
+        self.n = len(self.pl)
+        self.X = 1 + max(self.pl)
+
+    # shared = (tickets, posts, slots (M), l2 (X), mem, inside, done_cs)
+    # local  = (pc, j, t, tmp)
+    def init(self):
+        sh = (0, 0, (0,) * self.M, (None,) * self.X, 0, 0, 0)
+        return sh, tuple((self.W_TICKET, 0, 0, 0) for _ in range(self.n))
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    @staticmethod
+    def _set(t, i, v):
+        return t[:i] + (v,) + t[i + 1:]
+
+    def step(self, a, sh, lo):
+        tickets, posts, slots, l2, mem, inside, done_cs = sh
+        pc, j, t, tmp = lo
+        x = self.pl[a]
+        if pc == self.W_TICKET:
+            t = tickets
+            go = t <= self.K if self.mutant == "enter_at_k" else t < self.K
+            return ((tickets + 1, posts, slots, l2, mem, inside, done_cs),
+                    (self.ACQ if go else self.W_POLL, j, t, 0))
+        if pc == self.W_POLL:
+            v = slots[t % self.M]
+            go = v == t + 1 if self.mutant == "poll_eq" else v >= t + 1
+            return sh, (self.ACQ if go else self.W_POLL, j, t, 0)
+        if pc == self.ACQ:
+            if self.mutant != "no_acquire" and l2[x] is not None and not l2[x][1]:
+                l2 = self._set(l2, x, None)
+            return (tickets, posts, slots, l2, mem, inside + 1, done_cs), (self.CS_LD, j, t, 0)
+        if pc == self.CS_LD:
+            if l2[x] is None:
+                l2 = self._set(l2, x, (mem, False))
+            return (tickets, posts, slots, l2, mem, inside, done_cs), (self.CS_ST, j, t, l2[x][0])
+        if pc == self.CS_ST:
+            if self.K == 1 and tmp != done_cs:
+                # a stale load: report it through the occupancy check's channel
+                inside = self.K + 100
+            l2 = self._set(l2, x, (tmp + 1, True))
+            return ((tickets, posts, slots, l2, mem, inside - 1, done_cs + 1),
+                    (self.P_WB, j, t, 0))
+        if pc == self.P_WB:
+            if self.mutant != "no_writeback" and l2[x] is not None and l2[x][1]:
+                mem = l2[x][0]
+                l2 = self._set(l2, x, (mem, False))
+            return (tickets, posts, slots, l2, mem, inside, done_cs), (self.P_DRAW, j, t, 0)
+        if pc == self.P_DRAW:
+            q = posts + self.K + (1 if self.mutant == "grant_next" else 0)
+            return ((tickets, posts + 1, slots, l2, mem, inside, done_cs),
+                    (self.P_GRANT, j, t, q))
+        if pc == self.P_GRANT:
+            i = tmp % self.M
+            v = tmp + 1 if self.mutant == "store" else max(slots[i], tmp + 1)
+            nxt = self.W_TICKET if j + 1 < self.ops else self.DONE
+            return ((tickets, posts, self._set(slots, i, v), l2, mem, inside, done_cs),
+                    (nxt, j + 1, 0, 0))
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        inside = sh[5]
+        if inside > self.K + 50:
+            return "a holder loaded the data word without an earlier holder's update"
+        if inside > self.K:
+            return f"occupancy {inside} > K={self.K}"
+        return None
+
+    def final_check(self, sh, los):
+        tickets, posts, slots, l2, mem, inside, done_cs = sh
+        total = self.n * self.ops
+        if tickets != total or posts != total or inside != 0:
+            return f"final tickets={tickets} posts={posts} inside={inside}"
+        if self.K == 1 and mem != total:
+            return f"final data {mem} != {total} admissions"
+        return None
+
+
 class WeightedSemModel:
     """Fetch-and-add semaphore with weighted requests, the admission rule of the serving
     queue (Algorithm 5 with u tickets drawn at once).  issued and released start at 0.

@@ -646,7 +646,10 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 // decrements count and hands its unit over only if a waiter is counted beyond K, to the
 // oldest waiter of its own group (at most 4 times in a row for one unit), else to the
 // first other group with a waiter; for K = 1 a post that reads count above 1 knows
-// before its decrement that a waiter exists.
+// before its decrement that a waiter exists; 8 two 64-bit monotone counters with a grant
+// slot per ticket (16 slots, so tickets share them): ticket t >= K waits until slot
+// t mod 16 holds at least t + 1, and the post that draws p raises slot (p + K) mod 16
+// to p + K + 1 (a maximum: grants for one slot may land in any order).
 // Each pair: wait, occupancy tracking, checksum update, admission count, post.
 // out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}; for the
 // Algorithm 4 kinds ticket and turn are unused and state[1] / state[2] report instead the
@@ -655,7 +658,7 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t total,
                     uint32_t imin, uint32_t imax, uint32_t* chk, uint32_t* maxocc,
                     uint32_t* state, double* seconds) {
-  if (nwg == 0 || K == 0 || kind < 0 || kind > 7) return -1;
+  if (nwg == 0 || K == 0 || kind < 0 || kind > 8) return -1;
   Word S{K + 1}, count{0}, ticket{0}, turn{0}, occ{0}, maxo{0}, adm{0};
   // kind 7: per group a queue of Q slots {ticket + 1, passes} after (drawn, served)
   constexpr uint32_t kGroups = 8, kBound = 4;
@@ -665,6 +668,11 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   std::vector<std::atomic<uint64_t>> slots(kind == 7 ? (size_t)kGroups * Q : 0);
   for (size_t i = 0; i < drawn.size(); ++i) drawn[i] = 0, served[i] = 0;
   for (auto& w : slots) w.store(0);
+  // kind 8: 64-bit tickets drawn and posts made, and the grant slots
+  constexpr uint32_t kGrantSlots = 16;
+  std::atomic<uint64_t> tickets64{0}, posts64{0};
+  std::vector<std::atomic<uint64_t>> grants(kind == 8 ? kGrantSlots : 0);
+  for (auto& w : grants) w.store(0);
   auto claim = [&](uint32_t g, uint32_t* t) {
     uint32_t v = served[g].load(std::memory_order_relaxed);
     while ((int32_t)(drawn[g].load(std::memory_order_relaxed) - v) > 0)
@@ -698,6 +706,12 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   std::atomic<uint64_t> wait_fail{0}, post_fail{0};
 
   auto wait = [&](Backoff& bo, uint32_t b) {
+    if (kind == 8) {
+      const uint64_t t = tickets64.fetch_add(1, std::memory_order_acq_rel);
+      if (t >= K)
+        while (grants[t % kGrantSlots].load(std::memory_order_acquire) <= t) relax();
+      return;
+    }
     if (kind == 7) {
       uint32_t k = 0;
       if (count.fetch_add(1, std::memory_order_acq_rel) >= K) {
@@ -742,6 +756,14 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
     }
   };
   auto post = [&](Backoff& bo, uint32_t b) {
+    if (kind == 8) {
+      const uint64_t q = posts64.fetch_add(1, std::memory_order_acq_rel) + K;
+      auto& g = grants[q % kGrantSlots];
+      uint64_t v = g.load(std::memory_order_relaxed);
+      while (v < q + 1 && !g.compare_exchange_weak(v, q + 1, std::memory_order_acq_rel)) {
+      }
+      return;
+    }
     if (kind == 7) {
       const uint32_t g = b % kGroups, k = pass[b];
       const bool stay = k + 1 < kBound;
@@ -806,8 +828,10 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
       if (w.load() != 0) return -3;
   }
   state[0] = alg4 ? S.load() : count.load();
-  state[1] = alg4 ? (uint32_t)std::min<uint64_t>(wait_fail.load(), 0xFFFFFFFFu) : ticket.load();
-  state[2] = alg4 ? (uint32_t)std::min<uint64_t>(post_fail.load(), 0xFFFFFFFFu) : turn.load();
+  state[1] = alg4 ? (uint32_t)std::min<uint64_t>(wait_fail.load(), 0xFFFFFFFFu)
+                  : kind == 8 ? (uint32_t)tickets64.load() : ticket.load();
+  state[2] = alg4 ? (uint32_t)std::min<uint64_t>(post_fail.load(), 0xFFFFFFFFu)
+                  : kind == 8 ? (uint32_t)posts64.load() : turn.load();
   state[3] = adm.load();
   if (seconds) *seconds = t;
   return *maxocc > K ? -2 : 0;

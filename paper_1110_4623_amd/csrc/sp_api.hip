@@ -229,9 +229,11 @@ int sp_init(int device, sp_ctx** out) {
   ctx->defaults[1][1].kind = SP_MUTEX_COHORT;
   ctx->defaults[1][1].p.poll_sleep = 0;
   ctx->defaults[1][1].p.cohort_passes = 64;
-  ctx->defaults[2][0].kind = SP_SEM_COUNTERS;  // 8.7 M pairs/s K = 32 at 256, 7.3 K = 256 at 2048
-  ctx->defaults[2][0].p.poll_sleep = 16;
-  ctx->defaults[2][1].kind = SP_SEM_ADAPTIVE;  // 6.5 M pairs/s K = 32 at 2048, 1.6 K = 4
+  // array semaphore: 12.4 M pairs/s K = 32 at 256, 42 M K = 256 at 2048 (two counters
+  // + s_sleep 16: 8.1 / 6.9); 12.1 M K = 32 at 2048, 1.55 M K = 4 (adaptive 6.5 / 1.6)
+  ctx->defaults[2][0].kind = SP_SEM_ARRAY;
+  ctx->defaults[2][0].p.poll_sleep = 0;
+  ctx->defaults[2][1].kind = SP_SEM_ARRAY;
   ctx->defaults[2][1].p.poll_sleep = 0;
   // resolve the "auto" fields (fan_in = XCD count, ...) as sp_set_default does
   for (int prim = 0; prim < 3; ++prim)
@@ -279,7 +281,7 @@ int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p) {
   if (!usable(ctx) || primitive > 2 || bucket > 1) return SP_E_INVAL;
-  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_MCS, SP_SEM_COHORT};
+  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_MCS, SP_SEM_ARRAY};
   if (kind > max_kind[primitive]) return SP_E_INVAL;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));

@@ -13,7 +13,7 @@ struct sp_sem {
   uint32_t* d_state = nullptr;
   uint64_t state_words = 0;
   uint32_t* d_owner = nullptr;  // K <= kMaxPool: owner word of each pool slot, kOwnerWords apart
-  uint32_t* d_cq = nullptr;     // SP_SEM_COHORT (and DEFAULT): the per-XCD queues
+  uint32_t* d_cq = nullptr;     // SP_SEM_COHORT, SP_SEM_ARRAY (and DEFAULT): the queues
   uint64_t cq_words = 0;
   uint32_t cq_stride = 0;
 };
@@ -27,8 +27,9 @@ constexpr uint32_t kMaxPool = 4096;
 constexpr uint32_t kOwnerWords = 8;
 // Algorithm 4's waiter backoff cap when the caller names no backoff policy (s_sleep units).
 constexpr uint32_t kAlg4BackoffCap = 8192;
-// Grant slots of each XCD's queue (cohort kind).  Any number is correct: a post waits for
-// a slot's previous ticket to take its grant before it writes the next one.
+// Grant slots of each XCD's queue (cohort kind; the array kind uses the first queue's).
+// Any number is correct: a cohort post waits for a slot's previous ticket to take its
+// grant before it writes the next one, an array post's grant is a maximum.
 constexpr uint32_t kCohortSlots = 4096;
 
 // The wait/hold/post workload.  With `data` (K uint32 words, packed, plain memory) every
@@ -103,7 +104,7 @@ __global__ SP_FULL_OCCUPANCY void k_sem(sp::SemState s, uint32_t stride, uint32_
 
 __global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg4,
                             const uint32_t* cq, uint32_t cq_stride, uint32_t cq_len,
-                            uint32_t* out) {
+                            const uint32_t* arr, uint32_t* out) {
   if (threadIdx.x == 0) {
     // cohort kind: local tickets drawn but never served, over every XCD's queue (0 at rest)
     uint32_t unserved = 0;
@@ -114,8 +115,9 @@ __global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg
       }
     out[0] = state[L_MAXOCC * stride];
     out[1] = alg4 ? state[L_S * stride] : state[L_COUNT * stride];
-    out[2] = state[L_TICKET * stride];
-    out[3] = state[L_TURN * stride];
+    // array kind: the low halves of its 64-bit tickets and posts counters
+    out[2] = arr ? arr[0] : state[L_TICKET * stride];
+    out[3] = arr ? arr[cq_stride] : state[L_TURN * stride];
     out[4] = state[L_ADM * stride];
     out[5] = state[L_COUNT * stride];
     out[6] = state[L_OCC * stride];
@@ -135,6 +137,7 @@ const void* sem_kernel_f(uint32_t kind) {
     case SP_SEM_COUNTERS: return (const void*)k_sem<SP_SEM_COUNTERS, FENCED>;
     case SP_SEM_ADAPTIVE: return (const void*)k_sem<SP_SEM_ADAPTIVE, FENCED>;
     case SP_SEM_COHORT: return (const void*)k_sem<SP_SEM_COHORT, FENCED>;
+    case SP_SEM_ARRAY: return (const void*)k_sem<SP_SEM_ARRAY, FENCED>;
     default: return nullptr;
   }
 }
@@ -149,7 +152,7 @@ extern "C" {
 
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out) {
   if (!spi::usable(ctx) || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
-  if (kind > SP_SEM_COHORT && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_SEM_ARRAY && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -163,9 +166,10 @@ int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp
   hipError_t e = hipMalloc(&s->d_state, s->state_words * sizeof(uint32_t));
   if (e == hipSuccess && K <= kMaxPool)
     e = hipMalloc(&s->d_owner, (size_t)K * kOwnerWords * sizeof(uint32_t));
-  if (e == hipSuccess && (kind == SP_SEM_COHORT || kind == SP_SEM_DEFAULT)) {
-    // queues for the cohort kind (a DEFAULT semaphore may resolve to it): allocated now,
-    // so that every run can be recorded into a graph
+  if (e == hipSuccess &&
+      (kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY || kind == SP_SEM_DEFAULT)) {
+    // queues for the cohort and array kinds (a DEFAULT semaphore may resolve to either):
+    // allocated now, so that every run can be recorded into a graph
     s->cq_stride = std::max<uint32_t>(2, spi::stride_words(q));
     s->cq_words = (uint64_t)sp::kXccQueues * (2 + kCohortSlots) * s->cq_stride;
     e = hipMalloc(&s->d_cq, s->cq_words * sizeof(uint32_t));
@@ -242,9 +246,12 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   ss.cq_stride = sem->cq_stride;
   ss.cq_len = kCohortSlots;
   ss.cohort_bound = q.cohort_passes;
-  if (kind == SP_SEM_COHORT && !sem->d_cq) return SP_E_INVAL;
+  const bool queued = kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY;
+  if (queued && !sem->d_cq) return SP_E_INVAL;
   SP_CHECK(spi::fill_u32(ctx, base, sem->state_words, 0, s));
   if (kind == SP_SEM_COHORT) SP_CHECK(spi::fill_u32(ctx, sem->d_cq, sem->cq_words, 0, s));
+  if (kind == SP_SEM_ARRAY)  // queue 0: two counter lines and the grant slots
+    SP_CHECK(spi::fill_u32(ctx, sem->d_cq, (uint64_t)(2 + kCohortSlots) * sem->cq_stride, 0, s));
   if (out_data) {
     SP_CHECK(spi::fill_u32(ctx, out_data, sem->K, 0, s));
     if (sem->K > 1) SP_CHECK(spi::fill_u32(ctx, sem->d_owner, (uint64_t)sem->K * kOwnerWords, 0, s));
@@ -263,8 +270,9 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, total_pairs);
   const uint32_t alg4 = kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF;
   const uint32_t* cq = kind == SP_SEM_COHORT ? sem->d_cq : nullptr;
+  const uint32_t* arr = kind == SP_SEM_ARRAY ? sem->d_cq : nullptr;
   hipLaunchKernelGGL(k_sem_state, dim3(1), dim3(64), 0, s, base, sw, alg4, cq, sem->cq_stride,
-                     kCohortSlots, out_state);
+                     kCohortSlots, arr, out_state);
   SP_HIP(ctx, hipGetLastError());
   SP_CHECK(spi::sync_unless_capturing(ctx, s));
   return rc;

@@ -9,7 +9,7 @@ from conftest import announce
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive", "cohort"]
+KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive", "cohort", "array"]
 
 
 def _run(ctx, kind, K, nwg, lanes, total, hold, seed, data=True, **params):
@@ -39,7 +39,7 @@ def _check(r, kind, K, nwg, total, seed):
         assert r["unserved"] == 0  # every local ticket served
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind in ("counters", "adaptive"):
+    elif kind in ("counters", "adaptive", "array"):
         assert s_or_count == 0 and ticket == turn == total
     else:
         assert s_or_count == 0 and ticket == turn
@@ -55,7 +55,7 @@ def test_small(ctx, kind, K):
     _check(r, kind, K, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort", "array"])
 @pytest.mark.parametrize("K", [1, 4, 32, 256])
 def test_full_size(ctx, kind, K):
     # 2048 workgroups, 2^20 wait/post pairs, holds uniform in [0, 2000] cycles
@@ -100,14 +100,14 @@ def test_spin_as_mutex(ctx, kind):
     _check(r, kind, 1, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "cohort"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "cohort", "array"])
 def test_capacity_above_agents_never_queues(ctx, kind):
     r = _run(ctx, kind, 64, 16, 64, 4000, 50, 7)
     _check(r, kind, 64, 16, 4000, 7)
 
 
 @pytest.mark.parametrize("kind", ["spin_backoff", "ticket", "sleep", "counters", "adaptive",
-                                  "cohort"])
+                                  "cohort", "array"])
 @pytest.mark.parametrize("K", [1, 32, 256])
 def test_coherent_critical_sections(ctx, kind, K):
     """coherent_cs: wait and post skip the cache maintenance (the workload's critical
@@ -125,3 +125,13 @@ def test_cohort_pass_bounds(ctx, passes):
         nwg, total, seed = 2048, 1 << 16, 11
         r = _run(ctx, "cohort", K, nwg, 256, total, 500, seed, cohort_passes=passes)
         _check(r, "cohort", K, nwg, total, seed)
+
+
+@pytest.mark.parametrize("K", [1, 2, 32, 4096])
+def test_array_grant_slots_reused(ctx, K):
+    """The array semaphore has 4096 grant slots: 2^18 tickets reuse each slot 64 times,
+    and with K = 4096 every ticket is granted by a post 4096 tickets earlier, whose slot
+    is its own (p + K = t).  Pool data exact, occupancy within K, counters quiescent."""
+    nwg, total, seed = 2048, 1 << 18, 0x5107
+    r = _run(ctx, "array", K, nwg, 256, total, 300, seed)
+    _check(r, "array", K, nwg, total, seed)

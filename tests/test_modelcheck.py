@@ -3,9 +3,10 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 
 import pytest
 
-from oracle.modelcheck import (BarrierModel, CohortLockModel, CohortSemModel, CondModel,
-                               FASemModel, MCSLockModel, MutexModel, QueueLockModel,
-                               SpinSemModel, WeightedSemModel, XcdBarrierModel, explore)
+from oracle.modelcheck import (ArraySemModel, BarrierModel, CohortLockModel, CohortSemModel,
+                               CondModel, FASemModel, MCSLockModel, MutexModel,
+                               QueueLockModel, SpinSemModel, WeightedSemModel,
+                               XcdBarrierModel, explore)
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
@@ -342,3 +343,33 @@ def test_cohort_semaphore_no_prediction_for_k2():
     sh, los = _predict_schedule(model)
     sh, los = _advance(model, sh, los, 0, CohortSemModel.DONE, limit=256)
     assert all(model.done(lo) for lo in los) and sh[0] == 0 and sh[6] == 0
+
+
+@pytest.mark.parametrize("K,placement,M", [(1, (0, 1, 0), 1), (1, (0, 1, 0), 2),
+                                          (2, (0, 1, 0), 1), (2, (0, 1, 0), 2),
+                                          (2, (0, 1, 1), 4)])
+def test_array_semaphore_correct(K, placement, M):
+    """Grant slots shared by several tickets (M below the 6 tickets drawn), grants landing
+    in any order: occupancy never above K, every waiter enters, with K = 1 no update of
+    the guarded word lost through the L2s."""
+    r = explore(ArraySemModel(K, placement, M, 2))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("mutant,K,M,expect", [
+    ("enter_at_k", 2, 1, "occupancy"),
+    ("grant_next", 2, 2, "occupancy"),
+    ("no_writeback", 1, 1, "without an earlier holder's update"),
+    ("no_acquire", 1, 1, "without an earlier holder's update"),
+])
+def test_array_semaphore_mutants_violate_safety(mutant, K, M, expect):
+    r = explore(ArraySemModel(K, (0, 1, 0), M, 2, mutant=mutant))
+    assert r.violation and expect in r.violation
+
+
+@pytest.mark.parametrize("mutant", ["store", "poll_eq"])
+def test_array_semaphore_grant_must_be_a_maximum(mutant):
+    """A plain store lets an earlier grant that lands late lower a shared slot, and an
+    exact-match poll misses its grant under a later one: both strand a waiter."""
+    r = explore(ArraySemModel(2, (0, 1, 0), 2, 2, mutant=mutant))
+    assert r.deadlock

@@ -51,7 +51,7 @@ def test_cohort_mutex_threaded_with_local_passes(L):
 
 
 @pytest.mark.parametrize("kind", ["spin", "spin_backoff", "spin_backoff_wait_only", "ticket",
-                                  "sleep", "counters", "adaptive", "cohort"])
+                                  "sleep", "counters", "adaptive", "cohort", "array"])
 @pytest.mark.parametrize("K", [1, 2, 4, 32])
 def test_sem_threaded_invariants(kind, K):
     seed, nwg, total = 7, 12, 2400
@@ -63,7 +63,7 @@ def test_sem_threaded_invariants(kind, K):
     assert admissions == total
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind in ("counters", "adaptive"):
+    elif kind in ("counters", "adaptive", "array"):
         assert s_or_count == 0 and ticket == turn == total  # every wait drew, every post counted
     else:
         assert s_or_count == 0 and ticket == turn
@@ -94,6 +94,17 @@ def test_cohort_semaphore_at_2048_agents(K):
     assert r["rc"] == 0 and 1 <= r["maxocc"] <= K
     assert (r["chk"] == oracle.sem_closed(seed, nwg, total)).all()
     assert r["state"] == (0, 0, 0, total)
+
+
+@pytest.mark.parametrize("K", [1, 4, 32, 256])
+def test_array_semaphore_at_2048_agents(K):
+    """Two counters with 16 grant slots shared by 2^14 tickets: every pair completes, the
+    bound holds, every wait drew a ticket and every post counted."""
+    seed, nwg, total = 0xA77A, 2048, 1 << 14
+    r = oracle.sem_threaded("array", K, seed, nwg, total)
+    assert r["rc"] == 0 and 1 <= r["maxocc"] <= K
+    assert (r["chk"] == oracle.sem_closed(seed, nwg, total)).all()
+    assert r["state"] == (0, total, total, total)
 
 
 def test_hardware_threads_reported():
