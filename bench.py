@@ -12,8 +12,8 @@ One step runs the whole path once over the full-size synthetic workloads:
      lock);
   4. semaphore: fetch-and-add semaphore (Algorithm 5 with s_sleep polling) with K = 32,
      2048 workgroups, 2^20 wait/post pairs holding uniform [0, 2000] cycles, then the
-     same workload on the library's default semaphore for this contention (the array
-     semaphore: two counters, a grant slot per ticket);
+     same workload on the library's default semaphore for this contention (the chain
+     semaphore: K chains of tickets, each holder granting the ticket K after its own);
   5. serving: 2 x 10^5 requests arriving as a Poisson stream at 10^5 req/s (lognormal
      hash-chain lengths, 1 GiB workspace budget in 64 KiB units), drained by 1024
      persistent workgroups, then the same stream served with one kernel launch per

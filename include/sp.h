@@ -113,6 +113,11 @@ enum sp_sem_kind {
                            /* 4096 (its own line) until it holds at least t + 1; the    */
                            /* post that draws p raises slot (p + K) mod 4096 to p + K + 1 */
                            /* with an atomic max, so no line is polled by the queue     */
+  SP_SEM_CHAIN = 8,        /* K chains of tickets: ticket t >= K enters once the holder  */
+                           /* of ticket t - K has posted, which stores t + 1 into slot t */
+                           /* mod M (M = the largest multiple of K <= 4096, each waiter  */
+                           /* polling its own line); the post needs no round trip.       */
+                           /* K <= 4096; each post follows its own workgroup's wait      */
   SP_SEM_DEFAULT = 15
 };
 
@@ -355,7 +360,8 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
 /* ---- semaphore (Section 5, Semaphore; Algorithms 4-5; Table 4 Wait()/Post()) ------------
  * sp_sem_create: a counting semaphore with initial value K >= 1.  Algorithm 4 keeps one
  * word S = K + 1; Algorithm 5 keeps count, ticket and turn on separate lines.
- * Errors: SP_E_INVAL (K == 0), SP_E_HIP.                                                */
+ * Errors: SP_E_INVAL (K == 0; SP_SEM_CHAIN with K > 4096), SP_E_HIP.  A SP_SEM_DEFAULT
+ * semaphore whose contention bucket names SP_SEM_CHAIN runs SP_SEM_ARRAY when K > 4096. */
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out);
 int sp_sem_destroy(sp_sem* s);
 /* Workload: total_pairs wait/post pairs split over nwg workgroups as in sp_mutex_run.
@@ -365,8 +371,8 @@ int sp_sem_destroy(sp_sem* s);
  * occupancy.  out_chk: device, nwg uint32.  out_state: device, 8 uint32 =
  * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, count,
  * occupancy, unserved} (SP_SEM_COUNTERS, SP_SEM_ADAPTIVE: count stays 0, ticket = tickets
- * drawn, turn = posts made; SP_SEM_ARRAY: the same, the low 32 bits of its 64-bit
- * counters; SP_SEM_COHORT: ticket and turn stay 0, unserved = local tickets drawn and not
+ * drawn, turn = posts made; SP_SEM_ARRAY, SP_SEM_CHAIN: the same, the low 32 bits of
+ * their 64-bit counters; SP_SEM_COHORT: ticket and turn stay 0, unserved = local tickets drawn and not
  * served, over every XCD's queue, 0 at rest).
  * out_data: device, K uint32 (zeroed by the call), or NULL; K <= 4096.  Guarded data:
  * each admission adds one to a word with a plain load and store made by the workgroup's

@@ -27,8 +27,9 @@ struct SemState {
   uint32_t cq_stride;
   uint32_t cq_len;       // power of two
   uint32_t cohort_bound; // local hand-overs of one unit in a row, at most
-  // SP_SEM_ARRAY uses queue 0's memory: line 0 the tickets drawn, line 1 the posts made
-  // (64-bit counters), then the cq_len 64-bit grant slots.
+  // SP_SEM_ARRAY and SP_SEM_CHAIN use queue 0's memory: line 0 the tickets drawn, line 1
+  // the posts made (64-bit counters), then the cq_len 64-bit grant slots.
+  uint32_t chain_len;    // SP_SEM_CHAIN: slots in use, the largest multiple of K <= cq_len
 };
 
 // Per-workgroup waiting state that persists across waits (SP_SEM_ADAPTIVE), or from a
@@ -36,6 +37,7 @@ struct SemState {
 struct SemHold {
   uint32_t interval;  // learned wall-clock ticks between two posts (0 = none yet)
   uint32_t pass;      // SP_SEM_COHORT: local hand-overs of the unit held, in a row
+  uint64_t ticket;    // SP_SEM_CHAIN: the ticket the unit held was taken with
 };
 
 // ---- cohort semaphore queues -------------------------------------------------------------
@@ -68,6 +70,9 @@ __device__ __forceinline__ uint64_t* as_posts(const SemState& s) {
 __device__ __forceinline__ uint64_t* as_slot(const SemState& s, uint64_t t) {
   return reinterpret_cast<uint64_t*>(cq_base(s, 0) +
                                      (size_t)(2 + (t & (s.cq_len - 1))) * s.cq_stride);
+}
+__device__ __forceinline__ uint64_t* chain_slot(const SemState& s, uint64_t t) {
+  return reinterpret_cast<uint64_t*>(cq_base(s, 0) + (size_t)(2 + t % s.chain_len) * s.cq_stride);
 }
 
 namespace detail {
@@ -171,6 +176,20 @@ __device__ __forceinline__ bool cq_grant(const SemState& s, uint32_t y, uint32_t
 //   ticket of the same slot is larger, so it admits the earlier one too, which the rule
 //   already allows; an earlier grant landing late cannot lower it.  64-bit counters and
 //   slots do not wrap.
+// SP_SEM_CHAIN ties each unit to a chain of tickets instead: ticket t >= K enters once
+// the holder of ticket t - K has posted, and that post stores t + 1 into slot t mod M
+// itself, with no atomic to wait for (M = chain_len, a multiple of K).  The post needs
+// the ticket its own workgroup's wait drew (SemHold::ticket), so it must follow that
+// wait; the posts counter is only counted, for the state at rest.
+//   At most K inside: entering ticket t >= K needs a post by the holder of t - K, so the
+//   tickets at or above K that have entered map one to one onto tickets that have
+//   posted, and at most K + posts tickets have entered.
+//   Every waiter enters: by induction, ticket t - K enters and posts.
+//   Slots: t and t + M (M a multiple of K) lie on one chain, t first, so the store for
+//   t + M comes after t has entered (the holder of t + M - K entered after t posted) and
+//   the store for t - M landed before t - K could enter; while t waits its slot holds
+//   t + 1 or an older ticket's value.  With M not a multiple of K a later chain's store
+//   could admit t early (the model checker finds the bound broken).
 // FENCED = false: the data the semaphore guards is accessed with agent-scope loads and
 // stores, which every XCD sees without cache maintenance, so wait skips the acquire
 // invalidation and post the release writeback.
@@ -248,6 +267,15 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
         }
       }
       if (hold) hold->pass = k;
+    } else if constexpr (KIND == SP_SEM_CHAIN) {
+      Wait w(ctl, s.poll_sleep);
+      const uint64_t t = add_relaxed64(as_tickets(s), 1);
+      hold->ticket = t;
+      if (t >= s.K) {
+        const uint64_t* g = chain_slot(s, t);
+        while (ld_relaxed64(g) <= t)
+          if (!(ok = w.tick())) break;
+      }
     } else if constexpr (KIND == SP_SEM_ARRAY) {
       Wait w(ctl, s.poll_sleep);
       const uint64_t t = add_relaxed64(as_tickets(s), 1);
@@ -281,7 +309,7 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
 }
 
 // `hold`: SP_SEM_COHORT needs the record its sem_wait filled in (the unit's local
-// hand-overs); other kinds ignore it.
+// hand-overs), SP_SEM_CHAIN requires it (the ticket, so not null); other kinds ignore it.
 template <int KIND, bool FENCED = true>
 __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold = nullptr) {
   __shared__ uint32_t s_ok;
@@ -362,6 +390,10 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
     } else if constexpr (KIND == SP_SEM_ARRAY) {
       const uint64_t q = add_relaxed64(as_posts(s), 1) + s.K;  // the ticket this post admits
       max_relaxed64(as_slot(s, q), q + 1);
+    } else if constexpr (KIND == SP_SEM_CHAIN) {
+      const uint64_t q = hold->ticket + s.K;  // the next ticket of this unit's chain
+      st_relaxed64(chain_slot(s, q), q + 1);
+      add_relaxed64(as_posts(s), 1);
     } else {
       const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);  // count -= 1
       if (old > s.K) add_relaxed(s.turn, 1);                   // admit one queued waiter

@@ -871,13 +871,19 @@ class ArraySemModel:
     mutant 'grant_next': the post grants ticket p + K + 1;
     mutant 'store': the grant is a plain store (a late earlier grant can lower a slot);
     mutant 'no_writeback': the post skips the writeback;
-    mutant 'no_acquire': the admitted waiter does not invalidate."""
+    mutant 'no_acquire': the admitted waiter does not invalidate.
+
+    rule 'chain' (the chain semaphore): the post keeps the ticket t its own wait drew,
+    counts itself in posts, and stores t + K + 1 into slot (t + K) mod M -- a plain
+    store, correct when M is a multiple of K (with any other M a later chain's store can
+    admit a waiter early: the bound breaks)."""
 
     W_TICKET, W_POLL, ACQ, CS_LD, CS_ST, P_WB, P_DRAW, P_GRANT, DONE = range(9)
 
     def __init__(self, K: int, placement: tuple, M: int, ops: int = 2,
-                 mutant: str | None = None):
+                 mutant: str | None = None, rule: str = "posts"):
         self.K, self.pl, self.M, self.ops, self.mutant = K, tuple(placement), M, ops, mutant
+        self.rule = rule
         self.n = len(self.pl)
         self.X = 1 + max(self.pl)
 
@@ -928,12 +934,14 @@ class ArraySemModel:
                 l2 = self._set(l2, x, (mem, False))
             return (tickets, posts, slots, l2, mem, inside, done_cs), (self.P_DRAW, j, t, 0)
         if pc == self.P_DRAW:
-            q = posts + self.K + (1 if self.mutant == "grant_next" else 0)
+            q = (t if self.rule == "chain" else posts) + self.K
+            q += 1 if self.mutant == "grant_next" else 0
             return ((tickets, posts + 1, slots, l2, mem, inside, done_cs),
                     (self.P_GRANT, j, t, q))
         if pc == self.P_GRANT:
             i = tmp % self.M
-            v = tmp + 1 if self.mutant == "store" else max(slots[i], tmp + 1)
+            plain = self.mutant == "store" or self.rule == "chain"
+            v = tmp + 1 if plain else max(slots[i], tmp + 1)
             nxt = self.W_TICKET if j + 1 < self.ops else self.DONE
             return ((tickets, posts, self._set(slots, i, v), l2, mem, inside, done_cs),
                     (nxt, j + 1, 0, 0))

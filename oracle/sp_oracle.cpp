@@ -649,7 +649,9 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 // before its decrement that a waiter exists; 8 two 64-bit monotone counters with a grant
 // slot per ticket (16 slots, so tickets share them): ticket t >= K waits until slot
 // t mod 16 holds at least t + 1, and the post that draws p raises slot (p + K) mod 16
-// to p + K + 1 (a maximum: grants for one slot may land in any order).
+// to p + K + 1 (a maximum: grants for one slot may land in any order); 9 K chains of
+// tickets: ticket t >= K waits until slot t mod M holds t + 1, which the holder of ticket
+// t - K stores when it posts (M = K x max(1, 16 / K), a multiple of K).
 // Each pair: wait, occupancy tracking, checksum update, admission count, post.
 // out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}; for the
 // Algorithm 4 kinds ticket and turn are unused and state[1] / state[2] report instead the
@@ -658,7 +660,7 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t total,
                     uint32_t imin, uint32_t imax, uint32_t* chk, uint32_t* maxocc,
                     uint32_t* state, double* seconds) {
-  if (nwg == 0 || K == 0 || kind < 0 || kind > 8) return -1;
+  if (nwg == 0 || K == 0 || kind < 0 || kind > 9) return -1;
   Word S{K + 1}, count{0}, ticket{0}, turn{0}, occ{0}, maxo{0}, adm{0};
   // kind 7: per group a queue of Q slots {ticket + 1, passes} after (drawn, served)
   constexpr uint32_t kGroups = 8, kBound = 4;
@@ -671,8 +673,10 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   // kind 8: 64-bit tickets drawn and posts made, and the grant slots
   constexpr uint32_t kGrantSlots = 16;
   std::atomic<uint64_t> tickets64{0}, posts64{0};
-  std::vector<std::atomic<uint64_t>> grants(kind == 8 ? kGrantSlots : 0);
+  const uint32_t chain_len = K * std::max<uint32_t>(1, kGrantSlots / K);
+  std::vector<std::atomic<uint64_t>> grants(kind == 8 ? kGrantSlots : kind == 9 ? chain_len : 0);
   for (auto& w : grants) w.store(0);
+  std::vector<uint64_t> my_ticket(kind == 9 ? nwg : 0);  // kind 9: the ticket each agent holds
   auto claim = [&](uint32_t g, uint32_t* t) {
     uint32_t v = served[g].load(std::memory_order_relaxed);
     while ((int32_t)(drawn[g].load(std::memory_order_relaxed) - v) > 0)
@@ -706,6 +710,13 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   std::atomic<uint64_t> wait_fail{0}, post_fail{0};
 
   auto wait = [&](Backoff& bo, uint32_t b) {
+    if (kind == 9) {
+      const uint64_t t = tickets64.fetch_add(1, std::memory_order_acq_rel);
+      my_ticket[b] = t;
+      if (t >= K)
+        while (grants[t % chain_len].load(std::memory_order_acquire) != t + 1) relax();
+      return;
+    }
     if (kind == 8) {
       const uint64_t t = tickets64.fetch_add(1, std::memory_order_acq_rel);
       if (t >= K)
@@ -756,6 +767,12 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
     }
   };
   auto post = [&](Backoff& bo, uint32_t b) {
+    if (kind == 9) {
+      const uint64_t q = my_ticket[b] + K;
+      grants[q % chain_len].store(q + 1, std::memory_order_release);
+      posts64.fetch_add(1, std::memory_order_relaxed);
+      return;
+    }
     if (kind == 8) {
       const uint64_t q = posts64.fetch_add(1, std::memory_order_acq_rel) + K;
       auto& g = grants[q % kGrantSlots];
@@ -829,9 +846,9 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   }
   state[0] = alg4 ? S.load() : count.load();
   state[1] = alg4 ? (uint32_t)std::min<uint64_t>(wait_fail.load(), 0xFFFFFFFFu)
-                  : kind == 8 ? (uint32_t)tickets64.load() : ticket.load();
+                  : kind >= 8 ? (uint32_t)tickets64.load() : ticket.load();
   state[2] = alg4 ? (uint32_t)std::min<uint64_t>(post_fail.load(), 0xFFFFFFFFu)
-                  : kind == 8 ? (uint32_t)posts64.load() : turn.load();
+                  : kind >= 8 ? (uint32_t)posts64.load() : turn.load();
   state[3] = adm.load();
   if (seconds) *seconds = t;
   return *maxocc > K ? -2 : 0;

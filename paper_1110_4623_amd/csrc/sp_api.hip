@@ -229,11 +229,12 @@ int sp_init(int device, sp_ctx** out) {
   ctx->defaults[1][1].kind = SP_MUTEX_COHORT;
   ctx->defaults[1][1].p.poll_sleep = 0;
   ctx->defaults[1][1].p.cohort_passes = 64;
-  // array semaphore: 12.4 M pairs/s K = 32 at 256, 42 M K = 256 at 2048 (two counters
-  // + s_sleep 16: 8.1 / 6.9); 12.1 M K = 32 at 2048, 1.55 M K = 4 (adaptive 6.5 / 1.6)
-  ctx->defaults[2][0].kind = SP_SEM_ARRAY;
+  // chain semaphore (the array kind above K = 4096): 13.6 M pairs/s K = 32 at 256, 42.7 M
+  // K = 256 at 2048 (array 12.4 / 42.3, two counters + s_sleep 16 8.1 / 6.9); 13.1 M
+  // K = 32 at 2048, 1.69 M K = 4 (array 12.1 / 1.53, adaptive 6.3 / 1.55)
+  ctx->defaults[2][0].kind = SP_SEM_CHAIN;
   ctx->defaults[2][0].p.poll_sleep = 0;
-  ctx->defaults[2][1].kind = SP_SEM_ARRAY;
+  ctx->defaults[2][1].kind = SP_SEM_CHAIN;
   ctx->defaults[2][1].p.poll_sleep = 0;
   // resolve the "auto" fields (fan_in = XCD count, ...) as sp_set_default does
   for (int prim = 0; prim < 3; ++prim)
@@ -281,7 +282,7 @@ int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p) {
   if (!usable(ctx) || primitive > 2 || bucket > 1) return SP_E_INVAL;
-  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_MCS, SP_SEM_ARRAY};
+  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_MCS, SP_SEM_CHAIN};
   if (kind > max_kind[primitive]) return SP_E_INVAL;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));

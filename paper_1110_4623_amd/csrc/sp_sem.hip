@@ -27,9 +27,10 @@ constexpr uint32_t kMaxPool = 4096;
 constexpr uint32_t kOwnerWords = 8;
 // Algorithm 4's waiter backoff cap when the caller names no backoff policy (s_sleep units).
 constexpr uint32_t kAlg4BackoffCap = 8192;
-// Grant slots of each XCD's queue (cohort kind; the array kind uses the first queue's).
-// Any number is correct: a cohort post waits for a slot's previous ticket to take its
-// grant before it writes the next one, an array post's grant is a maximum.
+// Grant slots of each XCD's queue (cohort kind; the array and chain kinds use the first
+// queue's).  Any number is correct for the first two: a cohort post waits for a slot's
+// previous ticket to take its grant before it writes the next one, an array post's grant
+// is a maximum.  The chain kind uses the largest multiple of K that fits.
 constexpr uint32_t kCohortSlots = 4096;
 
 // The wait/hold/post workload.  With `data` (K uint32 words, packed, plain memory) every
@@ -115,7 +116,7 @@ __global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg
       }
     out[0] = state[L_MAXOCC * stride];
     out[1] = alg4 ? state[L_S * stride] : state[L_COUNT * stride];
-    // array kind: the low halves of its 64-bit tickets and posts counters
+    // array and chain kinds: the low halves of their 64-bit tickets and posts counters
     out[2] = arr ? arr[0] : state[L_TICKET * stride];
     out[3] = arr ? arr[cq_stride] : state[L_TURN * stride];
     out[4] = state[L_ADM * stride];
@@ -138,6 +139,7 @@ const void* sem_kernel_f(uint32_t kind) {
     case SP_SEM_ADAPTIVE: return (const void*)k_sem<SP_SEM_ADAPTIVE, FENCED>;
     case SP_SEM_COHORT: return (const void*)k_sem<SP_SEM_COHORT, FENCED>;
     case SP_SEM_ARRAY: return (const void*)k_sem<SP_SEM_ARRAY, FENCED>;
+    case SP_SEM_CHAIN: return (const void*)k_sem<SP_SEM_CHAIN, FENCED>;
     default: return nullptr;
   }
 }
@@ -152,7 +154,8 @@ extern "C" {
 
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out) {
   if (!spi::usable(ctx) || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
-  if (kind > SP_SEM_ARRAY && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_SEM_CHAIN && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  if (kind == SP_SEM_CHAIN && K > kCohortSlots) return SP_E_INVAL;  // a slot per chain at least
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -166,10 +169,10 @@ int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp
   hipError_t e = hipMalloc(&s->d_state, s->state_words * sizeof(uint32_t));
   if (e == hipSuccess && K <= kMaxPool)
     e = hipMalloc(&s->d_owner, (size_t)K * kOwnerWords * sizeof(uint32_t));
-  if (e == hipSuccess &&
-      (kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY || kind == SP_SEM_DEFAULT)) {
-    // queues for the cohort and array kinds (a DEFAULT semaphore may resolve to either):
-    // allocated now, so that every run can be recorded into a graph
+  if (e == hipSuccess && (kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY ||
+                          kind == SP_SEM_CHAIN || kind == SP_SEM_DEFAULT)) {
+    // queues for the cohort, array and chain kinds (a DEFAULT semaphore may resolve to
+    // any of them): allocated now, so that every run can be recorded into a graph
     s->cq_stride = std::max<uint32_t>(2, spi::stride_words(q));
     s->cq_words = (uint64_t)sp::kXccQueues * (2 + kCohortSlots) * s->cq_stride;
     e = hipMalloc(&s->d_cq, s->cq_words * sizeof(uint32_t));
@@ -218,6 +221,8 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
     q = d.p;
     q.timeout_ms = t;
     q.coherent_cs = coherent;
+    // the chain kind needs a slot per chain; above that the array kind (same admission rule)
+    if (kind == SP_SEM_CHAIN && sem->K > kCohortSlots) kind = SP_SEM_ARRAY;
   }
   if (kind == SP_SEM_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) {
     // No policy chosen: exponential, capped at 8192 units.  With posts retrying at once,
@@ -246,11 +251,12 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   ss.cq_stride = sem->cq_stride;
   ss.cq_len = kCohortSlots;
   ss.cohort_bound = q.cohort_passes;
-  const bool queued = kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY;
+  ss.chain_len = sem->K <= kCohortSlots ? kCohortSlots / sem->K * sem->K : kCohortSlots;
+  const bool queued = kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN;
   if (queued && !sem->d_cq) return SP_E_INVAL;
   SP_CHECK(spi::fill_u32(ctx, base, sem->state_words, 0, s));
   if (kind == SP_SEM_COHORT) SP_CHECK(spi::fill_u32(ctx, sem->d_cq, sem->cq_words, 0, s));
-  if (kind == SP_SEM_ARRAY)  // queue 0: two counter lines and the grant slots
+  if (kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN)  // queue 0: two counters, the slots
     SP_CHECK(spi::fill_u32(ctx, sem->d_cq, (uint64_t)(2 + kCohortSlots) * sem->cq_stride, 0, s));
   if (out_data) {
     SP_CHECK(spi::fill_u32(ctx, out_data, sem->K, 0, s));
@@ -270,7 +276,7 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, total_pairs);
   const uint32_t alg4 = kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF;
   const uint32_t* cq = kind == SP_SEM_COHORT ? sem->d_cq : nullptr;
-  const uint32_t* arr = kind == SP_SEM_ARRAY ? sem->d_cq : nullptr;
+  const uint32_t* arr = kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN ? sem->d_cq : nullptr;
   hipLaunchKernelGGL(k_sem_state, dim3(1), dim3(64), 0, s, base, sw, alg4, cq, sem->cq_stride,
                      kCohortSlots, arr, out_state);
   SP_HIP(ctx, hipGetLastError());

@@ -259,7 +259,8 @@ def barrier(ctx, rounds: int = 10_000, lanes: int = 256, seed: int = 42, quick: 
 # ---- semaphores ---------------------------------------------------------------------------
 
 SEMS = [("spin", {}), ("spin_backoff", {"backoff": "exp"}), ("ticket", {}), ("sleep", {}),
-        ("counters", {}), ("adaptive", {}), ("cohort", {}), ("array", {})]
+        ("counters", {}), ("adaptive", {}), ("cohort", {}), ("array", {}),
+        ("chain", {})]
 
 
 def sem(ctx, budget_s: float = 0.3, nwg: int = 2048, lanes: int = 256, seed: int = 42,

@@ -163,6 +163,7 @@ def semaphore_candidates():
     out += [("cohort", {"poll_sleep": ps, "cohort_passes": cp}) for ps in (0, 4)
             for cp in (16, 64)]
     out += [("array", {"poll_sleep": ps}) for ps in (0, 1, 4)]
+    out += [("chain", {"poll_sleep": ps}) for ps in (0, 1, 4)]
     return out
 
 

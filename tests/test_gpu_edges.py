@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 BARRIERS = ["central", "central_split", "tree", "flag", "xcd", "grid_sync"]
 MUTEXES = ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep", "ring", "array",
            "adaptive", "cohort", "mcs"]
-SEMS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive", "cohort", "array"]
+SEMS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive", "cohort", "array",
+        "chain"]
 
 
 @pytest.mark.parametrize("kind", BARRIERS)
@@ -72,7 +73,7 @@ def _sem_quiescent(r, kind, K, total):
     assert r["maxocc"] <= K and (r["maxocc"] >= 1) == (total > 0)
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind in ("counters", "adaptive", "array"):
+    elif kind in ("counters", "adaptive", "array", "chain"):
         assert s_or_count == 0 and ticket == turn == total
     else:
         assert s_or_count == 0 and ticket == turn
@@ -92,7 +93,8 @@ def test_semaphore_few_operations(ctx, kind, K, nwg, total):
     _sem_quiescent(r, kind, K, total)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort", "array"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort", "array",
+                                  "chain"])
 @pytest.mark.parametrize("K", [5, 300])
 def test_semaphore_odd_grid(ctx, kind, K):
     # 300 workgroups, 12345 pairs: 45 workgroups take one pair more than the rest
@@ -101,7 +103,8 @@ def test_semaphore_odd_grid(ctx, kind, K):
     _sem_quiescent(r, kind, K, 12345)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort", "array"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort", "array",
+                                  "chain"])
 def test_semaphore_capacity_above_agents(ctx, kind):
     r = _sem(ctx, kind, 64, 16, 4000, 7)
     assert (r["chk"] == oracle.sem_closed(7, 16, 4000)).all()

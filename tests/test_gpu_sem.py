@@ -9,7 +9,8 @@ from conftest import announce
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive", "cohort", "array"]
+KINDS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive", "cohort", "array",
+         "chain"]
 
 
 def _run(ctx, kind, K, nwg, lanes, total, hold, seed, data=True, **params):
@@ -39,7 +40,7 @@ def _check(r, kind, K, nwg, total, seed):
         assert r["unserved"] == 0  # every local ticket served
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind in ("counters", "adaptive", "array"):
+    elif kind in ("counters", "adaptive", "array", "chain"):
         assert s_or_count == 0 and ticket == turn == total
     else:
         assert s_or_count == 0 and ticket == turn
@@ -55,7 +56,8 @@ def test_small(ctx, kind, K):
     _check(r, kind, K, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort", "array"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort", "array",
+                                  "chain"])
 @pytest.mark.parametrize("K", [1, 4, 32, 256])
 def test_full_size(ctx, kind, K):
     # 2048 workgroups, 2^20 wait/post pairs, holds uniform in [0, 2000] cycles
@@ -100,14 +102,14 @@ def test_spin_as_mutex(ctx, kind):
     _check(r, kind, 1, nwg, total, seed)
 
 
-@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "cohort", "array"])
+@pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "cohort", "array", "chain"])
 def test_capacity_above_agents_never_queues(ctx, kind):
     r = _run(ctx, kind, 64, 16, 64, 4000, 50, 7)
     _check(r, kind, 64, 16, 4000, 7)
 
 
 @pytest.mark.parametrize("kind", ["spin_backoff", "ticket", "sleep", "counters", "adaptive",
-                                  "cohort", "array"])
+                                  "cohort", "array", "chain"])
 @pytest.mark.parametrize("K", [1, 32, 256])
 def test_coherent_critical_sections(ctx, kind, K):
     """coherent_cs: wait and post skip the cache maintenance (the workload's critical
@@ -127,11 +129,31 @@ def test_cohort_pass_bounds(ctx, passes):
         _check(r, "cohort", K, nwg, total, seed)
 
 
-@pytest.mark.parametrize("K", [1, 2, 32, 4096])
-def test_array_grant_slots_reused(ctx, K):
-    """The array semaphore has 4096 grant slots: 2^18 tickets reuse each slot 64 times,
-    and with K = 4096 every ticket is granted by a post 4096 tickets earlier, whose slot
-    is its own (p + K = t).  Pool data exact, occupancy within K, counters quiescent."""
+@pytest.mark.parametrize("kind", ["array", "chain"])
+@pytest.mark.parametrize("K", [1, 2, 3, 32, 4096])
+def test_grant_slots_reused(ctx, kind, K):
+    """4096 grant slots (the chain kind: the largest multiple of K, 4095 for K = 3): 2^18
+    tickets reuse each slot 64 times, and with K = 4096 every ticket's grant comes from
+    the ticket 4096 before it, in the same slot.  Guarded data exact (K > 1: the pool of
+    K slots, K <= 4096), occupancy within K, counters quiescent."""
     nwg, total, seed = 2048, 1 << 18, 0x5107
-    r = _run(ctx, "array", K, nwg, 256, total, 300, seed)
-    _check(r, "array", K, nwg, total, seed)
+    r = _run(ctx, kind, K, nwg, 256, total, 300, seed)
+    _check(r, kind, K, nwg, total, seed)
+
+
+def test_chain_capacity_limit(ctx):
+    """The chain kind needs a slot per chain: K above 4096 is refused at creation, and a
+    default semaphore that resolves to it runs the array kind instead."""
+    import paper_1110_4623_amd as sp
+    with pytest.raises(sp.SpError):
+        sp.Semaphore(ctx, "chain", 4097)
+    own = sp.Context(0)  # a context of its own: the changed default stays in it
+    try:
+        own.set_default("semaphore", 0, "chain")
+        nwg, total, seed = 64, 1 << 12, 3
+        r = _run(own, "default", 5000, nwg, 64, total, 100, seed, data=False)
+        _check(r, "array", 5000, nwg, total, seed)
+        r = _run(own, "default", 4, nwg, 64, total, 100, seed, data=False)
+        _check(r, "chain", 4, nwg, total, seed)
+    finally:
+        own.close()

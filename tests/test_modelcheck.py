@@ -373,3 +373,31 @@ def test_array_semaphore_grant_must_be_a_maximum(mutant):
     exact-match poll misses its grant under a later one: both strand a waiter."""
     r = explore(ArraySemModel(2, (0, 1, 0), 2, 2, mutant=mutant))
     assert r.deadlock
+
+
+@pytest.mark.parametrize("K,M", [(1, 1), (1, 2), (2, 2), (2, 4), (3, 3)])
+def test_chain_semaphore_correct(K, M):
+    """The chain rule with M a multiple of K: the holder of ticket t grants t + K with a
+    plain store; occupancy never above K, everyone enters, no lost update at K = 1."""
+    r = explore(ArraySemModel(K, (0, 1, 0), M, 2, rule="chain"))
+    assert r.ok, r.violation
+
+
+def test_chain_semaphore_needs_slots_a_multiple_of_k():
+    """With M not a multiple of K another chain's store reaches a waiter's slot: one slot
+    for two chains admits a third holder, three slots for two chains strand a waiter."""
+    r = explore(ArraySemModel(2, (0, 1, 0), 1, 2, rule="chain"))
+    assert r.violation and "occupancy" in r.violation
+    r = explore(ArraySemModel(2, (0, 1, 0), 3, 2, rule="chain"))
+    assert r.deadlock
+
+
+@pytest.mark.parametrize("mutant,K,M,expect", [
+    ("enter_at_k", 2, 2, "occupancy"),
+    ("grant_next", 2, 2, "occupancy"),
+    ("no_writeback", 1, 1, "without an earlier holder's update"),
+    ("no_acquire", 1, 1, "without an earlier holder's update"),
+])
+def test_chain_semaphore_mutants(mutant, K, M, expect):
+    r = explore(ArraySemModel(K, (0, 1, 0), M, 2, mutant=mutant, rule="chain"))
+    assert r.violation and expect in r.violation

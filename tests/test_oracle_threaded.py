@@ -51,7 +51,8 @@ def test_cohort_mutex_threaded_with_local_passes(L):
 
 
 @pytest.mark.parametrize("kind", ["spin", "spin_backoff", "spin_backoff_wait_only", "ticket",
-                                  "sleep", "counters", "adaptive", "cohort", "array"])
+                                  "sleep", "counters", "adaptive", "cohort", "array",
+                                  "chain"])
 @pytest.mark.parametrize("K", [1, 2, 4, 32])
 def test_sem_threaded_invariants(kind, K):
     seed, nwg, total = 7, 12, 2400
@@ -63,7 +64,7 @@ def test_sem_threaded_invariants(kind, K):
     assert admissions == total
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind in ("counters", "adaptive", "array"):
+    elif kind in ("counters", "adaptive", "array", "chain"):
         assert s_or_count == 0 and ticket == turn == total  # every wait drew, every post counted
     else:
         assert s_or_count == 0 and ticket == turn
@@ -102,6 +103,19 @@ def test_array_semaphore_at_2048_agents(K):
     bound holds, every wait drew a ticket and every post counted."""
     seed, nwg, total = 0xA77A, 2048, 1 << 14
     r = oracle.sem_threaded("array", K, seed, nwg, total)
+    assert r["rc"] == 0 and 1 <= r["maxocc"] <= K
+    assert (r["chk"] == oracle.sem_closed(seed, nwg, total)).all()
+    assert r["state"] == (0, total, total, total)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("K", [1, 3, 32, 256])
+def test_chain_semaphore_at_2048_agents(K):
+    """K chains over K x max(1, 16 / K) slots (K = 3: 15 slots), each waiter waiting for
+    exactly its own ticket's value: a store from another chain or a later ticket of the
+    same slot would leave it waiting (the timeout would fire)."""
+    seed, nwg, total = 0xC4A1, 2048, 1 << 14
+    r = oracle.sem_threaded("chain", K, seed, nwg, total)
     assert r["rc"] == 0 and 1 <= r["maxocc"] <= K
     assert (r["chk"] == oracle.sem_closed(seed, nwg, total)).all()
     assert r["state"] == (0, total, total, total)
