@@ -49,6 +49,9 @@ NWG, LANES, ROUNDS = 2048, 256, 10_000
 C1_NWG, C1_LANES, C1_ROUNDS = 16, 64, 1000
 MUTEX_TOTAL, SEM_TOTAL, SEM_K = 1 << 20, 1 << 20, 32
 CURVE_NWG, CURVE_OPS = (64, 256, 1024), 1 << 18
+# read-modify-writes per wait/post pair on each semaphore kind's busiest contended word
+SEM_RMW_PER_PAIR = {"spin": 4, "spin_backoff": 4, "ticket": 2, "sleep": 2, "cohort": 2,
+                    "counters": 1, "adaptive": 1, "array": 1, "chain": 1}
 SERVE_RATE, SERVE_N, SERVE_NWG = 1e5, 200_000, 1024
 
 
@@ -266,6 +269,10 @@ def main() -> int:
     mtx_def_rate = float(np.mean([MUTEX_TOTAL / (r["mtx_def_ms"] * 1e-3) for r in results]))
     sem_rate = float(np.mean([SEM_TOTAL / (r["sem_ms"] * 1e-3) for r in results]))
     sem_def_rate = float(np.mean([SEM_TOTAL / (r["sem_def_ms"] * 1e-3) for r in results]))
+    # the kind the default semaphore ran (bucket 1: at least 64 workgroups per unit) and
+    # the read-modify-writes per pair on its busiest contended word
+    sem_def_kind = ctx.get_default("semaphore", 1 if NWG // SEM_K >= 64 else 0)
+    sem_def_rmw = SEM_RMW_PER_PAIR[sem_def_kind]
     coh_us = float(np.mean([r["bar_coh_ms"] for r in results])) * 1e3 / ROUNDS
 
     def med(key, field):
@@ -347,15 +354,19 @@ def main() -> int:
                          "A_dist_atomics_per_s_2p20_words": round(a_dist, 1),
                          "B_stream_read_GB_per_s": round(b_stream / 1e9, 1),
                          "L_coh_one_way_us": round(sig_us, 4)},
-            # The mutex and semaphore against their own bounds: a contended semaphore
-            # pair makes two read-modify-writes on contended words (one per wait, one per
-            # post, in every kind here), so at most A1 / 2 pairs per second; a lock
-            # hand-over moves ownership at least one one-way hop, so at most 1 / L_coh
+            # The mutex and semaphore against their own bounds.  A contended word takes
+            # at most A1 read-modify-writes per second, so a semaphore kind that makes r
+            # of them per pair on its busiest word admits at most A1 / r pairs per second:
+            # Algorithm 5 r = 2 (count, up in the wait and down in the post), the ticket
+            # kinds r = 1 (the tickets word in the wait, the posts word in the post).  A
+            # lock hand-over moves ownership at least one one-way hop, so at most 1 / L_coh
             # acquisitions per second (the critical section's own time left out).
             "bounds": {
-                "semaphore_k32_pairs_bound_per_s": round(a1 / 2, 1),
-                "semaphore_k32_default_kind_frac": round(sem_def_rate / (a1 / 2), 4),
+                "semaphore_k32_alg5_bound_per_s": round(a1 / 2, 1),
                 "semaphore_k32_alg5_frac": round(sem_rate / (a1 / 2), 4),
+                "semaphore_k32_default_kind": sem_def_kind,
+                "semaphore_k32_default_kind_bound_per_s": round(a1 / sem_def_rmw, 1),
+                "semaphore_k32_default_kind_frac": round(sem_def_rate / (a1 / sem_def_rmw), 4),
                 "mutex_acq_bound_per_s": round(1e6 / sig_us, 1),
                 "mutex_default_kind_frac": round(mtx_def_rate * sig_us * 1e-6, 4),
                 "mutex_ticket_frac": round(mtx_rate * sig_us * 1e-6, 4)},

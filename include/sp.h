@@ -251,10 +251,15 @@ void sp_params_default(sp_params* p);
  * Section 7: tuning backoff per GPU and contention level).  Until a call replaces them,
  * the defaults are a tuning pass's winners on an MI355X: barrier central (low) and
  * per-XCD with 64 stamp copies (high); mutex spin with the paper's backoff, I_max 8
- * (low) and the XCD-cohort lock (high); semaphore
- * two counters with s_sleep 16 (low) and adaptive (high).                               */
+ * (low) and the XCD-cohort lock (high); semaphore the chain kind (both; the array kind
+ * where K > 4096).                                                                      */
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p);
+/* Reads back what *_DEFAULT resolves to for a primitive class and bucket (as above):
+ * *kind (host) and, unless p is NULL, *p (host) with the "auto" fields resolved.
+ * Errors: SP_E_INVAL (bad context, class or bucket, kind NULL).                         */
+int sp_get_default(const sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t* kind,
+                   sp_params* p);
 const char* sp_strerror(int code);
 int sp_last_hip_error(const sp_ctx* ctx);
 /* Writes the XCC id of every workgroup of a plain launch of nwg x lanes into

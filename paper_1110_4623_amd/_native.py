@@ -180,6 +180,7 @@ def _load():
         "sp_device_info_get": (i32, [vp, P(DeviceInfo)]),
         "sp_params_default": (None, [P(Params)]),
         "sp_set_default": (i32, [vp, u32, u32, u32, P(Params)]),
+        "sp_get_default": (i32, [vp, u32, u32, P(u32), P(Params)]),
         "sp_strerror": (ctypes.c_char_p, [i32]),
         "sp_last_hip_error": (i32, [vp]),
         "sp_probe_xcc": (i32, [vp, u32, u32, vp, vp]),

@@ -179,6 +179,15 @@ class Context:
         check(lib.sp_set_default(self.h, prim, bucket, kinds[kind], ctypes.byref(p)),
               "sp_set_default", self.h)
 
+    def get_default(self, primitive: str, bucket: int) -> str:
+        """The kind name that a DEFAULT object of this class resolves to in this bucket."""
+        prim = {"barrier": 0, "mutex": 1, "semaphore": 2}[primitive]
+        kinds = [N.BARRIER_KINDS, N.MUTEX_KINDS, N.SEM_KINDS][prim]
+        k = ctypes.c_uint32(0)
+        check(lib.sp_get_default(self.h, prim, bucket, ctypes.byref(k), None),
+              "sp_get_default", self.h)
+        return {v: n for n, v in kinds.items()}[k.value]
+
     def probe_xcc(self, nwg: int, lanes: int = 64) -> np.ndarray:
         out = self.zeros(nwg)
         check(lib.sp_probe_xcc(self.h, nwg, lanes, self.ptr(out), self.stream()), "sp_probe_xcc",

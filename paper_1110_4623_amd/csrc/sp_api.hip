@@ -291,6 +291,14 @@ int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t ki
   return SP_OK;
 }
 
+int sp_get_default(const sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t* kind,
+                   sp_params* p) {
+  if (!usable(ctx) || primitive > 2 || bucket > 1 || !kind) return SP_E_INVAL;
+  *kind = ctx->defaults[primitive][bucket].kind;
+  if (p) *p = ctx->defaults[primitive][bucket].p;
+  return SP_OK;
+}
+
 int sp_probe_xcc(sp_ctx* ctx, uint32_t nwg, uint32_t lanes, uint32_t* out, void* stream) {
   if (!usable(ctx) || !out || nwg == 0 || !spi::lanes_ok(lanes)) return SP_E_INVAL;
   hipStream_t s = spi::as_stream(stream);

@@ -61,6 +61,10 @@ def test_one_step_prints_the_contract_line():
     for k in ("semaphore_k32_default_kind_frac", "semaphore_k32_alg5_frac",
               "mutex_default_kind_frac", "mutex_ticket_frac"):
         assert 0 < m["bounds"][k] < 1, k
+    import bench
+    kind = m["bounds"]["semaphore_k32_default_kind"]
+    assert m["bounds"]["semaphore_k32_default_kind_bound_per_s"] == round(
+        m["ceilings"]["A1_contended_atomics_per_s"] / bench.SEM_RMW_PER_PAIR[kind], 1)
     assert m["central_barrier_16wg_checksums_deterministic"] is True
     for name in ("barrier_default_us_per_round", "mutex_default_acq_per_s",
                  "semaphore_k32_default_pairs_per_s"):
@@ -97,3 +101,10 @@ def test_cpu_baseline_leg_checks_checksums_against_the_oracle():
     words[0, 3] += 1
     bad_curve = {n: (good[n][0], words, good[n][2])}
     assert bench.cpu_baseline(ref, ref1, bad_curve, budget_s=0.5)["curves_match_oracle"] is False
+
+
+def test_semaphore_bound_covers_every_kind():
+    """Every semaphore kind has a read-modify-write count for its busiest word."""
+    import bench
+    from paper_1110_4623_amd import _native as N
+    assert set(bench.SEM_RMW_PER_PAIR) == set(N.SEM_KINDS) - {"default"}

@@ -147,8 +147,11 @@ def test_chain_capacity_limit(ctx):
     import paper_1110_4623_amd as sp
     with pytest.raises(sp.SpError):
         sp.Semaphore(ctx, "chain", 4097)
+    assert ctx.get_default("semaphore", 0) == ctx.get_default("semaphore", 1) == "chain"
     own = sp.Context(0)  # a context of its own: the changed default stays in it
     try:
+        own.set_default("semaphore", 0, "array")
+        assert own.get_default("semaphore", 0) == "array"
         own.set_default("semaphore", 0, "chain")
         nwg, total, seed = 64, 1 << 12, 3
         r = _run(own, "default", 5000, nwg, 64, total, 100, seed, data=False)
