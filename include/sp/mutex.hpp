@@ -15,8 +15,8 @@ struct MutexState {
   uint32_t* ticket;     // ticket mutex: next ticket, one line per lock
   uint32_t* turn;       // ticket mutex: ticket being served; ring: head; one line per lock
   uint32_t* queue;      // ring / array: qlen slots per lock, qstride words apart;
-                        // cohort: per lock and XCC id, two lines (local ticket, 64-bit
-                        // grant word), qstride (even) words apart
+                        // cohort: per lock and XCC id, kCohortLines lines (local ticket,
+                        // 64-bit grant slots), qstride (even) words apart
   uint32_t qlen;        // slots per lock (power of two; the ring needs >= contenders)
   uint32_t qstride;     // words between slots
   uint32_t cohort_bound;  // cohort: holders of one XCD in a row, at most
@@ -36,17 +36,24 @@ struct MutexHold {
 };
 
 // Cohort lock state of `lock` for the XCD with XCC id x (kXccSlots per lock: the XCC id
-// register has four bits, so every XCD has its own cohort whatever the count): line 0 the
-// local ticket counter, line 1 the 64-bit grant word = local turn (bits 0-23, modulo
-// 2^24) | session (bits 24-31) | global ticket of the session (bits 32-63), written only
-// by the local holder, so one store hands over turn, session and global ticket at once.
+// register has four bits, so every XCD has its own cohort whatever the count):
+// kCohortLines lines, line 0 the local ticket counter, then kCohortGrants 64-bit grant
+// slots.  Local ticket t polls slot t mod kCohortGrants (a few waiters per line instead
+// of the XCD's whole queue on one), which holds local turn (bits 0-23, modulo 2^24) |
+// session (bits 24-31) | global ticket of the session (bits 32-63); the holder of local
+// ticket t writes slot t + 1, so one store hands over turn, session and global ticket at
+// once.  A slot is rewritten (for ticket t + kCohortGrants) only after ticket t entered.
 constexpr uint32_t kXccSlots = 16;
+constexpr uint32_t kCohortGrants = 32;
+constexpr uint32_t kCohortLines = 1 + kCohortGrants;
 constexpr uint32_t kTurnMask = 0xFFFFFFu;
 __device__ __forceinline__ uint32_t* cohort_ticket(const MutexState& s, uint32_t lock, uint32_t x) {
-  return s.queue + ((size_t)lock * kXccSlots + x) * 2 * s.qstride;
+  return s.queue + ((size_t)lock * kXccSlots + x) * kCohortLines * s.qstride;
 }
-__device__ __forceinline__ uint64_t* cohort_grant(const MutexState& s, uint32_t lock, uint32_t x) {
-  const size_t line = ((size_t)lock * kXccSlots + x) * 2 + 1;
+__device__ __forceinline__ uint64_t* cohort_grant(const MutexState& s, uint32_t lock, uint32_t x,
+                                                  uint32_t t) {
+  const size_t line =
+      ((size_t)lock * kXccSlots + x) * kCohortLines + 1 + (t & (kCohortGrants - 1));
   return reinterpret_cast<uint64_t*>(s.queue + line * s.qstride);
 }
 
@@ -75,13 +82,14 @@ __device__ __forceinline__ uint32_t* mcs_node(const MutexState& s, uint32_t lock
 //                         grant is overwritten only after its owner entered and left, so
 //                         any number of slots is correct; more slots spread the polling.
 //   SP_MUTEX_COHORT       XCD-cohort lock (lock cohorting, made for per-XCD L2s): a ticket
-//                         lock per XCD in front of a global ticket lock.  The grant word
-//                         a local waiter polls carries the session (0 = the XCD does not
-//                         hold the global lock; k > 0 = it does, k holders of this XCD
-//                         took it in a row) and the session's global ticket.  A local
-//                         holder that reads session 0 takes the global lock.  Unlock
-//                         passes the global lock with the local one (one store of the
-//                         grant word: turn + 1, session k + 1) when a local ticket beyond
+//                         lock per XCD in front of a global ticket lock.  The grant a
+//                         local waiter polls (in its ticket's slot, a line shared by few
+//                         waiters) carries the session (0 = the XCD does not hold the
+//                         global lock; k > 0 = it does, k holders of this XCD took it in
+//                         a row) and the session's global ticket.  A local holder that
+//                         reads session 0 takes the global lock.  Unlock passes the
+//                         global lock with the local one (one store into the next local
+//                         ticket's slot: turn + 1, session k + 1) when a local ticket beyond
 //                         one's own was drawn and k + 1 < cohort_bound; that hand-over
 //                         needs no L2 writeback, since both holders use this XCD's L2
 //                         (the critical section's stores have completed into it).
@@ -189,7 +197,7 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
     } else if constexpr (KIND == SP_MUTEX_COHORT) {
       const uint32_t x = xcc_id();
       const uint32_t t = add_relaxed(cohort_ticket(s, lock, x), 1);
-      const uint64_t* grant = cohort_grant(s, lock, x);
+      const uint64_t* grant = cohort_grant(s, lock, x, t);
       uint64_t v;
       for (;;) {
         v = ld_relaxed64(grant);
@@ -273,8 +281,8 @@ __device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold
     wave_stores_complete();
     __syncthreads();
     if (!is_leader()) return;
-    uint64_t* grant = cohort_grant(s, lock, x);
     const uint32_t t = hold->ticket, k = hold->session + 1, g = hold->global;
+    uint64_t* grant = cohort_grant(s, lock, x, t + 1);  // the next local ticket's slot
     const uint64_t next_turn = (t + 1) & kTurnMask;
     if ((int32_t)(drawn - (t + 1)) > 0 && k < s.cohort_bound) {
       // The next holder runs on this XCD: pass the global lock with the local one.  The

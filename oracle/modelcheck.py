@@ -286,30 +286,34 @@ class QueueLockModel:
 
 class CohortLockModel:
     """XCD-cohort lock: a local ticket lock per cohort (agent a belongs to cohort a mod C)
-    in front of a global ticket lock.  The cohort's grant word holds the local turn and
-    the session together (one store writes both, one load reads both): session 0 says
-    the cohort does not hold the global lock, k > 0 that it does and k holders have
-    passed it on.  A local holder that reads session 0 takes the global lock.  Unlock:
-    when a local waiter exists (local tickets drawn beyond one's own) and k + 1 < B,
-    grant (turn + 1, k + 1) -- the global lock stays with the cohort; else release the
-    global lock, then grant (turn + 1, 0).
+    in front of a global ticket lock.  Each cohort has G grant slots; local ticket t polls
+    slot t mod G, which holds the local turn and the session together (one store writes
+    both, one load reads both): session 0 says the cohort does not hold the global lock,
+    k > 0 that it does and k holders have passed it on.  A local holder that reads
+    session 0 takes the global lock.  Unlock (by the holder of local ticket t) writes slot
+    (t + 1) mod G: when a local waiter exists (local tickets drawn beyond one's own) and
+    k + 1 < B, grant (t + 1, k + 1) -- the global lock stays with the cohort; else release
+    the global lock, then grant (t + 1, 0).  G = 1 is the single grant word; with G > 1
+    tickets t and t + G share a slot, which is rewritten only after t has entered.
     mutant 'keep_session': a global release grants (turn + 1, k + 1);
     mutant 'no_waiter_check': pass locally even when nobody of the cohort waits;
     mutant 'skip_global_wait': a holder reading session 0 takes a global ticket but
-    enters without waiting for its turn."""
+    enters without waiting for its turn;
+    mutant 'own_slot': the grant goes into the holder's own slot t mod G."""
 
     (ACQ, POLL_L, G_ACQ, POLL_G, CS_IN, CS_LD, CS_ST, CS_OUT, REL, REL_G, REL_L,
      DONE) = range(12)
 
     def __init__(self, n: int = 4, ops: int = 2, C: int = 2, B: int = 2,
-                 mutant: str | None = None):
-        self.n, self.ops, self.C, self.B, self.mutant = n, ops, C, B, mutant
+                 mutant: str | None = None, G: int = 1):
+        self.n, self.ops, self.C, self.B, self.mutant, self.G = n, ops, C, B, mutant, G
 
     def init(self):
-        C = self.C
-        # shared = (gticket, gturn, lticket, lturn, sess, data, inside, entries)
+        C, G = self.C, self.G
+        # shared = (gticket, gturn, lticket, slots (C x G of (turn, session)), data,
+        #           inside, entries)
         # local  = (pc, j, tmp, t, s)
-        sh = (0, 0, (0,) * C, (0,) * C, (0,) * C, 0, 0, 0)
+        sh = (0, 0, (0,) * C, tuple(((0, 0),) * G for _ in range(C)), 0, 0, 0)
         return sh, tuple((self.ACQ, 0, 0, 0, 0) for _ in range(self.n))
 
     def done(self, lo):
@@ -319,57 +323,63 @@ class CohortLockModel:
     def _set(tup, i, v):
         return tup[:i] + (v,) + tup[i + 1:]
 
+    def _grant(self, slots, c, t, turn, sess):
+        i = (t if self.mutant == "own_slot" else t + 1) % self.G
+        return self._set(slots, c, self._set(slots[c], i, (turn, sess)))
+
     def step(self, a, sh, lo):
-        gt, gturn, lt, ltn, sess, data, inside, entries = sh
+        gt, gturn, lt, slots, data, inside, entries = sh
         pc, j, tmp, t, s = lo
         c = a % self.C
         nxt = self.ACQ if j + 1 < self.ops else self.DONE
         if pc == self.ACQ:
-            return (gt, gturn, self._set(lt, c, lt[c] + 1), ltn, sess, data, inside,
+            return (gt, gturn, self._set(lt, c, lt[c] + 1), slots, data, inside,
                     entries), (self.POLL_L, j, tmp, lt[c], s)
         if pc == self.POLL_L:  # reads turn and session in one load
-            if ltn[c] != t:
+            turn, sess = slots[c][t % self.G]
+            if turn != t:
                 return sh, (self.POLL_L, j, tmp, t, s)
-            return sh, ((self.G_ACQ if sess[c] == 0 else self.CS_IN), j, tmp, t, sess[c])
+            return sh, ((self.G_ACQ if sess == 0 else self.CS_IN), j, tmp, t, sess)
         if pc == self.G_ACQ:
             after = self.CS_IN if self.mutant == "skip_global_wait" else self.POLL_G
-            return (gt + 1, gturn, lt, ltn, sess, data, inside, entries), (after, j, gt, t, s)
+            return (gt + 1, gturn, lt, slots, data, inside, entries), (after, j, gt, t, s)
         if pc == self.POLL_G:
             return sh, ((self.CS_IN if gturn == tmp else self.POLL_G), j, tmp, t, s)
         if pc == self.CS_IN:
-            return (gt, gturn, lt, ltn, sess, data, inside + 1, entries), (self.CS_LD, j, tmp, t, s)
+            return (gt, gturn, lt, slots, data, inside + 1, entries), (self.CS_LD, j, tmp, t, s)
         if pc == self.CS_LD:
             return sh, (self.CS_ST, j, data, t, s)
         if pc == self.CS_ST:
-            return (gt, gturn, lt, ltn, sess, tmp + 1, inside, entries), (self.CS_OUT, j, tmp, t, s)
+            return (gt, gturn, lt, slots, tmp + 1, inside, entries), (self.CS_OUT, j, tmp, t, s)
         if pc == self.CS_OUT:
-            return (gt, gturn, lt, ltn, sess, data, inside - 1, entries + 1), (self.REL, j, tmp, t, s)
+            return (gt, gturn, lt, slots, data, inside - 1, entries + 1), (self.REL, j, tmp, t, s)
         if pc == self.REL:
             waiter = lt[c] > t + 1 or self.mutant == "no_waiter_check"
-            if waiter and s + 1 < self.B:  # pass: one store of the grant word
-                return (gt, gturn, lt, self._set(ltn, c, t + 1), self._set(sess, c, s + 1),
+            if waiter and s + 1 < self.B:  # pass: one store of the grant
+                return (gt, gturn, lt, self._grant(slots, c, t, t + 1, s + 1),
                         data, inside, entries), (nxt, j + 1, tmp, t, s)
             return sh, (self.REL_G, j, tmp, t, s)
         if pc == self.REL_G:
-            return (gt, gturn + 1, lt, ltn, sess, data, inside, entries), (self.REL_L, j, tmp, t, s)
+            return (gt, gturn + 1, lt, slots, data, inside, entries), (self.REL_L, j, tmp, t, s)
         if pc == self.REL_L:
             k = s + 1 if self.mutant == "keep_session" else 0
-            return (gt, gturn, lt, self._set(ltn, c, t + 1), self._set(sess, c, k), data, inside,
+            return (gt, gturn, lt, self._grant(slots, c, t, t + 1, k), data, inside,
                     entries), (nxt, j + 1, tmp, t, s)
         raise AssertionError(pc)
 
     def check(self, sh, los):
-        if sh[6] > 1:
-            return f"mutual exclusion violated: {sh[6]} inside"
+        if sh[5] > 1:
+            return f"mutual exclusion violated: {sh[5]} inside"
         return None
 
     def final_check(self, sh, los):
-        gt, gturn, lt, ltn, sess, data, inside, entries = sh
+        gt, gturn, lt, slots, data, inside, entries = sh
         total = self.n * self.ops
         if data != total or entries != total:
             return f"final data {data} entries {entries} != {total}"
-        if gt != gturn or lt != ltn or any(sess):
-            return f"final state gticket {gt} gturn {gturn} local {lt} {ltn} sess {sess}"
+        # each cohort's next ticket finds its turn with session 0
+        if gt != gturn or any(slots[c][lt[c] % self.G] != (lt[c], 0) for c in range(self.C)):
+            return f"final state gticket {gt} gturn {gturn} local {lt} slots {slots}"
         return None
 
 

@@ -476,17 +476,18 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
   for (auto& w : cs) w.store(0);
   std::atomic<int> bad{0};
   // kind 8 (cohort): agent b belongs to cohort b mod kCoh; per lock and cohort a local
-  // ticket counter and a grant word = local turn | session << 32 (session 0 = the cohort
-  // does not hold the global lock, k > 0 = it does and k holders passed it on); at most
-  // kPasses holders in a row.
-  constexpr uint32_t kCoh = 8, kPasses = 4;
+  // ticket counter and kGrants grant slots, local ticket t polling slot t mod kGrants for
+  // local turn t | session << 32 (session 0 = the cohort does not hold the global lock,
+  // k > 0 = it does and k holders passed it on); at most kPasses holders in a row.
+  constexpr uint32_t kCoh = 8, kPasses = 4, kGrants = 4;
   // kind 9 (MCS): per lock and agent a node {next (agent + 1, 0 = none), locked}; the
   // lock's tail is lockw (agent + 1, 0 = free)
   std::vector<Word> mnext(kind == 9 ? (size_t)L * nwg : 0), mlocked(mnext.size());
   for (size_t i = 0; i < mnext.size(); ++i) mnext[i] = 0, mlocked[i] = 0;
   std::vector<Word> lt(kind == 8 ? (size_t)L * kCoh : 0);
-  std::vector<std::atomic<uint64_t>> grant(lt.size());
-  for (size_t i = 0; i < lt.size(); ++i) lt[i] = 0, grant[i] = 0;
+  std::vector<std::atomic<uint64_t>> grant(lt.size() * kGrants);
+  for (size_t i = 0; i < lt.size(); ++i) lt[i] = 0;
+  for (auto& g : grant) g = 0;
 
   // returns the ticket the lock was taken with (ticket, ring and array kinds); cohort:
   // the local ticket, and the session it read in the upper 32 bits
@@ -553,7 +554,8 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
         const size_t c = (size_t)l * kCoh + b % kCoh;
         const uint32_t my = lt[c].fetch_add(1, std::memory_order_relaxed);
         uint64_t v;
-        while ((uint32_t)(v = grant[c].load(std::memory_order_acquire)) != my) relax();
+        auto& slot = grant[c * kGrants + my % kGrants];
+        while ((uint32_t)(v = slot.load(std::memory_order_acquire)) != my) relax();
         const uint32_t k = (uint32_t)(v >> 32);
         if (k == 0) {
           const uint32_t g = ticket[l].fetch_add(1, std::memory_order_relaxed);
@@ -590,12 +592,13 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
       const size_t c = (size_t)l * kCoh + b % kCoh;
       const uint32_t k = (uint32_t)(held >> 32) + 1;
       const bool waiter = (int32_t)(lt[c].load(std::memory_order_relaxed) - (my + 1)) > 0;
+      auto& next = grant[c * kGrants + (my + 1) % kGrants];  // the next local ticket's slot
       if (waiter && k < kPasses) {  // pass the global lock with the local one
-        grant[c].store(((uint64_t)k << 32) | (my + 1), std::memory_order_release);
+        next.store(((uint64_t)k << 32) | (my + 1), std::memory_order_release);
       } else {
         const uint32_t t = turn[l].load(std::memory_order_relaxed);  // only the holder writes
         turn[l].store(t + 1, std::memory_order_release);
-        grant[c].store(my + 1, std::memory_order_release);  // session 0
+        next.store(my + 1, std::memory_order_release);  // session 0
       }
       return;
     }

@@ -155,10 +155,10 @@ BBLayout bb_layout(uint32_t mutex_kind, uint32_t nwg, uint32_t capacity, const s
   L.sw = spi::stride_words(q);
   L.Q = 64;
   while (L.Q < nwg) L.Q <<= 1;
-  // the array lock's slots, or the cohort lock's two lines per XCC id (64-bit grant words)
+  // the array lock's slots, or the cohort lock's lines per XCC id (64-bit grant slots)
   L.qstride = mutex_kind == SP_MUTEX_COHORT ? std::max<uint32_t>(L.sw, 2) : L.sw;
   const uint64_t qwords = mutex_kind == SP_MUTEX_ARRAY    ? (uint64_t)L.Q * L.sw
-                          : mutex_kind == SP_MUTEX_COHORT ? 2ull * sp::kXccSlots * L.qstride
+                          : mutex_kind == SP_MUTEX_COHORT ? (uint64_t)sp::kCohortLines * sp::kXccSlots * L.qstride
                                                           : 0;
   L.qoff = (5ull * L.sw + 1) & ~1ull;  // 8-byte aligned for the grant words
   L.mutex_words = L.qoff + qwords;

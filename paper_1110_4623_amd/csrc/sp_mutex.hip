@@ -118,7 +118,8 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
     if (ctx->defaults[1][b].kind == SP_MUTEX_COHORT)
       cohort_sw = std::max(cohort_sw, spi::stride_words(ctx->defaults[1][b].p));
   if (cohort_sw) {
-    const uint64_t words = (uint64_t)nlocks * 2 * sp::kXccSlots * std::max<uint32_t>(cohort_sw, 2);
+    const uint64_t words =
+        (uint64_t)nlocks * sp::kCohortLines * sp::kXccSlots * std::max<uint32_t>(cohort_sw, 2);
     if (e == hipSuccess && words <= (1ull << 28)) {
       e = hipMalloc(&m->d_queue, words * sizeof(uint32_t));
       if (e == hipSuccess) m->queue_words = words;
@@ -191,11 +192,12 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
       kind == SP_MUTEX_MCS) {
     // The ring needs a slot per contender (each workgroup has at most one arrival
     // outstanding); the array lock is correct with any number and polls one line each;
-    // the cohort lock keeps two lines per lock and XCC id (ticket, 64-bit grant word);
+    // the cohort lock keeps kCohortLines lines per lock and XCC id (ticket, 64-bit grant
+    // slots);
     // the MCS lock one node (next, locked) per lock and workgroup.
     uint32_t Q = 64;
     while (Q < nwg) Q <<= 1;
-    if (kind == SP_MUTEX_COHORT) Q = 2 * sp::kXccSlots;
+    if (kind == SP_MUTEX_COHORT) Q = sp::kCohortLines * sp::kXccSlots;
     if (kind == SP_MUTEX_MCS) Q = nwg;
     ms.qlen = Q;
     ms.qstride = kind == SP_MUTEX_RING ? 1 : sw;  // ring entries packed, others padded

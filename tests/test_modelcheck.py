@@ -195,6 +195,19 @@ def test_cohort_lock_mutants_fail(mutant, n, ops, B):
     assert not r.ok
 
 
+@pytest.mark.parametrize("n,ops,C,B", [(3, 2, 1, 3), (3, 3, 1, 2), (3, 2, 2, 2)])
+def test_cohort_lock_grant_slots_shared(n, ops, C, B):
+    """Two grant slots per cohort: local tickets t and t + 2 share a slot, and the grant
+    for t + 2 is written only after t has entered -- the lock stays correct."""
+    r = explore(CohortLockModel(n, ops, C=C, B=B, G=2))
+    assert r.ok, r.violation
+
+
+def test_cohort_lock_grant_into_own_slot_deadlocks():
+    r = explore(CohortLockModel(3, 2, C=1, B=3, mutant="own_slot", G=2))
+    assert r.deadlock
+
+
 # ---- the per-XCD barrier as the library runs it, with its caches ----------------------
 
 # (xcd, cu) per agent.  TWO_XCDS: XCD 0 holds agents 0 and 2 on one CU (agent 0 is the
