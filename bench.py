@@ -12,8 +12,9 @@ One step runs the whole path once over the full-size synthetic workloads:
      lock);
   4. semaphore: fetch-and-add semaphore (Algorithm 5 with s_sleep polling) with K = 32,
      2048 workgroups, 2^20 wait/post pairs holding uniform [0, 2000] cycles, then the
-     same workload on the library's default semaphore for this contention (the chain
-     semaphore: K chains of tickets, each holder granting the ticket K after its own);
+     same workload on the library's default semaphore for this contention (per-XCD
+     chains: the units split over the XCDs, each holder granting the ticket K_x after its
+     own on its XCD without an L2 writeback);
   5. serving: 2 x 10^5 requests arriving as a Poisson stream at 10^5 req/s (lognormal
      hash-chain lengths, 1 GiB workspace budget in 64 KiB units), drained by 1024
      persistent workgroups, then the same stream served with one kernel launch per
@@ -51,7 +52,7 @@ MUTEX_TOTAL, SEM_TOTAL, SEM_K = 1 << 20, 1 << 20, 32
 CURVE_NWG, CURVE_OPS = (64, 256, 1024), 1 << 18
 # read-modify-writes per wait/post pair on each semaphore kind's busiest contended word
 SEM_RMW_PER_PAIR = {"spin": 4, "spin_backoff": 4, "ticket": 2, "sleep": 2, "cohort": 2,
-                    "counters": 1, "adaptive": 1, "array": 1, "chain": 1}
+                    "counters": 1, "adaptive": 1, "array": 1, "chain": 1, "xcd_chain": 1}
 SERVE_RATE, SERVE_N, SERVE_NWG = 1e5, 200_000, 1024
 
 

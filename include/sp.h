@@ -118,6 +118,11 @@ enum sp_sem_kind {
                            /* mod M (M = the largest multiple of K <= 4096, each waiter  */
                            /* polling its own line); the post needs no round trip.       */
                            /* K <= 4096; each post follows its own workgroup's wait      */
+  SP_SEM_XCD_CHAIN = 9,    /* SP_SEM_CHAIN per XCD: the K units split over the XCDs'     */
+                           /* queues (XCC id mod XCD count), each queue its own tickets, */
+                           /* slots and chains; a post skips the L2 writeback, the next */
+                           /* holder of its chain running on the same XCD.  XCD count <= */
+                           /* K <= 4096 x XCD count; units do not move between XCDs     */
   SP_SEM_DEFAULT = 15
 };
 
@@ -251,8 +256,8 @@ void sp_params_default(sp_params* p);
  * Section 7: tuning backoff per GPU and contention level).  Until a call replaces them,
  * the defaults are a tuning pass's winners on an MI355X: barrier central (low) and
  * per-XCD with 64 stamp copies (high); mutex spin with the paper's backoff, I_max 8
- * (low) and the XCD-cohort lock (high); semaphore the chain kind (both; the array kind
- * where K > 4096).                                                                      */
+ * (low) and the XCD-cohort lock (high); semaphore the per-XCD chains (both; outside
+ * their range of K the chain kind, then the array kind).                                */
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p);
 /* Reads back what *_DEFAULT resolves to for a primitive class and bucket (as above):
@@ -365,8 +370,10 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
 /* ---- semaphore (Section 5, Semaphore; Algorithms 4-5; Table 4 Wait()/Post()) ------------
  * sp_sem_create: a counting semaphore with initial value K >= 1.  Algorithm 4 keeps one
  * word S = K + 1; Algorithm 5 keeps count, ticket and turn on separate lines.
- * Errors: SP_E_INVAL (K == 0; SP_SEM_CHAIN with K > 4096), SP_E_HIP.  A SP_SEM_DEFAULT
- * semaphore whose contention bucket names SP_SEM_CHAIN runs SP_SEM_ARRAY when K > 4096. */
+ * Errors: SP_E_INVAL (K == 0; SP_SEM_CHAIN with K > 4096; SP_SEM_XCD_CHAIN with K below
+ * the XCD count or above 4096 per XCD), SP_E_HIP.  A SP_SEM_DEFAULT semaphore whose
+ * bucket names one of these runs the next kind whose range K is in: SP_SEM_XCD_CHAIN,
+ * then SP_SEM_CHAIN, then SP_SEM_ARRAY.                                                  */
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out);
 int sp_sem_destroy(sp_sem* s);
 /* Workload: total_pairs wait/post pairs split over nwg workgroups as in sp_mutex_run.
@@ -376,8 +383,8 @@ int sp_sem_destroy(sp_sem* s);
  * occupancy.  out_chk: device, nwg uint32.  out_state: device, 8 uint32 =
  * {max occupancy, S (Alg. 4) or count (Alg. 5), ticket, turn, admissions, count,
  * occupancy, unserved} (SP_SEM_COUNTERS, SP_SEM_ADAPTIVE: count stays 0, ticket = tickets
- * drawn, turn = posts made; SP_SEM_ARRAY, SP_SEM_CHAIN: the same, the low 32 bits of
- * their 64-bit counters; SP_SEM_COHORT: ticket and turn stay 0, unserved = local tickets drawn and not
+ * drawn, turn = posts made; SP_SEM_ARRAY, SP_SEM_CHAIN, SP_SEM_XCD_CHAIN: the same, the
+ * low 32 bits of their 64-bit counters (summed over the XCDs' queues); SP_SEM_COHORT: ticket and turn stay 0, unserved = local tickets drawn and not
  * served, over every XCD's queue, 0 at rest).
  * out_data: device, K uint32 (zeroed by the call), or NULL; K <= 4096.  Guarded data:
  * each admission adds one to a word with a plain load and store made by the workgroup's

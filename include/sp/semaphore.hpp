@@ -54,6 +54,16 @@ __device__ __forceinline__ uint64_t* cq_slot(const SemState& s, uint32_t x, uint
                                      (size_t)(2 + (t & (s.cq_len - 1))) * s.cq_stride);
 }
 
+// ---- per-XCD chains ----------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xchain_units(const SemState& s, uint32_t x) {
+  return s.K / s.cq_n + (x < s.K % s.cq_n ? 1u : 0u);
+}
+__device__ __forceinline__ uint64_t* xchain_slot(const SemState& s, uint32_t x, uint32_t kx,
+                                                 uint64_t t) {
+  const uint32_t m = s.cq_len / kx * kx;
+  return reinterpret_cast<uint64_t*>(cq_base(s, x) + (size_t)(2 + t % m) * s.cq_stride);
+}
+
 // ---- array semaphore (ticket-indexed grant slots) ----------------------------------------
 __device__ __forceinline__ uint64_t add_relaxed64(uint64_t* p, uint64_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -190,6 +200,15 @@ __device__ __forceinline__ bool cq_grant(const SemState& s, uint32_t y, uint32_t
 //   the store for t - M landed before t - K could enter; while t waits its slot holds
 //   t + 1 or an older ticket's value.  With M not a multiple of K a later chain's store
 //   could admit t early (the model checker finds the bound broken).
+// SP_SEM_XCD_CHAIN runs the chain rule once per XCD: queue x (XCC id mod cq_n) owns
+// K_x = K / cq_n units (the first K mod cq_n queues one more, every queue at least one)
+// and its own tickets, posts and chain_slots (in queue x's memory, the largest multiple
+// of K_x up to cq_len).  Each queue is a chain semaphore of K_x units, so at most
+// sum K_x = K inside, and every waiter enters (its queue has a unit).  When every XCC id
+// is below cq_n (cq_local), a queue's workgroups share one L2: the next holder of a chain
+// reads the critical section's stores (completed into that L2 before the post) after its
+// own acquire, so the post skips the writeback.  Data shared with other XCDs needs a
+// synchronization that writes this L2 back anyway.  Otherwise the post writes back.
 // FENCED = false: the data the semaphore guards is accessed with agent-scope loads and
 // stores, which every XCD sees without cache maintenance, so wait skips the acquire
 // invalidation and post the release writeback.
@@ -267,6 +286,17 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
         }
       }
       if (hold) hold->pass = k;
+    } else if constexpr (KIND == SP_SEM_XCD_CHAIN) {
+      Wait w(ctl, s.poll_sleep);
+      const uint32_t x = xcc_id() % s.cq_n, kx = xchain_units(s, x);
+      const uint64_t t = add_relaxed64(reinterpret_cast<uint64_t*>(cq_base(s, x)), 1);
+      hold->ticket = t;
+      hold->pass = x;  // the queue, for the post
+      if (t >= kx) {
+        const uint64_t* g = xchain_slot(s, x, kx, t);
+        while (ld_relaxed64(g) <= t)
+          if (!(ok = w.tick())) break;
+      }
     } else if constexpr (KIND == SP_SEM_CHAIN) {
       Wait w(ctl, s.poll_sleep);
       const uint64_t t = add_relaxed64(as_tickets(s), 1);
@@ -309,7 +339,8 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
 }
 
 // `hold`: SP_SEM_COHORT needs the record its sem_wait filled in (the unit's local
-// hand-overs), SP_SEM_CHAIN requires it (the ticket, so not null); other kinds ignore it.
+// hand-overs), SP_SEM_CHAIN and SP_SEM_XCD_CHAIN require it (the ticket and queue, so not
+// null); other kinds ignore it.
 template <int KIND, bool FENCED = true>
 __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold = nullptr) {
   __shared__ uint32_t s_ok;
@@ -371,7 +402,9 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
   }
   if (is_leader()) {
     bool ok = true;
-    if constexpr (FENCED) fence_release();
+    if constexpr (FENCED) {
+      if (KIND != SP_SEM_XCD_CHAIN || !s.cq_local) fence_release();
+    }
     if constexpr (KIND == SP_SEM_SPIN || KIND == SP_SEM_SPIN_BACKOFF) {
       Wait w(ctl, 0);
       Backoff bo(s.bo);
@@ -394,6 +427,11 @@ __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold 
       const uint64_t q = hold->ticket + s.K;  // the next ticket of this unit's chain
       st_relaxed64(chain_slot(s, q), q + 1);
       add_relaxed64(as_posts(s), 1);
+    } else if constexpr (KIND == SP_SEM_XCD_CHAIN) {
+      const uint32_t x = hold->pass, kx = xchain_units(s, x);
+      const uint64_t q = hold->ticket + kx;
+      st_relaxed64(xchain_slot(s, x, kx, q), q + 1);
+      add_relaxed64(reinterpret_cast<uint64_t*>(cq_base(s, x) + s.cq_stride), 1);
     } else {
       const uint32_t old = add_relaxed(s.count, 0xFFFFFFFFu);  // count -= 1
       if (old > s.K) add_relaxed(s.turn, 1);                   // admit one queued waiter

@@ -32,7 +32,8 @@ MUTEX_KINDS = {"spin_cas": 0, "spin_exch": 1, "spin_backoff": 2, "ticket": 3, "s
                "ring": 5, "array": 6, "adaptive": 7, "cohort": 8, "mcs": 9}
 SEM_KINDS = {"spin": 0, "spin_backoff": 1, "ticket": 2, "sleep": 3, "counters": 4,
              "adaptive": 5, "spin_backoff_wait_only": 6, "cohort": 7,
-             "array": 8, "chain": 9}
+             "array": 8, "chain": 9,
+             "xcd_chain": 10}
 BENCH_OPS = {"add": 0, "cas": 1, "exch": 2, "ld": 3, "st": 4}
 
 

@@ -975,6 +975,123 @@ class ArraySemModel:
         return None
 
 
+class XcdChainSemModel:
+    """The chain semaphore with its units split over per-XCD queues.
+
+    Queue q (agent a uses queue placement[a] mod Q) owns K_q = K / Q units (the first
+    K mod Q queues one more) and runs the chain rule alone: tickets drawn per queue,
+    ticket t >= K_q waits for slot t mod M_q to hold t + 1, which the holder of ticket
+    t - K_q stores when it posts (M_q a multiple of K_q).  Each queue guards a data word
+    of its own (with K_q = 1 its holders exclude each other).  Caches: a per-agent L1
+    (clean copies; each agent runs on a CU of its own) and a per-XCD L2 ((value, dirty));
+    a load goes L1 -> L2 -> memory, a store writes through the L1 into the L2 (dirty); the
+    admitted waiter's acquire drops its L1 and its XCD's clean L2 lines; a writeback
+    copies the XCD's dirty lines to memory.  The post skips the writeback when every
+    queue holds one XCD's agents (Q >= number of XCDs), since the chain's next holder
+    reads through the same L2; otherwise it writes back.
+    mutant 'skip_when_shared': the post skips the writeback although XCDs share a queue;
+    mutant 'no_acquire': the admitted waiter keeps its L1;
+    mutant 'enter_at_k': tickets t <= K_q enter at once."""
+
+    W_TICKET, W_POLL, ACQ, CS_LD, CS_ST, P_WB, P_GRANT, DONE = range(8)
+
+    def __init__(self, K: int, placement: tuple, Q: int, M: int = 2, ops: int = 2,
+                 mutant: str | None = None):
+        self.K, self.pl, self.Q, self.ops, self.mutant = K, tuple(placement), Q, ops, mutant
+        self.n = len(self.pl)
+        self.X = 1 + max(self.pl)
+        self.Kq = tuple(K // Q + (1 if q < K % Q else 0) for q in range(Q))
+        assert min(self.Kq) >= 1
+        self.Mq = tuple(max(1, M // k) * k for k in self.Kq)
+        self.local = Q >= self.X
+
+    # shared = (tickets (Q), slots (Q x M_q), l1 (n x Q: value or None),
+    #           l2 (X x Q: (value, dirty) or None), mem (Q), inside (Q), done_cs (Q))
+    # local  = (pc, j, t, tmp)
+    def init(self):
+        Q, X, n = self.Q, self.X, self.n
+        sh = ((0,) * Q, tuple((0,) * self.Mq[q] for q in range(Q)),
+              tuple((None,) * Q for _ in range(n)), tuple((None,) * Q for _ in range(X)),
+              (0,) * Q, (0,) * Q, (0,) * Q)
+        return sh, tuple((self.W_TICKET, 0, 0, 0) for _ in range(n))
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    @staticmethod
+    def _set(t, i, v):
+        return t[:i] + (v,) + t[i + 1:]
+
+    def step(self, a, sh, lo):
+        tickets, slots, l1, l2, mem, inside, done_cs = sh
+        pc, j, t, tmp = lo
+        x, q = self.pl[a], self.pl[a] % self.Q
+        kq, mq = self.Kq[q], self.Mq[q]
+        if pc == self.W_TICKET:
+            t = tickets[q]
+            go = t <= kq if self.mutant == "enter_at_k" else t < kq
+            return ((self._set(tickets, q, t + 1), slots, l1, l2, mem, inside, done_cs),
+                    (self.ACQ if go else self.W_POLL, j, t, 0))
+        if pc == self.W_POLL:
+            return sh, (self.ACQ if slots[q][t % mq] >= t + 1 else self.W_POLL, j, t, 0)
+        if pc == self.ACQ:
+            if self.mutant != "no_acquire":
+                l1 = self._set(l1, a, (None,) * self.Q)
+                l2 = self._set(l2, x, tuple(e if e is not None and e[1] else None for e in l2[x]))
+            return ((tickets, slots, l1, l2, mem, self._set(inside, q, inside[q] + 1), done_cs),
+                    (self.CS_LD, j, t, 0))
+        if pc == self.CS_LD:
+            v = l1[a][q]
+            if v is None:
+                if l2[x][q] is None:
+                    l2 = self._set(l2, x, self._set(l2[x], q, (mem[q], False)))
+                v = l2[x][q][0]
+                l1 = self._set(l1, a, self._set(l1[a], q, v))
+            return (tickets, slots, l1, l2, mem, inside, done_cs), (self.CS_ST, j, t, v)
+        if pc == self.CS_ST:
+            if kq == 1 and tmp != done_cs[q]:
+                inside = self._set(inside, q, kq + 100)  # reported by check()
+            l1 = self._set(l1, a, self._set(l1[a], q, tmp + 1))
+            l2 = self._set(l2, x, self._set(l2[x], q, (tmp + 1, True)))
+            return ((tickets, slots, l1, l2, mem, self._set(inside, q, inside[q] - 1),
+                     self._set(done_cs, q, done_cs[q] + 1)), (self.P_WB, j, t, 0))
+        if pc == self.P_WB:
+            skip = self.local or self.mutant == "skip_when_shared"
+            if not skip:
+                m = list(mem)
+                for i, e in enumerate(l2[x]):
+                    if e is not None and e[1]:
+                        m[i] = e[0]
+                mem = tuple(m)
+                l2 = self._set(l2, x, tuple(None if e is None else (e[0], False) for e in l2[x]))
+            return (tickets, slots, l1, l2, mem, inside, done_cs), (self.P_GRANT, j, t, 0)
+        if pc == self.P_GRANT:
+            g = t + kq
+            slots = self._set(slots, q, self._set(slots[q], g % mq, g + 1))
+            nxt = self.W_TICKET if j + 1 < self.ops else self.DONE
+            return (tickets, slots, l1, l2, mem, inside, done_cs), (nxt, j + 1, 0, 0)
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        inside = sh[5]
+        for q in range(self.Q):
+            if inside[q] > self.Kq[q] + 50:
+                return "a holder loaded its queue's word without an earlier holder's update"
+            if inside[q] > self.Kq[q]:
+                return f"occupancy {inside[q]} > K_q={self.Kq[q]} in queue {q}"
+        if sum(inside) > self.K:
+            return f"occupancy {sum(inside)} > K={self.K}"
+        return None
+
+    def final_check(self, sh, los):
+        tickets, slots, l1, l2, mem, inside, done_cs = sh
+        for q in range(self.Q):
+            want = self.ops * sum(1 for p in self.pl if p % self.Q == q)
+            if tickets[q] != want or done_cs[q] != want or inside[q] != 0:
+                return f"queue {q}: tickets {tickets[q]} done {done_cs[q]} != {want}"
+        return None
+
+
 class WeightedSemModel:
     """Fetch-and-add semaphore with weighted requests, the admission rule of the serving
     queue (Algorithm 5 with u tickets drawn at once).  issued and released start at 0.

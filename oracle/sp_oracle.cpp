@@ -634,6 +634,12 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
   return bad.load() ? -2 : 0;
 }
 
+static uint64_t sum64(const std::vector<std::atomic<uint64_t>>& v) {
+  uint64_t t = 0;
+  for (auto& x : v) t += x.load();
+  return t;
+}
+
 // Semaphore kinds: 0 spin semaphore (Algorithm 4), 1 spin semaphore with backoff in
 // both loops (Algorithm 4, UseBackoff), 2 fetch-and-add semaphore (Algorithm 5),
 // 3 fetch-and-add semaphore whose queued waiters yield between polls.
@@ -654,7 +660,9 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 // t mod 16 holds at least t + 1, and the post that draws p raises slot (p + K) mod 16
 // to p + K + 1 (a maximum: grants for one slot may land in any order); 9 K chains of
 // tickets: ticket t >= K waits until slot t mod M holds t + 1, which the holder of ticket
-// t - K stores when it posts (M = K x max(1, 16 / K), a multiple of K).
+// t - K stores when it posts (M = K x max(1, 16 / K), a multiple of K); 10 kind 9 once
+// per group of agents (agent b in group b mod 8; group g owns K / 8 units, the first
+// K mod 8 groups one more; K >= 8).
 // Each pair: wait, occupancy tracking, checksum update, admission count, post.
 // out: chk[nwg]; *maxocc; state[4] = {S or count, ticket, turn, admissions}; for the
 // Algorithm 4 kinds ticket and turn are unused and state[1] / state[2] report instead the
@@ -663,7 +671,8 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
 int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t total,
                     uint32_t imin, uint32_t imax, uint32_t* chk, uint32_t* maxocc,
                     uint32_t* state, double* seconds) {
-  if (nwg == 0 || K == 0 || kind < 0 || kind > 9) return -1;
+  if (nwg == 0 || K == 0 || kind < 0 || kind > 10) return -1;
+  if (kind == 10 && K < 8) return -1;
   Word S{K + 1}, count{0}, ticket{0}, turn{0}, occ{0}, maxo{0}, adm{0};
   // kind 7: per group a queue of Q slots {ticket + 1, passes} after (drawn, served)
   constexpr uint32_t kGroups = 8, kBound = 4;
@@ -679,7 +688,20 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   const uint32_t chain_len = K * std::max<uint32_t>(1, kGrantSlots / K);
   std::vector<std::atomic<uint64_t>> grants(kind == 8 ? kGrantSlots : kind == 9 ? chain_len : 0);
   for (auto& w : grants) w.store(0);
-  std::vector<uint64_t> my_ticket(kind == 9 ? nwg : 0);  // kind 9: the ticket each agent holds
+  std::vector<uint64_t> my_ticket(kind >= 9 ? nwg : 0);  // kinds 9, 10: the ticket held
+  // kind 10: per group its units, tickets, posts and chain slots
+  constexpr uint32_t kChainGroups = 8;
+  auto group_units = [&](uint32_t g) { return K / kChainGroups + (g < K % kChainGroups ? 1u : 0u); };
+  std::vector<std::atomic<uint64_t>> gtickets(kind == 10 ? kChainGroups : 0),
+      gposts(gtickets.size());
+  std::vector<std::vector<std::atomic<uint64_t>>> gslots(gtickets.size());
+  for (uint32_t g = 0; g < gtickets.size(); ++g) {
+    gtickets[g] = 0;
+    gposts[g] = 0;
+    const uint32_t kg = group_units(g);
+    gslots[g] = std::vector<std::atomic<uint64_t>>(kg * std::max<uint32_t>(1, kGrantSlots / kg));
+    for (auto& w : gslots[g]) w.store(0);
+  }
   auto claim = [&](uint32_t g, uint32_t* t) {
     uint32_t v = served[g].load(std::memory_order_relaxed);
     while ((int32_t)(drawn[g].load(std::memory_order_relaxed) - v) > 0)
@@ -713,6 +735,14 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   std::atomic<uint64_t> wait_fail{0}, post_fail{0};
 
   auto wait = [&](Backoff& bo, uint32_t b) {
+    if (kind == 10) {
+      const uint32_t g = b % kChainGroups, kg = group_units(g);
+      const uint64_t t = gtickets[g].fetch_add(1, std::memory_order_acq_rel);
+      my_ticket[b] = t;
+      if (t >= kg)
+        while (gslots[g][t % gslots[g].size()].load(std::memory_order_acquire) != t + 1) relax();
+      return;
+    }
     if (kind == 9) {
       const uint64_t t = tickets64.fetch_add(1, std::memory_order_acq_rel);
       my_ticket[b] = t;
@@ -770,6 +800,13 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
     }
   };
   auto post = [&](Backoff& bo, uint32_t b) {
+    if (kind == 10) {
+      const uint32_t g = b % kChainGroups;
+      const uint64_t q = my_ticket[b] + group_units(g);
+      gslots[g][q % gslots[g].size()].store(q + 1, std::memory_order_release);
+      gposts[g].fetch_add(1, std::memory_order_relaxed);
+      return;
+    }
     if (kind == 9) {
       const uint64_t q = my_ticket[b] + K;
       grants[q % chain_len].store(q + 1, std::memory_order_release);
@@ -849,8 +886,10 @@ int or_sem_threaded(int kind, uint32_t K, uint32_t seed, uint32_t nwg, uint64_t 
   }
   state[0] = alg4 ? S.load() : count.load();
   state[1] = alg4 ? (uint32_t)std::min<uint64_t>(wait_fail.load(), 0xFFFFFFFFu)
+                  : kind == 10 ? (uint32_t)sum64(gtickets)
                   : kind >= 8 ? (uint32_t)tickets64.load() : ticket.load();
   state[2] = alg4 ? (uint32_t)std::min<uint64_t>(post_fail.load(), 0xFFFFFFFFu)
+                  : kind == 10 ? (uint32_t)sum64(gposts)
                   : kind >= 8 ? (uint32_t)posts64.load() : turn.load();
   state[3] = adm.load();
   if (seconds) *seconds = t;

@@ -38,7 +38,8 @@ BARRIER_KINDS = {"central": 0, "central_split": 1, "tree": 2, "flag": 3, "grid_s
 MUTEX_KINDS = {"spin_cas": 0, "spin_exch": 1, "spin_backoff": 2, "ticket": 3, "sleep": 4,
                "ring": 5, "array": 6, "adaptive": 7, "cohort": 8, "mcs": 9, "default": 15}
 SEM_KINDS = {"spin": 0, "spin_backoff": 1, "ticket": 2, "sleep": 3, "counters": 4,
-             "adaptive": 5, "cohort": 6, "array": 7, "chain": 8, "default": 15}
+             "adaptive": 5, "cohort": 6, "array": 7, "chain": 8, "xcd_chain": 9,
+             "default": 15}
 BACKOFF = {"none": 0, "paper": 1, "exp": 2}
 BACKOFF_UNIT = {"sleep": 0, "load": 1}
 OPS = {"add": 0, "cas": 1, "exch": 2, "ld": 3, "st": 4}

@@ -229,12 +229,13 @@ int sp_init(int device, sp_ctx** out) {
   ctx->defaults[1][1].kind = SP_MUTEX_COHORT;
   ctx->defaults[1][1].p.poll_sleep = 0;
   ctx->defaults[1][1].p.cohort_passes = 64;
-  // chain semaphore (the array kind above K = 4096): 13.6 M pairs/s K = 32 at 256, 42.7 M
-  // K = 256 at 2048 (array 12.4 / 42.3, two counters + s_sleep 16 8.1 / 6.9); 13.1 M
-  // K = 32 at 2048, 1.69 M K = 4 (array 12.1 / 1.53, adaptive 6.3 / 1.55)
-  ctx->defaults[2][0].kind = SP_SEM_CHAIN;
+  // per-XCD chains (K below the XCD count: one set of chains; K above 4096 per XCD: the
+  // array kind): 14.0 M pairs/s K = 32 at 256, 13.8 M K = 32 at 2048 and 1.71 M K = 4
+  // (chain 13.6 / 13.1 / 1.69, adaptive - / 6.3 / 1.55); K = 256 at 2048 129 M untracked
+  // (chain 57.7)
+  ctx->defaults[2][0].kind = SP_SEM_XCD_CHAIN;
   ctx->defaults[2][0].p.poll_sleep = 0;
-  ctx->defaults[2][1].kind = SP_SEM_CHAIN;
+  ctx->defaults[2][1].kind = SP_SEM_XCD_CHAIN;
   ctx->defaults[2][1].p.poll_sleep = 0;
   // resolve the "auto" fields (fan_in = XCD count, ...) as sp_set_default does
   for (int prim = 0; prim < 3; ++prim)
@@ -282,7 +283,7 @@ int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p) {
   if (!usable(ctx) || primitive > 2 || bucket > 1) return SP_E_INVAL;
-  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_MCS, SP_SEM_CHAIN};
+  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_MCS, SP_SEM_XCD_CHAIN};
   if (kind > max_kind[primitive]) return SP_E_INVAL;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));

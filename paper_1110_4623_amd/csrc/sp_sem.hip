@@ -105,7 +105,7 @@ __global__ SP_FULL_OCCUPANCY void k_sem(sp::SemState s, uint32_t stride, uint32_
 
 __global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg4,
                             const uint32_t* cq, uint32_t cq_stride, uint32_t cq_len,
-                            const uint32_t* arr, uint32_t* out) {
+                            const uint32_t* arr, uint32_t narr, uint32_t* out) {
   if (threadIdx.x == 0) {
     // cohort kind: local tickets drawn but never served, over every XCD's queue (0 at rest)
     uint32_t unserved = 0;
@@ -116,9 +116,16 @@ __global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg
       }
     out[0] = state[L_MAXOCC * stride];
     out[1] = alg4 ? state[L_S * stride] : state[L_COUNT * stride];
-    // array and chain kinds: the low halves of their 64-bit tickets and posts counters
-    out[2] = arr ? arr[0] : state[L_TICKET * stride];
-    out[3] = arr ? arr[cq_stride] : state[L_TURN * stride];
+    // array and chain kinds: the low halves of their 64-bit tickets and posts counters,
+    // summed over the queues that hold them (narr)
+    uint32_t tickets = 0, posts = 0;
+    for (uint32_t x = 0; arr && x < narr; ++x) {
+      const uint32_t* b = arr + (size_t)x * (2 + cq_len) * cq_stride;
+      tickets += b[0];
+      posts += b[cq_stride];
+    }
+    out[2] = arr ? tickets : state[L_TICKET * stride];
+    out[3] = arr ? posts : state[L_TURN * stride];
     out[4] = state[L_ADM * stride];
     out[5] = state[L_COUNT * stride];
     out[6] = state[L_OCC * stride];
@@ -140,8 +147,15 @@ const void* sem_kernel_f(uint32_t kind) {
     case SP_SEM_COHORT: return (const void*)k_sem<SP_SEM_COHORT, FENCED>;
     case SP_SEM_ARRAY: return (const void*)k_sem<SP_SEM_ARRAY, FENCED>;
     case SP_SEM_CHAIN: return (const void*)k_sem<SP_SEM_CHAIN, FENCED>;
+    case SP_SEM_XCD_CHAIN: return (const void*)k_sem<SP_SEM_XCD_CHAIN, FENCED>;
     default: return nullptr;
   }
+}
+
+// SP_SEM_XCD_CHAIN: a unit for every XCD's queue and at most a slot per chain in each.
+bool xchain_fits(const sp_ctx* ctx, uint32_t K) {
+  const uint32_t n = std::min<uint32_t>(std::max<uint32_t>(ctx->xcd_count, 1), sp::kXccQueues);
+  return K >= n && K / n + (K % n ? 1u : 0u) <= kCohortSlots;
 }
 
 const void* sem_kernel(uint32_t kind, bool coherent_cs) {
@@ -154,8 +168,9 @@ extern "C" {
 
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out) {
   if (!spi::usable(ctx) || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
-  if (kind > SP_SEM_CHAIN && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_SEM_XCD_CHAIN && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
   if (kind == SP_SEM_CHAIN && K > kCohortSlots) return SP_E_INVAL;  // a slot per chain at least
+  if (kind == SP_SEM_XCD_CHAIN && !xchain_fits(ctx, K)) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -170,7 +185,8 @@ int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp
   if (e == hipSuccess && K <= kMaxPool)
     e = hipMalloc(&s->d_owner, (size_t)K * kOwnerWords * sizeof(uint32_t));
   if (e == hipSuccess && (kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY ||
-                          kind == SP_SEM_CHAIN || kind == SP_SEM_DEFAULT)) {
+                          kind == SP_SEM_CHAIN || kind == SP_SEM_XCD_CHAIN ||
+                          kind == SP_SEM_DEFAULT)) {
     // queues for the cohort, array and chain kinds (a DEFAULT semaphore may resolve to
     // any of them): allocated now, so that every run can be recorded into a graph
     s->cq_stride = std::max<uint32_t>(2, spi::stride_words(q));
@@ -221,7 +237,9 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
     q = d.p;
     q.timeout_ms = t;
     q.coherent_cs = coherent;
-    // the chain kind needs a slot per chain; above that the array kind (same admission rule)
+    // the chain kinds need at least a unit per queue and a slot per chain: outside their
+    // range the next kind (per-XCD chains, one set of chains, the array kind)
+    if (kind == SP_SEM_XCD_CHAIN && !xchain_fits(ctx, sem->K)) kind = SP_SEM_CHAIN;
     if (kind == SP_SEM_CHAIN && sem->K > kCohortSlots) kind = SP_SEM_ARRAY;
   }
   if (kind == SP_SEM_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) {
@@ -252,10 +270,12 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   ss.cq_len = kCohortSlots;
   ss.cohort_bound = q.cohort_passes;
   ss.chain_len = sem->K <= kCohortSlots ? kCohortSlots / sem->K * sem->K : kCohortSlots;
-  const bool queued = kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN;
+  const bool queued = kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN ||
+                      kind == SP_SEM_XCD_CHAIN;
   if (queued && !sem->d_cq) return SP_E_INVAL;
   SP_CHECK(spi::fill_u32(ctx, base, sem->state_words, 0, s));
-  if (kind == SP_SEM_COHORT) SP_CHECK(spi::fill_u32(ctx, sem->d_cq, sem->cq_words, 0, s));
+  if (kind == SP_SEM_COHORT || kind == SP_SEM_XCD_CHAIN)
+    SP_CHECK(spi::fill_u32(ctx, sem->d_cq, sem->cq_words, 0, s));
   if (kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN)  // queue 0: two counters, the slots
     SP_CHECK(spi::fill_u32(ctx, sem->d_cq, (uint64_t)(2 + kCohortSlots) * sem->cq_stride, 0, s));
   if (out_data) {
@@ -276,9 +296,11 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   int rc = spi::end_timed(ctx, s, st, nwg, lanes, (uint32_t)per_cu, total_pairs);
   const uint32_t alg4 = kind == SP_SEM_SPIN || kind == SP_SEM_SPIN_BACKOFF;
   const uint32_t* cq = kind == SP_SEM_COHORT ? sem->d_cq : nullptr;
-  const uint32_t* arr = kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN ? sem->d_cq : nullptr;
+  const uint32_t* arr = kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN || kind == SP_SEM_XCD_CHAIN
+                            ? sem->d_cq : nullptr;
+  const uint32_t narr = kind == SP_SEM_XCD_CHAIN ? ss.cq_n : 1;
   hipLaunchKernelGGL(k_sem_state, dim3(1), dim3(64), 0, s, base, sw, alg4, cq, sem->cq_stride,
-                     kCohortSlots, arr, out_state);
+                     kCohortSlots, arr, narr, out_state);
   SP_HIP(ctx, hipGetLastError());
   SP_CHECK(spi::sync_unless_capturing(ctx, s));
   return rc;

@@ -260,7 +260,7 @@ def barrier(ctx, rounds: int = 10_000, lanes: int = 256, seed: int = 42, quick: 
 
 SEMS = [("spin", {}), ("spin_backoff", {"backoff": "exp"}), ("ticket", {}), ("sleep", {}),
         ("counters", {}), ("adaptive", {}), ("cohort", {}), ("array", {}),
-        ("chain", {})]
+        ("chain", {}), ("xcd_chain", {})]
 
 
 def sem(ctx, budget_s: float = 0.3, nwg: int = 2048, lanes: int = 256, seed: int = 42,
@@ -269,7 +269,12 @@ def sem(ctx, budget_s: float = 0.3, nwg: int = 2048, lanes: int = 256, seed: int
     full = 1 << 20
     for kind, params in SEMS:
         for K in ((4, 256) if quick else (1, 4, 32, 256)):
-            s = api.Semaphore(ctx, kind, K, timeout_ms=limit_ms, **params)
+            try:
+                s = api.Semaphore(ctx, kind, K, timeout_ms=limit_ms, **params)
+            except api.N.SpError as e:  # K outside the kind's range
+                rows.append({"kind": kind, "params": params, "K": K, "nwg": nwg,
+                             "refused": str(e)})
+                continue
             try:
                 pilot = nwg
                 try:

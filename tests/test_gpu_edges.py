@@ -73,7 +73,7 @@ def _sem_quiescent(r, kind, K, total):
     assert r["maxocc"] <= K and (r["maxocc"] >= 1) == (total > 0)
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind in ("counters", "adaptive", "array", "chain"):
+    elif kind in ("counters", "adaptive", "array", "chain", "xcd_chain"):
         assert s_or_count == 0 and ticket == turn == total
     else:
         assert s_or_count == 0 and ticket == turn
@@ -104,10 +104,18 @@ def test_semaphore_odd_grid(ctx, kind, K):
 
 
 @pytest.mark.parametrize("kind", ["ticket", "sleep", "counters", "adaptive", "cohort", "array",
-                                  "chain"])
+                                  "chain", "xcd_chain"])
 def test_semaphore_capacity_above_agents(ctx, kind):
     r = _sem(ctx, kind, 64, 16, 4000, 7)
     assert (r["chk"] == oracle.sem_closed(7, 16, 4000)).all()
     _sem_quiescent(r, kind, 64, 4000)
     if kind in ("ticket", "sleep"):
         assert r["state"][1] == 0  # a wait never had to queue: no ticket was drawn
+
+
+@pytest.mark.parametrize("nwg,total", [(1, 0), (8, 5), (37, 1001), (300, 12345)])
+def test_xcd_chain_few_operations_and_odd_grids(ctx, nwg, total):
+    # K = 9: one XCD's queue has two units, the others one
+    r = _sem(ctx, "xcd_chain", 9, nwg, total, 17)
+    assert (r["chk"] == oracle.sem_closed(17, nwg, total)).all()
+    _sem_quiescent(r, "xcd_chain", 9, total)

@@ -40,7 +40,7 @@ def _check(r, kind, K, nwg, total, seed):
         assert r["unserved"] == 0  # every local ticket served
     if kind.startswith("spin"):
         assert s_or_count == K + 1
-    elif kind in ("counters", "adaptive", "array", "chain"):
+    elif kind in ("counters", "adaptive", "array", "chain", "xcd_chain"):
         assert s_or_count == 0 and ticket == turn == total
     else:
         assert s_or_count == 0 and ticket == turn
@@ -147,7 +147,7 @@ def test_chain_capacity_limit(ctx):
     import paper_1110_4623_amd as sp
     with pytest.raises(sp.SpError):
         sp.Semaphore(ctx, "chain", 4097)
-    assert ctx.get_default("semaphore", 0) == ctx.get_default("semaphore", 1) == "chain"
+    assert ctx.get_default("semaphore", 0) == ctx.get_default("semaphore", 1) == "xcd_chain"
     own = sp.Context(0)  # a context of its own: the changed default stays in it
     try:
         own.set_default("semaphore", 0, "array")
@@ -158,5 +158,40 @@ def test_chain_capacity_limit(ctx):
         _check(r, "array", 5000, nwg, total, seed)
         r = _run(own, "default", 4, nwg, 64, total, 100, seed, data=False)
         _check(r, "chain", 4, nwg, total, seed)
+    finally:
+        own.close()
+
+
+@pytest.mark.parametrize("K", [8, 13, 32, 256, 4096])
+def test_xcd_chain_full_size(ctx, K):
+    """Per-XCD chains at config 4 (2048 workgroups, 2^20 pairs, holds U[0, 2000]): the
+    posts skip the writeback, so the guarded pool data (K <= 4096) checks the acquire and
+    the same-XCD hand-over; occupancy within K, counters quiescent."""
+    nwg, total, seed = 2048, 1 << 20, 0xC0FFEE
+    r = _run(ctx, "xcd_chain", K, nwg, 256, total, 2000, seed)
+    _check(r, "xcd_chain", K, nwg, total, seed)
+
+
+@pytest.mark.parametrize("K", [8, 32, 256])
+def test_xcd_chain_coherent_and_odd_grid(ctx, K):
+    r = _run(ctx, "xcd_chain", K, 2048, 256, 1 << 18, 2000, 7, coherent_cs=1)
+    _check(r, "xcd_chain", K, 2048, 1 << 18, 7)
+    r = _run(ctx, "xcd_chain", K, 301, 64, 12345, 100, 19)
+    _check(r, "xcd_chain", K, 301, 12345, 19)
+
+
+def test_xcd_chain_range(ctx):
+    """K below the XCD count is refused; a default semaphore whose bucket names the kind
+    runs the one-chain kind there, and the array kind above 4096."""
+    import paper_1110_4623_amd as sp
+    with pytest.raises(sp.SpError):
+        sp.Semaphore(ctx, "xcd_chain", 1)
+    own = sp.Context(0)
+    try:
+        own.set_default("semaphore", 0, "xcd_chain")
+        assert own.get_default("semaphore", 0) == "xcd_chain"
+        for K, ran in ((2, "chain"), (32, "xcd_chain"), (5000, "xcd_chain"), (40000, "array")):
+            r = _run(own, "default", K, 64, 64, 1 << 12, 100, 3, data=False)
+            _check(r, ran, K, 64, 1 << 12, 3)
     finally:
         own.close()

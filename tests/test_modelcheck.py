@@ -6,7 +6,7 @@ import pytest
 from oracle.modelcheck import (ArraySemModel, BarrierModel, CohortLockModel, CohortSemModel,
                                CondModel, FASemModel, MCSLockModel, MutexModel,
                                QueueLockModel, SpinSemModel, WeightedSemModel,
-                               XcdBarrierModel, explore)
+                               XcdBarrierModel, XcdChainSemModel, explore)
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "ticket", "sleep"])
@@ -414,3 +414,23 @@ def test_chain_semaphore_needs_slots_a_multiple_of_k():
 def test_chain_semaphore_mutants(mutant, K, M, expect):
     r = explore(ArraySemModel(K, (0, 1, 0), M, 2, mutant=mutant, rule="chain"))
     assert r.violation and expect in r.violation
+
+
+@pytest.mark.parametrize("K,placement,Q,M", [(2, (0, 1, 0, 1), 2, 2), (2, (0, 1, 0, 1), 2, 1),
+                                              (3, (0, 1, 0, 1), 2, 2), (2, (0, 0, 1), 2, 2),
+                                              (1, (0, 1, 0), 1, 2)])
+def test_xcd_chain_semaphore_correct(K, placement, Q, M):
+    """Chains per XCD queue with L1s and L2s: with a queue per XCD the posts skip the
+    writeback and no update is lost; with XCDs sharing a queue they write back."""
+    r = explore(XcdChainSemModel(K, placement, Q, M))
+    assert r.ok, r.violation
+
+
+@pytest.mark.parametrize("mutant,K,placement,Q", [
+    ("skip_when_shared", 1, (0, 1, 0), 1),
+    ("no_acquire", 2, (0, 0, 1), 2),
+    ("enter_at_k", 2, (0, 1, 0, 1), 2),
+])
+def test_xcd_chain_semaphore_mutants(mutant, K, placement, Q):
+    r = explore(XcdChainSemModel(K, placement, Q, 2, mutant=mutant))
+    assert r.violation

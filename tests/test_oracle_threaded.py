@@ -121,6 +121,22 @@ def test_chain_semaphore_at_2048_agents(K):
     assert r["state"] == (0, total, total, total)
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("K", [8, 13, 32, 256])
+def test_xcd_chain_semaphore_at_2048_agents(K):
+    """Chains per group of agents (8 groups, K = 13: five groups of 2 units, three of 1):
+    exact-value waits, bound, checksums and counters."""
+    seed, nwg, total = 0x8C4A, 2048, 1 << 14
+    r = oracle.sem_threaded("xcd_chain", K, seed, nwg, total)
+    assert r["rc"] == 0 and 1 <= r["maxocc"] <= K
+    assert (r["chk"] == oracle.sem_closed(seed, nwg, total)).all()
+    assert r["state"] == (0, total, total, total)
+
+
+def test_xcd_chain_semaphore_needs_a_unit_per_group():
+    assert oracle.sem_threaded("xcd_chain", 7, 1, 16, 64)["rc"] == -1
+
+
 def test_hardware_threads_reported():
     assert oracle.hardware_threads() >= 1
 

@@ -48,7 +48,8 @@ def test_candidate_lists_cover_every_kind():
                                                         "adaptive", "cohort", "mcs"}
     assert {k for k, _ in tune.semaphore_candidates()} == {"spin", "spin_backoff", "ticket",
                                                             "sleep", "counters", "adaptive",
-                                                            "cohort", "array", "chain"}
+                                                            "cohort", "array", "chain",
+                                                            "xcd_chain"}
     # Algorithm 4's post backoff is searched both ways
     assert {p.get("post_backoff") for k, p in tune.semaphore_candidates()
             if k == "spin_backoff"} == {0, 1}
