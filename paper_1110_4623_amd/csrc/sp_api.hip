@@ -230,9 +230,9 @@ int sp_init(int device, sp_ctx** out) {
   ctx->defaults[1][1].p.poll_sleep = 0;
   ctx->defaults[1][1].p.cohort_passes = 64;
   // per-XCD chains (K below the XCD count: one set of chains; K above 4096 per XCD: the
-  // array kind): 14.0 M pairs/s K = 32 at 256, 13.8 M K = 32 at 2048 and 1.71 M K = 4
-  // (chain 13.6 / 13.1 / 1.69, adaptive - / 6.3 / 1.55); K = 256 at 2048 129 M untracked
-  // (chain 57.7)
+  // array kind): 20.8 M pairs/s K = 32 at 256, 126 M K = 256 at 2048 (one set of chains
+  // 18.6 / 57.7); 20.3 M K = 32 at 2048, 2.31 M K = 4 (chains 17.9 / 2.31, adaptive
+  // 6.3 / 1.55)
   ctx->defaults[2][0].kind = SP_SEM_XCD_CHAIN;
   ctx->defaults[2][0].p.poll_sleep = 0;
   ctx->defaults[2][1].kind = SP_SEM_XCD_CHAIN;
