@@ -55,6 +55,8 @@ __device__ __forceinline__ uint64_t* cq_slot(const SemState& s, uint32_t x, uint
 }
 
 // ---- per-XCD chains ----------------------------------------------------------------------
+// Units of queue x; at least one, since K >= cq_n for this kind (sp_sem_create refuses a
+// smaller K, and a default semaphore runs the one-chain kind there).
 __device__ __forceinline__ uint32_t xchain_units(const SemState& s, uint32_t x) {
   return s.K / s.cq_n + (x < s.K % s.cq_n ? 1u : 0u);
 }
