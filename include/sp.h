@@ -252,7 +252,8 @@ int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out);
 void sp_params_default(sp_params* p);
 /* Installs the default kind and parameters that *_DEFAULT resolves to for a primitive
  * class (0 barrier, 1 mutex, 2 semaphore) and contention bucket (0 = low: fewer than
- * 64 workgroups per resource, 1 = high).  Used by the autotuner (future-work item of
+ * 64 workgroups per resource -- per lock, per semaphore unit; for a barrier fewer than
+ * 40 workgroups -- 1 = high).  Used by the autotuner (future-work item of
  * Section 7: tuning backoff per GPU and contention level).  Until a call replaces them,
  * the defaults are a tuning pass's winners on an MI355X: barrier central (low) and
  * per-XCD with 64 stamp copies (high); mutex spin with the paper's backoff, I_max 8

@@ -255,8 +255,10 @@ class Barrier(_Handle):
         """How the last run synchronized (per-XCD path used, or why not)."""
         i = N.BarrierInfo()
         check(lib.sp_barrier_info_get(self.h, ctypes.byref(i)), "sp_barrier_info_get", self.ctx.h)
-        return {"xcd_path": bool(i.xcd_path), "misplaced": i.misplaced,
-                "cu_overflow": i.cu_overflow, "near_placed": i.near_placed}
+        names = {v: k for k, v in N.BARRIER_KINDS.items()}
+        return {"kind": names.get(i.kind, i.kind), "xcd_path": bool(i.xcd_path),
+                "misplaced": i.misplaced, "cu_overflow": i.cu_overflow,
+                "near_placed": i.near_placed}
 
     def run_hash(self, lanes: int, rounds: int, seed: int):
         """Hash-exchange workload; returns (checksums as uint32 numpy array, stats)."""

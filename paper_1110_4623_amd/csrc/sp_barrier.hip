@@ -210,7 +210,7 @@ int sp_barrier_create(sp_ctx* ctx, uint32_t kind, uint32_t nwg, const sp_params*
   *out = nullptr;
   sp_params q;
   if (kind == SP_BARRIER_DEFAULT) {
-    const sp_default_entry& d = ctx->defaults[0][spi::bucket_of(nwg)];
+    const sp_default_entry& d = ctx->defaults[0][spi::barrier_bucket_of(nwg)];
     kind = d.kind;
     sp_params dp = d.p;
     if (p && p->timeout_ms) dp.timeout_ms = p->timeout_ms;  // an explicit timeout applies

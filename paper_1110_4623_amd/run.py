@@ -53,7 +53,8 @@ def main(argv=None) -> int:
             b = api.Barrier(ctx, a.kind or "xcd", a.nwg)
             try:
                 _, st = b.run_hash(a.lanes, a.rounds, a.seed)
-                out.update(kind=a.kind or "xcd", nwg=a.nwg, lanes=a.lanes, rounds=a.rounds,
+                # info() names the kind that ran (a default barrier's resolved kind)
+                out.update(nwg=a.nwg, lanes=a.lanes, rounds=a.rounds,
                            us_per_round=st["kernel_ms"] * 1e3 / a.rounds, **b.info())
             finally:
                 b.close()

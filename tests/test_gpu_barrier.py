@@ -304,3 +304,19 @@ def test_one_more_than_resident_is_refused(ctx):
             b.run_hash(64, 1, 1)
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("nwg,xcd", [(32, False), (39, False), (40, True), (63, True)])
+def test_default_barrier_split_at_40_workgroups(ctx, nwg, xcd):
+    """A default barrier runs the central counter below 40 workgroups and the per-XCD
+    barrier from 40 on (the measured crossover); both give the oracle's checksums."""
+    import paper_1110_4623_amd as sp
+    announce("default barrier", f"nwg={nwg}")
+    b = sp.Barrier(ctx, "default", nwg)
+    try:
+        chk, _ = b.run_hash(256, 200, 5)
+        assert (chk == oracle.barrier_closed(5, nwg, 200)).all()
+        assert b.info()["kind"] == ("xcd" if xcd else "central")
+        assert b.info()["xcd_path"] == xcd
+    finally:
+        b.close()
