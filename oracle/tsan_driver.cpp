@@ -60,17 +60,18 @@ int main() {
       expect(got == want, "mutex words");
     }
   }
-  {  // semaphores: every kind, K = 2
-    const uint32_t nwg = 6;
-    const uint64_t total = 300;
-    std::vector<uint32_t> want(nwg), got(nwg);
-    uint32_t maxocc = 0, state[4];
-    or_sem_closed(seed, nwg, total, want.data());
-    for (int kind = 0; kind <= 7; ++kind) {
-      expect(or_sem_threaded(kind, 2, seed, nwg, total, 1, 4, got.data(), &maxocc, state,
+  {  // semaphores: every kind, K = 2 (the per-group chains, kind 10, need a unit per
+     // group of eight: K = 9 over 16 agents)
+    for (int kind = 0; kind <= 10; ++kind) {
+      const uint32_t nwg = kind == 10 ? 16 : 6, K = kind == 10 ? 9 : 2;
+      const uint64_t total = 300;
+      std::vector<uint32_t> want(nwg), got(nwg);
+      uint32_t maxocc = 0, state[4];
+      or_sem_closed(seed, nwg, total, want.data());
+      expect(or_sem_threaded(kind, K, seed, nwg, total, 1, 4, got.data(), &maxocc, state,
                              nullptr) == 0,
              "semaphore rc");
-      expect(got == want && maxocc <= 2 && state[3] == total, "semaphore outputs");
+      expect(got == want && maxocc <= K && state[3] == total, "semaphore outputs");
     }
   }
   {  // serving queue: 64 requests, 4 agents, budget 3 units
