@@ -195,3 +195,22 @@ def test_xcd_chain_range(ctx):
             _check(r, ran, K, 64, 1 << 12, 3)
     finally:
         own.close()
+
+
+@pytest.mark.parametrize("kind", ["array", "chain", "xcd_chain"])
+@pytest.mark.parametrize("pad", [4, 4096])
+def test_slot_kinds_with_small_and_large_padding(ctx, kind, pad):
+    """The grant slots and 64-bit counters at 4-byte padding (lines two words apart, still
+    8-byte aligned) and 4 KiB padding: pool data exact, bound and counters."""
+    nwg, total, seed = 2048, 1 << 16, 0x9AD
+    r = _run(ctx, kind, 32, nwg, 256, total, 500, seed, pad_bytes=pad)
+    _check(r, kind, 32, nwg, total, seed)
+
+
+@pytest.mark.parametrize("kind,K", [("chain", 4096), ("xcd_chain", 8 * 4096), ("array", 1 << 20)])
+def test_slot_kinds_at_their_largest_k(ctx, kind, K):
+    """The largest K each slot kind takes (a slot per chain; per XCD for the per-XCD
+    chains): 2048 workgroups never queue, every ticket below K enters at once."""
+    nwg, total, seed = 2048, 1 << 16, 21
+    r = _run(ctx, kind, K, nwg, 256, total, 100, seed, data=False)
+    _check(r, kind, K, nwg, total, seed)
