@@ -23,21 +23,24 @@ struct SemState {
   uint32_t* cq;
   uint32_t cq_n;         // queues in use, 1..kXccQueues
   uint32_t cq_local;     // 1: every XCC id is below cq_n, so queue x holds XCD x's
-                         // workgroups only (the K = 1 writeback skip relies on it)
+                         // workgroups only (the cohort kind's K = 1 writeback skip and
+                         // the per-XCD chains' skip rely on it)
   uint32_t cq_stride;
   uint32_t cq_len;       // power of two
   uint32_t cohort_bound; // local hand-overs of one unit in a row, at most
   // SP_SEM_ARRAY and SP_SEM_CHAIN use queue 0's memory: line 0 the tickets drawn, line 1
-  // the posts made (64-bit counters), then the cq_len 64-bit grant slots.
+  // the posts made (64-bit counters), then the cq_len 64-bit grant slots; SP_SEM_XCD_CHAIN
+  // lays out every queue in use that way.
   uint32_t chain_len;    // SP_SEM_CHAIN: slots in use, the largest multiple of K <= cq_len
 };
 
 // Per-workgroup waiting state that persists across waits (SP_SEM_ADAPTIVE), or from a
-// wait to its post (SP_SEM_COHORT).
+// wait to its post (SP_SEM_COHORT, SP_SEM_CHAIN, SP_SEM_XCD_CHAIN).
 struct SemHold {
   uint32_t interval;  // learned wall-clock ticks between two posts (0 = none yet)
-  uint32_t pass;      // SP_SEM_COHORT: local hand-overs of the unit held, in a row
-  uint64_t ticket;    // SP_SEM_CHAIN: the ticket the unit held was taken with
+  uint32_t pass;      // SP_SEM_COHORT: local hand-overs of the unit held, in a row;
+                      // SP_SEM_XCD_CHAIN: the queue the unit belongs to
+  uint64_t ticket;    // SP_SEM_CHAIN, SP_SEM_XCD_CHAIN: the ticket the unit was taken with
 };
 
 // ---- cohort semaphore queues -------------------------------------------------------------
@@ -66,7 +69,7 @@ __device__ __forceinline__ uint64_t* xchain_slot(const SemState& s, uint32_t x, 
   return reinterpret_cast<uint64_t*>(cq_base(s, x) + (size_t)(2 + t % m) * s.cq_stride);
 }
 
-// ---- array semaphore (ticket-indexed grant slots) ----------------------------------------
+// ---- array semaphore (ticket-indexed grant slots); 64-bit counters of the slot kinds ----
 __device__ __forceinline__ uint64_t add_relaxed64(uint64_t* p, uint64_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
