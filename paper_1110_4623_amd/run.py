@@ -45,6 +45,8 @@ def main(argv=None) -> int:
     ap.add_argument("--bytes", type=int, default=1 << 30)
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--repeat", type=int, default=1)
+    ap.add_argument("--data", action="store_true",
+                    help="sem: holders also update the guarded data (K <= 4096)")
     a = ap.parse_args(argv)
     ctx = api.Context(0)
     out = {"what": a.what}
@@ -70,10 +72,12 @@ def main(argv=None) -> int:
         elif a.what == "sem":
             s = api.Semaphore(ctx, a.kind or "sleep", a.K)
             try:
-                r = s.run(a.nwg, a.lanes, a.total, a.hold, a.seed, track=False)
+                r = s.run(a.nwg, a.lanes, a.total, a.hold, a.seed, track=False, data=a.data)
                 out.update(kind=a.kind or "sleep", K=a.K, nwg=a.nwg, total=a.total,
                            pairs_per_s=a.total / (r["stats"]["kernel_ms"] * 1e-3),
                            admissions=r["state"][3])
+                if a.data:
+                    out["data_sum"] = int(r["data"].astype("u8").sum())
             finally:
                 s.close()
         elif a.what == "serve":

@@ -17,6 +17,7 @@ CASES = [
     ["barrier", "--kind", "default", "--nwg", "32", "--rounds", "100"],
     ["mutex", "--kind", "cohort", "--nwg", "256", "--total", "4096"],
     ["sem", "--kind", "xcd_chain", "--nwg", "256", "--total", "4096", "--K", "32"],
+    ["sem", "--kind", "chain", "--nwg", "256", "--total", "4096", "--K", "32", "--data"],
     ["copy", "--bytes", str(1 << 24)],
     ["micro", "--op", "ld", "--T", "4096", "--nwg", "64", "--ops", "4"],
     ["serve", "--rate", "1e5", "--n", "2000"],
@@ -32,6 +33,8 @@ def test_run_prints_one_json_line(args):
     assert p.returncode == 0, p.stderr[-2000:]
     lines = [json.loads(l) for l in p.stdout.splitlines() if l.startswith("{")]
     assert len(lines) == 1 and lines[0]["what"] == args[0]
+    if "--data" in args:
+        assert lines[0]["data_sum"] == 4096
     if args[0] == "barrier":
         assert lines[0]["kind"] == ("central" if "32" in args else "xcd")
         assert lines[0]["us_per_round"] > 0
