@@ -105,21 +105,21 @@ __global__ SP_FULL_OCCUPANCY void k_sem(sp::SemState s, uint32_t stride, uint32_
 
 __global__ void k_sem_state(const uint32_t* state, uint32_t stride, uint32_t alg4,
                             const uint32_t* cq, uint32_t cq_stride, uint32_t cq_len,
-                            const uint32_t* arr, uint32_t narr, uint32_t* out) {
+                            const uint32_t* arr, uint32_t nq, uint32_t* out) {
   if (threadIdx.x == 0) {
-    // cohort kind: local tickets drawn but never served, over every XCD's queue (0 at rest)
+    // cohort kind: local tickets drawn but never served, over the queues in use (0 at rest)
     uint32_t unserved = 0;
     if (cq)
-      for (uint32_t x = 0; x < sp::kXccQueues; ++x) {
+      for (uint32_t x = 0; x < nq; ++x) {
         const uint32_t* b = cq + (size_t)x * (2 + cq_len) * cq_stride;
         unserved += b[0] - b[cq_stride];
       }
     out[0] = state[L_MAXOCC * stride];
     out[1] = alg4 ? state[L_S * stride] : state[L_COUNT * stride];
     // array and chain kinds: the low halves of their 64-bit tickets and posts counters,
-    // summed over the queues that hold them (narr)
+    // summed over the queues that hold them
     uint32_t tickets = 0, posts = 0;
-    for (uint32_t x = 0; arr && x < narr; ++x) {
+    for (uint32_t x = 0; arr && x < nq; ++x) {
       const uint32_t* b = arr + (size_t)x * (2 + cq_len) * cq_stride;
       tickets += b[0];
       posts += b[cq_stride];
@@ -274,10 +274,11 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
                       kind == SP_SEM_XCD_CHAIN;
   if (queued && !sem->d_cq) return SP_E_INVAL;
   SP_CHECK(spi::fill_u32(ctx, base, sem->state_words, 0, s));
-  if (kind == SP_SEM_COHORT || kind == SP_SEM_XCD_CHAIN)
-    SP_CHECK(spi::fill_u32(ctx, sem->d_cq, sem->cq_words, 0, s));
-  if (kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN)  // queue 0: two counters, the slots
-    SP_CHECK(spi::fill_u32(ctx, sem->d_cq, (uint64_t)(2 + kCohortSlots) * sem->cq_stride, 0, s));
+  // the queues a run uses: one per XCD (cohort, per-XCD chains) or queue 0 (array, chain)
+  const uint32_t nq = kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN ? 1u : ss.cq_n;
+  if (queued)
+    SP_CHECK(spi::fill_u32(ctx, sem->d_cq, (uint64_t)nq * (2 + kCohortSlots) * sem->cq_stride,
+                           0, s));
   if (out_data) {
     SP_CHECK(spi::fill_u32(ctx, out_data, sem->K, 0, s));
     if (sem->K > 1) SP_CHECK(spi::fill_u32(ctx, sem->d_owner, (uint64_t)sem->K * kOwnerWords, 0, s));
@@ -298,9 +299,8 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   const uint32_t* cq = kind == SP_SEM_COHORT ? sem->d_cq : nullptr;
   const uint32_t* arr = kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN || kind == SP_SEM_XCD_CHAIN
                             ? sem->d_cq : nullptr;
-  const uint32_t narr = kind == SP_SEM_XCD_CHAIN ? ss.cq_n : 1;
   hipLaunchKernelGGL(k_sem_state, dim3(1), dim3(64), 0, s, base, sw, alg4, cq, sem->cq_stride,
-                     kCohortSlots, arr, narr, out_state);
+                     kCohortSlots, arr, queued ? nq : 0u, out_state);
   SP_HIP(ctx, hipGetLastError());
   SP_CHECK(spi::sync_unless_capturing(ctx, s));
   return rc;
