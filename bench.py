@@ -48,6 +48,7 @@ os.environ.setdefault("SP_NO_TORCH", "1")
 METRIC = "µs/barrier round, mutex & semaphore ops/s vs #WGs; persistent-queue p99 latency"
 NWG, LANES, ROUNDS = 2048, 256, 10_000
 C1_NWG, C1_LANES, C1_ROUNDS = 16, 64, 1000
+AB_ROUNDS = 2000  # the split central barrier against A1 (outside the timed region)
 MUTEX_TOTAL, SEM_TOTAL, SEM_K = 1 << 20, 1 << 20, 32
 CURVE_NWG, CURVE_OPS = (64, 256, 1024), 1 << 18
 # read-modify-writes per wait/post pair on each semaphore kind's busiest contended word
@@ -74,7 +75,8 @@ def measured_traffic(kernel_sources_dir: str) -> float | None:
         return None
 
 
-def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20.0) -> dict:
+def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20.0,
+                 atomic_chk=None) -> dict:
     """The CPU oracle on this host, and the check of this run's barrier checksums against
     it (both outside the timed region).
 
@@ -99,6 +101,9 @@ def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20
     ref = oracle.barrier_closed(42, NWG, ROUNDS)
     t_closed = time.perf_counter() - t_closed  # the closed form: ground truth, not a baseline
     ref1 = oracle.barrier_closed(42, C1_NWG, C1_ROUNDS)
+    atomic_ok = None
+    if atomic_chk is not None:
+        atomic_ok = bool((atomic_chk == oracle.barrier_closed(42, NWG, AB_ROUNDS)).all())
     curves_ok = None
     if curve_out is not None:
         curves_ok = True
@@ -114,7 +119,8 @@ def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20
             "closed_form_seconds": round(t_closed, 4),
             "headline_checksums_match_oracle": bool((headline_chk == ref).all()),
             "config1_checksums_match_oracle": bool((config1_chk == ref1).all()),
-            "curves_match_oracle": curves_ok}
+            "curves_match_oracle": curves_ok,
+            "atomic_barrier_checksums_match_oracle": atomic_ok}
 
 
 def environment(ctx, resident_per_cu: int) -> dict:
@@ -223,6 +229,15 @@ def main() -> int:
     c1_us = float(np.median([st["kernel_ms"] for _, st in c1])) * 1e3 / C1_ROUNDS
     c1_chk = c1[0][0]
     c1_same = all((chk == c1_chk).all() for chk, _ in c1)
+    # The contended-atomic barrier against A1: the split central counter (every workgroup
+    # adds one to one word, the last one stores the release word the others poll) with
+    # coherently accessed data, so that no fence separates the atomics, 2048 workgroups x
+    # AB_ROUNDS rounds (best of two).
+    bar_ab = sp.Barrier(ctx, "central_split", NWG, coherent_cs=1)
+    ab = [bar_ab.run_hash(LANES, AB_ROUNDS, 42) for _ in range(2)]
+    bar_ab.close()
+    ab_us = min(st["kernel_ms"] for _, st in ab) * 1e3 / AB_ROUNDS
+    ab_chk = ab[0][0]
     # Section 4's machine card on this GPU: the twelve tests of Section 3 at 2048
     # workgroups (leader per workgroup, 1000 accesses, noncontentious words 256 B apart),
     # and the ceilings: A1 (timed steps), A_dist (adds spread over 2^20 words 128 B apart),
@@ -370,7 +385,13 @@ def main() -> int:
                 "semaphore_k32_default_kind_frac": round(sem_def_rate / (a1 / sem_def_rmw), 4),
                 "mutex_acq_bound_per_s": round(1e6 / sig_us, 1),
                 "mutex_default_kind_frac": round(mtx_def_rate * sig_us * 1e-6, 4),
-                "mutex_ticket_frac": round(mtx_rate * sig_us * 1e-6, 4)},
+                "mutex_ticket_frac": round(mtx_rate * sig_us * 1e-6, 4),
+                # one read-modify-write per workgroup per round on one word: at most A1
+                # arrivals per second
+                "atomic_barrier_split_central_coherent_2048wg": {
+                    "us_per_round": round(ab_us, 4),
+                    "arrivals_per_s": round(NWG / (ab_us * 1e-6), 1),
+                    "frac_of_A1": round(NWG / (ab_us * 1e-6) / a1, 4)}},
             # other views of the headline kernel (not bounds)
             "barrier_arrivals_vs_A1": round(arrivals / a1, 4),
             "barrier_hbm_view": {"algorithmic_bytes_per_launch": alg_bytes,
@@ -397,7 +418,8 @@ def main() -> int:
         "env": environment(ctx, results[0]["bar_occ"]),
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(results[0]["bar_chk"], c1_chk, curve_out)
+        line["cpu_baseline"] = cpu_baseline(results[0]["bar_chk"], c1_chk, curve_out,
+                                            atomic_chk=ab_chk)
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0

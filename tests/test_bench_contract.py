@@ -61,6 +61,8 @@ def test_one_step_prints_the_contract_line():
     for k in ("semaphore_k32_default_kind_frac", "semaphore_k32_alg5_frac",
               "mutex_default_kind_frac", "mutex_ticket_frac"):
         assert 0 < m["bounds"][k] < 1, k
+    ab = m["bounds"]["atomic_barrier_split_central_coherent_2048wg"]
+    assert 0 < ab["frac_of_A1"] < 1.5 and ab["us_per_round"] > 0
     import bench
     kind = m["bounds"]["semaphore_k32_default_kind"]
     assert m["bounds"]["semaphore_k32_default_kind_bound_per_s"] == round(
@@ -101,6 +103,13 @@ def test_cpu_baseline_leg_checks_checksums_against_the_oracle():
     words[0, 3] += 1
     bad_curve = {n: (good[n][0], words, good[n][2])}
     assert bench.cpu_baseline(ref, ref1, bad_curve, budget_s=0.5)["curves_match_oracle"] is False
+    # the atomic barrier's checksums (2048 x AB_ROUNDS), one planted wrong word
+    refab = oracle.barrier_closed(42, bench.NWG, bench.AB_ROUNDS)
+    assert bench.cpu_baseline(ref, ref1, budget_s=0.5,
+                              atomic_chk=refab)["atomic_barrier_checksums_match_oracle"] is True
+    refab[100] ^= 4
+    assert bench.cpu_baseline(ref, ref1, budget_s=0.5,
+                              atomic_chk=refab)["atomic_barrier_checksums_match_oracle"] is False
 
 
 def test_semaphore_bound_covers_every_kind():
