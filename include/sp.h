@@ -464,8 +464,9 @@ int sp_bench_atomic(sp_ctx* ctx, uint32_t op, uint32_t nwg, uint32_t lanes, uint
 int sp_bench_paper12(sp_ctx* ctx, uint32_t test, uint32_t nwg, uint32_t lanes, uint32_t n_ops,
                      uint32_t stride_bytes, uint32_t* buf, uint64_t* out_sum, sp_stats* st,
                      void* stream);
-/* sp_bench_stream: reads `bytes` (multiple of 16) of buf with 16-byte loads and sums the
- * uint32 words into out_sum (device, 1 uint64).  nwg = 0 picks a grid.                 */
+/* sp_bench_stream: reads `bytes` (multiple of 16) of buf with 16-byte loads (four in
+ * flight per lane) and sums the uint32 words into out_sum (device, 1 uint64).  nwg = 0:
+ * 32 workgroups of 256 lanes per CU.                                                    */
 int sp_bench_stream(sp_ctx* ctx, const void* buf, uint64_t bytes, uint32_t nwg, uint32_t reps,
                     uint64_t* out_sum, sp_stats* st, void* stream);
 /* sp_bench_clock: one lane spins for `ms` milliseconds of the constant-rate wall clock

@@ -74,13 +74,17 @@ def test_paper12_leaves_zeros(ctx, test):
     assert int(words.astype(np.int64).sum()) == 0
 
 
-def test_stream_sum(ctx):
+@pytest.mark.parametrize("n,nwg", [(1 << 24, 0), (3 * (1 << 20) + 20, 7), ((1 << 22) + 4, 64)])
+def test_stream_sum(ctx, n, nwg):
+    """Every word read once per repetition: the unrolled steps (four loads per lane) and
+    the ragged tail, with the default grid and with small ones."""
     import paper_1110_4623_amd as sp
-    n = 1 << 24
-    announce("stream", n)
+    announce("stream", n, nwg)
     buf = ctx.upload(np.arange(n, dtype=np.uint32))
-    s, st = sp.stream_read(ctx, buf, 4 * n, reps=2)
+    s, st = sp.stream_read(ctx, buf, 4 * n, reps=2, nwg=nwg)
     assert s == 2 * (n * (n - 1) // 2)
+    if nwg:
+        return
     dst = ctx.zeros(n)
     sp.copy(ctx, dst, buf, 4 * n)
     assert (ctx.read(dst, "u32", n) == np.arange(n, dtype=np.uint32)).all()
