@@ -51,6 +51,7 @@ C1_NWG, C1_LANES, C1_ROUNDS = 16, 64, 1000
 AB_ROUNDS = 2000  # the split central barrier against A1 (outside the timed region)
 MUTEX_TOTAL, SEM_TOTAL, SEM_K = 1 << 20, 1 << 20, 32
 CURVE_NWG, CURVE_OPS = (64, 256, 1024), 1 << 18
+SEM_KS = (1, 4, 32, 256)
 # read-modify-writes per wait/post pair on each semaphore kind's busiest contended word
 SEM_RMW_PER_PAIR = {"spin": 4, "spin_backoff": 4, "ticket": 2, "sleep": 2, "cohort": 2,
                     "counters": 1, "adaptive": 1, "array": 1, "chain": 1, "xcd_chain": 1}
@@ -76,7 +77,7 @@ def measured_traffic(kernel_sources_dir: str) -> float | None:
 
 
 def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20.0,
-                 atomic_chk=None) -> dict:
+                 atomic_chk=None, sem_k_chk=None) -> dict:
     """The CPU oracle on this host, and the check of this run's barrier checksums against
     it (both outside the timed region).
 
@@ -104,6 +105,10 @@ def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20
     atomic_ok = None
     if atomic_chk is not None:
         atomic_ok = bool((atomic_chk == oracle.barrier_closed(42, NWG, AB_ROUNDS)).all())
+    sem_k_ok = None
+    if sem_k_chk is not None:
+        want = oracle.sem_closed(42, NWG, CURVE_OPS)
+        sem_k_ok = all(bool((c == want).all()) for c in sem_k_chk.values())
     curves_ok = None
     if curve_out is not None:
         curves_ok = True
@@ -120,7 +125,8 @@ def cpu_baseline(headline_chk, config1_chk, curve_out=None, budget_s: float = 20
             "headline_checksums_match_oracle": bool((headline_chk == ref).all()),
             "config1_checksums_match_oracle": bool((config1_chk == ref1).all()),
             "curves_match_oracle": curves_ok,
-            "atomic_barrier_checksums_match_oracle": atomic_ok}
+            "atomic_barrier_checksums_match_oracle": atomic_ok,
+            "semaphore_vs_K_checksums_match_oracle": sem_k_ok}
 
 
 def environment(ctx, resident_per_cu: int) -> dict:
@@ -273,6 +279,15 @@ def main() -> int:
         curves["semaphore_k32_default_pairs_per_s"][n] = round(
             CURVE_OPS / (sres["stats"]["kernel_ms"] * 1e-3), 1)
         curve_out[n] = (bchk, words, sres["chk"])
+    # Config 4's semaphore range at 2048 workgroups: the default kind at every K (2^18
+    # pairs each; checked against the closed form like the curves)
+    sem_vs_k, sem_k_chk = {}, {}
+    for K in SEM_KS:
+        s = sp.Semaphore(ctx, "default", K)
+        sres = s.run(NWG, LANES, CURVE_OPS, 2000, 42, track=False)
+        s.close()
+        sem_vs_k[K] = round(CURVE_OPS / (sres["stats"]["kernel_ms"] * 1e-3), 1)
+        sem_k_chk[K] = sres["chk"]
 
     bar_ms = float(np.mean([r["bar_ms"] for r in results]))
     us_round = bar_ms * 1e3 / ROUNDS
@@ -359,6 +374,7 @@ def main() -> int:
             "serve_results_identical": all(r["serve_same"] for r in results),
             "shader_clock_mhz_before_after": [round(clock_before, 1), round(clock_after, 1)],
             "curves_vs_nwg": curves,
+            "semaphore_default_2048wg_pairs_per_s_vs_K": sem_vs_k,
             # Section 4's card and the ceilings the primitives are compared with
             "machine_card_2048wg": {
                 "atomic_to_volatile_contentious": mcard["atomic_to_volatile"],
@@ -419,7 +435,7 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(results[0]["bar_chk"], c1_chk, curve_out,
-                                            atomic_chk=ab_chk)
+                                            atomic_chk=ab_chk, sem_k_chk=sem_k_chk)
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0

@@ -61,6 +61,8 @@ def test_one_step_prints_the_contract_line():
     for k in ("semaphore_k32_default_kind_frac", "semaphore_k32_alg5_frac",
               "mutex_default_kind_frac", "mutex_ticket_frac"):
         assert 0 < m["bounds"][k] < 1, k
+    assert sorted(int(k) for k in m["semaphore_default_2048wg_pairs_per_s_vs_K"]) == [1, 4, 32, 256]
+    assert min(m["semaphore_default_2048wg_pairs_per_s_vs_K"].values()) > 0
     ab = m["bounds"]["atomic_barrier_split_central_coherent_2048wg"]
     assert 0 < ab["frac_of_A1"] < 1.5 and ab["us_per_round"] > 0
     import bench
@@ -107,6 +109,13 @@ def test_cpu_baseline_leg_checks_checksums_against_the_oracle():
     refab = oracle.barrier_closed(42, bench.NWG, bench.AB_ROUNDS)
     assert bench.cpu_baseline(ref, ref1, budget_s=0.5,
                               atomic_chk=refab)["atomic_barrier_checksums_match_oracle"] is True
+    want = oracle.sem_closed(42, bench.NWG, bench.CURVE_OPS)
+    ok = bench.cpu_baseline(ref, ref1, budget_s=0.5, sem_k_chk={1: want, 32: want})
+    assert ok["semaphore_vs_K_checksums_match_oracle"] is True
+    wrong = want.copy()
+    wrong[5] ^= 1
+    ok = bench.cpu_baseline(ref, ref1, budget_s=0.5, sem_k_chk={1: want, 32: wrong})
+    assert ok["semaphore_vs_K_checksums_match_oracle"] is False
     refab[100] ^= 4
     assert bench.cpu_baseline(ref, ref1, budget_s=0.5,
                               atomic_chk=refab)["atomic_barrier_checksums_match_oracle"] is False
