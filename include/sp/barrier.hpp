@@ -72,6 +72,11 @@ __device__ __forceinline__ bool poll_until(const uint32_t* p, uint32_t stamp, Wa
     if (!w.tick()) return false;
   return true;
 }
+__device__ __forceinline__ bool poll_until_cu(const uint32_t* p, uint32_t stamp, Wait& w) {
+  while (!reached(ld_cu(p), stamp))
+    if (!w.tick()) return false;
+  return true;
+}
 
 // Leader part of the counter-based barriers.  Each leader publishes its workgroup's
 // stores with a release fence before arriving and acquires after the wait.
@@ -218,7 +223,11 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
 //      release) and publishes the XCD's stamp.
 //   3. Each CU leader polls the stamps of every XCD that has members; once all are
 //      published it acquires (agent scope) and releases the other workgroups of its CU
-//      with one store to the CU's release line, which they poll.  With xcopies = C > 0
+//      with one store to the CU's release line, which they poll.  That line is stored and
+//      polled at workgroup scope: the CU's workgroups share its L1, and a store by one
+//      wavefront is seen by the CU's other wavefronts there (what makes workgroup scope
+//      coherent without cache maintenance), so the signal stays within the CU instead of
+//      taking a memory round trip.  With xcopies = C > 0
 //      the masters write their stamps into C lines that each hold all of them packed,
 //      and the CUs spread their polls over the copies by their rank in their XCD (fewer
 //      pollers per line).
@@ -228,7 +237,7 @@ __device__ __forceinline__ bool flag_wait(const BarrierState& s, uint32_t stamp,
 // lines), so it is shared by the workgroups of one CU: all of them are waiting when
 // their leader invalidates, so nothing stale can re-enter the L1 before they read.
 // If an XCD holds more members than its flag block or more than kCuLines CUs, every
-// workgroup falls back to the counter tree.  All flags are agent-scope atomics.
+// workgroup falls back to the counter tree.  All other flags are agent-scope atomics.
 struct XcdLocal {
   uint32_t x;        // the XCD this workgroup runs on
   uint32_t k;        // member index within the XCD (0 = master)
@@ -320,13 +329,13 @@ __device__ __forceinline__ bool xcd_wait(uint32_t stamp, const Ctl& ctl, const X
     if (!ok) return false;
     if (is_leader()) {
       fence_acquire();  // completes before the release store is issued
-      st_relaxed(rel, stamp);
+      st_cu(rel, stamp);  // only this CU's workgroups poll the line
     }
     __syncthreads();
     return true;
   }
   if (is_leader()) {
-    ok = poll_until(rel, stamp, w);
+    ok = poll_until_cu(rel, stamp, w);
     s_ok = ok;
   }
   __syncthreads();
