@@ -8,7 +8,7 @@ One step runs the whole path once over the full-size synthetic workloads:
      rounds of the hash exchange (the headline: microseconds per barrier round);
   3. mutex: ticket lock (Algorithm 3), 2048 workgroups x 256 lanes, one lock guarding 16
      words, 2^20 acquisitions with non-critical delays uniform in [0, 1000] cycles, then
-     the same workload on the library's default mutex for this contention (the XCD-cohort
+     the same workload on the library's default mutex for this contention (the CU-cohort
      lock);
   4. semaphore: fetch-and-add semaphore (Algorithm 5 with s_sleep polling) with K = 32,
      2048 workgroups, 2^20 wait/post pairs holding uniform [0, 2000] cycles, then the
@@ -391,8 +391,10 @@ def main() -> int:
             # of them per pair on its busiest word admits at most A1 / r pairs per second:
             # Algorithm 5 r = 2 (count, up in the wait and down in the post), the ticket
             # kinds r = 1 (the tickets word in the wait, the posts word in the post).  A
-            # lock hand-over moves ownership at least one one-way hop, so at most 1 / L_coh
-            # acquisitions per second (the critical section's own time left out).
+            # lock hand-over through memory moves ownership at least one one-way hop, so at
+            # most 1 / L_coh acquisitions per second (the critical section's own time left
+            # out); the CU-cohort lock's hand-overs within a CU stay in the CU's L1, so for
+            # it the figure is a reference, not a bound.
             "bounds": {
                 "semaphore_k32_alg5_bound_per_s": round(a1 / 2, 1),
                 "semaphore_k32_alg5_frac": round(sem_rate / (a1 / 2), 4),

@@ -82,6 +82,13 @@ enum sp_mutex_kind {
                              /* each waiter polls only its own node; unlock hands over  */
                              /* to the successor or frees the tail with a CAS.  State:  */
                              /* one padded node per lock and workgroup of the run       */
+  SP_MUTEX_CU_COHORT = 10,   /* CU-cohort lock: SP_MUTEX_COHORT with a ticket lock per  */
+                             /* CU in front of each XCD's; a holder passes the XCD lock */
+                             /* to a waiter of its own CU (at most cohort_passes times  */
+                             /* in a row) through a word in the CU's shared L1, with no */
+                             /* cache maintenance.  State: 16 x 256 x 3 padded lines    */
+                             /* per lock besides the XCD cohorts' (sp_mutex_run refuses */
+                             /* more than 2^28 words)                                   */
   SP_MUTEX_DEFAULT = 15
 };
 
@@ -257,8 +264,9 @@ void sp_params_default(sp_params* p);
  * Section 7: tuning backoff per GPU and contention level).  Until a call replaces them,
  * the defaults are a tuning pass's winners on an MI355X: barrier central (low) and
  * per-XCD with 64 stamp copies (high); mutex spin with the paper's backoff, I_max 8
- * (low) and the XCD-cohort lock (high); semaphore the per-XCD chains (both; outside
- * their range of K the chain kind, then the array kind).                                */
+ * (low) and the CU-cohort lock (high; a run with fewer than two workgroups per CU and
+ * lock runs the XCD-cohort lock with the same parameters instead); semaphore the per-XCD
+ * chains (both; outside their range of K the chain kind, then the array kind).          */
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p);
 /* Reads back what *_DEFAULT resolves to for a primitive class and bucket (as above):

@@ -19,8 +19,11 @@ struct MutexState {
                         // 64-bit grant slots), qstride (even) words apart
   uint32_t qlen;        // slots per lock (power of two; the ring needs >= contenders)
   uint32_t qstride;     // words between slots
-  uint32_t cohort_bound;  // cohort: holders of one XCD in a row, at most
+  uint32_t cohort_bound;  // cohort: holders of one XCD in a row, at most; CU cohort: also
+                          // holders of one CU in a row
   BackoffCfg bo;        // backoff between failed attempts
+  uint32_t* cuq;        // CU cohort: per lock, XCC id and CU id, kCuLines lines (CU ticket,
+                        // CU grant, session record), qstride (>= 4) words apart
 };
 
 // What the leader remembers about a lock it holds: for the ticket mutex, the ticket it
@@ -33,6 +36,9 @@ struct MutexHold {
   uint32_t session;  // SP_MUTEX_COHORT: holders of this XCD before this one since the
                      // cohort took the global lock (0 = this holder took it)
   uint32_t global;   // SP_MUTEX_COHORT: the global ticket the cohort holds
+  uint32_t cu_ticket;   // SP_MUTEX_CU_COHORT: the ticket drawn on this CU
+  uint32_t cu_session;  // SP_MUTEX_CU_COHORT: holders of this CU before this one since the
+                        // CU's cohort took the XCD lock (0 = this holder took it)
 };
 
 // Cohort lock state of `lock` for the XCD with XCC id x (kXccSlots per lock: the XCC id
@@ -56,6 +62,74 @@ __device__ __forceinline__ uint64_t* cohort_grant(const MutexState& s, uint32_t 
       ((size_t)lock * kXccSlots + x) * kCohortLines + 1 + (t & (kCohortGrants - 1));
   return reinterpret_cast<uint64_t*>(s.queue + line * s.qstride);
 }
+
+// CU cohort state of `lock` for the CU with id c (HW_ID bits [15:8], kCuIds values) on the
+// XCD with XCC id x: line 0 the CU's ticket counter, line 1 its grant word (CU turn, bits
+// 0-23, modulo 2^24 | CU session, bits 24-31), line 2 the record of the XCD cohort lock
+// the CU's session holds (words 0-2: local ticket, session, global ticket) and in word 3
+// the count of CU tickets drawn as some waiter last announced it (a lower bound: racing
+// announcements may land out of order).  Grant, record and announcement are stored and
+// loaded at workgroup scope: only workgroups of that CU touch them, and they share the
+// CU's L1, in which a store by one wavefront is seen by the others.
+constexpr uint32_t kCuIds = 256;
+constexpr uint32_t kCuLines = 3;
+__device__ __forceinline__ uint32_t* cu_line(const MutexState& s, uint32_t lock, uint32_t x,
+                                             uint32_t c, uint32_t i) {
+  return s.cuq + ((((size_t)lock * kXccSlots + x) * kCuIds + c) * kCuLines + i) * s.qstride;
+}
+
+namespace detail {
+
+// The XCD cohort lock's two levels, shared by SP_MUTEX_COHORT and SP_MUTEX_CU_COHORT:
+// take XCD x's local ticket, wait for its grant, and queue for the global lock when the
+// grant says the XCD's cohort does not hold it.  Leader only.
+__device__ __forceinline__ bool cohort_acquire(const MutexState& s, uint32_t lock, uint32_t x,
+                                               Wait& w, uint32_t* t, uint32_t* k,
+                                               uint32_t* g) {
+  bool ok = true;
+  *t = add_relaxed(cohort_ticket(s, lock, x), 1);
+  const uint64_t* grant = cohort_grant(s, lock, x, *t);
+  uint64_t v;
+  for (;;) {
+    v = ld_relaxed64(grant);
+    if (((uint32_t)v & kTurnMask) == (*t & kTurnMask)) break;
+    if (!(ok = w.tick())) break;
+  }
+  *k = ((uint32_t)v >> 24) & 0xFF;
+  *g = (uint32_t)(v >> 32);
+  if (ok && *k == 0) {  // the cohort does not hold the global lock: queue for it
+    *g = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
+    const uint32_t* turn = s.turn + (size_t)lock * s.stride;
+    while (ld_relaxed(turn) != *g)
+      if (!(ok = w.tick())) break;
+  }
+  return ok;
+}
+
+// Hands the XCD cohort lock held with local ticket t (session k - 1, global ticket g) on:
+// within the XCD when a later local ticket was drawn (`drawn`, loaded by the caller) and
+// the session may grow, else back to the global queue.  Leader only, after the critical
+// section's stores have completed.
+template <bool FENCED>
+__device__ __forceinline__ void cohort_release(const MutexState& s, uint32_t lock, uint32_t x,
+                                               uint32_t drawn, uint32_t t, uint32_t k,
+                                               uint32_t g) {
+  uint64_t* grant = cohort_grant(s, lock, x, t + 1);  // the next local ticket's slot
+  const uint64_t next_turn = (t + 1) & kTurnMask;
+  if ((int32_t)(drawn - (t + 1)) > 0 && k < s.cohort_bound) {
+    // The next holder runs on this XCD: pass the global lock with the local one.  The
+    // critical section's stores have completed into this XCD's L2, which the next holder
+    // reads through after its own acquire: no writeback.
+    st_relaxed64(grant, ((uint64_t)g << 32) | ((uint64_t)k << 24) | next_turn);
+  } else {
+    uint32_t* turn = s.turn + (size_t)lock * s.stride;
+    if constexpr (FENCED) st_release(turn, g + 1);  // writes back every local holder's stores
+    else st_relaxed(turn, g + 1);
+    st_relaxed64(grant, next_turn);  // session 0: the next local holder queues globally
+  }
+}
+
+}  // namespace detail
 
 // MCS lock node of workgroup w for `lock`: word 0 = next (workgroup + 1, 0 = none), word 1
 // = locked; qlen nodes per lock (one per workgroup of the launch), qstride words apart.
@@ -125,7 +199,8 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
   if (is_leader()) {
     uint32_t* m = s.lockw + (size_t)lock * s.stride;
     Wait w(ctl, (KIND == SP_MUTEX_SLEEP || KIND == SP_MUTEX_RING || KIND == SP_MUTEX_ARRAY ||
-                 KIND == SP_MUTEX_COHORT || KIND == SP_MUTEX_MCS)
+                 KIND == SP_MUTEX_COHORT || KIND == SP_MUTEX_CU_COHORT ||
+                 KIND == SP_MUTEX_MCS)
                     ? s.poll_sleep : 0);
     Backoff bo(s.bo);
     bool ok = true;
@@ -195,27 +270,46 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
       }
       if (hold) hold->ticket = t;
     } else if constexpr (KIND == SP_MUTEX_COHORT) {
-      const uint32_t x = xcc_id();
-      const uint32_t t = add_relaxed(cohort_ticket(s, lock, x), 1);
-      const uint64_t* grant = cohort_grant(s, lock, x, t);
-      uint64_t v;
-      for (;;) {
-        v = ld_relaxed64(grant);
-        if (((uint32_t)v & kTurnMask) == (t & kTurnMask)) break;
-        if (!(ok = w.tick())) break;
-      }
-      uint32_t k = ((uint32_t)v >> 24) & 0xFF, g = (uint32_t)(v >> 32);
-      if (ok && k == 0) {  // the cohort does not hold the global lock: queue for it
-        g = add_relaxed(s.ticket + (size_t)lock * s.stride, 1);
-        const uint32_t* turn = s.turn + (size_t)lock * s.stride;
-        while (ld_relaxed(turn) != g)
-          if (!(ok = w.tick())) break;
-      }
+      uint32_t t, k, g;
+      ok = detail::cohort_acquire(s, lock, xcc_id(), w, &t, &k, &g);
       if (hold) {
         hold->ticket = t;
         hold->session = k;
         hold->global = g;
       }
+    } else if constexpr (KIND == SP_MUTEX_CU_COHORT) {
+      const uint32_t x = xcc_id(), c = cu_in_xcc();
+      const uint32_t tc = add_relaxed(cu_line(s, lock, x, c, 0), 1);
+      const uint32_t* cgrant = cu_line(s, lock, x, c, 1);
+      uint32_t* rec = cu_line(s, lock, x, c, 2);
+      st_cu(rec + 3, tc + 1);  // tell the holder that a later CU ticket was drawn
+      uint32_t v;
+      for (;;) {
+        v = ld_cu(cgrant);
+        if ((v & kTurnMask) == (tc & kTurnMask)) break;
+        if (!(ok = w.tick())) break;
+      }
+      const uint32_t kc = v >> 24;
+      uint32_t t = 0, k = 0, g = 0;
+      if (ok && kc > 0) {
+        // This CU's cohort holds the XCD lock: its record says how, and the previous
+        // holder ran on this CU, whose L1 its stores went through (no acquire).
+        t = ld_cu(rec);
+        k = ld_cu(rec + 1);
+        g = ld_cu(rec + 2);
+      } else if (ok) {
+        ok = detail::cohort_acquire(s, lock, x, w, &t, &k, &g);
+        if constexpr (FENCED) fence_acquire();
+        // for the CU's later holders of this session (complete before the first CU grant)
+        st_cu(rec, t);
+        st_cu(rec + 1, k);
+        st_cu(rec + 2, g);
+      }
+      hold->ticket = t;
+      hold->session = k;
+      hold->global = g;
+      hold->cu_ticket = tc;
+      hold->cu_session = kc;
     } else if constexpr (KIND == SP_MUTEX_MCS) {
       uint32_t* node = mcs_node(s, lock, blockIdx.x);
       st_relaxed(node, 0);      // next: none
@@ -241,7 +335,7 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
         if (!ok || cas_relaxed(m, 0, 1) == 0) break;
       }
     }
-    if constexpr (FENCED) fence_acquire();
+    if constexpr (FENCED && KIND != SP_MUTEX_CU_COHORT) fence_acquire();
     s_ok = ok;
   }
   __syncthreads();
@@ -281,19 +375,31 @@ __device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold
     wave_stores_complete();
     __syncthreads();
     if (!is_leader()) return;
-    const uint32_t t = hold->ticket, k = hold->session + 1, g = hold->global;
-    uint64_t* grant = cohort_grant(s, lock, x, t + 1);  // the next local ticket's slot
-    const uint64_t next_turn = (t + 1) & kTurnMask;
-    if ((int32_t)(drawn - (t + 1)) > 0 && k < s.cohort_bound) {
-      // The next holder runs on this XCD: pass the global lock with the local one.  The
-      // critical section's stores have completed into this XCD's L2 (waited for above),
-      // which the next holder reads through after its own acquire: no writeback.
-      st_relaxed64(grant, ((uint64_t)g << 32) | ((uint64_t)k << 24) | next_turn);
+    detail::cohort_release<FENCED>(s, lock, x, drawn, hold->ticket, hold->session + 1,
+                                   hold->global);
+    return;
+  }
+  if constexpr (KIND == SP_MUTEX_CU_COHORT) {
+    // Whether a later CU ticket was drawn comes from the waiters' announcement in the
+    // CU's L1, not from the ticket counter at memory: no round trip on a CU hand-over (a
+    // stale announcement only ends the CU's session early).
+    const uint32_t x = xcc_id(), c = cu_in_xcc();
+    const uint32_t drawn_c = is_leader() ? ld_cu(cu_line(s, lock, x, c, 2) + 3) : 0;
+    wave_stores_complete();
+    __syncthreads();
+    if (!is_leader()) return;
+    uint32_t* cgrant = cu_line(s, lock, x, c, 1);
+    const uint32_t tc = hold->cu_ticket, kc = hold->cu_session + 1;
+    const uint32_t next_turn = (tc + 1) & kTurnMask;
+    if ((int32_t)(drawn_c - (tc + 1)) > 0 && kc < s.cohort_bound) {
+      // The next holder runs on this CU: it keeps the XCD lock and reads the critical
+      // section's stores through this CU's L1 (they have completed): no cache maintenance.
+      st_cu(cgrant, (kc << 24) | next_turn);
     } else {
-      uint32_t* turn = s.turn + (size_t)lock * s.stride;
-      if constexpr (FENCED) st_release(turn, g + 1);  // writes back every local holder's stores
-      else st_relaxed(turn, g + 1);
-      st_relaxed64(grant, next_turn);  // session 0: the next local holder queues globally
+      const uint32_t drawn = ld_relaxed(cohort_ticket(s, lock, x));
+      detail::cohort_release<FENCED>(s, lock, x, drawn, hold->ticket, hold->session + 1,
+                                     hold->global);
+      st_cu(cgrant, next_turn);  // session 0: the CU's next holder takes the XCD lock
     }
     return;
   }

@@ -29,7 +29,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 BARRIER_KINDS = {"central": 0, "tree": 1, "flag": 2, "xcd": 3, "split": 4}
 MUTEX_KINDS = {"spin_cas": 0, "spin_exch": 1, "spin_backoff": 2, "ticket": 3, "sleep": 4,
-               "ring": 5, "array": 6, "adaptive": 7, "cohort": 8, "mcs": 9}
+               "ring": 5, "array": 6, "adaptive": 7, "cohort": 8, "mcs": 9,
+               "cu_cohort": 10}
 SEM_KINDS = {"spin": 0, "spin_backoff": 1, "ticket": 2, "sleep": 3, "counters": 4,
              "adaptive": 5, "spin_backoff_wait_only": 6, "cohort": 7,
              "array": 8, "chain": 9,

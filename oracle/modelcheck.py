@@ -975,6 +975,147 @@ class ArraySemModel:
         return None
 
 
+class CuCohortLockModel:
+    """CU-cohort lock, with caches: a ticket lock per CU group in front of the XCD-cohort
+    lock (a ticket lock per XCD in front of a global ticket lock); one lock, one data word.
+
+    placement: per agent (xcd, cu), CU ids global; the group of an agent is its CU.  Each
+    group has a ticket counter, an announcement word (the count of tickets drawn as the
+    last announcer saw it: drawing and announcing are separate steps, so announcements can
+    lag and land out of order), a grant (turn, session) and a record of the XCD lock its
+    session holds (local ticket, session); each XCD a local ticket counter and a grant
+    (turn, session); the global lock a ticket and a turn.  Lock: draw and announce a group
+    ticket, wait for its grant; session k > 0: read the record and enter with no cache
+    maintenance; session 0: take the XCD lock (and the global one when the XCD grant says
+    session 0), acquire (the CU's L1 and the XCD's clean L2 lines dropped), write the
+    record.  Unlock: when an announcement shows a later group ticket and k + 1 < B, grant
+    (turn + 1, k + 1) within the group; else hand the XCD lock on (within the XCD when a
+    later local ticket was drawn and its session may grow, without a writeback; else write
+    the XCD's L2 back and advance the global turn), then grant (turn + 1, 0).  Caches: an
+    L1 per CU, shared by the CU's agents (a load goes L1 -> L2 -> memory, a store updates
+    the CU's L1 and dirties the XCD's L2), an L2 per XCD.
+    mutant 'no_acquire': the holder that took the XCD lock keeps its caches;
+    mutant 'group_by_xcd': the groups are the XCDs (a CU id read wrongly), so a pass
+    within a group can cross CUs without an acquire;
+    mutant 'no_waiter_check': pass within the group with no later ticket announced."""
+
+    (DRAW_C, ANN, POLL_C, DRAW_X, POLL_X, DRAW_G, POLL_G, ACQ, CS_LD, CS_ST, REL,
+     DONE) = range(12)
+
+    def __init__(self, placement: tuple, ops: int = 2, B: int = 2, mutant: str | None = None):
+        self.pl, self.ops, self.B, self.mutant = tuple(placement), ops, B, mutant
+        self.n = len(self.pl)
+        self.X = 1 + max(x for x, _ in self.pl)
+        self.NC = 1 + max(c for _, c in self.pl)
+        self.grp = tuple((x if mutant == "group_by_xcd" else c) for x, c in self.pl)
+        self.NG = 1 + max(max(self.grp), self.NC - 1)
+
+    # shared = (gt, gturn, xt (X), xg (X of (turn, session)), ct (NG), ann (NG),
+    #           cg (NG of (turn, session)), rec (NG of (ticket, session)),
+    #           l1 (NC: value or None), l2 (X: (value, dirty) or None), mem,
+    #           inside, done_cs, bad)
+    # local  = (pc, j, tc, kc, tx, kx, tmp)
+    def init(self):
+        X, NG, NC = self.X, self.NG, self.NC
+        sh = (0, 0, (0,) * X, ((0, 0),) * X, (0,) * NG, (0,) * NG, ((0, 0),) * NG,
+              ((0, 0),) * NG, (None,) * NC, (None,) * X, 0, 0, 0, None)
+        return sh, tuple((self.DRAW_C, 0, 0, 0, 0, 0, 0) for _ in range(self.n))
+
+    def done(self, lo):
+        return lo[0] == self.DONE
+
+    @staticmethod
+    def _set(t, i, v):
+        return t[:i] + (v,) + t[i + 1:]
+
+    def step(self, a, sh, lo):
+        gt, gturn, xt, xg, ct, ann, cg, rec, l1, l2, mem, inside, done_cs, bad = sh
+        pc, j, tc, kc, tx, kx, tmp = lo
+        x, cu = self.pl[a]
+        g = self.grp[a]
+        S = self._set
+
+        def out(pc2, **kw):
+            v = dict(gt=gt, gturn=gturn, xt=xt, xg=xg, ct=ct, ann=ann, cg=cg, rec=rec, l1=l1,
+                     l2=l2, mem=mem, inside=inside, done_cs=done_cs, bad=bad, tc=tc, kc=kc,
+                     tx=tx, kx=kx, tmp=tmp, j=j)
+            v.update(kw)
+            return ((v["gt"], v["gturn"], v["xt"], v["xg"], v["ct"], v["ann"], v["cg"],
+                     v["rec"], v["l1"], v["l2"], v["mem"], v["inside"], v["done_cs"], v["bad"]),
+                    (pc2, v["j"], v["tc"], v["kc"], v["tx"], v["kx"], v["tmp"]))
+
+        if pc == self.DRAW_C:
+            return out(self.ANN, ct=S(ct, g, ct[g] + 1), tc=ct[g])
+        if pc == self.ANN:
+            return out(self.POLL_C, ann=S(ann, g, tc + 1))
+        if pc == self.POLL_C:
+            turn, sess = cg[g]
+            if turn != tc:
+                return sh, lo
+            if sess > 0:
+                rt, rk = rec[g]
+                return out(self.CS_LD, kc=sess, tx=rt, kx=rk)
+            return out(self.DRAW_X, kc=0)
+        if pc == self.DRAW_X:
+            return out(self.POLL_X, xt=S(xt, x, xt[x] + 1), tx=xt[x])
+        if pc == self.POLL_X:
+            turn, sess = xg[x]
+            if turn != tx:
+                return sh, lo
+            return out(self.ACQ if sess > 0 else self.DRAW_G, kx=sess)
+        if pc == self.DRAW_G:
+            return out(self.POLL_G, gt=gt + 1, tmp=gt)
+        if pc == self.POLL_G:
+            return out(self.ACQ) if gturn == tmp else (sh, lo)
+        if pc == self.ACQ:
+            if self.mutant != "no_acquire":
+                l1 = S(l1, cu, None)
+                l2 = S(l2, x, l2[x] if l2[x] is not None and l2[x][1] else None)
+            return out(self.CS_LD, l1=l1, l2=l2, rec=S(rec, g, (tx, kx)))
+        if pc == self.CS_LD:
+            v = l1[cu]
+            if v is None:
+                if l2[x] is None:
+                    l2 = S(l2, x, (mem, False))
+                v = l2[x][0]
+                l1 = S(l1, cu, v)
+            return out(self.CS_ST, l1=l1, l2=l2, tmp=v, inside=inside + 1)
+        if pc == self.CS_ST:
+            if inside > 1:
+                bad = bad or "two holders inside"
+            elif tmp != done_cs:
+                bad = bad or f"stale read: {tmp} after {done_cs} sections"
+            return out(self.REL, l1=S(l1, cu, tmp + 1), l2=S(l2, x, (tmp + 1, True)),
+                       inside=inside - 1, done_cs=done_cs + 1, bad=bad)
+        if pc == self.REL:
+            waiter = ann[g] > tc + 1 or self.mutant == "no_waiter_check"
+            nxt = self.DRAW_C if j + 1 < self.ops else self.DONE
+            if waiter and kc + 1 < self.B:
+                return out(nxt, cg=S(cg, g, (tc + 1, kc + 1)), j=j + 1)
+            if xt[x] > tx + 1 and kx + 1 < self.B:
+                xg = S(xg, x, (tx + 1, kx + 1))
+            else:
+                if l2[x] is not None and l2[x][1]:
+                    mem = l2[x][0]
+                    l2 = S(l2, x, (mem, False))
+                gturn = gturn + 1
+                xg = S(xg, x, (tx + 1, 0))
+            return out(nxt, xg=xg, l2=l2, mem=mem, gturn=gturn, cg=S(cg, g, (tc + 1, 0)), j=j + 1)
+        raise AssertionError(pc)
+
+    def check(self, sh, los):
+        return sh[13]
+
+    def final_check(self, sh, los):
+        gt, gturn, xt, xg, ct, ann, cg = sh[:7]
+        if sh[12] != self.n * self.ops:
+            return f"{sh[12]} sections of {self.n * self.ops}"
+        if gturn != gt or any(xg[x][0] != xt[x] for x in range(self.X)) or \
+                any(cg[i][0] != ct[i] for i in range(self.NG)):
+            return "a lock level not released at the end"
+        return None
+
+
 class XcdChainSemModel:
     """The chain semaphore with its units split over per-XCD queues.
 
@@ -1343,7 +1484,10 @@ class XcdBarrierModel:
                                after arriving at the registration barrier, so another agent
                                of the CU can read the rank before it is written (and poll
                                another CU's release line).
-    The release lines are indexed by (XCD, rank of the CU), as in the library."""
+    The release lines are indexed by (XCD, rank of the CU), as in the library.  Flags are
+    words every reader sees once stored; for the release line, which only its CU's agents
+    read, that holds at workgroup scope too (they share the CU's L1), which is how the
+    library stores and polls it."""
 
     (WRITE, COMPLETE, ARRIVE, SCAN, WB, PUB, POLL, ACQ, REL, WAIT_REL, INV_L1, READ,
      REG_X, REG_CU, REG_RANK, REG_RANKST, REG_WB, REG_ARRIVE, REG_POLL, REG_ACQ, REG_READ,

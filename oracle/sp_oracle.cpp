@@ -458,13 +458,14 @@ int or_barrier_threaded(int kind, uint32_t seed, uint32_t N, uint32_t R, uint32_
 // proportion to the distance from the head, 8 cohort lock, 9 MCS queue lock (a linked
 // queue of per-agent nodes: lock exchanges the tail with one's node and, behind a
 // predecessor, links in and waits on one's own node; unlock hands over to the successor
-// or, when none has linked in, swings the tail back to empty with a compare-and-swap).
+// or, when none has linked in, swings the tail back to empty with a compare-and-swap),
+// 10 CU-cohort lock (kind 8 with a ticket lock per CU group in front of each cohort's).
 // Workload: see or_mutex_closed.  An owner word checks mutual exclusion inside every
 // critical section.  Returns 0, or -2 on a mutual-exclusion violation.
 int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uint32_t L,
                       uint32_t W, uint32_t imin, uint32_t imax, uint32_t* words,
                       double* seconds) {
-  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 9) return -1;
+  if (nwg == 0 || L == 0 || W == 0 || kind < 0 || kind > 10) return -1;
   std::vector<Word> lockw(L), ticket(L), turn(L), owner(L);
   for (uint32_t l = 0; l < L; ++l) lockw[l] = 0, ticket[l] = 0, turn[l] = 0, owner[l] = 0;
   // kinds 5 (ring) and 6 (array): Q slots per lock, Q a power of two >= agents
@@ -484,10 +485,54 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
   // lock's tail is lockw (agent + 1, 0 = free)
   std::vector<Word> mnext(kind == 9 ? (size_t)L * nwg : 0), mlocked(mnext.size());
   for (size_t i = 0; i < mnext.size(); ++i) mnext[i] = 0, mlocked[i] = 0;
-  std::vector<Word> lt(kind == 8 ? (size_t)L * kCoh : 0);
+  std::vector<Word> lt(kind == 8 || kind == 10 ? (size_t)L * kCoh : 0);
   std::vector<std::atomic<uint64_t>> grant(lt.size() * kGrants);
   for (size_t i = 0; i < lt.size(); ++i) lt[i] = 0;
   for (auto& g : grant) g = 0;
+  // kind 10 (CU cohort): agent b of cohort b mod kCoh sits in CU group (b / kCoh) mod kCu
+  // of it; per lock and CU group a ticket counter, a grant word (CU turn | CU session <<
+  // 32), the record of the cohort lock the group's session holds (what kind 8's lock
+  // returned) and the announcement of the tickets drawn (a lower bound, stores in any
+  // order); at most kPasses holders of a group in a row.  cu_hold keeps each agent's CU
+  // ticket | CU session << 32 while it holds a lock.
+  constexpr uint32_t kCu = 4;
+  const size_t ncu = kind == 10 ? (size_t)L * kCoh * kCu : 0;
+  std::vector<Word> cut(ncu), cann(ncu);
+  std::vector<std::atomic<uint64_t>> cgrant(ncu), crec(ncu);
+  for (size_t i = 0; i < ncu; ++i) cut[i] = 0, cann[i] = 0, cgrant[i] = 0, crec[i] = 0;
+  std::vector<uint64_t> cu_hold(kind == 10 ? nwg : 0);
+
+  // kind 8's two levels: the cohort's local ticket lock, then the global one unless the
+  // grant says the cohort holds it; returns the local ticket | session read << 32
+  auto cohort_lock = [&](uint32_t l, uint32_t b) -> uint64_t {
+    const size_t c = (size_t)l * kCoh + b % kCoh;
+    const uint32_t my = lt[c].fetch_add(1, std::memory_order_relaxed);
+    uint64_t v;
+    auto& slot = grant[c * kGrants + my % kGrants];
+    while ((uint32_t)(v = slot.load(std::memory_order_acquire)) != my) relax();
+    const uint32_t k = (uint32_t)(v >> 32);
+    if (k == 0) {
+      const uint32_t g = ticket[l].fetch_add(1, std::memory_order_relaxed);
+      while (turn[l].load(std::memory_order_acquire) != g) relax();
+    }
+    return ((uint64_t)k << 32) | my;
+  };
+  auto cohort_unlock = [&](uint32_t l, uint32_t b, uint64_t held) {
+    const size_t c = (size_t)l * kCoh + b % kCoh;
+    const uint32_t my = (uint32_t)held, k = (uint32_t)(held >> 32) + 1;
+    const bool waiter = (int32_t)(lt[c].load(std::memory_order_relaxed) - (my + 1)) > 0;
+    auto& next = grant[c * kGrants + (my + 1) % kGrants];  // the next local ticket's slot
+    if (waiter && k < kPasses) {  // pass the global lock with the local one
+      next.store(((uint64_t)k << 32) | (my + 1), std::memory_order_release);
+    } else {
+      const uint32_t t = turn[l].load(std::memory_order_relaxed);  // only the holder writes
+      turn[l].store(t + 1, std::memory_order_release);
+      next.store(my + 1, std::memory_order_release);  // session 0
+    }
+  };
+  auto cu_of = [&](uint32_t l, uint32_t b) -> size_t {
+    return ((size_t)l * kCoh + b % kCoh) * kCu + (b / kCoh) % kCu;
+  };
 
   // returns the ticket the lock was taken with (ticket, ring and array kinds); cohort:
   // the local ticket, and the session it read in the upper 32 bits
@@ -550,18 +595,20 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
         }
         return 0;
       }
-      case 8: {  // cohort: the local ticket lock, then the global one unless inherited
-        const size_t c = (size_t)l * kCoh + b % kCoh;
-        const uint32_t my = lt[c].fetch_add(1, std::memory_order_relaxed);
+      case 8:
+        return cohort_lock(l, b);
+      case 10: {  // the CU group's ticket lock, then kind 8's unless the group holds it
+        const size_t u = cu_of(l, b);
+        const uint32_t tc = cut[u].fetch_add(1, std::memory_order_relaxed);
+        cann[u].store(tc + 1, std::memory_order_relaxed);
         uint64_t v;
-        auto& slot = grant[c * kGrants + my % kGrants];
-        while ((uint32_t)(v = slot.load(std::memory_order_acquire)) != my) relax();
-        const uint32_t k = (uint32_t)(v >> 32);
-        if (k == 0) {
-          const uint32_t g = ticket[l].fetch_add(1, std::memory_order_relaxed);
-          while (turn[l].load(std::memory_order_acquire) != g) relax();
-        }
-        return ((uint64_t)k << 32) | my;
+        while ((uint32_t)(v = cgrant[u].load(std::memory_order_acquire)) != tc) relax();
+        const uint32_t kc = (uint32_t)(v >> 32);
+        cu_hold[b] = ((uint64_t)kc << 32) | tc;
+        if (kc > 0) return crec[u].load(std::memory_order_relaxed);
+        const uint64_t held = cohort_lock(l, b);
+        crec[u].store(held, std::memory_order_relaxed);  // for the group's later holders
+        return held;
       }
       default:
         for (;;) {
@@ -589,16 +636,18 @@ int or_mutex_threaded(int kind, uint32_t seed, uint32_t nwg, uint64_t total, uin
       return;
     }
     if (kind == 8) {
-      const size_t c = (size_t)l * kCoh + b % kCoh;
-      const uint32_t k = (uint32_t)(held >> 32) + 1;
-      const bool waiter = (int32_t)(lt[c].load(std::memory_order_relaxed) - (my + 1)) > 0;
-      auto& next = grant[c * kGrants + (my + 1) % kGrants];  // the next local ticket's slot
-      if (waiter && k < kPasses) {  // pass the global lock with the local one
-        next.store(((uint64_t)k << 32) | (my + 1), std::memory_order_release);
+      cohort_unlock(l, b, held);
+      return;
+    }
+    if (kind == 10) {
+      const size_t u = cu_of(l, b);
+      const uint32_t tc = (uint32_t)cu_hold[b], kc = (uint32_t)(cu_hold[b] >> 32) + 1;
+      const bool waiter = (int32_t)(cann[u].load(std::memory_order_relaxed) - (tc + 1)) > 0;
+      if (waiter && kc < kPasses) {  // the group's next holder keeps the cohort lock
+        cgrant[u].store(((uint64_t)kc << 32) | (tc + 1), std::memory_order_release);
       } else {
-        const uint32_t t = turn[l].load(std::memory_order_relaxed);  // only the holder writes
-        turn[l].store(t + 1, std::memory_order_release);
-        next.store(my + 1, std::memory_order_release);  // session 0
+        cohort_unlock(l, b, held);
+        cgrant[u].store(tc + 1, std::memory_order_release);  // session 0
       }
       return;
     }

@@ -49,12 +49,14 @@ int main() {
     }
   }
   {  // mutexes: every kind, two locks of three words; 16 agents put two in each of the
-     // cohort lock's eight cohorts, so its local hand-overs run too
-    const uint32_t nwg = 16, L = 2, W = 3;
+     // cohort lock's eight cohorts, so its local hand-overs run too, and 64 two in each
+     // CU group of the CU-cohort lock (8 cohorts x 4 groups)
+    const uint32_t L = 2, W = 3;
     const uint64_t total = 300;
     std::vector<uint32_t> want(L * W), got(L * W);
-    or_mutex_closed(seed, nwg, total, L, W, want.data());
-    for (int kind = 0; kind <= 9; ++kind) {
+    for (int kind = 0; kind <= 10; ++kind) {
+      const uint32_t nwg = kind == 10 ? 64 : 16;
+      or_mutex_closed(seed, nwg, total, L, W, want.data());
       expect(or_mutex_threaded(kind, seed, nwg, total, L, W, 1, 4, got.data(), nullptr) == 0,
              "mutex rc");
       expect(got == want, "mutex words");

@@ -36,7 +36,8 @@ SP_E_RANGE = -6
 BARRIER_KINDS = {"central": 0, "central_split": 1, "tree": 2, "flag": 3, "grid_sync": 4,
                  "xcd": 5, "default": 15}
 MUTEX_KINDS = {"spin_cas": 0, "spin_exch": 1, "spin_backoff": 2, "ticket": 3, "sleep": 4,
-               "ring": 5, "array": 6, "adaptive": 7, "cohort": 8, "mcs": 9, "default": 15}
+               "ring": 5, "array": 6, "adaptive": 7, "cohort": 8, "mcs": 9, "cu_cohort": 10,
+               "default": 15}
 SEM_KINDS = {"spin": 0, "spin_backoff": 1, "ticket": 2, "sleep": 3, "counters": 4,
              "adaptive": 5, "cohort": 6, "array": 7, "chain": 8, "xcd_chain": 9,
              "default": 15}

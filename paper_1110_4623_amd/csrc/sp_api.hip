@@ -225,8 +225,10 @@ int sp_init(int device, sp_ctx** out) {
   ctx->defaults[1][0].kind = SP_MUTEX_SPIN_BACKOFF;
   ctx->defaults[1][0].p.backoff = SP_BACKOFF_PAPER;
   ctx->defaults[1][0].p.backoff_max = 8;
-  // XCD-cohort lock: 0.81 M/s on one lock at 1024, 11.0 M/s on 16 locks at 2048 (array 0.68 / 9.2)
-  ctx->defaults[1][1].kind = SP_MUTEX_COHORT;
+  // CU-cohort lock (the XCD-cohort lock below two contenders per CU and lock): one lock
+  // 1.13 M/s at 2048 workgroups, 1.18 at 1024 (XCD-cohort lock 0.74 / 0.77, ticket 0.65);
+  // 16 locks at 2048 run the XCD-cohort lock, 13.1 M/s (array 9.2)
+  ctx->defaults[1][1].kind = SP_MUTEX_CU_COHORT;
   ctx->defaults[1][1].p.poll_sleep = 0;
   ctx->defaults[1][1].p.cohort_passes = 64;
   // per-XCD chains (K below the XCD count: one set of chains; K above 4096 per XCD: the
@@ -283,7 +285,7 @@ int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p) {
   if (!usable(ctx) || primitive > 2 || bucket > 1) return SP_E_INVAL;
-  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_MCS, SP_SEM_XCD_CHAIN};
+  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_CU_COHORT, SP_SEM_XCD_CHAIN};
   if (kind > max_kind[primitive]) return SP_E_INVAL;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));

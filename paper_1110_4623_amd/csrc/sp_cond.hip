@@ -202,6 +202,7 @@ int bb_run(sp_ctx* ctx, uint32_t mutex_kind, uint32_t nwg, uint32_t producers, u
   ms.qlen = L.Q;
   ms.qstride = L.qstride;
   ms.cohort_bound = q.cohort_passes;
+  ms.cuq = nullptr;
   uint32_t* cond = base + L.mutex_words;
   sp::CondState nf{cond + C_NF_WAITERS * kLine, cond + C_NF_SIGNALS * kLine, q.poll_sleep};
   sp::CondState ne{cond + C_NE_WAITERS * kLine, cond + C_NE_SIGNALS * kLine, q.poll_sleep};

@@ -138,5 +138,13 @@ inline uint32_t bucket_of(uint32_t contenders) { return contenders >= 64 ? 1u : 
 // to 32 workgroups and the per-XCD barrier from 48 on (1.75 / 2.39 / 3.88 against 2.72 /
 // 2.72 / 2.85 us per round at 16 / 32 / 48, 256 lanes), so the high bucket starts at 40.
 inline uint32_t barrier_bucket_of(uint32_t nwg) { return nwg >= 40 ? 1u : 0u; }
+// A default mutex whose bucket names the CU-cohort lock runs it only where a lock has at
+// least two contenders per CU on average; below that few hand-overs stay within a CU and
+// the XCD-cohort lock is faster (one lock, 16 words, M acquisitions/s, XCD-cohort
+// against CU-cohort: 256 workgroups 0.78 / 0.71, 512 0.78 / 0.93, 1024 0.77 / 1.18, 2048
+// 0.74 / 1.13; 2048 workgroups on 8 locks 6.58 / 6.91, on 16 locks 13.1 / 12.7).
+inline bool cu_cohort_pays(uint64_t nwg, uint64_t nlocks, uint64_t cu_count) {
+  return nwg >= 2 * nlocks * cu_count;
+}
 
 }  // namespace spi

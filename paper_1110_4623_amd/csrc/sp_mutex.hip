@@ -21,6 +21,20 @@ struct sp_mutex {
 
 namespace {
 
+// The cohort locks' state: lines per lock (each XCC id's ticket and grant slots, and for
+// the CU cohort lock each CU's ticket, grant and session record), and the words between
+// lines (64-bit grant words need two, the CU cohort's three-word record four).
+uint32_t cohort_lines(uint32_t kind) {
+  const uint32_t xcd = sp::kCohortLines * sp::kXccSlots;
+  return kind == SP_MUTEX_CU_COHORT ? xcd + sp::kXccSlots * sp::kCuIds * sp::kCuLines : xcd;
+}
+uint32_t cohort_stride(uint32_t kind, uint32_t sw) {
+  return std::max<uint32_t>(sw, kind == SP_MUTEX_CU_COHORT ? 4 : 2);
+}
+uint64_t cohort_words(uint32_t kind, uint32_t nlocks, uint32_t sw) {
+  return (uint64_t)nlocks * cohort_lines(kind) * cohort_stride(kind, sw);
+}
+
 // With `owner` set, the leader swaps its id into the lock's owner word on entry and
 // back out on exit; any other value seen means two workgroups were inside at once.
 template <int KIND, bool FENCED>
@@ -74,6 +88,7 @@ const void* mutex_kernel_f(uint32_t kind) {
     case SP_MUTEX_ADAPTIVE: return (const void*)k_mutex<SP_MUTEX_ADAPTIVE, FENCED>;
     case SP_MUTEX_COHORT: return (const void*)k_mutex<SP_MUTEX_COHORT, FENCED>;
     case SP_MUTEX_MCS: return (const void*)k_mutex<SP_MUTEX_MCS, FENCED>;
+    case SP_MUTEX_CU_COHORT: return (const void*)k_mutex<SP_MUTEX_CU_COHORT, FENCED>;
     default: return nullptr;
   }
 }
@@ -91,7 +106,7 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
   if (!spi::usable(ctx) || !out || nlocks == 0 || words_per_lock == 0 || nlocks > (1u << 20) ||
       words_per_lock > (1u << 16))
     return SP_E_INVAL;
-  if (kind > SP_MUTEX_MCS && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_MUTEX_CU_COHORT && kind != SP_MUTEX_DEFAULT) return SP_E_INVAL;
   *out = nullptr;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));
@@ -112,14 +127,21 @@ int sp_mutex_create(sp_ctx* ctx, uint32_t kind, uint32_t nlocks, uint32_t words_
   // The cohort lock's state depends only on the lock count and padding: allocate it now
   // (for a DEFAULT mutex when a built-in default is the cohort lock), so that even the
   // first run can be recorded into a graph.
-  uint32_t cohort_sw = 0;
-  if (kind == SP_MUTEX_COHORT) cohort_sw = spi::stride_words(q);
-  for (int b = 0; b < 2 && kind == SP_MUTEX_DEFAULT; ++b)
-    if (ctx->defaults[1][b].kind == SP_MUTEX_COHORT)
-      cohort_sw = std::max(cohort_sw, spi::stride_words(ctx->defaults[1][b].p));
-  if (cohort_sw) {
-    const uint64_t words =
-        (uint64_t)nlocks * sp::kCohortLines * sp::kXccSlots * std::max<uint32_t>(cohort_sw, 2);
+  uint64_t words = 0;
+  if (kind == SP_MUTEX_COHORT || kind == SP_MUTEX_CU_COHORT)
+    words = cohort_words(kind, nlocks, spi::stride_words(q));
+  for (int b = 0; b < 2 && kind == SP_MUTEX_DEFAULT; ++b) {
+    const sp_default_entry& d = ctx->defaults[1][b];
+    uint32_t dk = d.kind;
+    // the CU-cohort lock runs only with two contenders per CU and lock, which a grid of
+    // at most maxThreadsPerMultiProcessor / 64 workgroups per CU may not reach
+    const uint64_t max_wg = (uint64_t)ctx->cu_count * (ctx->prop.maxThreadsPerMultiProcessor / 64);
+    if (dk == SP_MUTEX_CU_COHORT && !spi::cu_cohort_pays(max_wg, nlocks, ctx->cu_count))
+      dk = SP_MUTEX_COHORT;
+    if (dk == SP_MUTEX_COHORT || dk == SP_MUTEX_CU_COHORT)
+      words = std::max(words, cohort_words(dk, nlocks, spi::stride_words(d.p)));
+  }
+  if (words) {
     if (e == hipSuccess && words <= (1ull << 28)) {
       e = hipMalloc(&m->d_queue, words * sizeof(uint32_t));
       if (e == hipSuccess) m->queue_words = words;
@@ -167,10 +189,12 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
     q = d.p;
     q.timeout_ms = t;
     q.coherent_cs = m->p.coherent_cs;  // a property of the caller's critical sections
+    if (kind == SP_MUTEX_CU_COHORT && !spi::cu_cohort_pays(nwg, m->nlocks, ctx->cu_count))
+      kind = SP_MUTEX_COHORT;
   }
   if (kind == SP_MUTEX_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) q.backoff = SP_BACKOFF_EXP;
   if (kind == SP_MUTEX_SPIN_CAS || kind == SP_MUTEX_SLEEP || kind == SP_MUTEX_ADAPTIVE ||
-      kind == SP_MUTEX_MCS)
+      kind == SP_MUTEX_MCS || kind == SP_MUTEX_CU_COHORT)
     q.backoff = SP_BACKOFF_NONE;
   const void* kern = mutex_kernel(kind, q.coherent_cs != 0);
   if (!kern) return SP_E_INVAL;
@@ -188,8 +212,9 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
   ms.qlen = 1;
   ms.qstride = 1;
   ms.cohort_bound = q.cohort_passes;
+  ms.cuq = nullptr;
   if (kind == SP_MUTEX_RING || kind == SP_MUTEX_ARRAY || kind == SP_MUTEX_COHORT ||
-      kind == SP_MUTEX_MCS) {
+      kind == SP_MUTEX_MCS || kind == SP_MUTEX_CU_COHORT) {
     // The ring needs a slot per contender (each workgroup has at most one arrival
     // outstanding); the array lock is correct with any number and polls one line each;
     // the cohort lock keeps kCohortLines lines per lock and XCC id (ticket, 64-bit grant
@@ -198,11 +223,13 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
     uint32_t Q = 64;
     while (Q < nwg) Q <<= 1;
     if (kind == SP_MUTEX_COHORT) Q = sp::kCohortLines * sp::kXccSlots;
+    if (kind == SP_MUTEX_CU_COHORT) Q = cohort_lines(kind);
     if (kind == SP_MUTEX_MCS) Q = nwg;
     ms.qlen = Q;
     ms.qstride = kind == SP_MUTEX_RING ? 1 : sw;  // ring entries packed, others padded
     if ((kind == SP_MUTEX_COHORT || kind == SP_MUTEX_MCS) && ms.qstride < 2)
       ms.qstride = 2;  // 64-bit grant words; an MCS node's two words
+    if (kind == SP_MUTEX_CU_COHORT) ms.qstride = cohort_stride(kind, sw);
     const uint64_t words = (uint64_t)m->nlocks * Q * ms.qstride;
     if (words > (1ull << 28)) return SP_E_INVAL;  // 1 GiB of slots at most
     if (words > m->queue_words) {
@@ -215,6 +242,8 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
       m->queue_words = words;
     }
     ms.queue = m->d_queue;
+    if (kind == SP_MUTEX_CU_COHORT)  // the CU cohorts' lines follow the XCD cohorts'
+      ms.cuq = ms.queue + (uint64_t)m->nlocks * sp::kCohortLines * sp::kXccSlots * ms.qstride;
     SP_CHECK(spi::fill_u32(ctx, m->d_queue, words, 0, s));
   }
   SP_CHECK(spi::fill_u32(ctx, m->d_state, m->state_words, 0, s));

@@ -167,7 +167,8 @@ def ceilings(ctx, rows) -> dict:
 
 MUTEX_VARIANTS = [("spin_cas", {}), ("spin_backoff", {"backoff": "exp"}),
                   ("spin_backoff", {"backoff": "paper"}), ("ticket", {}), ("sleep", {}),
-                  ("ring", {}), ("array", {}), ("adaptive", {}), ("cohort", {}), ("mcs", {})]
+                  ("ring", {}), ("array", {}), ("adaptive", {}), ("cohort", {}), ("mcs", {}),
+                  ("cu_cohort", {})]
 
 
 def mutex(ctx, budget_s: float = 0.3, lanes: int = 256, seed: int = 42, quick: bool = False,

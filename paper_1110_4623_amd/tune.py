@@ -103,6 +103,7 @@ def mutex_candidates():
     out += [("mcs", {"poll_sleep": ps}) for ps in (0, 1)]
     out += [("cohort", {"poll_sleep": ps, "cohort_passes": cp}) for ps in (0, 4)
             for cp in (16, 64)]
+    out += [("cu_cohort", {"poll_sleep": 0, "cohort_passes": cp}) for cp in (16, 64)]
     return out
 
 

@@ -21,8 +21,11 @@ def test_default_barrier(ctx, nwg):
     assert (chk == oracle.barrier_closed(9, nwg, 500)).all()
 
 
-@pytest.mark.parametrize("nwg", [16, 1024])
+@pytest.mark.parametrize("nwg", [16, 256, 1024, 2048])
 def test_default_mutex(ctx, nwg):
+    """The default mutex at low contention (spin lock with backoff), at one contender per
+    CU (the XCD-cohort lock) and at four and eight (the CU-cohort lock): exact counts, no
+    two holders at once."""
     import paper_1110_4623_amd as sp
     announce("default mutex", nwg)
     m = sp.Mutex(ctx, "default", 1, 16, verify=1)

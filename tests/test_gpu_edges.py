@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 BARRIERS = ["central", "central_split", "tree", "flag", "xcd", "grid_sync"]
 MUTEXES = ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep", "ring", "array",
-           "adaptive", "cohort", "mcs"]
+           "adaptive", "cohort", "mcs", "cu_cohort"]
 SEMS = ["spin", "spin_backoff", "ticket", "sleep", "counters", "adaptive", "cohort", "array",
         "chain"]
 

@@ -10,7 +10,7 @@ from conftest import announce
 pytestmark = pytest.mark.gpu
 
 KINDS = ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep", "ring", "array", "adaptive",
-         "cohort", "mcs"]
+         "cohort", "mcs", "cu_cohort"]
 
 
 def _run(ctx, kind, nwg, lanes, total, L, W, delay, seed, **params):
@@ -48,13 +48,14 @@ def test_full_size_single_lock(ctx, kind):
     # (ticket, ring, array) run all 2^20 acquisitions; the spin and polling locks hand the
     # lock over far more slowly with 2048 contenders (every waiter hammers the lock word),
     # so they run 2^14 acquisitions at the same contention.
-    total = 1 << 20 if kind in ("ticket", "ring", "array", "adaptive", "cohort", "mcs") else 1 << 14
+    total = 1 << 20 if kind in ("ticket", "ring", "array", "adaptive", "cohort", "mcs",
+                                "cu_cohort") else 1 << 14
     words, st, fin = _run(ctx, kind, 2048, 256, total, 1, 16, 1000, 0xC0FFEE)
     assert (words == total).all()
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_backoff", "sleep", "ticket", "array", "ring",
-                                  "cohort", "mcs"])
+                                  "cohort", "mcs", "cu_cohort"])
 @pytest.mark.parametrize("L,W", [(16, 256), (256, 16)])
 def test_full_size_many_locks(ctx, kind, L, W):
     total, seed = 1 << 20, 42
@@ -107,24 +108,27 @@ def test_coherent_critical_sections_full_size_ticket(ctx):
           f"coherent {total / st_c['kernel_ms'] * 1e3:.3e} acq/s", flush=True)
 
 
+@pytest.mark.parametrize("kind", ["cohort", "cu_cohort"])
 @pytest.mark.parametrize("passes", [1, 2, 64, 255])
 @pytest.mark.parametrize("L,W,delay", [(1, 16, 1000), (1, 256, 0), (16, 256, 100)])
-def test_cohort_local_hand_overs(ctx, passes, L, W, delay):
+def test_cohort_local_hand_overs(ctx, kind, passes, L, W, delay):
     """The cohort lock hands the lock to a holder of the same XCD without the L2
-    writeback: at 2048 contenders most hand-overs are local, and the counts (W words
+    writeback, the CU-cohort lock also to a holder of the same CU without any cache
+    maintenance: at 2048 contenders most hand-overs are local, and the counts (W words
     spread over eight lines at W = 256) and the owner check stay exact for any bound."""
     total, seed = 1 << 18, 5
-    words, st, _ = _run(ctx, "cohort", 2048, 256, total, L, W, delay, seed,
+    words, st, _ = _run(ctx, kind, 2048, 256, total, L, W, delay, seed,
                         cohort_passes=passes, verify=1)
     assert st["device_error"] == 0
     assert (words == oracle.mutex_closed(seed, 2048, total, L, W)).all()
 
 
+@pytest.mark.parametrize("kind", ["cohort", "cu_cohort"])
 @pytest.mark.parametrize("pad", [4, 4096])
-def test_cohort_padding_and_coherent(ctx, pad):
+def test_cohort_padding_and_coherent(ctx, kind, pad):
     total, seed = 1 << 16, 9
     for coherent in (0, 1):
-        words, st, _ = _run(ctx, "cohort", 1024, 128, total, 4, 32, 100, seed, pad_bytes=pad,
+        words, st, _ = _run(ctx, kind, 1024, 128, total, 4, 32, 100, seed, pad_bytes=pad,
                             coherent_cs=coherent, verify=1)
         assert st["device_error"] == 0
         assert (words == oracle.mutex_closed(seed, 1024, total, 4, 32)).all()

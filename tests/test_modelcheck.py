@@ -4,7 +4,7 @@ tests that pin the checker itself: each planted mistake must be caught (CPU only
 import pytest
 
 from oracle.modelcheck import (ArraySemModel, BarrierModel, CohortLockModel, CohortSemModel,
-                               CondModel, FASemModel, MCSLockModel, MutexModel,
+                               CondModel, CuCohortLockModel, FASemModel, MCSLockModel, MutexModel,
                                QueueLockModel, SpinSemModel, WeightedSemModel,
                                XcdBarrierModel, XcdChainSemModel, explore)
 
@@ -205,6 +205,47 @@ def test_cohort_lock_grant_slots_shared(n, ops, C, B):
 
 def test_cohort_lock_grant_into_own_slot_deadlocks():
     r = explore(CohortLockModel(3, 2, C=1, B=3, mutant="own_slot", G=2))
+    assert r.deadlock
+
+
+# ---- the CU-cohort lock, with an L1 per CU and an L2 per XCD ------------------------------
+
+# (xcd, cu) per agent: agents 0 and 1 share CU 0 of XCD 0, agent 2 is on CU 1 of XCD 0,
+# agent 3 on CU 2 of XCD 1.  So hand-overs within a CU, between CUs of an XCD and between
+# XCDs all occur.
+CU3 = ((0, 0), (0, 0), (0, 1))
+CU4 = ((0, 0), (0, 0), (0, 1), (1, 2))
+
+
+@pytest.mark.parametrize("pl,ops,B", [(CU3, 2, 2), (CU3, 2, 3), (CU4, 1, 2), (CU4, 1, 3)])
+def test_cu_cohort_lock_correct(pl, ops, B):
+    """Mutual exclusion, no stale read of the guarded word through any L1 or L2, every
+    acquisition completes and every level of the lock ends released, on all interleavings:
+    a holder that inherits the XCD lock within its CU reads through the L1 the previous
+    holder's stores went through, with no acquire."""
+    r = explore(CuCohortLockModel(pl, ops, B))
+    assert r.ok, r.violation
+
+
+@pytest.mark.slow
+def test_cu_cohort_lock_correct_two_xcds_twice():
+    r = explore(CuCohortLockModel(CU4, 2, 2))
+    assert r.ok and r.states > 10 ** 6, (r.states, r.violation)
+
+
+@pytest.mark.parametrize("mutant,pl,ops,B", [("no_acquire", CU3, 2, 2),
+                                             ("group_by_xcd", CU3, 2, 2),
+                                             ("group_by_xcd", ((0, 0), (0, 1)), 2, 2)])
+def test_cu_cohort_lock_cache_mutants_read_stale(mutant, pl, ops, B):
+    """Without the acquire when the XCD lock is taken, or with groups that span CUs (a
+    hand-over within the group then skips the acquire between two L1s), a holder reads a
+    stale copy of the word."""
+    r = explore(CuCohortLockModel(pl, ops, B, mutant))
+    assert not r.ok and "stale" in r.violation
+
+
+def test_cu_cohort_lock_pass_without_waiter_deadlocks():
+    r = explore(CuCohortLockModel(CU3, 1, 3, "no_waiter_check"))
     assert r.deadlock
 
 

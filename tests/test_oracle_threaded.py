@@ -31,7 +31,7 @@ def test_barrier_per_xcd_protocol_at_full_grid():
 
 
 @pytest.mark.parametrize("kind", ["spin_cas", "spin_exch", "spin_backoff", "ticket", "sleep",
-                                  "ring", "array", "adaptive", "cohort", "mcs"])
+                                  "ring", "array", "adaptive", "cohort", "mcs", "cu_cohort"])
 @pytest.mark.parametrize("L,W", [(1, 1), (1, 16), (3, 4)])
 def test_mutex_threaded_matches_closed(kind, L, W):
     seed, nwg, total = 0xC0FFEE, 8, 3000
@@ -46,6 +46,17 @@ def test_cohort_mutex_threaded_with_local_passes(L):
     agents are ever inside together (the owner check)."""
     seed, nwg, total = 11, 32, 6400
     words, rc, _ = oracle.mutex_threaded("cohort", seed, nwg, total, L, 8)
+    assert rc == 0
+    assert (words == oracle.mutex_closed(seed, nwg, total, L, 8)).all()
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_cu_cohort_mutex_threaded_with_cu_passes(L):
+    """128 agents, four in each CU group of each of the 8 cohorts: hand-overs within a group
+    (keeping the cohort lock), within a cohort and across cohorts all happen; counts stay
+    exact and no two agents are ever inside together (the owner check)."""
+    seed, nwg, total = 13, 128, 12800
+    words, rc, _ = oracle.mutex_threaded("cu_cohort", seed, nwg, total, L, 8)
     assert rc == 0
     assert (words == oracle.mutex_closed(seed, nwg, total, L, 8)).all()
 

@@ -45,7 +45,8 @@ def test_candidate_lists_cover_every_kind():
                                                           "flag", "tree"}
     assert {k for k, _ in tune.mutex_candidates()} == {"spin_cas", "spin_exch", "spin_backoff",
                                                         "ticket", "sleep", "ring", "array",
-                                                        "adaptive", "cohort", "mcs"}
+                                                        "adaptive", "cohort", "mcs",
+                                                        "cu_cohort"}
     assert {k for k, _ in tune.semaphore_candidates()} == {"spin", "spin_backoff", "ticket",
                                                             "sleep", "counters", "adaptive",
                                                             "cohort", "array", "chain",
