@@ -54,7 +54,8 @@ CURVE_NWG, CURVE_OPS = (64, 256, 1024), 1 << 18
 SEM_KS = (1, 4, 32, 256)
 # read-modify-writes per wait/post pair on each semaphore kind's busiest contended word
 SEM_RMW_PER_PAIR = {"spin": 4, "spin_backoff": 4, "ticket": 2, "sleep": 2, "cohort": 2,
-                    "counters": 1, "adaptive": 1, "array": 1, "chain": 1, "xcd_chain": 1}
+                    "counters": 1, "adaptive": 1, "array": 1, "chain": 1, "xcd_chain": 1,
+                    "cu_lock": 1}
 SERVE_RATE, SERVE_N, SERVE_NWG = 1e5, 200_000, 1024
 
 

@@ -130,6 +130,9 @@ enum sp_sem_kind {
                            /* slots and chains; a post skips the L2 writeback, the next */
                            /* holder of its chain running on the same XCD.  XCD count <= */
                            /* K <= 4096 x XCD count; units do not move between XCDs     */
+  SP_SEM_CU_LOCK = 10,     /* K = 1 only: the binary semaphore run as the CU-cohort lock */
+                           /* (SP_MUTEX_CU_COHORT): a unit passed between workgroups of  */
+                           /* one CU goes through the CU's L1 with no cache maintenance  */
   SP_SEM_DEFAULT = 15
 };
 
@@ -266,7 +269,8 @@ void sp_params_default(sp_params* p);
  * per-XCD with 64 stamp copies (high); mutex spin with the paper's backoff, I_max 8
  * (low) and the CU-cohort lock (high; a run with fewer than two workgroups per CU and
  * lock runs the XCD-cohort lock with the same parameters instead); semaphore the per-XCD
- * chains (both; outside their range of K the chain kind, then the array kind).          */
+ * chains (both; outside their range of K the chain kind, then the array kind; K = 1 with
+ * at least two workgroups per CU SP_SEM_CU_LOCK).                                       */
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p);
 /* Reads back what *_DEFAULT resolves to for a primitive class and bucket (as above):
@@ -382,7 +386,9 @@ int sp_mutex_run(sp_mutex* m, uint32_t nwg, uint32_t lanes, uint64_t total_acq,
  * Errors: SP_E_INVAL (K == 0; SP_SEM_CHAIN with K > 4096; SP_SEM_XCD_CHAIN with K below
  * the XCD count or above 4096 per XCD), SP_E_HIP.  A SP_SEM_DEFAULT semaphore whose
  * bucket names one of these runs the next kind whose range K is in: SP_SEM_XCD_CHAIN,
- * then SP_SEM_CHAIN, then SP_SEM_ARRAY.                                                  */
+ * then SP_SEM_CHAIN, then SP_SEM_ARRAY; at K = 1 SP_SEM_CHAIN gives way to
+ * SP_SEM_CU_LOCK in a run with at least two workgroups per CU.  SP_SEM_CU_LOCK needs
+ * K = 1 (else SP_E_INVAL).                                                             */
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out);
 int sp_sem_destroy(sp_sem* s);
 /* Workload: total_pairs wait/post pairs split over nwg workgroups as in sp_mutex_run.

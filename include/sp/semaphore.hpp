@@ -3,6 +3,7 @@
 #pragma once
 
 #include "atomics.hpp"
+#include "mutex.hpp"
 
 namespace sp {
 
@@ -41,7 +42,27 @@ struct SemHold {
   uint32_t pass;      // SP_SEM_COHORT: local hand-overs of the unit held, in a row;
                       // SP_SEM_XCD_CHAIN: the queue the unit belongs to
   uint64_t ticket;    // SP_SEM_CHAIN, SP_SEM_XCD_CHAIN: the ticket the unit was taken with
+  MutexHold lock;     // SP_SEM_CU_LOCK: what the lock's unlock needs
 };
+
+// SP_SEM_CU_LOCK: K = 1 makes the semaphore a binary one, i.e. a lock, run here as the
+// CU-cohort lock.  Its state sits in the semaphore's memory: the global ticket and turn on
+// the ticket / turn lines, the XCD cohorts' lines and then the CU cohorts' lines in the
+// queue memory, cq_stride (>= 4) words apart.
+__device__ __forceinline__ MutexState cu_lock_state(const SemState& s) {
+  MutexState m{};
+  m.stride = 0;  // one lock
+  m.poll_sleep = s.poll_sleep;
+  m.ticket = s.ticket;
+  m.turn = s.turn;
+  m.queue = s.cq;
+  m.qlen = 1;
+  m.qstride = s.cq_stride;
+  m.cohort_bound = s.cohort_bound;
+  m.bo = s.bo;
+  m.cuq = s.cq + (size_t)kXccSlots * kCohortLines * s.cq_stride;
+  return m;
+}
 
 // ---- cohort semaphore queues -------------------------------------------------------------
 constexpr uint32_t kXccQueues = 16;  // the XCC id register has four bits
@@ -219,6 +240,8 @@ __device__ __forceinline__ bool cq_grant(const SemState& s, uint32_t y, uint32_t
 // invalidation and post the release writeback.
 template <int KIND, bool FENCED = true>
 __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = nullptr) {
+  if constexpr (KIND == SP_SEM_CU_LOCK)
+    return mutex_lock<SP_MUTEX_CU_COHORT, FENCED>(cu_lock_state(s), 0, ctl, &hold->lock);
   __shared__ uint32_t s_ok;
   if (is_leader()) {
     bool ok = true;
@@ -348,6 +371,10 @@ __device__ bool sem_wait(const SemState& s, const Ctl& ctl, SemHold* hold = null
 // null); other kinds ignore it.
 template <int KIND, bool FENCED = true>
 __device__ bool sem_post(const SemState& s, const Ctl& ctl, const SemHold* hold = nullptr) {
+  if constexpr (KIND == SP_SEM_CU_LOCK) {
+    mutex_unlock<SP_MUTEX_CU_COHORT, FENCED>(cu_lock_state(s), 0, &hold->lock, &ctl);
+    return true;
+  }
   __shared__ uint32_t s_ok;
   wave_stores_complete();
   __syncthreads();

@@ -39,7 +39,7 @@ MUTEX_KINDS = {"spin_cas": 0, "spin_exch": 1, "spin_backoff": 2, "ticket": 3, "s
                "ring": 5, "array": 6, "adaptive": 7, "cohort": 8, "mcs": 9, "cu_cohort": 10,
                "default": 15}
 SEM_KINDS = {"spin": 0, "spin_backoff": 1, "ticket": 2, "sleep": 3, "counters": 4,
-             "adaptive": 5, "cohort": 6, "array": 7, "chain": 8, "xcd_chain": 9,
+             "adaptive": 5, "cohort": 6, "array": 7, "chain": 8, "xcd_chain": 9, "cu_lock": 10,
              "default": 15}
 BACKOFF = {"none": 0, "paper": 1, "exp": 2}
 BACKOFF_UNIT = {"sleep": 0, "load": 1}

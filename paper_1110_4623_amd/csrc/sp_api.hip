@@ -285,7 +285,7 @@ int sp_device_info_get(const sp_ctx* ctx, sp_device_info* out) {
 int sp_set_default(sp_ctx* ctx, uint32_t primitive, uint32_t bucket, uint32_t kind,
                    const sp_params* p) {
   if (!usable(ctx) || primitive > 2 || bucket > 1) return SP_E_INVAL;
-  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_CU_COHORT, SP_SEM_XCD_CHAIN};
+  const uint32_t max_kind[3] = {SP_BARRIER_XCD, SP_MUTEX_CU_COHORT, SP_SEM_CU_LOCK};
   if (kind > max_kind[primitive]) return SP_E_INVAL;
   sp_params q;
   SP_CHECK(spi::normalize(ctx, p, &q));

@@ -148,6 +148,7 @@ const void* sem_kernel_f(uint32_t kind) {
     case SP_SEM_ARRAY: return (const void*)k_sem<SP_SEM_ARRAY, FENCED>;
     case SP_SEM_CHAIN: return (const void*)k_sem<SP_SEM_CHAIN, FENCED>;
     case SP_SEM_XCD_CHAIN: return (const void*)k_sem<SP_SEM_XCD_CHAIN, FENCED>;
+    case SP_SEM_CU_LOCK: return (const void*)k_sem<SP_SEM_CU_LOCK, FENCED>;
     default: return nullptr;
   }
 }
@@ -168,7 +169,8 @@ extern "C" {
 
 int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp_sem** out) {
   if (!spi::usable(ctx) || !out || K == 0 || K >= (1u << 30)) return SP_E_INVAL;
-  if (kind > SP_SEM_XCD_CHAIN && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  if (kind > SP_SEM_CU_LOCK && kind != SP_SEM_DEFAULT) return SP_E_INVAL;
+  if (kind == SP_SEM_CU_LOCK && K != 1) return SP_E_INVAL;  // a binary semaphore
   if (kind == SP_SEM_CHAIN && K > kCohortSlots) return SP_E_INVAL;  // a slot per chain at least
   if (kind == SP_SEM_XCD_CHAIN && !xchain_fits(ctx, K)) return SP_E_INVAL;
   *out = nullptr;
@@ -186,10 +188,11 @@ int sp_sem_create(sp_ctx* ctx, uint32_t kind, uint32_t K, const sp_params* p, sp
     e = hipMalloc(&s->d_owner, (size_t)K * kOwnerWords * sizeof(uint32_t));
   if (e == hipSuccess && (kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY ||
                           kind == SP_SEM_CHAIN || kind == SP_SEM_XCD_CHAIN ||
-                          kind == SP_SEM_DEFAULT)) {
+                          kind == SP_SEM_CU_LOCK || kind == SP_SEM_DEFAULT)) {
     // queues for the cohort, array and chain kinds (a DEFAULT semaphore may resolve to
     // any of them): allocated now, so that every run can be recorded into a graph
-    s->cq_stride = std::max<uint32_t>(2, spi::stride_words(q));
+    // even, for the 64-bit slots; at least 4 for the CU-cohort lock's session record
+    s->cq_stride = std::max<uint32_t>(4, spi::stride_words(q));
     s->cq_words = (uint64_t)sp::kXccQueues * (2 + kCohortSlots) * s->cq_stride;
     e = hipMalloc(&s->d_cq, s->cq_words * sizeof(uint32_t));
   }
@@ -241,6 +244,10 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
     // range the next kind (per-XCD chains, one set of chains, the array kind)
     if (kind == SP_SEM_XCD_CHAIN && !xchain_fits(ctx, sem->K)) kind = SP_SEM_CHAIN;
     if (kind == SP_SEM_CHAIN && sem->K > kCohortSlots) kind = SP_SEM_ARRAY;
+    // K = 1 with at least two workgroups per CU: the CU-cohort lock (2048 workgroups,
+    // holds U[0, 2000] clocks: 0.76 against 0.59 M pairs/s for one chain, fenced)
+    if (kind == SP_SEM_CHAIN && sem->K == 1 && spi::cu_cohort_pays(nwg, 1, ctx->cu_count))
+      kind = SP_SEM_CU_LOCK;
   }
   if (kind == SP_SEM_SPIN_BACKOFF && q.backoff == SP_BACKOFF_NONE) {
     // No policy chosen: exponential, capped at 8192 units.  With posts retrying at once,
@@ -271,14 +278,16 @@ int sp_sem_run(sp_sem* sem, uint32_t nwg, uint32_t lanes, uint64_t total_pairs,
   ss.cohort_bound = q.cohort_passes;
   ss.chain_len = sem->K <= kCohortSlots ? kCohortSlots / sem->K * sem->K : kCohortSlots;
   const bool queued = kind == SP_SEM_COHORT || kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN ||
-                      kind == SP_SEM_XCD_CHAIN;
+                      kind == SP_SEM_XCD_CHAIN || kind == SP_SEM_CU_LOCK;
   if (queued && !sem->d_cq) return SP_E_INVAL;
   SP_CHECK(spi::fill_u32(ctx, base, sem->state_words, 0, s));
   // the queues a run uses: one per XCD (cohort, per-XCD chains) or queue 0 (array, chain)
   const uint32_t nq = kind == SP_SEM_ARRAY || kind == SP_SEM_CHAIN ? 1u : ss.cq_n;
-  if (queued)
-    SP_CHECK(spi::fill_u32(ctx, sem->d_cq, (uint64_t)nq * (2 + kCohortSlots) * sem->cq_stride,
-                           0, s));
+  const uint64_t cu_lock_lines =
+      (uint64_t)sp::kXccSlots * (sp::kCohortLines + sp::kCuIds * sp::kCuLines);
+  const uint64_t qwords = kind == SP_SEM_CU_LOCK ? cu_lock_lines * sem->cq_stride
+                                                 : (uint64_t)nq * (2 + kCohortSlots) * sem->cq_stride;
+  if (queued) SP_CHECK(spi::fill_u32(ctx, sem->d_cq, qwords, 0, s));
   if (out_data) {
     SP_CHECK(spi::fill_u32(ctx, out_data, sem->K, 0, s));
     if (sem->K > 1) SP_CHECK(spi::fill_u32(ctx, sem->d_owner, (uint64_t)sem->K * kOwnerWords, 0, s));

@@ -264,7 +264,7 @@ def barrier(ctx, rounds: int = 10_000, lanes: int = 256, seed: int = 42, quick: 
 SEMS = [("spin", {}), ("spin_backoff", {"backoff": "exp", "backoff_max": 8192, "post_backoff": 0}),
         ("ticket", {}), ("sleep", {}),
         ("counters", {}), ("adaptive", {}), ("cohort", {}), ("array", {}),
-        ("chain", {}), ("xcd_chain", {})]
+        ("chain", {}), ("xcd_chain", {}), ("cu_lock", {})]
 
 
 def sem(ctx, budget_s: float = 0.3, nwg: int = 2048, lanes: int = 256, seed: int = 42,

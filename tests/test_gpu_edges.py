@@ -81,6 +81,17 @@ def _sem_quiescent(r, kind, K, total):
         assert r["unserved"] == 0
 
 
+@pytest.mark.parametrize("nwg,total", [(1, 0), (64, 0), (1, 50), (64, 5), (37, 1001),
+                                       (2048, 3001)])
+def test_cu_lock_semaphore_few_operations(ctx, nwg, total):
+    """The K = 1 CU-cohort-lock semaphore with no work, fewer pairs than workgroups and a
+    ragged split."""
+    r = _sem(ctx, "cu_lock", 1, nwg, total, 17)
+    want = oracle.sem_closed(17, nwg, total)
+    assert (r["chk"] == want).all()
+    _sem_quiescent(r, "cu_lock", 1, total)
+
+
 @pytest.mark.parametrize("kind", SEMS)
 @pytest.mark.parametrize("K", [1, 3])
 @pytest.mark.parametrize("nwg,total", [(1, 0), (64, 0), (1, 50), (64, 5), (37, 1001)])

@@ -197,10 +197,38 @@ def test_xcd_chain_range(ctx):
         own.close()
 
 
+@pytest.mark.parametrize("coherent", [0, 1])
+def test_cu_lock_full_size(ctx, coherent):
+    """K = 1 as the CU-cohort lock at config 4 (2048 workgroups, 2^20 pairs, holds U[0,
+    2000]): the guarded word counts every admission although hand-overs within a CU skip
+    all cache maintenance; occupancy 1, counters quiescent."""
+    nwg, total, seed = 2048, 1 << 20, 0xC0FFEE
+    r = _run(ctx, "cu_lock", 1, nwg, 256, total, 2000, seed, coherent_cs=coherent)
+    _check(r, "cu_lock", 1, nwg, total, seed)
+
+
+@pytest.mark.parametrize("pad", [4, 4096])
+def test_cu_lock_padding(ctx, pad):
+    r = _run(ctx, "cu_lock", 1, 2048, 256, 1 << 16, 500, 0x51, pad_bytes=pad)
+    _check(r, "cu_lock", 1, 2048, 1 << 16, 0x51)
+
+
+def test_cu_lock_range_and_default(ctx):
+    """Only K = 1 is accepted; a default semaphore whose bucket names the per-XCD chains
+    runs the CU-cohort lock at K = 1 from two workgroups per CU (one set of chains below),
+    the guarded word exact either way."""
+    import paper_1110_4623_amd as sp
+    with pytest.raises(sp.SpError):
+        sp.Semaphore(ctx, "cu_lock", 2)
+    for nwg in (64, 256, 512, 2048):
+        r = _run(ctx, "default", 1, nwg, 256, 1 << 14, 500, 21)
+        _check(r, "cu_lock" if nwg >= 512 else "chain", 1, nwg, 1 << 14, 21)
+
+
 @pytest.mark.parametrize("kind", ["array", "chain", "xcd_chain"])
 @pytest.mark.parametrize("pad", [4, 4096])
 def test_slot_kinds_with_small_and_large_padding(ctx, kind, pad):
-    """The grant slots and 64-bit counters at 4-byte padding (lines two words apart, still
+    """The grant slots and 64-bit counters at 4-byte padding (lines four words apart, still
     8-byte aligned) and 4 KiB padding: pool data exact, bound and counters."""
     nwg, total, seed = 2048, 1 << 16, 0x9AD
     r = _run(ctx, kind, 32, nwg, 256, total, 500, seed, pad_bytes=pad)
