@@ -343,8 +343,8 @@ __device__ bool mutex_lock(const MutexState& s, uint32_t lock, const Ctl& ctl,
 }
 
 // `hold`: the record mutex_lock filled in (leader's copy).  It may be nullptr except for
-// SP_MUTEX_ARRAY and SP_MUTEX_COHORT: the ticket and ring mutexes then load turn / head
-// to find the value to publish.  `ctl` bounds SP_MUTEX_MCS's wait for a successor that
+// SP_MUTEX_ARRAY, SP_MUTEX_COHORT and SP_MUTEX_CU_COHORT (whose mutex_lock needs it too):
+// the ticket and ring mutexes then load turn / head to find the value to publish.  `ctl` bounds SP_MUTEX_MCS's wait for a successor that
 // has taken the tail but not linked in yet (no other kind waits in unlock).
 template <int KIND, bool FENCED = true>
 __device__ void mutex_unlock(const MutexState& s, uint32_t lock, const MutexHold* hold = nullptr,
