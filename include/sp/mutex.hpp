@@ -171,6 +171,16 @@ __device__ __forceinline__ uint32_t* mcs_node(const MutexState& s, uint32_t lock
 //                         grants the local turn with session 0.  Cohorts are the actual
 //                         XCDs (XCC id), never merged: the local hand-over relies on the
 //                         shared L2.
+//   SP_MUTEX_CU_COHORT    CU-cohort lock: SP_MUTEX_COHORT behind a ticket lock per CU.  A
+//                         waiter draws a CU ticket, announces it in the CU's record line
+//                         and polls the CU's grant word at workgroup scope (in the CU's
+//                         L1).  Session k > 0: the CU's cohort holds the XCD lock (the
+//                         record says how), enter with no cache maintenance, since the
+//                         previous holder's stores went through this L1.  Session 0: take
+//                         the XCD-cohort lock, acquire, write the record.  Unlock passes
+//                         within the CU (session k + 1) when a later CU ticket was
+//                         announced and k + 1 < cohort_bound, else hands the XCD lock on
+//                         and grants session 0.
 //   SP_MUTEX_MCS          MCS queue lock: each workgroup has a node per lock (next, locked)
 //                         in its own line; lock stores next = none and locked = 1, then
 //                         exchanges the lock word (the queue's tail) with its node id;
